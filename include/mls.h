@@ -1,0 +1,205 @@
+/*
+ * mls.h -- C ABI of the MI355X moving-least-squares immersed-boundary
+ * transfer library (libmls_hip.so).
+ *
+ * Method: V. Spandan, D. Lohse, M. D. de Tullio, R. Verzicco, "A fast moving
+ * least squares approximation with adaptive Lagrangian mesh refinement for
+ * large scale immersed boundary simulations", arXiv:1805.01113, Sec. 2.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Marker and field arrays are DEVICE pointers owned by the caller; the
+ *    library never frees them and never allocates caller-visible memory.
+ *    Host pointers appear only in mls_grid (copied at context creation) and in
+ *    the out-parameters of mls_sync / mls_stats_get / mls_*_info.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  Every
+ *    compute entry point only enqueues work on that stream and returns.
+ *  - Argument errors are detected on the host and returned at once, nothing
+ *    is enqueued.  Errors found on the device (support outside a wall axis,
+ *    singular moment matrix, out-of-range force) set a sticky device error
+ *    word holding the lowest offending marker index; mls_sync reports it.
+ *  - Staggered grid (marker-and-cell): velocity component c (0=u, 1=v, 2=w)
+ *    lives on the cell faces along axis c and on the cell centres along the
+ *    other two axes.  Axis d has n[d] cells with face coordinates
+ *    faces[d][0..n[d]].  On a periodic axis a component has n[d] nodes; on a
+ *    wall axis the face component has n[d]+1 nodes (both walls included).
+ *    Fields are C-order arrays [z][y][x] of FP32 over a component's nodes.
+ *  - Support (Sec. 2, text of figure 1): the home node of the marker plus its
+ *    neighbours, 3 per axis (N_e = 27), on each component's own grid.  The
+ *    home node is the one whose control volume contains the marker
+ *    (half-open [lo, hi): ties go to the upper node).  A centre node owns its
+ *    cell; a face node owns the interval between the two adjacent centres.
+ *    Periodic coordinates are wrapped in FP64.
+ *  - Shape-function layout (SoA): phi[(c*27 + k)*n + l] is the FP32 weight of
+ *    support node k of marker l for component c, with
+ *    k = (a_x+1) + 3 (a_y+1) + 9 (a_z+1) and a_d in {-1,0,1} the node offset
+ *    from the home node.  home[c*n + l] packs the wrapped home node indices of
+ *    component c as i | j << 11 | k << 22 (so a component grid may have at
+ *    most 2048 x 2048 x 1024 nodes).
+ *  - Calls on one context are not thread-safe; issue them from one thread.
+ */
+#ifndef MLS_H
+#define MLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mls_ctx mls_ctx;
+
+typedef enum {
+    MLS_OK = 0,
+    MLS_E_ARG = -1,        /* invalid argument (host check) */
+    MLS_E_SUPPORT = -2,    /* a 3-node support leaves a wall axis (device) */
+    MLS_E_SINGULAR = -3,   /* moment matrix not positive definite even in FP64 (device) */
+    MLS_E_NONFINITE = -4,  /* non-finite marker coordinate (device) */
+    MLS_E_HIP = -5,        /* HIP runtime error */
+    MLS_E_NOMEM = -6,      /* device allocation failed */
+    MLS_E_RANGE = -7       /* a spread contribution exceeds the fixed-point range (device) */
+} mls_status;
+
+typedef enum {
+    MLS_W_GAUSS_SHIFTED = 0, /* w(s) = max(0, exp(-(s/eps)^2) - exp(-(R/eps)^2)) per axis (default) */
+    MLS_W_GAUSS = 1,         /* w(s) = exp(-(s/eps)^2) per axis */
+    MLS_W_CONST = 2          /* w = 1 */
+} mls_weight_kind;
+
+typedef enum {
+    MLS_EXACT = 0,   /* eq. 3-6 per marker */
+    MLS_FAST = 1,    /* eq. 9-10: Shepard blend of a sub-node table */
+    MLS_LEARNED = 2  /* MLP surrogate with exact-MLS fallback */
+} mls_method;
+
+/* The Eulerian grid as the paper states the problem (Sec. 2): per axis the
+ * cell count, a periodic flag and the n[d]+1 increasing face coordinates
+ * (HOST pointers, FP64, copied by mls_ctx_create).  At most one axis may be
+ * non-uniform (the paper's grid stretched in one direction). */
+typedef struct {
+    int32_t n[3];
+    int32_t periodic[3];
+    const double *faces[3];
+} mls_grid;
+
+/* Weight function W of eq. 2-4 as a tensor product of 1-D weights of the
+ * node offset s measured in units of the local spacing H_d = half the
+ * distance between the outer support nodes on axis d.  The paper leaves the
+ * form open (Sec. 2, after eq. 2); eps = 1, radius = 1.5 is the default. */
+typedef struct {
+    int32_t kind;     /* mls_weight_kind */
+    double eps;
+    double radius;
+} mls_weight;
+
+typedef struct {
+    double kappa_tau;     /* FP32 moment-matrix solves with 1-norm condition
+                             number above this are redone in FP64 (default 1e6;
+                             0 routes every solve to FP64) */
+    int32_t n_sub;        /* fast-MLS sub-nodes per axis of the home control
+                             volume, boundaries included (default 9 -> 729) */
+    double fallback_tol;  /* learned: consistency residual above which the
+                             marker falls back to exact MLS (default 1e-4) */
+} mls_opts;
+
+typedef struct {
+    int64_t fp64_solves;     /* (marker, component) solves routed to FP64 */
+    int64_t fallbacks;       /* learned: (marker, component) fallbacks to exact */
+    int64_t learned;         /* learned: (marker, component) accepted */
+    double kappa_max;        /* largest FP32 kappa_1 seen (0 if none) */
+    int64_t spread_entries;  /* (tile, marker) pairs of the last spread */
+    int64_t spread_tiles;    /* tiles of the forcing grid */
+} mls_stats;
+
+/* Library version string. */
+const char *mls_version(void);
+
+/* Create a context on the current HIP device for one grid, weight and
+ * option set.  Copies the grid (host FP64) to the device, precomputes node
+ * coordinates and control-volume widths, and sizes the spreading tiles.
+ * weight/opts may be NULL for the defaults.  Returns MLS_E_ARG for a grid
+ * that is not increasing, has fewer than 3 cells on an axis, exceeds the
+ * packed-index limits, has more than one non-uniform axis, or a periodic axis
+ * whose cell count is neither <= 16 nor a multiple of 4. */
+mls_status mls_ctx_create(mls_ctx **ctx, const mls_grid *grid, const mls_weight *weight,
+                          const mls_opts *opts);
+void mls_ctx_destroy(mls_ctx *ctx);
+
+/* Reserve device scratch for up to n_markers markers so that later calls
+ * with at most that many markers allocate nothing (needed before capturing
+ * a step in a HIP graph). */
+mls_status mls_reserve(mls_ctx *ctx, int64_t n_markers);
+
+/* Transfer-function build (Sec. 2, eq. 1-6 exact; eq. 9-10 fast).
+ * For n markers at x,y,z (device FP32 SoA, any position on periodic axes):
+ * writes home[3][n] (packed home indices, see above), phi[3][27][n] (FP32
+ * shape functions, Phi^T = p^T A^-1 B of eq. 6 in marker-centred, spacing-
+ * scaled coordinates, which gives the same Phi as the paper's absolute basis)
+ * and, if route != NULL, route[3][n] (bit 0: FP64 solve, bit 1: learned
+ * accepted, bit 2: learned fell back to exact).  MLS_EXACT assembles the 4x4
+ * moment matrix A = sum_k W_k p_k p_k^T (eq. 3) per (marker, component),
+ * solves it in FP32 and redoes the solve in FP64 when its condition number
+ * exceeds opts.kappa_tau.  MLS_FAST builds, on first use, the tables of exact
+ * shape functions at the n_sub^3 sub-nodes of the home control volume (one
+ * table on a uniform grid, one per plane and staggering type along a
+ * stretched axis, Sec. 2 last paragraph) and blends the 8 corners of the
+ * enclosing sub-cell with inverse-square-distance (Shepard) weights, eq. 9-10.
+ * MLS_LEARNED requires a loaded network (mls_mlp_load).  Markers whose
+ * support leaves a wall axis get NaN phi and raise MLS_E_SUPPORT. */
+mls_status mls_build(mls_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
+                     int32_t method, uint32_t *home, float *phi, uint8_t *route, void *stream);
+
+/* Interpolation Q = Phi^T q (eq. 6) of the three staggered velocity fields
+ * u, v, w (device FP32, component grids as above) onto the n markers:
+ * U[l] = sum_k phi[0][k][l] u[node_k], likewise V from v, W from w.
+ * home/phi as written by mls_build.  Outputs are FP32 device arrays of n. */
+mls_status mls_interp(mls_ctx *ctx, int64_t n, const uint32_t *home, const float *phi,
+                      const float *u, const float *v, const float *w,
+                      float *U, float *V, float *W, void *stream);
+
+/* Conservative spreading (eq. 7-8) of marker forces onto the grid, ADDED into
+ * fx, fy, fz (device FP32 component fields; zeroing them is the caller's):
+ *   h_l = sum_k phi_k (dx_k + dy_k + dz_k)/3,  dV_l = A_l h_l,
+ *   c_l = dV_l / sum_k phi_k dV_k,            f_k += c_l phi_k F_l,
+ * with dx_k, dy_k, dz_k the control-volume widths of support node k on the
+ * component's grid and dV_k = dx_k dy_k dz_k.  area = A_l (device FP32, n).
+ * The result is bitwise reproducible: markers are binned by tiles of the
+ * forcing grid and each tile sums its contributions in 64-bit fixed point,
+ * whose sum does not depend on order.  A contribution larger than the
+ * fixed-point bound (|c_l phi_k F_l| > 8 max|A_l F_l| / h_min^2, which a
+ * shape function with |phi| <= 2 and sum phi dV close to dV never reaches)
+ * raises MLS_E_RANGE. */
+mls_status mls_spread(mls_ctx *ctx, int64_t n, const uint32_t *home, const float *phi,
+                      const float *area, const float *Fx, const float *Fy, const float *Fz,
+                      float *fx, float *fy, float *fz, void *stream);
+
+/* Synchronise `stream`, then report and clear the device error word.
+ * Returns MLS_OK or the device error; *first_bad (if non-NULL) receives the
+ * lowest offending marker index (or -1). */
+mls_status mls_sync(mls_ctx *ctx, void *stream, int64_t *first_bad);
+
+/* Human-readable description of the last error on this context. */
+const char *mls_last_error(const mls_ctx *ctx);
+
+/* Counters accumulated since creation or the last reset (synchronises the
+ * device). */
+mls_status mls_stats_get(mls_ctx *ctx, mls_stats *out);
+mls_status mls_stats_reset(mls_ctx *ctx);
+
+/* fast-MLS tables (built on first use; this call builds them if needed).
+ * Reports count tables of n_sub^3 rows of row_stride floats each (the 27
+ * shape-function values of a sub-node, then padding), sub-node index
+ * s = jx + n_sub (jy + n_sub jz).  Table t holds home plane t - first[type]
+ * along the stretched axis (type 0: centre-staggered components, 1: the
+ * face-staggered one); on a uniform grid there is one table for all
+ * components and *stretched_axis = -1.  If dst is not NULL, all tables are
+ * copied into it (device, count * n_sub^3 * row_stride floats) on stream. */
+mls_status mls_fast_tables(mls_ctx *ctx, float *dst, int64_t *count, int32_t *row_stride,
+                           int32_t first[2], int32_t *stretched_axis, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLS_H */

@@ -539,13 +539,14 @@ int orc_build_fast(const double *faces, const int32_t *n, const int32_t *periodi
 {
     grid3 g;
     grid_unpack(faces, n, periodic, &g);
-    /* which axes are uniform: all cell widths equal */
+    /* which axes are uniform: all cell widths equal (to 1e-12 relative, the
+       rounding of the face coordinates) */
     int uniform[3];
     for (int d = 0; d < 3; ++d) {
         uniform[d] = 1;
         double w0 = g.f[d][1] - g.f[d][0];
         for (int i = 1; i < g.n[d]; ++i)
-            if (g.f[d][i + 1] - g.f[d][i] != w0) { uniform[d] = 0; break; }
+            if (fabs((g.f[d][i + 1] - g.f[d][i]) - w0) > 1e-12 * w0) { uniform[d] = 0; break; }
     }
     long ns = (long)nsub * nsub * nsub;
     /* table cache keyed by the home indices along non-uniform axes

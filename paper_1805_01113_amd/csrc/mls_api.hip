@@ -1,0 +1,417 @@
+// C ABI of the MLS transfer library: context, argument checks, scratch
+// management and error reporting.  Kernels live in mls_build.hip and
+// mls_transfer.hip.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+
+#include "mls_internal.h"
+
+using namespace mls;
+
+struct mls_ctx {
+    Ctx c;
+};
+
+namespace {
+
+constexpr unsigned long long kNoError = ~0ull;
+
+mls_status fail(mls_ctx *ctx, mls_status st, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+
+mls_status fail(mls_ctx *ctx, mls_status st, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        ctx->c.last_error = buf;
+    }
+    return st;
+}
+
+mls_status hip_fail(mls_ctx *ctx, hipError_t e, const char *what)
+{
+    return fail(ctx, e == hipErrorOutOfMemory ? MLS_E_NOMEM : MLS_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Nodes of component c along axis d.
+int32_t comp_nodes(const Axis &a, int c, int d)
+{
+    return (c == d && !a.periodic) ? a.n + 1 : a.n;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mls_version(void) { return "mls_hip 0.1.0 (gfx950)"; }
+
+mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight *weight, const mls_opts *opts)
+{
+    if (!out || !grid) return MLS_E_ARG;
+    *out = nullptr;
+    auto *ctx = new (std::nothrow) mls_ctx();
+    if (!ctx) return MLS_E_NOMEM;
+    Ctx &c = ctx->c;
+    hipError_t e = hipGetDevice(&c.device);
+    if (e != hipSuccess) { delete ctx; return MLS_E_HIP; }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device) == hipSuccess && cus > 0)
+        c.cu_count = cus;
+
+    // ---- grid checks and host-side geometry ----
+    double hmin = std::numeric_limits<double>::infinity();
+    int nonuniform = 0;
+    for (int d = 0; d < 3; ++d) {
+        const int n = grid->n[d];
+        const double *f = grid->faces[d];
+        if (n < 3 || !f) { delete ctx; return MLS_E_ARG; }
+        c.h_faces[d].assign(f, f + n + 1);
+        for (int i = 0; i <= n; ++i)
+            if (!std::isfinite(f[i]) || (i > 0 && !(f[i] > f[i - 1]))) { delete ctx; return MLS_E_ARG; }
+        c.h_centres[d].resize(n);
+        for (int i = 0; i < n; ++i) c.h_centres[d][i] = 0.5 * (f[i] + f[i + 1]);
+        Axis &a = c.g.ax[d];
+        a.n = n;
+        a.periodic = grid->periodic[d] ? 1 : 0;
+        a.f0 = f[0];
+        a.L = f[n] - f[0];
+        a.inv_h = (double)n / a.L;
+        const double w0 = f[1] - f[0];
+        double wmin = w0, wmax = w0;
+        bool bitwise = true;   // widths equal: one fast-MLS table serves the axis
+        for (int i = 1; i < n; ++i) {
+            const double wi = f[i + 1] - f[i];
+            bitwise = bitwise && (std::fabs(wi - w0) <= 1e-12 * w0);   // equal up to face rounding
+            wmin = std::min(wmin, wi);
+            wmax = std::max(wmax, wi);
+        }
+        a.uniform = (wmax <= wmin * (1.0 + 1e-9)) ? 1 : 0;
+        if (!bitwise) { ++nonuniform; c.stretched_axis = d; }
+        if (a.periodic) {
+            if (n <= kMaxTile) a.tile = n;
+            else if (n % 16 == 0) a.tile = 16;
+            else if (n % 8 == 0) a.tile = 8;
+            else if (n % 4 == 0) a.tile = 4;
+            else { delete ctx; return MLS_E_ARG; }
+        } else {
+            a.tile = kMaxTile;
+        }
+    }
+    if (nonuniform > 1) c.stretched_axis = -2;   // fast-MLS unavailable (more than one stretched axis)
+    for (int cc = 0; cc < 3; ++cc)
+        for (int d = 0; d < 3; ++d) c.g.dims[cc][d] = comp_nodes(c.g.ax[d], cc, d);
+    for (int cc = 0; cc < 3; ++cc)
+        if (c.g.dims[cc][0] > 2048 || c.g.dims[cc][1] > 2048 || c.g.dims[cc][2] > 1024) { delete ctx; return MLS_E_ARG; }
+
+    // control-volume widths (centre nodes: cells; face nodes: between centres)
+    std::vector<float> wc[3], wf[3];
+    for (int d = 0; d < 3; ++d) {
+        const Axis &a = c.g.ax[d];
+        const auto &f = c.h_faces[d];
+        const auto &ce = c.h_centres[d];
+        const int n = a.n;
+        wc[d].resize(n);
+        for (int i = 0; i < n; ++i) {
+            wc[d][i] = (float)(f[i + 1] - f[i]);
+            hmin = std::min(hmin, f[i + 1] - f[i]);
+        }
+        const int nf = a.periodic ? n : n + 1;
+        wf[d].resize(nf);
+        for (int i = 0; i < nf; ++i) {
+            double lo, hi;
+            if (a.periodic) {
+                lo = i == 0 ? ce[n - 1] - a.L : ce[i - 1];
+                hi = ce[i];
+            } else {
+                lo = i == 0 ? f[0] : ce[i - 1];
+                hi = i == n ? f[n] : ce[i];
+            }
+            wf[d][i] = (float)(hi - lo);
+            hmin = std::min(hmin, hi - lo);
+        }
+    }
+    c.g.h_min = hmin;
+    int64_t nt = 1;
+    for (int d = 0; d < 3; ++d) {
+        const Axis &a = c.g.ax[d];
+        const int nn = a.periodic ? a.n : a.n + 1;
+        c.g.ntile[d] = (nn + a.tile - 1) / a.tile;
+        nt *= c.g.ntile[d];
+    }
+    c.g.ntiles = nt;
+
+    // ---- weight and options ----
+    mls_weight wdef = {MLS_W_GAUSS_SHIFTED, 1.0, 1.5};
+    const mls_weight &W = weight ? *weight : wdef;
+    if (W.kind < 0 || W.kind > 2 || !(W.eps > 0.0) || !(W.radius > 0.0)) { delete ctx; return MLS_E_ARG; }
+    c.w.kind = W.kind;
+    c.w.inv_eps = (float)(1.0 / W.eps);
+    c.w.inv_eps_d = 1.0 / W.eps;
+    c.w.cut_d = std::exp(-(W.radius / W.eps) * (W.radius / W.eps));
+    c.w.cut = (float)c.w.cut_d;
+    c.opts.kappa_tau = 1e6;
+    c.opts.n_sub = 9;
+    c.opts.fallback_tol = 1e-4;
+    if (opts) {
+        if (!(opts->kappa_tau >= 0.0) || opts->n_sub < 2 || opts->n_sub > 65 || !(opts->fallback_tol >= 0.0)) {
+            delete ctx;
+            return MLS_E_ARG;
+        }
+        c.opts = *opts;
+    }
+
+    // ---- device geometry block ----
+    size_t bytes = 0;
+    size_t off_f[3], off_c[3], off_wc[3], off_wf[3];
+    auto take = [&](size_t nbytes) { size_t o = bytes; bytes += (nbytes + 255) & ~size_t(255); return o; };
+    for (int d = 0; d < 3; ++d) {
+        off_f[d] = take(c.h_faces[d].size() * sizeof(double));
+        off_c[d] = take(c.h_centres[d].size() * sizeof(double));
+        off_wc[d] = take(wc[d].size() * sizeof(float));
+        off_wf[d] = take(wf[d].size() * sizeof(float));
+    }
+    std::vector<unsigned char> blob(bytes, 0);
+    for (int d = 0; d < 3; ++d) {
+        memcpy(&blob[off_f[d]], c.h_faces[d].data(), c.h_faces[d].size() * sizeof(double));
+        memcpy(&blob[off_c[d]], c.h_centres[d].data(), c.h_centres[d].size() * sizeof(double));
+        memcpy(&blob[off_wc[d]], wc[d].data(), wc[d].size() * sizeof(float));
+        memcpy(&blob[off_wf[d]], wf[d].data(), wf[d].size() * sizeof(float));
+    }
+    e = hipMalloc(&c.geom_block, bytes);
+    if (e != hipSuccess) { delete ctx; return MLS_E_NOMEM; }
+    e = hipMemcpy(c.geom_block, blob.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { hipFree(c.geom_block); delete ctx; return MLS_E_HIP; }
+    auto *base = static_cast<unsigned char *>(c.geom_block);
+    for (int d = 0; d < 3; ++d) {
+        Axis &a = c.g.ax[d];
+        a.faces = reinterpret_cast<const double *>(base + off_f[d]);
+        a.centres = reinterpret_cast<const double *>(base + off_c[d]);
+        a.width_c = reinterpret_cast<const float *>(base + off_wc[d]);
+        a.width_f = reinterpret_cast<const float *>(base + off_wf[d]);
+    }
+    if (hipMalloc((void **)&c.err, sizeof(ErrWord)) != hipSuccess ||
+        hipMalloc((void **)&c.stats, sizeof(DevStats)) != hipSuccess ||
+        hipMalloc((void **)&c.work, 64 * sizeof(uint32_t)) != hipSuccess) {
+        mls_ctx_destroy(ctx);
+        return MLS_E_NOMEM;
+    }
+    const unsigned long long none = kNoError;
+    hipMemcpy(c.err, &none, sizeof(none), hipMemcpyHostToDevice);
+    hipMemset(c.stats, 0, sizeof(DevStats));
+    hipMemset(c.work, 0, 64 * sizeof(uint32_t));
+    const int64_t nb = (nt + 2047) / 2048;
+    if (hipMalloc((void **)&c.tile_count, nt * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void **)&c.tile_off, (nt + 1) * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void **)&c.tile_cursor, nt * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void **)&c.block_sums, (nb + 1) * sizeof(uint32_t)) != hipSuccess) {
+        mls_ctx_destroy(ctx);
+        return MLS_E_NOMEM;
+    }
+    if (hipDeviceSynchronize() != hipSuccess) { mls_ctx_destroy(ctx); return MLS_E_HIP; }
+    *out = ctx;
+    return MLS_OK;
+}
+
+void mls_ctx_destroy(mls_ctx *ctx)
+{
+    if (!ctx) return;
+    Ctx &c = ctx->c;
+    hipDeviceSynchronize();
+    hipFree(c.geom_block);
+    hipFree(c.err);
+    hipFree(c.stats);
+    hipFree(c.tables);
+    hipFree(c.table_geo);
+    hipFree(c.tile_count);
+    hipFree(c.tile_off);
+    hipFree(c.tile_cursor);
+    hipFree(c.block_sums);
+    hipFree(c.entries);
+    hipFree(c.work);
+    delete ctx;
+}
+
+mls_status mls_reserve(mls_ctx *ctx, int64_t n)
+{
+    if (!ctx || n < 0) return MLS_E_ARG;
+    Ctx &c = ctx->c;
+    if (n > (int64_t)0x1fffffff) return fail(ctx, MLS_E_ARG, "too many markers (%lld)", (long long)n);
+    if (n <= c.cap_markers) return MLS_OK;
+    hipDeviceSynchronize();
+    hipFree(c.entries);
+    c.entries = nullptr;
+    c.cap_markers = 0;
+    hipError_t e = hipMalloc((void **)&c.entries, (size_t)8 * (size_t)n * sizeof(uint32_t));
+    if (e != hipSuccess) return hip_fail(ctx, e, "spread scratch");
+    c.cap_markers = n;
+    return MLS_OK;
+}
+
+static mls_status ensure_tables(mls_ctx *ctx, hipStream_t s)
+{
+    Ctx &c = ctx->c;
+    if (c.tables) return MLS_OK;
+    if (c.stretched_axis == -2)
+        return fail(ctx, MLS_E_ARG, "fast-MLS needs a grid stretched along at most one axis");
+    const int64_t rows = (int64_t)c.opts.n_sub * c.opts.n_sub * c.opts.n_sub;
+    if (c.stretched_axis < 0) {
+        c.n_tables = 1;
+        c.table_first[0] = c.table_first[1] = 0;
+    } else {
+        const Axis &a = c.g.ax[c.stretched_axis];
+        const int n0 = a.n;
+        const int n1 = a.periodic ? a.n : a.n + 1;
+        c.table_first[0] = 0;
+        c.table_first[1] = n0;
+        c.n_tables = n0 + n1;
+    }
+    hipError_t e = hipMalloc((void **)&c.tables, (size_t)c.n_tables * rows * kTableStride * sizeof(float));
+    if (e != hipSuccess) { c.tables = nullptr; return hip_fail(ctx, e, "fast-MLS tables"); }
+    e = hipMalloc((void **)&c.table_geo, (size_t)c.n_tables * 6 * sizeof(float));
+    if (e != hipSuccess) { hipFree(c.tables); c.tables = nullptr; return hip_fail(ctx, e, "fast-MLS tables"); }
+    e = launch_table_build(c, s);
+    if (e != hipSuccess) {
+        hipFree(c.tables); hipFree(c.table_geo);
+        c.tables = nullptr; c.table_geo = nullptr;
+        return hip_fail(ctx, e, "fast-MLS table build");
+    }
+    return MLS_OK;
+}
+
+mls_status mls_build(mls_ctx *ctx, int64_t n, const float *x, const float *y, const float *z, int32_t method,
+                     uint32_t *home, float *phi, uint8_t *route, void *stream)
+{
+    if (!ctx) return MLS_E_ARG;
+    if (n < 0 || n > (int64_t)0x1fffffff) return fail(ctx, MLS_E_ARG, "bad marker count %lld", (long long)n);
+    if (n > 0 && (!x || !y || !z || !home || !phi)) return fail(ctx, MLS_E_ARG, "null array");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Ctx &c = ctx->c;
+    hipError_t e;
+    switch (method) {
+    case MLS_EXACT:
+        e = launch_build_exact(c, n, x, y, z, home, phi, route, s);
+        break;
+    case MLS_FAST: {
+        mls_status st = ensure_tables(ctx, s);
+        if (st != MLS_OK) return st;
+        e = launch_build_fast(c, n, x, y, z, home, phi, route, s);
+        break;
+    }
+    default:
+        return fail(ctx, MLS_E_ARG, "unknown or unavailable method %d", method);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "build launch");
+    return MLS_OK;
+}
+
+mls_status mls_interp(mls_ctx *ctx, int64_t n, const uint32_t *home, const float *phi, const float *u,
+                      const float *v, const float *w, float *U, float *V, float *W, void *stream)
+{
+    if (!ctx) return MLS_E_ARG;
+    if (n < 0 || n > (int64_t)0x1fffffff) return fail(ctx, MLS_E_ARG, "bad marker count");
+    if (n > 0 && (!home || !phi || !u || !v || !w || !U || !V || !W)) return fail(ctx, MLS_E_ARG, "null array");
+    hipError_t e = launch_interp(ctx->c, n, home, phi, u, v, w, U, V, W, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(ctx, e, "interp launch");
+    return MLS_OK;
+}
+
+mls_status mls_spread(mls_ctx *ctx, int64_t n, const uint32_t *home, const float *phi, const float *area,
+                      const float *Fx, const float *Fy, const float *Fz, float *fx, float *fy, float *fz,
+                      void *stream)
+{
+    if (!ctx) return MLS_E_ARG;
+    if (n < 0 || n > (int64_t)0x1fffffff) return fail(ctx, MLS_E_ARG, "bad marker count");
+    if (n > 0 && (!home || !phi || !area || !Fx || !Fy || !Fz || !fx || !fy || !fz))
+        return fail(ctx, MLS_E_ARG, "null array");
+    if (n == 0) return MLS_OK;
+    mls_status st = mls_reserve(ctx, n);
+    if (st != MLS_OK) return st;
+    hipError_t e = launch_spread(ctx->c, n, home, phi, area, Fx, Fy, Fz, fx, fy, fz, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(ctx, e, "spread launch");
+    return MLS_OK;
+}
+
+mls_status mls_sync(mls_ctx *ctx, void *stream, int64_t *first_bad)
+{
+    if (first_bad) *first_bad = -1;
+    if (!ctx) return MLS_E_ARG;
+    Ctx &c = ctx->c;
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(ctx, e, "stream synchronize");
+    unsigned long long w = 0;
+    e = hipMemcpy(&w, c.err, sizeof(w), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "error word read");
+    if (w == kNoError) return MLS_OK;
+    const unsigned long long none = kNoError;
+    hipMemcpy(c.err, &none, sizeof(none), hipMemcpyHostToDevice);
+    const int status = -(int)(w & 0xff);
+    const int64_t marker = (int64_t)(w >> 8);
+    if (first_bad) *first_bad = marker;
+    static const char *names[] = {"ok", "argument", "support leaves a wall axis", "singular moment matrix",
+                                  "non-finite coordinate", "hip", "no memory", "spread contribution out of range"};
+    const int idx = -status;
+    return fail(ctx, (mls_status)status, "device error at marker %lld: %s", (long long)marker,
+                (idx >= 0 && idx < 8) ? names[idx] : "unknown");
+}
+
+const char *mls_last_error(const mls_ctx *ctx)
+{
+    return ctx ? ctx->c.last_error.c_str() : "null context";
+}
+
+mls_status mls_stats_get(mls_ctx *ctx, mls_stats *out)
+{
+    if (!ctx || !out) return MLS_E_ARG;
+    Ctx &c = ctx->c;
+    if (hipDeviceSynchronize() != hipSuccess) return MLS_E_HIP;
+    DevStats d;
+    if (hipMemcpy(&d, c.stats, sizeof(d), hipMemcpyDeviceToHost) != hipSuccess) return MLS_E_HIP;
+    out->fp64_solves = (int64_t)d.fp64_solves;
+    out->fallbacks = (int64_t)d.fallbacks;
+    out->learned = (int64_t)d.learned;
+    float km;
+    memcpy(&km, &d.kappa_max_bits, sizeof(km));
+    out->kappa_max = km;
+    uint32_t total = 0;
+    if (c.cap_markers > 0)
+        hipMemcpy(&total, c.tile_off + c.g.ntiles, sizeof(total), hipMemcpyDeviceToHost);
+    out->spread_entries = total;
+    out->spread_tiles = c.g.ntiles;
+    return MLS_OK;
+}
+
+mls_status mls_stats_reset(mls_ctx *ctx)
+{
+    if (!ctx) return MLS_E_ARG;
+    if (hipDeviceSynchronize() != hipSuccess) return MLS_E_HIP;
+    return hipMemset(ctx->c.stats, 0, sizeof(DevStats)) == hipSuccess ? MLS_OK : MLS_E_HIP;
+}
+
+mls_status mls_fast_tables(mls_ctx *ctx, float *dst, int64_t *count, int32_t *row_stride, int32_t first[2],
+                           int32_t *stretched_axis, void *stream)
+{
+    if (!ctx) return MLS_E_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    mls_status st = ensure_tables(ctx, s);
+    if (st != MLS_OK) return st;
+    Ctx &c = ctx->c;
+    if (count) *count = c.n_tables;
+    if (row_stride) *row_stride = kTableStride;
+    if (first) { first[0] = c.table_first[0]; first[1] = c.table_first[1]; }
+    if (stretched_axis) *stretched_axis = c.stretched_axis;
+    if (dst) {
+        const size_t bytes = (size_t)c.n_tables * c.opts.n_sub * c.opts.n_sub * c.opts.n_sub * kTableStride *
+                             sizeof(float);
+        hipError_t e = hipMemcpyAsync(dst, c.tables, bytes, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "table copy");
+    }
+    return MLS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,432 @@
+// Transfer-function build kernels: exact MLS (eq. 3-6) and fast-MLS
+// (eq. 9-10), one lane per marker.
+//
+// A lane locates its marker on the six (axis, staggering type) node sets,
+// evaluates the 1-D weights and moments once per set, and then, for each of
+// the three velocity components, assembles the 4x4 moment matrix from the
+// 1-D moments, solves it in FP32 (FP64 if its condition number exceeds the
+// routing threshold) and writes the 27 shape-function values.  Stores are
+// SoA, so a wavefront writes 64 consecutive floats per (component, node).
+#include "mls_device.h"
+
+namespace mls {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+struct SetGeo {      // one (axis, staggering type) node set of a marker
+    AxisGeo g;
+    float w[3];
+    Moments<float> m;
+};
+
+__device__ __forceinline__ void set_weights(const Weight &W, SetGeo &sg)
+{
+    float m0 = 0.f, m1 = 0.f, m2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float w = weight1(W, sg.g.s[a]);
+        sg.w[a] = w;
+        m0 += w;
+        m1 += w * sg.g.s[a];
+        m2 += w * sg.g.s[a] * sg.g.s[a];
+    }
+    sg.m = {m0, m1, m2};
+}
+
+// FP64 re-solve of one (marker, component): recompute the offsets, weights
+// and moments in FP64 from the position.  Returns false if A is singular.
+__device__ bool solve_fp64(const Grid &g, const Weight &W, int c, const double pos[3], double phi[27])
+{
+    double s[3][3], w[3][3];
+    Moments<double> m[3];
+    for (int d = 0; d < 3; ++d) {
+        axis_offsets_d(g.ax[d], d == c, pos[d], s[d]);
+        double m0 = 0, m1 = 0, m2 = 0;
+        for (int a = 0; a < 3; ++a) {
+            w[d][a] = weight1_d(W, s[d][a]);
+            m0 += w[d][a]; m1 += w[d][a] * s[d][a]; m2 += w[d][a] * s[d][a] * s[d][a];
+        }
+        m[d] = {m0, m1, m2};
+    }
+    double A[10], L[10], gam[4];
+    assemble(m[0], m[1], m[2], A);
+    if (!cholesky4(A, L)) return false;
+    const double e0[4] = {1.0, 0.0, 0.0, 0.0};
+    chol_solve(L, e0, gam);
+    for (int k = 0; k < kNe; ++k) {
+        int a = k % 3, b = (k / 3) % 3, cc = k / 9;
+        double W3 = w[0][a] * w[1][b] * w[2][cc];
+        phi[k] = W3 * (gam[0] + gam[1] * s[0][a] + gam[2] * s[1][b] + gam[3] * s[2][cc]);
+    }
+    return true;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_build_exact(const Grid g, const Weight W, float tau, int64_t n,
+              const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
+              uint32_t *__restrict__ home, float *__restrict__ phi, uint8_t *__restrict__ route,
+              ErrWord *err, DevStats *st)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned long long routed = 0;
+    float kmax = 0.f;
+    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n; l += stride) {
+        const double pos[3] = {(double)x[l], (double)y[l], (double)z[l]};
+        SetGeo sg[3][2];   // [axis][is_face]
+        bool ok = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                ok = ok && axis_geo(g.ax[d], t, pos[d], sg[d][t].g);
+            }
+        }
+        if (!ok) {
+            raise_error(err, l, isfinite(pos[0]) && isfinite(pos[1]) && isfinite(pos[2]) ? MLS_E_SUPPORT
+                                                                                       : MLS_E_NONFINITE);
+            for (int c = 0; c < 3; ++c) {
+                home[(int64_t)c * n + l] = 0xffffffffu;
+                for (int k = 0; k < kNe; ++k) phi[((int64_t)c * kNe + k) * n + l] = __builtin_nanf("");
+                if (route) route[(int64_t)c * n + l] = 0;
+            }
+            continue;
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            set_weights(W, sg[d][0]);
+            set_weights(W, sg[d][1]);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const SetGeo &X = sg[0][c == 0], &Y = sg[1][c == 1], &Z = sg[2][c == 2];
+            home[(int64_t)c * n + l] = pack_home(X.g.ih, Y.g.ih, Z.g.ih);
+            float A[10], L[10], gam[4];
+            assemble(X.m, Y.m, Z.m, A);
+            bool fp32_ok = cholesky4(A, L);
+            float kap = 0.f;
+            if (fp32_ok) {
+                kap = cond1_and_gamma(A, L, gam);
+                fp32_ok = kap <= tau && isfinite(kap);
+                kmax = fmaxf(kmax, isfinite(kap) ? kap : 3.0e38f);
+            }
+            float *out = phi + (int64_t)c * kNe * n + l;
+            if (fp32_ok) {
+#pragma unroll
+                for (int cz = 0; cz < 3; ++cz) {
+#pragma unroll
+                    for (int by = 0; by < 3; ++by) {
+                        const float wyz = Y.w[by] * Z.w[cz];
+                        const float pyz = gam[0] + gam[2] * Y.g.s[by] + gam[3] * Z.g.s[cz];
+#pragma unroll
+                        for (int ax = 0; ax < 3; ++ax) {
+                            const int k = ax + 3 * by + 9 * cz;
+                            out[(int64_t)k * n] = X.w[ax] * wyz * (pyz + gam[1] * X.g.s[ax]);
+                        }
+                    }
+                }
+                if (route) route[(int64_t)c * n + l] = 0;
+            } else {
+                double ph[27];
+                ++routed;
+                if (!solve_fp64(g, W, c, pos, ph)) {
+                    raise_error(err, l, MLS_E_SINGULAR);
+                    for (int k = 0; k < kNe; ++k) out[(int64_t)k * n] = __builtin_nanf("");
+                } else {
+                    for (int k = 0; k < kNe; ++k) out[(int64_t)k * n] = (float)ph[k];
+                }
+                if (route) route[(int64_t)c * n + l] = 1;
+            }
+        }
+    }
+    // one atomic per wavefront for the statistics
+    unsigned long long tot = routed;
+    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+    float km = kmax;
+    for (int off = 32; off > 0; off >>= 1) km = fmaxf(km, __shfl_xor(km, off));
+    if ((threadIdx.x & 63) == 0) {
+        if (tot) atomicAdd(&st->fp64_solves, tot);
+        if (km > 0.f) atomicMax(&st->kappa_max_bits, __float_as_uint(km));
+    }
+}
+
+// ---- fast-MLS --------------------------------------------------------------
+
+// Shepard blend of one component from its table.  xi: in-cell offsets,
+// geo: table's normalised home control volume [lo, hi) per axis.
+__device__ __forceinline__ void shepard(const float *__restrict__ tab, const float *__restrict__ geo,
+                                        int nsub, const float xi[3], float *__restrict__ out, int64_t n)
+{
+    int j0[3];
+    float t0[3], step[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const float lo = geo[2 * d], hi = geo[2 * d + 1];
+        step[d] = (hi - lo) / (float)(nsub - 1);
+        float t = (xi[d] - lo) / (hi - lo) * (float)(nsub - 1);
+        int j = (int)floorf(t);
+        j = min(max(j, 0), nsub - 2);
+        j0[d] = j;
+        t0[d] = lo + (float)j * step[d];
+    }
+    // squared distances to the 8 corners (normalised units)
+    float d2[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        float acc = 0.f;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            float xs = t0[d] + (float)((i >> d) & 1) * step[d];
+            float e = xi[d] - xs;
+            acc += e * e;
+        }
+        d2[i] = acc;
+    }
+    // alpha_i = prod_{j != i} d_j^2 / sum_m prod_{j != m} d_j^2 (eq. 10 in a
+    // form that stays finite when the marker sits on a sub-node)
+    float pre[8], suf[8];
+    pre[0] = 1.f;
+#pragma unroll
+    for (int i = 1; i < 8; ++i) pre[i] = pre[i - 1] * d2[i - 1];
+    suf[7] = 1.f;
+#pragma unroll
+    for (int i = 6; i >= 0; --i) suf[i] = suf[i + 1] * d2[i + 1];
+    float alpha[8], den = 0.f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) { alpha[i] = pre[i] * suf[i]; den += alpha[i]; }
+    const float rden = 1.f / den;
+    const float *row[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int s = (j0[0] + (i & 1)) + nsub * ((j0[1] + ((i >> 1) & 1)) + nsub * (j0[2] + ((i >> 2) & 1)));
+        row[i] = tab + (int64_t)s * kTableStride;
+        alpha[i] *= rden;
+    }
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float4 v = *reinterpret_cast<const float4 *>(row[i] + 4 * q);
+            acc.x += alpha[i] * v.x; acc.y += alpha[i] * v.y; acc.z += alpha[i] * v.z; acc.w += alpha[i] * v.w;
+        }
+        const float vals[4] = {acc.x, acc.y, acc.z, acc.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = 4 * q + e;
+            if (k < kNe) out[(int64_t)k * n] = vals[e];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_build_fast(const Grid g, const FastTables T, int64_t n,
+             const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
+             uint32_t *__restrict__ home, float *__restrict__ phi, uint8_t *__restrict__ route, ErrWord *err)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t rows = (int64_t)T.n_sub * T.n_sub * T.n_sub;
+    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n; l += stride) {
+        const double pos[3] = {(double)x[l], (double)y[l], (double)z[l]};
+        AxisGeo ag[3][2];
+        bool ok = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int t = 0; t < 2; ++t) ok = ok && axis_geo(g.ax[d], t, pos[d], ag[d][t]);
+        if (!ok) {
+            raise_error(err, l, isfinite(pos[0]) && isfinite(pos[1]) && isfinite(pos[2]) ? MLS_E_SUPPORT
+                                                                                       : MLS_E_NONFINITE);
+            for (int c = 0; c < 3; ++c) {
+                home[(int64_t)c * n + l] = 0xffffffffu;
+                for (int k = 0; k < kNe; ++k) phi[((int64_t)c * kNe + k) * n + l] = __builtin_nanf("");
+                if (route) route[(int64_t)c * n + l] = 0;
+            }
+            continue;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const AxisGeo &X = ag[0][c == 0], &Y = ag[1][c == 1], &Z = ag[2][c == 2];
+            home[(int64_t)c * n + l] = pack_home(X.ih, Y.ih, Z.ih);
+            int t = 0;
+            if (T.stretched_axis >= 0) {
+                const int d = T.stretched_axis;
+                const int ih = d == 0 ? X.ih : (d == 1 ? Y.ih : Z.ih);
+                t = T.first[c == d] + ih;
+            }
+            const float xi[3] = {X.xi, Y.xi, Z.xi};
+            shepard(T.tab + (int64_t)t * rows * kTableStride, T.geo + (int64_t)t * 6, T.n_sub, xi,
+                    phi + (int64_t)c * kNe * n + l, n);
+            if (route) route[(int64_t)c * n + l] = 0;
+        }
+    }
+}
+
+// Table build: one lane per (table, sub-node); exact MLS in FP64 at the
+// sub-node from the table's normalised support geometry.
+//   geo_in[t][d][0..2]: support node positions relative to the home node (units of H)
+//   geo_in[t][d][3..4]: home control volume lo, hi in the same units
+__global__ void __launch_bounds__(kBlock)
+k_table_build(const Weight W, int64_t count, int nsub, const double *__restrict__ geo_in,
+              float *__restrict__ tab, float *__restrict__ geo_out)
+{
+    const int64_t rows = (int64_t)nsub * nsub * nsub;
+    const int64_t total = count * rows;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = i / rows;
+        const int64_t s = i % rows;
+        const double *G = geo_in + t * 15;
+        int j[3] = {(int)(s % nsub), (int)((s / nsub) % nsub), (int)(s / ((int64_t)nsub * nsub))};
+        double off[3][3], w[3][3];
+        Moments<double> m[3];
+        for (int d = 0; d < 3; ++d) {
+            const double lo = G[d * 5 + 3], hi = G[d * 5 + 4];
+            const double xs = lo + (double)j[d] * (hi - lo) / (double)(nsub - 1);
+            double m0 = 0, m1 = 0, m2 = 0;
+            for (int a = 0; a < 3; ++a) {
+                off[d][a] = G[d * 5 + a] - xs;
+                w[d][a] = weight1_d(W, off[d][a]);
+                m0 += w[d][a]; m1 += w[d][a] * off[d][a]; m2 += w[d][a] * off[d][a] * off[d][a];
+            }
+            m[d] = {m0, m1, m2};
+        }
+        double A[10], L[10], gam[4] = {0, 0, 0, 0};
+        assemble(m[0], m[1], m[2], A);
+        const bool ok = cholesky4(A, L);
+        const double e0[4] = {1.0, 0.0, 0.0, 0.0};
+        if (ok) chol_solve(L, e0, gam);
+        float *row = tab + i * kTableStride;
+        for (int k = 0; k < kNe; ++k) {
+            int a = k % 3, b = (k / 3) % 3, cc = k / 9;
+            double v = w[0][a] * w[1][b] * w[2][cc] *
+                       (gam[0] + gam[1] * off[0][a] + gam[2] * off[1][b] + gam[3] * off[2][cc]);
+            row[k] = ok ? (float)v : __builtin_nanf("");
+        }
+        row[kNe] = 0.f;
+        if (s == 0) {
+            for (int d = 0; d < 3; ++d) {
+                geo_out[t * 6 + 2 * d] = (float)G[d * 5 + 3];
+                geo_out[t * 6 + 2 * d + 1] = (float)G[d * 5 + 4];
+            }
+        }
+    }
+}
+
+int grid_for(int64_t work, int cu)
+{
+    int64_t b = (work + kBlock - 1) / kBlock;
+    const int64_t cap = (int64_t)cu * 32;   // enough resident waves; lanes loop beyond
+    if (b > cap) b = cap;
+    return (int)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+hipError_t launch_build_exact(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
+                              uint32_t *home, float *phi, uint8_t *route, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const float tau = (float)(c.opts.kappa_tau > 3.0e38 ? 3.0e38 : c.opts.kappa_tau);
+    hipLaunchKernelGGL(k_build_exact, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.g, c.w, tau, n,
+                       x, y, z, home, phi, route, c.err, c.stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_fast(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
+                             uint32_t *home, float *phi, uint8_t *route, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_build_fast, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.g, fast_tables(c), n,
+                       x, y, z, home, phi, route, c.err);
+    return hipGetLastError();
+}
+
+// Host side of the table build: the normalised support geometry of every
+// table (uniform grid: one table; stretched axis: one per home plane and
+// staggering type) is derived from the host copy of the grid, then the
+// device computes the shape functions at the sub-nodes.
+hipError_t launch_table_build(const Ctx &c, hipStream_t s)
+{
+    const Grid &g = c.g;
+    const int d_s = c.stretched_axis;
+    std::vector<double> geo((size_t)c.n_tables * 15);
+    auto host_node = [&](int d, int is_face, long i) -> double {
+        const Axis &a = g.ax[d];
+        double shift = 0.0;
+        if (a.periodic) {
+            if (i < 0) { i += a.n; shift = -1.0; }
+            else if (i >= a.n) { i -= a.n; shift = 1.0; }
+        }
+        double v = is_face ? c.h_faces[d][i] : c.h_centres[d][i];
+        return v + shift * a.L;
+    };
+    auto fill = [&](int64_t t, const long ih[3], const int is_face[3]) {
+        for (int d = 0; d < 3; ++d) {
+            const Axis &a = g.ax[d];
+            double xm = host_node(d, is_face[d], ih[d] - 1);
+            double x0 = host_node(d, is_face[d], ih[d]);
+            double xp = host_node(d, is_face[d], ih[d] + 1);
+            double H = 0.5 * (xp - xm);
+            double lo, hi;
+            if (!is_face[d]) {
+                lo = host_node(d, 1, ih[d]);
+                hi = host_node(d, 1, ih[d] + 1);
+            } else {
+                lo = (!a.periodic && ih[d] == 0) ? c.h_faces[d][0] : host_node(d, 0, ih[d] - 1);
+                hi = (!a.periodic && ih[d] == a.n) ? c.h_faces[d][a.n] : host_node(d, 0, ih[d]);
+            }
+            double *G = &geo[(size_t)t * 15 + d * 5];
+            G[0] = (xm - x0) / H;
+            G[1] = 0.0;
+            G[2] = (xp - x0) / H;
+            G[3] = (lo - x0) / H;
+            G[4] = (hi - x0) / H;
+        }
+    };
+    if (d_s < 0) {
+        long ih[3] = {1, 1, 1};
+        int tf[3] = {0, 0, 0};
+        fill(0, ih, tf);
+    } else {
+        for (int type = 0; type < 2; ++type) {
+            const Axis &a = g.ax[d_s];
+            const int nodes = (type && !a.periodic) ? a.n + 1 : a.n;
+            for (int p = 0; p < nodes; ++p) {
+                long ih[3] = {1, 1, 1};
+                int tf[3] = {0, 0, 0};
+                ih[d_s] = p;
+                tf[d_s] = type;
+                // planes whose support would leave a wall get a table that is never used
+                if (!a.periodic && (p < 1 || p + 1 > (type ? a.n : a.n - 1))) ih[d_s] = 1;
+                fill(c.table_first[type] + p, ih, tf);
+            }
+        }
+    }
+    double *d_geo = nullptr;
+    hipError_t e = hipMalloc((void **)&d_geo, geo.size() * sizeof(double));
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(d_geo, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) { hipFree(d_geo); return e; }
+    const int64_t rows = (int64_t)c.opts.n_sub * c.opts.n_sub * c.opts.n_sub;
+    hipLaunchKernelGGL(k_table_build, dim3(grid_for(c.n_tables * rows, c.cu_count)), dim3(kBlock), 0, s, c.w,
+                       c.n_tables, (int)c.opts.n_sub, d_geo, c.tables, c.table_geo);
+    e = hipGetLastError();
+    const hipError_t e2 = hipStreamSynchronize(s);
+    hipFree(d_geo);
+    return e != hipSuccess ? e : e2;
+}
+
+FastTables fast_tables(const Ctx &c)
+{
+    FastTables t;
+    t.tab = c.tables;
+    t.geo = c.table_geo;
+    t.n_sub = c.opts.n_sub;
+    t.stretched_axis = c.stretched_axis;
+    t.first[0] = c.table_first[0];
+    t.first[1] = c.table_first[1];
+    return t;
+}
+
+}  // namespace mls

@@ -1,0 +1,298 @@
+// Device helpers: support selection on the staggered grid (Sec. 2), the
+// weight function, the 4x4 moment-matrix solve and the device error word.
+#pragma once
+
+#include "mls_internal.h"
+
+namespace mls {
+
+// Geometry of the 3-node support along one axis for one staggering type.
+struct AxisGeo {
+    int32_t ih;      // wrapped home node index
+    float s[3];      // (X_a - X)/H for a = -1, 0, +1
+    float xi;        // (X - X_0)/H
+};
+
+__device__ __forceinline__ void raise_error(ErrWord *err, int64_t marker, int status)
+{
+    unsigned long long w = ((unsigned long long)marker << 8) | (unsigned long long)(-status & 0xff);
+    atomicMin(&err->word, w);
+}
+
+// Unwrapped node coordinate.  i ranges over [-1, n+1] for periodic axes.
+// Kept free of fused multiply-adds so that the coordinates are the plain
+// IEEE results of their definitions.
+#pragma clang fp contract(off)
+__device__ __forceinline__ double face_x(const Axis &a, int i)
+{
+    double shift = 0.0;
+    if (a.periodic) {
+        if (i < 0) { i += a.n; shift = -1.0; }
+        else if (i >= a.n) { i -= a.n; shift = 1.0; }
+    }
+    return a.faces[i] + shift * a.L;
+}
+
+__device__ __forceinline__ double centre_x(const Axis &a, int i)
+{
+    double shift = 0.0;
+    if (a.periodic) {
+        if (i < 0) { i += a.n; shift = -1.0; }
+        else if (i >= a.n) { i -= a.n; shift = 1.0; }
+    }
+    return a.centres[i] + shift * a.L;
+}
+
+__device__ __forceinline__ double node_x(const Axis &a, int is_face, int i)
+{
+    return is_face ? face_x(a, i) : centre_x(a, i);
+}
+
+// Periodic wrap of x into [f0, f0 + L).
+__device__ __forceinline__ double wrap_x(const Axis &a, double x)
+{
+    double t = floor((x - a.f0) / a.L);
+    double X = x - t * a.L;
+    if (X >= a.f0 + a.L) X -= a.L;
+    if (X < a.f0) X += a.L;
+    return X;
+}
+
+// Home node along one axis: the node whose control volume [lo, hi) contains
+// the marker.  Returns false if the support leaves a wall axis or x is not
+// finite.  On success ih_u is the unwrapped home index (a periodic face axis
+// may return n, node 0 shifted by L) and X the wrapped coordinate.
+__device__ __forceinline__ bool locate(const Axis &a, int is_face, double x, int &ih_u, double &X)
+{
+    if (!isfinite(x)) return false;
+    const int n = a.n;
+    if (a.periodic) {
+        X = wrap_x(a, x);
+    } else {
+        X = x;
+        if (!(X >= a.faces[0] && X <= a.faces[n])) return false;
+    }
+    int i;
+    if (!is_face) {
+        if (X >= a.faces[n]) return false;
+        if (a.uniform) {
+            i = (int)floor((X - a.f0) * a.inv_h);
+            i = min(max(i, 0), n - 1);
+            while (i > 0 && X < a.faces[i]) --i;
+            while (i < n - 1 && X >= a.faces[i + 1]) ++i;
+        } else {
+            int lo = 0, hi = n;   // faces[lo] <= X < faces[hi]
+            while (hi - lo > 1) {
+                int mid = (lo + hi) >> 1;
+                if (a.faces[mid] <= X) lo = mid; else hi = mid;
+            }
+            i = lo;
+        }
+    } else {
+        if (X < a.centres[0]) {
+            i = 0;
+        } else if (X >= a.centres[n - 1]) {
+            i = n;
+        } else if (a.uniform) {
+            // centres[i-1] <= X < centres[i], i in [1, n-1]
+            i = (int)floor((X - a.f0) * a.inv_h + 0.5);
+            i = min(max(i, 1), n - 1);
+            while (i > 1 && X < a.centres[i - 1]) --i;
+            while (i < n - 1 && X >= a.centres[i]) ++i;
+        } else {
+            int lo = 0, hi = n - 1;   // centres[lo] <= X < centres[hi]
+            while (hi - lo > 1) {
+                int mid = (lo + hi) >> 1;
+                if (a.centres[mid] <= X) lo = mid; else hi = mid;
+            }
+            i = hi;
+        }
+    }
+    if (!a.periodic) {
+        const int last = is_face ? n : n - 1;
+        if (i - 1 < 0 || i + 1 > last) return false;
+    }
+    ih_u = i;
+    return true;
+}
+
+// Support geometry along one axis (FP64 offsets, rounded to FP32 after the
+// subtraction so that stretched axes keep their digits).
+__device__ __forceinline__ bool axis_geo(const Axis &a, int is_face, double x, AxisGeo &g)
+{
+    int ih;
+    double X;
+    if (!locate(a, is_face, x, ih, X)) return false;
+    double xm = node_x(a, is_face, ih - 1);
+    double x0 = node_x(a, is_face, ih);
+    double xp = node_x(a, is_face, ih + 1);
+    double H = 0.5 * (xp - xm);
+    g.s[0] = (float)((xm - X) / H);
+    g.s[1] = (float)((x0 - X) / H);
+    g.s[2] = (float)((xp - X) / H);
+    g.xi = (float)((X - x0) / H);
+    g.ih = (a.periodic && ih >= a.n) ? ih - a.n : ih;
+    return true;
+}
+
+// FP64 offsets for the rare FP64 route (recomputed from the position).
+__device__ __forceinline__ void axis_offsets_d(const Axis &a, int is_face, double x, double s[3])
+{
+    int ih;
+    double X;
+    locate(a, is_face, x, ih, X);
+    double xm = node_x(a, is_face, ih - 1);
+    double x0 = node_x(a, is_face, ih);
+    double xp = node_x(a, is_face, ih + 1);
+    double H = 0.5 * (xp - xm);
+    s[0] = (xm - X) / H;
+    s[1] = (x0 - X) / H;
+    s[2] = (xp - X) / H;
+}
+#pragma clang fp contract(on)
+
+// ---- weight function ------------------------------------------------------
+
+__device__ __forceinline__ float weight1(const Weight &w, float s)
+{
+    if (w.kind == MLS_W_CONST) return 1.0f;
+    float t = s * w.inv_eps;
+    float g = expf(-t * t);
+    if (w.kind == MLS_W_GAUSS) return g;
+    return fmaxf(g - w.cut, 0.0f);
+}
+
+__device__ __forceinline__ double weight1_d(const Weight &w, double s)
+{
+    if (w.kind == MLS_W_CONST) return 1.0;
+    double t = s * w.inv_eps_d;
+    double g = exp(-t * t);
+    if (w.kind == MLS_W_GAUSS) return g;
+    return fmax(g - w.cut_d, 0.0);
+}
+
+// ---- moment matrix --------------------------------------------------------
+// With a tensor-product weight W_k = wx(a) wy(b) wz(c) the moment matrix of
+// eq. 3 with p = [1, s_x, s_y, s_z] follows from three 1-D moments per axis,
+// m0 = sum w, m1 = sum w s, m2 = sum w s^2:
+//   A00 = m0x m0y m0z, A0x = m1x m0y m0z, Axx = m2x m0y m0z,
+//   Axy = m1x m1y m0z, ... (10 unique entries of the symmetric 4x4).
+
+template <typename T>
+struct Moments { T m0, m1, m2; };
+
+template <typename T>
+__device__ __forceinline__ void assemble(const Moments<T> mx, const Moments<T> my, const Moments<T> mz, T A[10])
+{
+    // A stored as a00 a01 a02 a03 a11 a12 a13 a22 a23 a33
+    A[0] = mx.m0 * my.m0 * mz.m0;
+    A[1] = mx.m1 * my.m0 * mz.m0;
+    A[2] = mx.m0 * my.m1 * mz.m0;
+    A[3] = mx.m0 * my.m0 * mz.m1;
+    A[4] = mx.m2 * my.m0 * mz.m0;
+    A[5] = mx.m1 * my.m1 * mz.m0;
+    A[6] = mx.m1 * my.m0 * mz.m1;
+    A[7] = mx.m0 * my.m2 * mz.m0;
+    A[8] = mx.m0 * my.m1 * mz.m1;
+    A[9] = mx.m0 * my.m0 * mz.m2;
+}
+
+// Cholesky factor of the symmetric 4x4 A (10 entries).  Returns false if A is
+// not numerically positive definite.  L stored row-wise lower: l00 l10 l11
+// l20 l21 l22 l30 l31 l32 l33; the diagonal holds 1/l_ii.
+template <typename T>
+__device__ __forceinline__ bool cholesky4(const T A[10], T L[10])
+{
+    T d0 = A[0];
+    if (!(d0 > T(0))) return false;
+    T l00 = sqrt(d0), r0 = T(1) / l00;
+    T l10 = A[1] * r0, l20 = A[2] * r0, l30 = A[3] * r0;
+    T d1 = A[4] - l10 * l10;
+    if (!(d1 > T(0))) return false;
+    T l11 = sqrt(d1), r1 = T(1) / l11;
+    T l21 = (A[5] - l20 * l10) * r1;
+    T l31 = (A[6] - l30 * l10) * r1;
+    T d2 = A[7] - l20 * l20 - l21 * l21;
+    if (!(d2 > T(0))) return false;
+    T l22 = sqrt(d2), r2 = T(1) / l22;
+    T l32 = (A[8] - l30 * l20 - l31 * l21) * r2;
+    T d3 = A[9] - l30 * l30 - l31 * l31 - l32 * l32;
+    if (!(d3 > T(0))) return false;
+    T r3 = T(1) / sqrt(d3);
+    L[0] = r0; L[1] = l10; L[2] = r1; L[3] = l20; L[4] = l21; L[5] = r2;
+    L[6] = l30; L[7] = l31; L[8] = l32; L[9] = r3;
+    return true;
+}
+
+// Solve A x = b with the factor above.
+template <typename T>
+__device__ __forceinline__ void chol_solve(const T L[10], const T b[4], T x[4])
+{
+    T y0 = b[0] * L[0];
+    T y1 = (b[1] - L[1] * y0) * L[2];
+    T y2 = (b[2] - L[3] * y0 - L[4] * y1) * L[5];
+    T y3 = (b[3] - L[6] * y0 - L[7] * y1 - L[8] * y2) * L[9];
+    x[3] = y3 * L[9];
+    x[2] = (y2 - L[8] * x[3]) * L[5];
+    x[1] = (y1 - L[4] * x[2] - L[7] * x[3]) * L[2];
+    x[0] = (y0 - L[1] * x[1] - L[3] * x[2] - L[6] * x[3]) * L[0];
+}
+
+// 1-norm condition number estimate ||A||_1 ||A^-1||_1 (exact for 4x4: all
+// four columns of the inverse are formed).  gamma receives A^-1 e_0.
+template <typename T>
+__device__ __forceinline__ T cond1_and_gamma(const T A[10], const T L[10], T gamma[4])
+{
+    const T full[16] = {A[0], A[1], A[2], A[3], A[1], A[4], A[5], A[6],
+                        A[2], A[5], A[7], A[8], A[3], A[6], A[8], A[9]};
+    T na = T(0), ni = T(0);
+    for (int j = 0; j < 4; ++j) {
+        T sa = fabs(full[0 * 4 + j]) + fabs(full[1 * 4 + j]) + fabs(full[2 * 4 + j]) + fabs(full[3 * 4 + j]);
+        na = sa > na ? sa : na;
+        T e[4] = {T(j == 0), T(j == 1), T(j == 2), T(j == 3)};
+        T col[4];
+        chol_solve(L, e, col);
+        if (j == 0) { gamma[0] = col[0]; gamma[1] = col[1]; gamma[2] = col[2]; gamma[3] = col[3]; }
+        T si = fabs(col[0]) + fabs(col[1]) + fabs(col[2]) + fabs(col[3]);
+        ni = si > ni ? si : ni;
+    }
+    return na * ni;
+}
+
+__device__ __forceinline__ uint32_t pack_home(int i, int j, int k)
+{
+    return (uint32_t)i | ((uint32_t)j << kPackI) | ((uint32_t)k << (kPackI + kPackJ));
+}
+
+__device__ __forceinline__ void unpack_home(uint32_t h, int &i, int &j, int &k)
+{
+    i = (int)(h & kMaskI);
+    j = (int)((h >> kPackI) & kMaskJ);
+    k = (int)(h >> (kPackI + kPackJ));
+}
+
+// A packed home is usable by interpolation and spreading if every support
+// node exists: the home index lies on the component grid and, on a wall axis,
+// both neighbours do too.  Markers whose build failed carry 0xffffffff.
+__device__ __forceinline__ bool home_ok(const Grid &g, int c, int i, int j, int k)
+{
+    const int idx[3] = {i, j, k};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int m = g.dims[c][d];
+        if (idx[d] >= m) return false;
+        if (!g.ax[d].periodic && (idx[d] < 1 || idx[d] + 1 >= m)) return false;
+    }
+    return true;
+}
+
+// Wrapped neighbour index along an axis (periodic) or plain (wall axis: the
+// support check guarantees it is in range).
+__device__ __forceinline__ int nb_index(int i, int a, int n, int periodic)
+{
+    int j = i + a;
+    if (periodic) { j = j < 0 ? j + n : (j >= n ? j - n : j); }
+    return j;
+}
+
+}  // namespace mls

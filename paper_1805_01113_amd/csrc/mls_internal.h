@@ -1,0 +1,125 @@
+// Internal declarations of the MI355X MLS transfer library.
+//
+// Device-side grid description, the device error word, the context and the
+// kernel launchers shared by the translation units.  Nothing here is part of
+// the C ABI (include/mls.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mls.h"
+
+namespace mls {
+
+constexpr int kNe = 27;           // 3x3x3 support nodes
+constexpr int kTableStride = 28;  // table row: 27 values + 1 pad (16-byte rows)
+constexpr int kMaxTile = 16;      // largest tile edge of the spreading grid
+constexpr int kPackI = 11, kPackJ = 11;  // home packing i | j << 11 | k << 22
+constexpr uint32_t kMaskI = (1u << kPackI) - 1, kMaskJ = (1u << kPackJ) - 1;
+
+// One axis of the Eulerian grid as the device sees it.
+struct Axis {
+    int32_t n;          // cells
+    int32_t periodic;   // 1 = periodic
+    int32_t uniform;    // 1 = all cell widths bitwise equal
+    int32_t tile;       // tile edge (nodes) of the spreading grid along this axis
+    double f0;          // faces[0]
+    double L;           // faces[n] - faces[0]
+    double inv_h;       // n / L: only used to guess the home node
+    const double *faces;    // n + 1
+    const double *centres;  // n, 0.5 * (f[i] + f[i+1])
+    const float *width_c;   // n     control-volume widths of centre nodes
+    const float *width_f;   // n + 1 control-volume widths of face nodes
+};
+
+struct Weight {
+    int32_t kind;
+    float inv_eps;   // 1/eps
+    float cut;       // exp(-(R/eps)^2) in FP32 (shifted Gaussian)
+    double inv_eps_d;
+    double cut_d;
+};
+
+// Everything a kernel needs to know about the grid.
+struct Grid {
+    Axis ax[3];
+    int32_t dims[3][3];   // dims[c][d]: nodes of component c along axis d
+    int32_t ntile[3];     // tiles per axis (spreading)
+    int64_t ntiles;       // product
+    double h_min;         // smallest node spacing over all axes and components
+};
+
+// Device error word: lowest offending marker index in the upper 56 bits, the
+// (negated) status in the low 8 bits; all ones = no error.
+struct ErrWord {
+    unsigned long long word;
+};
+
+struct DevStats {
+    unsigned long long fp64_solves;
+    unsigned long long fallbacks;
+    unsigned long long learned;
+    unsigned int kappa_max_bits;  // FP32 bits of the largest kappa (positive floats order as uints)
+    unsigned int pad;
+};
+
+// fast-MLS tables on the device.
+struct FastTables {
+    const float *tab;        // [count][n_sub^3][kTableStride]
+    const float *geo;        // [count][3 axes][2]: normalised home CV lo, hi
+    int32_t n_sub;
+    int32_t stretched_axis;  // -1 = uniform grid, one table
+    int32_t first[2];        // first table index of centre / face staggering
+};
+
+struct Ctx {
+    int device = 0;
+    Grid g{};
+    Weight w{};
+    mls_opts opts{};
+    std::vector<double> h_faces[3];
+    std::vector<double> h_centres[3];
+    std::string last_error;
+    // device allocations owned by the context
+    void *geom_block = nullptr;   // faces, centres, widths
+    ErrWord *err = nullptr;
+    DevStats *stats = nullptr;
+    // fast-MLS tables
+    float *tables = nullptr;
+    float *table_geo = nullptr;
+    int64_t n_tables = 0;
+    int32_t table_first[2] = {0, 0};
+    int32_t stretched_axis = -1;
+    // spreading scratch
+    int64_t cap_markers = 0;
+    uint32_t *tile_count = nullptr;    // ntiles
+    uint32_t *tile_off = nullptr;      // ntiles + 1
+    uint32_t *tile_cursor = nullptr;   // ntiles
+    uint32_t *block_sums = nullptr;    // scan partials
+    uint32_t *entries = nullptr;       // 8 * cap_markers
+    uint32_t *work = nullptr;          // persistent-kernel work counter(s)
+    int64_t last_entries_hint = 0;
+    int cu_count = 256;
+};
+
+// ---- launchers (enqueue only; return hipError_t) --------------------------
+
+hipError_t launch_build_exact(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
+                              uint32_t *home, float *phi, uint8_t *route, hipStream_t s);
+hipError_t launch_build_fast(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
+                             uint32_t *home, float *phi, uint8_t *route, hipStream_t s);
+hipError_t launch_table_build(const Ctx &c, hipStream_t s);
+hipError_t launch_interp(const Ctx &c, int64_t n, const uint32_t *home, const float *phi,
+                         const float *u, const float *v, const float *w,
+                         float *U, float *V, float *W, hipStream_t s);
+hipError_t launch_spread(Ctx &c, int64_t n, const uint32_t *home, const float *phi,
+                         const float *area, const float *Fx, const float *Fy, const float *Fz,
+                         float *fx, float *fy, float *fz, hipStream_t s);
+
+FastTables fast_tables(const Ctx &c);
+
+}  // namespace mls

@@ -1,0 +1,248 @@
+"""Thin ctypes binding of the C ABI in include/mls.h (argument marshalling only).
+
+Every step of the transfer runs in the HIP library libmls_hip.so; torch
+tensors are used only as device buffers and their streams.  The library is
+loaded on first use and a missing library raises -- there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmls_hip.so")
+
+MLS_EXACT, MLS_FAST, MLS_LEARNED = 0, 1, 2
+W_GAUSS_SHIFTED, W_GAUSS, W_CONST = 0, 1, 2
+STATUS = {0: "MLS_OK", -1: "MLS_E_ARG", -2: "MLS_E_SUPPORT", -3: "MLS_E_SINGULAR", -4: "MLS_E_NONFINITE",
+          -5: "MLS_E_HIP", -6: "MLS_E_NOMEM", -7: "MLS_E_RANGE"}
+
+_lib = None
+
+
+class MLSError(RuntimeError):
+    def __init__(self, status: int, message: str, first_bad: int = -1):
+        super().__init__("%s: %s" % (STATUS.get(status, status), message))
+        self.status = status
+        self.first_bad = first_bad
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("periodic", ctypes.c_int32 * 3),
+                ("faces", ctypes.POINTER(ctypes.c_double) * 3)]
+
+
+class _Weight(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("eps", ctypes.c_double), ("radius", ctypes.c_double)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("kappa_tau", ctypes.c_double), ("n_sub", ctypes.c_int32), ("fallback_tol", ctypes.c_double)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("fp64_solves", ctypes.c_int64), ("fallbacks", ctypes.c_int64), ("learned", ctypes.c_int64),
+                ("kappa_max", ctypes.c_double), ("spread_entries", ctypes.c_int64),
+                ("spread_tiles", ctypes.c_int64)]
+
+
+def load(path: str = LIB_PATH, need_torch: bool = True):
+    """Load libmls_hip.so.  torch is imported first so that the library binds
+    to the HIP runtime torch already uses."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if need_torch:
+        import torch  # noqa: F401
+    if not os.path.exists(path):
+        raise RuntimeError("libmls_hip.so is not built (%s); run __graft_entry__.build()" % path)
+    L = ctypes.CDLL(path)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.mls_version.restype = ctypes.c_char_p
+    L.mls_ctx_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(_Grid), ctypes.POINTER(_Weight),
+                                 ctypes.POINTER(_Opts)]
+    L.mls_ctx_destroy.argtypes = [P]
+    L.mls_ctx_destroy.restype = None
+    L.mls_reserve.argtypes = [P, I64]
+    L.mls_build.argtypes = [P, I64, P, P, P, I32, P, P, P, P]
+    L.mls_interp.argtypes = [P, I64, P, P, P, P, P, P, P, P, P]
+    L.mls_spread.argtypes = [P, I64, P, P, P, P, P, P, P, P, P, P]
+    L.mls_sync.argtypes = [P, P, ctypes.POINTER(I64)]
+    L.mls_last_error.argtypes = [P]
+    L.mls_last_error.restype = ctypes.c_char_p
+    L.mls_stats_get.argtypes = [P, ctypes.POINTER(_Stats)]
+    L.mls_stats_reset.argtypes = [P]
+    L.mls_fast_tables.argtypes = [P, P, ctypes.POINTER(I64), ctypes.POINTER(I32),
+                                  ctypes.POINTER(I32), ctypes.POINTER(I32), P]
+    for name in ("mls_ctx_create", "mls_reserve", "mls_build", "mls_interp", "mls_spread", "mls_sync",
+                 "mls_stats_get", "mls_stats_reset", "mls_fast_tables"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _check_dev(t, dtype, numel, name):
+    import torch
+    if t is None:
+        raise ValueError("%s is required" % name)
+    if not t.is_cuda or not t.is_contiguous() or t.dtype != dtype or t.numel() != numel:
+        raise ValueError("%s must be a contiguous CUDA %s tensor of %d elements (got %s %s %s)"
+                         % (name, dtype, numel, t.device, t.dtype, tuple(t.shape)))
+
+
+class Context:
+    """One grid + weight + option set (mls_ctx)."""
+
+    def __init__(self, faces: Sequence[np.ndarray], periodic: Sequence[bool], kind: int = W_GAUSS_SHIFTED,
+                 eps: float = 1.0, radius: float = 1.5, kappa_tau: float = 1e6, n_sub: int = 9,
+                 fallback_tol: float = 1e-4):
+        L = load()
+        self._lib = L
+        self.faces = [np.ascontiguousarray(f, dtype=np.float64) for f in faces]
+        self.periodic = [bool(p) for p in periodic]
+        self.n = [len(f) - 1 for f in self.faces]
+        g = _Grid()
+        for d in range(3):
+            g.n[d] = self.n[d]
+            g.periodic[d] = 1 if self.periodic[d] else 0
+            g.faces[d] = self.faces[d].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        w = _Weight(kind, eps, radius)
+        o = _Opts(kappa_tau, n_sub, fallback_tol)
+        self.n_sub = n_sub
+        h = ctypes.c_void_p()
+        st = L.mls_ctx_create(ctypes.byref(h), ctypes.byref(g), ctypes.byref(w), ctypes.byref(o))
+        if st != 0:
+            raise MLSError(st, "mls_ctx_create rejected the grid/weight/options")
+        self.h = h
+
+    @classmethod
+    def from_grid(cls, grid, **kw):
+        return cls(grid.faces, grid.periodic, **kw)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.mls_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _raise(self, st, what):
+        if st != 0:
+            raise MLSError(st, "%s: %s" % (what, self._lib.mls_last_error(self.h).decode()))
+
+    def dims(self, comp: int):
+        return tuple(self.n[d] + (1 if (d == comp and not self.periodic[d]) else 0) for d in range(3))
+
+    def shape(self, comp: int):
+        nx, ny, nz = self.dims(comp)
+        return (nz, ny, nx)
+
+    # ---- C ABI calls -------------------------------------------------------
+    def reserve(self, n: int):
+        self._raise(self._lib.mls_reserve(self.h, int(n)), "mls_reserve")
+
+    def build(self, x, y, z, method: int = MLS_EXACT, home=None, phi=None, route=None, stream=None):
+        import torch
+        n = x.numel()
+        for t, nm in ((x, "x"), (y, "y"), (z, "z")):
+            _check_dev(t, torch.float32, n, nm)
+        dev = x.device
+        if home is None:
+            home = torch.empty(3 * n, dtype=torch.int32, device=dev)
+        if phi is None:
+            phi = torch.empty(3 * 27 * n, dtype=torch.float32, device=dev)
+        _check_dev(home, torch.int32, 3 * n, "home")
+        _check_dev(phi, torch.float32, 81 * n, "phi")
+        if route is not None:
+            _check_dev(route, torch.uint8, 3 * n, "route")
+        st = self._lib.mls_build(self.h, n, _ptr(x), _ptr(y), _ptr(z), int(method), _ptr(home), _ptr(phi),
+                                 _ptr(route), _stream(stream))
+        self._raise(st, "mls_build")
+        return home, phi, route
+
+    def interp(self, home, phi, u, v, w, out=None, stream=None):
+        import torch
+        n = home.numel() // 3
+        _check_dev(home, torch.int32, 3 * n, "home")
+        _check_dev(phi, torch.float32, 81 * n, "phi")
+        for c, q in enumerate((u, v, w)):
+            _check_dev(q, torch.float32, int(np.prod(self.shape(c))), "field %d" % c)
+        if out is None:
+            out = torch.empty((3, n), dtype=torch.float32, device=home.device)
+        _check_dev(out, torch.float32, 3 * n, "out")
+        st = self._lib.mls_interp(self.h, n, _ptr(home), _ptr(phi), _ptr(u), _ptr(v), _ptr(w),
+                                  _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _stream(stream))
+        self._raise(st, "mls_interp")
+        return out
+
+    def spread(self, home, phi, area, F, fields, stream=None):
+        """Adds the eq. 7-8 forcing of marker forces F [3, n] into fields (u, v, w grids)."""
+        import torch
+        n = home.numel() // 3
+        _check_dev(home, torch.int32, 3 * n, "home")
+        _check_dev(phi, torch.float32, 81 * n, "phi")
+        _check_dev(area, torch.float32, n, "area")
+        _check_dev(F, torch.float32, 3 * n, "F")
+        for c, q in enumerate(fields):
+            _check_dev(q, torch.float32, int(np.prod(self.shape(c))), "force field %d" % c)
+        st = self._lib.mls_spread(self.h, n, _ptr(home), _ptr(phi), _ptr(area), _ptr(F[0]), _ptr(F[1]),
+                                  _ptr(F[2]), _ptr(fields[0]), _ptr(fields[1]), _ptr(fields[2]), _stream(stream))
+        self._raise(st, "mls_spread")
+        return fields
+
+    def sync(self, stream=None, raise_on_error=True):
+        bad = ctypes.c_int64(-1)
+        st = self._lib.mls_sync(self.h, _stream(stream), ctypes.byref(bad))
+        if st != 0 and raise_on_error:
+            raise MLSError(st, self._lib.mls_last_error(self.h).decode(), bad.value)
+        return st, bad.value
+
+    def stats(self):
+        s = _Stats()
+        self._raise(self._lib.mls_stats_get(self.h, ctypes.byref(s)), "mls_stats_get")
+        return {k: getattr(s, k) for k, _ in _Stats._fields_}
+
+    def stats_reset(self):
+        self._raise(self._lib.mls_stats_reset(self.h), "mls_stats_reset")
+
+    def fast_tables(self, stream=None):
+        """Copy of the fast-MLS tables: (array [count, n_sub^3, 27] on the device,
+        first[2], stretched_axis)."""
+        import torch
+        cnt = ctypes.c_int64()
+        stride = ctypes.c_int32()
+        first = (ctypes.c_int32 * 2)()
+        ax = ctypes.c_int32()
+        st = self._lib.mls_fast_tables(self.h, None, ctypes.byref(cnt), ctypes.byref(stride), first,
+                                       ctypes.byref(ax), _stream(stream))
+        self._raise(st, "mls_fast_tables")
+        rows = self.n_sub ** 3
+        buf = torch.empty((cnt.value, rows, stride.value), dtype=torch.float32, device="cuda")
+        st = self._lib.mls_fast_tables(self.h, ctypes.c_void_p(buf.data_ptr()), None, None, None, None,
+                                       _stream(stream))
+        self._raise(st, "mls_fast_tables")
+        return buf[:, :, :27], (first[0], first[1]), ax.value
+
+
+def unpack_home(home: np.ndarray, n: int) -> np.ndarray:
+    """Packed home [3*n] (uint32 bits) -> [3, n, 3] int (component, marker, axis)."""
+    h = np.asarray(home).astype(np.int64).reshape(3, n) & 0xFFFFFFFF
+    return np.stack([h & 0x7FF, (h >> 11) & 0x7FF, h >> 22], axis=-1)

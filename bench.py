@@ -1,0 +1,286 @@
+"""Throughput benchmark of the MLS immersed-boundary transfer on one MI355X.
+
+A step is one pass of the whole hot path over all markers of all bodies:
+jitter (<= 0.1 h, counter-based) -> transfer-function build (exact MLS by
+default) -> interpolation of u, v, w -> direct forcing F = (V_b - U)/dt ->
+conservative spreading into the forcing fields.  Default workload: 10,000
+bodies of 320/1280/5120 surface markers (22.66 M markers) in a periodic
+1024^3 staggered grid, one launch per phase over all bodies, the step
+captured once as a HIP graph and replayed.
+
+Prints ONE JSON line on stdout (progress goes to stderr):
+  value     markers/s over the timed graph replays (inputs resident in HBM)
+  roofline  dominant kernel: algorithmic bytes per launch / average duration
+            (HIP events around each launch in a timed eager pass)
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same markers
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    from paper_1805_01113_amd import workloads as W
+    if name == "uneven":
+        return W.uneven_bodies()
+    if name == "ellipsoids":
+        return W.ellipsoids()
+    if name == "stretched":
+        return W.stretched_channel()
+    if name == "sphere":
+        return W.single_sphere()
+    raise SystemExit("unknown workload %s" % name)
+
+
+def touched_nodes(torch, ctx, home, n):
+    """Unique (component, node) pairs in the supports of all markers (for the
+    algorithmic bytes of interpolation and spreading)."""
+    from paper_1805_01113_amd import mls  # noqa: F401
+    h = home.view(3, n).to(torch.int64) & 0xFFFFFFFF
+    total = 0
+    for c in range(3):
+        nx, ny, nz = ctx.dims(c)
+        mask = torch.zeros(nx * ny * nz, dtype=torch.bool, device=home.device)
+        i = h[c] & 0x7FF
+        j = (h[c] >> 11) & 0x7FF
+        k = h[c] >> 22
+        for dz in (-1, 0, 1):
+            kk = (k + dz) % nz if ctx.periodic[2] else k + dz
+            for dy in (-1, 0, 1):
+                jj = (j + dy) % ny if ctx.periodic[1] else j + dy
+                for dx in (-1, 0, 1):
+                    ii = (i + dx) % nx if ctx.periodic[0] else i + dx
+                    mask[(kk * ny + jj) * nx + ii] = True
+        total += int(mask.sum().item())
+        del mask
+    return total
+
+
+def cpu_baseline(wl, fields_dev, target_s):
+    """The FP64 oracle (build + interp + spread, three components) on the first
+    markers of the workload, sized to take about target_s seconds."""
+    from oracle import oracle as orc
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    os.environ.setdefault("OMP_NUM_THREADS", str(threads))
+    orc.build()
+    g = orc.Grid(wl.grid.faces, wl.grid.periodic)
+    fields = [f.cpu().numpy() for f in fields_dev]
+
+    def run(m):
+        x, y, z = wl.x[:m], wl.y[:m], wl.z[:m]
+        t0 = time.perf_counter()
+        refs = [orc.build_exact(g, c, x, y, z) for c in range(3)]
+        t1 = time.perf_counter()
+        for c in range(3):
+            orc.interp(g, c, refs[c]["home"], refs[c]["phi"], fields[c])
+        t2 = time.perf_counter()
+        for c in range(3):
+            f = np.zeros(wl.grid.shape(c))       # pages touched lazily
+            orc.spread(g, c, refs[c]["home"], refs[c]["phi"], wl.area[:m], wl.force[c, :m], f)
+            del f
+        t3 = time.perf_counter()
+        return t3 - t0, (t1 - t0, t2 - t1, t3 - t2)
+
+    m = min(wl.n, 20000)
+    t, _ = run(m)
+    m2 = int(min(wl.n, max(m, m * target_s / max(t, 1e-3))))
+    t, parts = run(m2)
+    return {"value": m2 / t, "unit": "markers/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d of %d markers (whole bodies in generation order), build+interp+spread, "
+                      "3 components, FP64; build %.1fs interp %.1fs spread %.1fs" % (m2, wl.n, *parts)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="uneven", choices=["uneven", "ellipsoids", "stretched", "sphere"])
+    ap.add_argument("--method", default="exact", choices=["exact", "fast"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the eager / per-body / fast comparisons")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1805_01113_amd import mls
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    mls.load()
+    t0 = time.time()
+    wl = make_workload(args.workload)
+    log("workload %s: %d markers, %d bodies, generated in %.1fs" % (wl.name, wl.n, len(wl.body_offsets) - 1,
+                                                                     time.time() - t0))
+    dev = "cuda"
+    n = wl.n
+    h_min = wl.grid.h_min
+    x0, y0, z0 = [torch.from_numpy(a).to(dev) for a in (wl.x, wl.y, wl.z)]
+    area = torch.from_numpy(wl.area).to(dev)
+    fields = wl.fields(dev)
+    forcing = [torch.zeros(wl.grid.shape(c), dtype=torch.float32, device=dev) for c in range(3)]
+    torch.cuda.synchronize()
+    log("fields ready (%.1f GB velocity + %.1f GB forcing)" % (sum(f.numel() for f in fields) * 4e-9,
+                                                                 sum(f.numel() for f in forcing) * 4e-9))
+    method = mls.MLS_EXACT if args.method == "exact" else mls.MLS_FAST
+    ctx = mls.Context(wl.grid.faces, wl.grid.periodic)
+    ctx.reserve(n)
+    bufs = mls.StepBuffers(ctx, x0, y0, z0, area, fields, forcing)
+    jitter = 0.1 * h_min
+    seed = 20180503
+    graph = mls.StepGraph(ctx, bufs, method=method, dt=1.0, jitter=jitter, seed=seed)
+    stream = torch.cuda.current_stream()
+
+    # ---- timed region: graph replays ------------------------------------------
+    graph.launch(args.warmup)
+    ctx.sync()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    graph.launch(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ctx.sync()
+    ms_graph = e0.elapsed_time(e1) / max(args.steps, 1)
+    value = n / (ms_graph * 1e-3)
+    log("graph: %.3f ms/step, %.3e markers/s" % (ms_graph, value))
+
+    # ---- per-kernel timing (eager steps, HIP events around each launch) -------
+    mls.timing_enable(ctx, True)
+    mls.timing_get(ctx, reset=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        mls.step(ctx, bufs, method=method, dt=1.0, jitter=jitter, seed=seed)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_eager = e0.elapsed_time(e1) / max(args.steps, 1)
+    kt = mls.timing_get(ctx, reset=True)
+    mls.timing_enable(ctx, False)
+    ctx.sync()
+    T = touched_nodes(torch, ctx, bufs.home, n)
+    t_per = T / n
+    # algorithmic bytes per marker: what each kernel must move at least once
+    alg = {
+        "jitter": 24.0,
+        "build_exact": 12 + 12 + 324.0,
+        "build_fast": 12 + 12 + 324.0,
+        "interp": 12 + 324 + 12 + 4.0 * t_per,
+        "force": 24.0,
+        "spread_tiles": 12 + 324 + 12 + 4 + 8.0 * t_per,
+        "spread_bin": 0.0,
+    }
+    kernels = {}
+    for k, (ms, cnt) in kt.items():
+        avg = ms / cnt
+        b = alg.get(k, 0.0) * n
+        kernels[k] = {"avg_ms": round(avg, 4), "launches": cnt, "alg_bytes": int(b),
+                      "GBs": round(b / (avg * 1e-3) / 1e9, 1) if b else None}
+    dom = max(((k, v) for k, v in kernels.items() if v["alg_bytes"]), key=lambda kv: kv[1]["avg_ms"])
+    step_bytes = sum(alg.get(k, 0.0) for k in kernels) * n
+    log("eager: %.3f ms/step; kernels: %s" % (ms_eager, json.dumps(kernels)))
+    roof = {"bound": "hbm", "kernel": dom[0], "achieved": dom[1]["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(dom[1]["GBs"] / HBM_PEAK_GBS, 4), "traffic": None,
+            "alg_bytes_per_marker": round(alg[dom[0]], 1), "markers_per_launch": n}
+
+    extra = {"ms_per_step_eager": round(ms_eager, 4), "kernels": kernels,
+             "touched_nodes_per_marker": round(t_per, 3),
+             "step_alg_bytes_per_marker": round(step_bytes / n, 1),
+             "step_hbm_frac": round(step_bytes / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    if not args.no_extra:
+        # per-body launches (what a loop over bodies would do), one step
+        offs = wl.body_offsets
+        nb = len(offs) - 1
+        sub = int(min(nb, 2000))
+        torch.cuda.synchronize()
+        t_a = time.perf_counter()
+        for b in range(sub):
+            s, e = int(offs[b]), int(offs[b + 1])
+            sb = mls._StepBuf()
+            sb.n = e - s
+            for key, t, w in (("x0", x0, 1), ("y0", y0, 1), ("z0", z0, 1), ("x", bufs.x, 1), ("y", bufs.y, 1),
+                              ("z", bufs.z, 1), ("area", area, 1)):
+                setattr(sb, key, t.data_ptr() + 4 * s)
+            sb.home = bufs.home.data_ptr()
+            sb.phi = bufs.phi.data_ptr()
+            sb.U = bufs.U.data_ptr()
+            sb.F = bufs.F.data_ptr()
+            sb.u, sb.v, sb.w = [f.data_ptr() for f in fields]
+            sb.fx, sb.fy, sb.fz = [f.data_ptr() for f in forcing]
+            d = mls._desc(method, 1.0, jitter, seed)
+            import ctypes
+            st = ctx._lib.mls_step(ctx.h, ctypes.byref(d), ctypes.byref(sb), stream.cuda_stream)
+            assert st == 0
+        torch.cuda.synchronize()
+        t_b = time.perf_counter()
+        ctx.sync()
+        per_body_rate = int(offs[sub]) / (t_b - t_a)
+        extra["per_body_launches"] = {"markers_per_s": round(per_body_rate, 1), "bodies_timed": sub,
+                                      "note": "one mls_step per body (host loop), same kernels"}
+        log("per-body: %.3e markers/s over %d bodies" % (per_body_rate, sub))
+        # the other build method through the same graph path
+        other = mls.MLS_FAST if method == mls.MLS_EXACT else mls.MLS_EXACT
+        g2 = mls.StepGraph(ctx, bufs, method=other, dt=1.0, jitter=jitter, seed=seed)
+        g2.launch(args.warmup)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        g2.launch(args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ctx.sync()
+        ms2 = e0.elapsed_time(e1) / max(args.steps, 1)
+        extra["graph_" + ("fast" if other == mls.MLS_FAST else "exact")] = {
+            "ms_per_step": round(ms2, 4), "markers_per_s": round(n / (ms2 * 1e-3), 1)}
+        log("graph %s: %.3f ms/step" % ("fast" if other == mls.MLS_FAST else "exact", ms2))
+        g2.close()
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(wl, fields, args.cpu_seconds)
+        log("cpu baseline: %.3e markers/s on %d threads" % (cpu["value"], cpu["cores"]))
+
+    out = {
+        "metric": "markers/s build+interp+spread: learned/batched vs exact MLS, 1 GPU, ≤1e-4 err",
+        "value": round(value, 1),
+        "unit": "markers/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_graph, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "markers": n, "bodies": int(len(wl.body_offsets) - 1),
+                   "grid": list(wl.grid.n), "method": args.method, "execution": "hipgraph_batched",
+                   "step": "jitter+build+interp+force+spread"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+    graph.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

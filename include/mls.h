@@ -198,6 +198,77 @@ mls_status mls_stats_reset(mls_ctx *ctx);
 mls_status mls_fast_tables(mls_ctx *ctx, float *dst, int64_t *count, int32_t *row_stride,
                            int32_t first[2], int32_t *stretched_axis, void *stream);
 
+/* ---- one immersed-boundary time step (batched over all bodies) ----------
+ * Markers of all bodies are stored back to back (any number of bodies of any
+ * size); every phase is one grid-stride launch over the whole marker array.
+ * A step runs, in order on `stream`:
+ *   jitter   x = x0 + delta, delta uniform in [-jitter, jitter) per axis from a
+ *            counter-based generator (the SplitMix64 output function applied to
+ *            seed + (counter + 1) * 0x9E3779B97F4A7C15 with
+ *            counter = (step * n + marker) * 3 + axis, top 24 bits), skipped
+ *            when jitter == 0 (then x0 is built directly);
+ *   build    mls_build with `method`;
+ *   interp   U = Phi^T u (eq. 6);
+ *   force    F = (V_b - U) / dt, the direct forcing of Sec. 2 (V_b = 0 if NULL);
+ *   spread   f += c_l phi F (eq. 7-8);
+ * and then increments the context's device step counter, which the jitter
+ * of the next step reads.  All buffers are caller-owned device arrays:
+ * x0,y0,z0 [n] (read), x,y,z [n] (written by jitter), area [n], vb [3][n] or
+ * NULL, home [3][n], phi [3][27][n], route [3][n] or NULL, U [3][n], F [3][n],
+ * the velocity fields u,v,w and the forcing fields fx,fy,fz. */
+typedef struct {
+    int32_t method;
+    float dt;
+    float jitter;
+    uint64_t seed;
+} mls_step_desc;
+
+typedef struct {
+    int64_t n;
+    const float *x0, *y0, *z0;
+    float *x, *y, *z;
+    const float *area;
+    const float *vb;
+    uint32_t *home;
+    float *phi;
+    uint8_t *route;
+    const float *u, *v, *w;
+    float *U;
+    float *F;
+    float *fx, *fy, *fz;
+} mls_step_buffers;
+
+/* Enqueue one step.  Reserves scratch on first use for n markers. */
+mls_status mls_step(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buffers *buf, void *stream);
+
+/* Set the device step counter read by the jitter (enqueued on stream). */
+mls_status mls_step_counter_set(mls_ctx *ctx, uint64_t step, void *stream);
+
+/* A step captured once as a HIP graph and replayed: the capture contains no
+ * allocation, no memset node and no host synchronisation, so a replay costs
+ * one graph launch.  The buffers are baked into the graph; they must stay
+ * allocated until mls_graph_destroy. */
+typedef struct mls_graph mls_graph;
+mls_status mls_graph_create(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buffers *buf,
+                            mls_graph **out);
+mls_status mls_graph_launch(mls_graph *graph, int32_t n_steps, void *stream);
+void mls_graph_destroy(mls_graph *graph);
+
+/* ---- per-kernel timing (HIP events on the launch stream) -----------------
+ * When enabled, the library records a HIP event pair around each launch of
+ * the kernels below (not inside a graph capture); mls_timing_get
+ * synchronises and returns the summed milliseconds and launch counts. */
+enum {
+    MLS_K_BUILD_EXACT = 0, MLS_K_BUILD_FAST = 1, MLS_K_BUILD_LEARNED = 2, MLS_K_INTERP = 3,
+    MLS_K_SPREAD_BIN = 4, MLS_K_SPREAD_TILES = 5, MLS_K_JITTER = 6, MLS_K_FORCE = 7, MLS_K_COUNT = 16
+};
+typedef struct {
+    double ms[MLS_K_COUNT];
+    int64_t launches[MLS_K_COUNT];
+} mls_timing;
+mls_status mls_timing_enable(mls_ctx *ctx, int32_t on);
+mls_status mls_timing_get(mls_ctx *ctx, mls_timing *out, int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

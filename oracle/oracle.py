@@ -245,3 +245,37 @@ def spread(grid: Grid, comp, home, phi, area, F, f=None):
     cl = np.empty(n)
     lib().orc_spread(*grid.args(), comp, n, _p(home), _p(phi), _p(area), _p(F), _p(f), _p(cl))
     return f, cl
+
+
+# ---------------------------------------------------------------------------
+# Counter-based jitter of the batched time step (SplitMix64 output function,
+# Steele, Lea & Flood, OOPSLA 2014), written here independently of the HIP
+# library from the published definition.
+# ---------------------------------------------------------------------------
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed, ctr):
+    """Output of a SplitMix64 stream started at `seed` after ctr+1 advances."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (np.asarray(ctr, dtype=np.uint64) + np.uint64(1)) * _GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        return z ^ (z >> np.uint64(31))
+
+
+def jitter(x0, y0, z0, step, amp, seed):
+    """x = x0 + (u - 1/2)(2 amp) per axis, u = top 24 bits of
+    splitmix64(seed, (step n + l) 3 + axis) / 2^24, all in FP32."""
+    n = len(x0)
+    l = np.arange(n, dtype=np.uint64)
+    out = []
+    amp2 = np.float32(2.0) * np.float32(amp)
+    for axis, a0 in enumerate((x0, y0, z0)):
+        ctr = (np.uint64(step) * np.uint64(n) + l) * np.uint64(3) + np.uint64(axis)
+        u = (splitmix64(seed, ctr) >> np.uint64(40)).astype(np.float32) * np.float32(2.0 ** -24)
+        d = (u - np.float32(0.5)) * amp2
+        out.append((np.asarray(a0, dtype=np.float32) + d).astype(np.float32))
+    return out

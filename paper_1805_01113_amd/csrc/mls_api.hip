@@ -11,9 +11,6 @@
 
 using namespace mls;
 
-struct mls_ctx {
-    Ctx c;
-};
 
 namespace {
 
@@ -197,7 +194,8 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
     }
     if (hipMalloc((void **)&c.err, sizeof(ErrWord)) != hipSuccess ||
         hipMalloc((void **)&c.stats, sizeof(DevStats)) != hipSuccess ||
-        hipMalloc((void **)&c.work, 64 * sizeof(uint32_t)) != hipSuccess) {
+        hipMalloc((void **)&c.work, 64 * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void **)&c.step_ctr, sizeof(unsigned long long)) != hipSuccess) {
         mls_ctx_destroy(ctx);
         return MLS_E_NOMEM;
     }
@@ -205,6 +203,7 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
     hipMemcpy(c.err, &none, sizeof(none), hipMemcpyHostToDevice);
     hipMemset(c.stats, 0, sizeof(DevStats));
     hipMemset(c.work, 0, 64 * sizeof(uint32_t));
+    hipMemset(c.step_ctr, 0, sizeof(unsigned long long));
     const int64_t nb = (nt + 2047) / 2048;
     if (hipMalloc((void **)&c.tile_count, nt * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void **)&c.tile_off, (nt + 1) * sizeof(uint32_t)) != hipSuccess ||
@@ -234,6 +233,8 @@ void mls_ctx_destroy(mls_ctx *ctx)
     hipFree(c.block_sums);
     hipFree(c.entries);
     hipFree(c.work);
+    hipFree(c.step_ctr);
+    for (hipEvent_t ev : c.ev_pool) hipEventDestroy(ev);
     delete ctx;
 }
 
@@ -294,12 +295,15 @@ mls_status mls_build(mls_ctx *ctx, int64_t n, const float *x, const float *y, co
     Ctx &c = ctx->c;
     hipError_t e;
     switch (method) {
-    case MLS_EXACT:
+    case MLS_EXACT: {
+        TimedLaunch t(c, MLS_K_BUILD_EXACT, s);
         e = launch_build_exact(c, n, x, y, z, home, phi, route, s);
         break;
+    }
     case MLS_FAST: {
         mls_status st = ensure_tables(ctx, s);
         if (st != MLS_OK) return st;
+        TimedLaunch t(c, MLS_K_BUILD_FAST, s);
         e = launch_build_fast(c, n, x, y, z, home, phi, route, s);
         break;
     }
@@ -316,7 +320,11 @@ mls_status mls_interp(mls_ctx *ctx, int64_t n, const uint32_t *home, const float
     if (!ctx) return MLS_E_ARG;
     if (n < 0 || n > (int64_t)0x1fffffff) return fail(ctx, MLS_E_ARG, "bad marker count");
     if (n > 0 && (!home || !phi || !u || !v || !w || !U || !V || !W)) return fail(ctx, MLS_E_ARG, "null array");
-    hipError_t e = launch_interp(ctx->c, n, home, phi, u, v, w, U, V, W, static_cast<hipStream_t>(stream));
+    hipError_t e;
+    {
+        TimedLaunch t(ctx->c, MLS_K_INTERP, static_cast<hipStream_t>(stream));
+        e = launch_interp(ctx->c, n, home, phi, u, v, w, U, V, W, static_cast<hipStream_t>(stream));
+    }
     if (e != hipSuccess) return hip_fail(ctx, e, "interp launch");
     return MLS_OK;
 }

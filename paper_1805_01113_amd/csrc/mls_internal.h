@@ -104,6 +104,25 @@ struct Ctx {
     uint32_t *work = nullptr;          // persistent-kernel work counter(s)
     int64_t last_entries_hint = 0;
     int cu_count = 256;
+    // time step
+    unsigned long long *step_ctr = nullptr;
+    // per-kernel timing
+    bool timing = false;
+    bool capturing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_marks;
+    size_t ev_used = 0;
+};
+
+// Timing marks around a launch (no-ops unless timing is on and no graph is
+// being captured).
+struct TimedLaunch {
+    Ctx &c;
+    int id;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedLaunch(Ctx &c_, int id_, hipStream_t s_);
+    ~TimedLaunch();
 };
 
 // ---- launchers (enqueue only; return hipError_t) --------------------------
@@ -120,6 +139,17 @@ hipError_t launch_spread(Ctx &c, int64_t n, const uint32_t *home, const float *p
                          const float *area, const float *Fx, const float *Fy, const float *Fz,
                          float *fx, float *fy, float *fz, hipStream_t s);
 
+hipError_t launch_jitter(const Ctx &c, int64_t n, const float *x0, const float *y0, const float *z0,
+                         float *x, float *y, float *z, float amp, uint64_t seed, hipStream_t s);
+hipError_t launch_force(const Ctx &c, int64_t n, const float *vb, const float *U, float dt, float *F,
+                        hipStream_t s);
+hipError_t launch_step_advance(const Ctx &c, hipStream_t s);
+
 FastTables fast_tables(const Ctx &c);
 
 }  // namespace mls
+
+// The opaque handle of the C ABI.
+struct mls_ctx {
+    mls::Ctx c;
+};

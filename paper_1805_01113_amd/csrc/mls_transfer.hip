@@ -372,6 +372,7 @@ hipError_t launch_spread(Ctx &c, int64_t n, const uint32_t *home, const float *p
     if (n == 0) return hipSuccess;
     const int64_t nt = c.g.ntiles;
     const int64_t nb = (nt + kScanChunk - 1) / kScanChunk;
+    TimedLaunch* tb = new TimedLaunch(c, MLS_K_SPREAD_BIN, s);
     hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(nt, c.cu_count)), dim3(kBlock), 0, s, c.tile_count, nt);
     hipLaunchKernelGGL(k_bin<false>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.g, n, home,
                        c.tile_count, c.tile_cursor, c.entries, c.err);
@@ -381,8 +382,10 @@ hipError_t launch_spread(Ctx &c, int64_t n, const uint32_t *home, const float *p
                        c.tile_off, c.tile_cursor, c.work);
     hipLaunchKernelGGL(k_bin<true>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.g, n, home,
                        c.tile_count, c.tile_cursor, c.entries, c.err);
+    delete tb;
     const double inv_hmin2 = 1.0 / (c.g.h_min * c.g.h_min);
     const int persist = c.cu_count * 4;
+    TimedLaunch tt(c, MLS_K_SPREAD_TILES, s);
     hipLaunchKernelGGL(k_spread_tiles, dim3(persist), dim3(kBlock), 0, s, c.g, n, home, phi, area, Fx, Fy, Fz,
                        fx, fy, fz, c.tile_off, c.entries, c.work, inv_hmin2, c.err);
     return hipGetLastError();

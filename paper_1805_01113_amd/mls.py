@@ -49,6 +49,24 @@ class _Stats(ctypes.Structure):
                 ("spread_tiles", ctypes.c_int64)]
 
 
+class _StepDesc(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("dt", ctypes.c_float), ("jitter", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+class _StepBuf(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64)] + [(k, ctypes.c_void_p) for k in (
+        "x0", "y0", "z0", "x", "y", "z", "area", "vb", "home", "phi", "route", "u", "v", "w", "U", "F",
+        "fx", "fy", "fz")]
+
+
+K_NAMES = ["build_exact", "build_fast", "build_learned", "interp", "spread_bin", "spread_tiles", "jitter", "force"]
+
+
+class _Timing(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 16), ("launches", ctypes.c_int64 * 16)]
+
+
 def load(path: str = LIB_PATH, need_torch: bool = True):
     """Load libmls_hip.so.  torch is imported first so that the library binds
     to the HIP runtime torch already uses."""
@@ -77,8 +95,17 @@ def load(path: str = LIB_PATH, need_torch: bool = True):
     L.mls_stats_reset.argtypes = [P]
     L.mls_fast_tables.argtypes = [P, P, ctypes.POINTER(I64), ctypes.POINTER(I32),
                                   ctypes.POINTER(I32), ctypes.POINTER(I32), P]
+    L.mls_step.argtypes = [P, ctypes.POINTER(_StepDesc), ctypes.POINTER(_StepBuf), P]
+    L.mls_step_counter_set.argtypes = [P, ctypes.c_uint64, P]
+    L.mls_graph_create.argtypes = [P, ctypes.POINTER(_StepDesc), ctypes.POINTER(_StepBuf), ctypes.POINTER(P)]
+    L.mls_graph_launch.argtypes = [P, I32, P]
+    L.mls_graph_destroy.argtypes = [P]
+    L.mls_graph_destroy.restype = None
+    L.mls_timing_enable.argtypes = [P, I32]
+    L.mls_timing_get.argtypes = [P, ctypes.POINTER(_Timing), I32]
     for name in ("mls_ctx_create", "mls_reserve", "mls_build", "mls_interp", "mls_spread", "mls_sync",
-                 "mls_stats_get", "mls_stats_reset", "mls_fast_tables"):
+                 "mls_stats_get", "mls_stats_reset", "mls_fast_tables", "mls_step", "mls_step_counter_set",
+                 "mls_graph_create", "mls_graph_launch", "mls_timing_enable", "mls_timing_get"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -240,6 +267,96 @@ class Context:
                                        _stream(stream))
         self._raise(st, "mls_fast_tables")
         return buf[:, :, :27], (first[0], first[1]), ax.value
+
+
+class StepBuffers:
+    """Device buffers of one batched time step (all bodies back to back)."""
+
+    def __init__(self, ctx: "Context", x0, y0, z0, area, fields, forcing, vb=None, route=False):
+        import torch
+        n = x0.numel()
+        dev = x0.device
+        self.n = n
+        self.x0, self.y0, self.z0, self.area = x0, y0, z0, area
+        self.x = torch.empty_like(x0)
+        self.y = torch.empty_like(y0)
+        self.z = torch.empty_like(z0)
+        self.vb = vb
+        self.home = torch.empty(3 * n, dtype=torch.int32, device=dev)
+        self.phi = torch.empty(81 * n, dtype=torch.float32, device=dev)
+        self.route = torch.zeros(3 * n, dtype=torch.uint8, device=dev) if route else None
+        self.fields = fields
+        self.forcing = forcing
+        self.U = torch.empty((3, n), dtype=torch.float32, device=dev)
+        self.F = torch.empty((3, n), dtype=torch.float32, device=dev)
+        for t, nm in ((x0, "x0"), (y0, "y0"), (z0, "z0"), (area, "area")):
+            _check_dev(t, torch.float32, n, nm)
+        for c in range(3):
+            _check_dev(fields[c], torch.float32, int(np.prod(ctx.shape(c))), "field %d" % c)
+            _check_dev(forcing[c], torch.float32, int(np.prod(ctx.shape(c))), "forcing %d" % c)
+        if vb is not None:
+            _check_dev(vb, torch.float32, 3 * n, "vb")
+
+    def struct(self):
+        b = _StepBuf()
+        b.n = self.n
+        for k in ("x0", "y0", "z0", "x", "y", "z", "area", "vb", "home", "phi", "route", "U", "F"):
+            setattr(b, k, _ptr(getattr(self, k)))
+        b.u, b.v, b.w = [t.data_ptr() for t in self.fields]
+        b.fx, b.fy, b.fz = [t.data_ptr() for t in self.forcing]
+        return b
+
+
+def _desc(method, dt, jitter, seed):
+    return _StepDesc(int(method), float(dt), float(jitter), int(seed))
+
+
+def step(ctx: "Context", bufs: StepBuffers, method=MLS_EXACT, dt=1.0, jitter=0.0, seed=0, stream=None):
+    d = _desc(method, dt, jitter, seed)
+    b = bufs.struct()
+    ctx._raise(ctx._lib.mls_step(ctx.h, ctypes.byref(d), ctypes.byref(b), _stream(stream)), "mls_step")
+
+
+def step_counter_set(ctx: "Context", value: int, stream=None):
+    ctx._raise(ctx._lib.mls_step_counter_set(ctx.h, int(value), _stream(stream)), "mls_step_counter_set")
+
+
+class StepGraph:
+    """One step captured as a HIP graph (mls_graph_create) and replayed."""
+
+    def __init__(self, ctx: "Context", bufs: StepBuffers, method=MLS_EXACT, dt=1.0, jitter=0.0, seed=0):
+        self.ctx = ctx
+        self.bufs = bufs      # keeps the baked-in buffers alive
+        d = _desc(method, dt, jitter, seed)
+        b = bufs.struct()
+        h = ctypes.c_void_p()
+        ctx._raise(ctx._lib.mls_graph_create(ctx.h, ctypes.byref(d), ctypes.byref(b), ctypes.byref(h)),
+                   "mls_graph_create")
+        self.h = h
+
+    def launch(self, n_steps=1, stream=None):
+        self.ctx._raise(self.ctx._lib.mls_graph_launch(self.h, int(n_steps), _stream(stream)), "mls_graph_launch")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx._lib.mls_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def timing_enable(ctx: "Context", on=True):
+    ctx._raise(ctx._lib.mls_timing_enable(ctx.h, 1 if on else 0), "mls_timing_enable")
+
+
+def timing_get(ctx: "Context", reset=True):
+    t = _Timing()
+    ctx._raise(ctx._lib.mls_timing_get(ctx.h, ctypes.byref(t), 1 if reset else 0), "mls_timing_get")
+    return {K_NAMES[i]: (t.ms[i], t.launches[i]) for i in range(len(K_NAMES)) if t.launches[i] > 0}
 
 
 def unpack_home(home: np.ndarray, n: int) -> np.ndarray:

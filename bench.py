@@ -48,8 +48,8 @@ def make_workload(name):
 def touched_nodes(torch, ctx, home, n):
     """Unique (component, node) pairs in the supports of all markers (for the
     algorithmic bytes of interpolation and spreading)."""
-    from paper_1805_01113_amd import mls  # noqa: F401
-    h = home.view(3, n).to(torch.int64) & 0xFFFFFFFF
+    from paper_1805_01113_amd import mls
+    h = mls.unblock(home, n)[:, :, 0].to(torch.int64) & 0xFFFFFFFF
     total = 0
     for c in range(3):
         nx, ny, nz = ctx.dims(c)
@@ -113,7 +113,19 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the eager / per-body / fast comparisons")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="only run a plain device-to-device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
+    if args.copy_gib > 0:
+        import torch
+        nbytes = int(args.copy_gib * (1 << 30))
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": 3}), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
@@ -132,7 +144,12 @@ def main():
     h_min = wl.grid.h_min
     x0, y0, z0 = [torch.from_numpy(a).to(dev) for a in (wl.x, wl.y, wl.z)]
     area = torch.from_numpy(wl.area).to(dev)
-    fields = wl.fields(dev)
+    from paper_1805_01113_amd import workloads as W
+    fields = []
+    for c in range(3):
+        fields.append(W.fourier_field(wl.grid, c, wl.modes[c], wl.lengths, device=dev))
+        torch.cuda.synchronize()
+        log("velocity component %d ready" % c)
     forcing = [torch.zeros(wl.grid.shape(c), dtype=torch.float32, device=dev) for c in range(3)]
     torch.cuda.synchronize()
     log("fields ready (%.1f GB velocity + %.1f GB forcing)" % (sum(f.numel() for f in fields) * 4e-9,

@@ -30,12 +30,17 @@
  *    (half-open [lo, hi): ties go to the upper node).  A centre node owns its
  *    cell; a face node owns the interval between the two adjacent centres.
  *    Periodic coordinates are wrapped in FP64.
- *  - Shape-function layout (SoA): phi[(c*27 + k)*n + l] is the FP32 weight of
- *    support node k of marker l for component c, with
+ *  - Shape-function layout (SoA inside blocks of 64 markers, one wavefront):
+ *    with npad = n rounded up to a multiple of 64, b = l / 64 and r = l % 64,
+ *      phi[((b*3 + c)*27 + k)*64 + r]   (81 * npad floats)
+ *    is the FP32 weight of support node k of marker l for component c, with
  *    k = (a_x+1) + 3 (a_y+1) + 9 (a_z+1) and a_d in {-1,0,1} the node offset
- *    from the home node.  home[c*n + l] packs the wrapped home node indices of
- *    component c as i | j << 11 | k << 22 (so a component grid may have at
- *    most 2048 x 2048 x 1024 nodes).
+ *    from the home node;
+ *      home[(b*3 + c)*64 + r]           (3 * npad uint32)
+ *    packs the wrapped home node indices of component c as
+ *    i | j << 11 | k << 22 (a component grid may have at most
+ *    2048 x 2048 x 1024 nodes); route flags use the layout of home.
+ *    Padding entries past n are never read or written.
  *  - Calls on one context are not thread-safe; issue them from one thread.
  */
 #ifndef MLS_H
@@ -94,8 +99,9 @@ typedef struct {
 } mls_weight;
 
 typedef struct {
-    double kappa_tau;     /* FP32 moment-matrix solves with 1-norm condition
-                             number above this are redone in FP64 (default 1e6;
+    double kappa_tau;     /* FP32 moment-matrix solves whose condition-number
+                             bound ||A||_F ||L^-1||_F^2 (>= kappa_2(A), A = L L^T)
+                             exceeds this are redone in FP64 (default 1e6;
                              0 routes every solve to FP64) */
     int32_t n_sub;        /* fast-MLS sub-nodes per axis of the home control
                              volume, boundaries included (default 9 -> 729) */
@@ -107,7 +113,7 @@ typedef struct {
     int64_t fp64_solves;     /* (marker, component) solves routed to FP64 */
     int64_t fallbacks;       /* learned: (marker, component) fallbacks to exact */
     int64_t learned;         /* learned: (marker, component) accepted */
-    double kappa_max;        /* largest FP32 kappa_1 seen (0 if none) */
+    double kappa_max;        /* largest FP32 condition-number bound seen (0 if none) */
     int64_t spread_entries;  /* (tile, marker) pairs of the last spread */
     int64_t spread_tiles;    /* tiles of the forcing grid */
 } mls_stats;
@@ -133,14 +139,15 @@ mls_status mls_reserve(mls_ctx *ctx, int64_t n_markers);
 
 /* Transfer-function build (Sec. 2, eq. 1-6 exact; eq. 9-10 fast).
  * For n markers at x,y,z (device FP32 SoA, any position on periodic axes):
- * writes home[3][n] (packed home indices, see above), phi[3][27][n] (FP32
+ * writes home (3 * npad, packed home indices, see above), phi (81 * npad FP32
  * shape functions, Phi^T = p^T A^-1 B of eq. 6 in marker-centred, spacing-
  * scaled coordinates, which gives the same Phi as the paper's absolute basis)
- * and, if route != NULL, route[3][n] (bit 0: FP64 solve, bit 1: learned
+ * and, if route != NULL, route (3 * npad; bit 0: FP64 solve, bit 1: learned
  * accepted, bit 2: learned fell back to exact).  MLS_EXACT assembles the 4x4
  * moment matrix A = sum_k W_k p_k p_k^T (eq. 3) per (marker, component),
- * solves it in FP32 and redoes the solve in FP64 when its condition number
- * exceeds opts.kappa_tau.  MLS_FAST builds, on first use, the tables of exact
+ * solves it in FP32 (Cholesky) and redoes the solve in FP64 when the bound
+ * ||A||_F ||L^-1||_F^2 of its 2-norm condition number exceeds
+ * opts.kappa_tau.  MLS_FAST builds, on first use, the tables of exact
  * shape functions at the n_sub^3 sub-nodes of the home control volume (one
  * table on a uniform grid, one per plane and staggering type along a
  * stretched axis, Sec. 2 last paragraph) and blends the 8 corners of the
@@ -214,7 +221,7 @@ mls_status mls_fast_tables(mls_ctx *ctx, float *dst, int64_t *count, int32_t *ro
  * and then increments the context's device step counter, which the jitter
  * of the next step reads.  All buffers are caller-owned device arrays:
  * x0,y0,z0 [n] (read), x,y,z [n] (written by jitter), area [n], vb [3][n] or
- * NULL, home [3][n], phi [3][27][n], route [3][n] or NULL, U [3][n], F [3][n],
+ * NULL, home, phi and route (or NULL) in the blocked layout above, U [3][n], F [3][n],
  * the velocity fields u,v,w and the forcing fields fx,fy,fz. */
 typedef struct {
     int32_t method;

@@ -89,6 +89,12 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
             wmax = std::max(wmax, wi);
         }
         a.uniform = (wmax <= wmin * (1.0 + 1e-9)) ? 1 : 0;
+        // exactly uniform: the stored coordinates are reproduced bit for bit by
+        // f0 + i h and f0 + (i + 1/2) h (the device then computes them)
+        a.h = a.L / (double)n;
+        a.exact = a.uniform;
+        for (int i = 0; i <= n && a.exact; ++i) a.exact = (f[i] == a.f0 + (double)i * a.h);
+        for (int i = 0; i < n && a.exact; ++i) a.exact = (c.h_centres[d][i] == a.f0 + ((double)i + 0.5) * a.h);
         if (!bitwise) { ++nonuniform; c.stretched_axis = d; }
         if (a.periodic) {
             if (n <= kMaxTile) a.tile = n;
@@ -142,6 +148,25 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
         nt *= c.g.ntile[d];
     }
     c.g.ntiles = nt;
+    // smallest control-volume width within two nodes of each tile, per axis
+    std::vector<float> thmin[3];
+    for (int d = 0; d < 3; ++d) {
+        const Axis &a = c.g.ax[d];
+        thmin[d].resize(c.g.ntile[d]);
+        for (int t = 0; t < c.g.ntile[d]; ++t) {
+            double m = std::numeric_limits<double>::infinity();
+            for (int i = t * a.tile - 2; i <= (t + 1) * a.tile + 1; ++i) {
+                int ic = i, jf = i;
+                if (a.periodic) {
+                    ic = ((i % a.n) + a.n) % a.n;
+                    jf = ic;
+                }
+                if (ic >= 0 && ic < (int)wc[d].size()) m = std::min(m, (double)wc[d][ic]);
+                if (jf >= 0 && jf < (int)wf[d].size()) m = std::min(m, (double)wf[d][jf]);
+            }
+            thmin[d][t] = (float)m;
+        }
+    }
 
     // ---- weight and options ----
     mls_weight wdef = {MLS_W_GAUSS_SHIFTED, 1.0, 1.5};
@@ -173,12 +198,15 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
         off_wc[d] = take(wc[d].size() * sizeof(float));
         off_wf[d] = take(wf[d].size() * sizeof(float));
     }
+    size_t off_th[3];
+    for (int d = 0; d < 3; ++d) off_th[d] = take(thmin[d].size() * sizeof(float));
     std::vector<unsigned char> blob(bytes, 0);
     for (int d = 0; d < 3; ++d) {
         memcpy(&blob[off_f[d]], c.h_faces[d].data(), c.h_faces[d].size() * sizeof(double));
         memcpy(&blob[off_c[d]], c.h_centres[d].data(), c.h_centres[d].size() * sizeof(double));
         memcpy(&blob[off_wc[d]], wc[d].data(), wc[d].size() * sizeof(float));
         memcpy(&blob[off_wf[d]], wf[d].data(), wf[d].size() * sizeof(float));
+        memcpy(&blob[off_th[d]], thmin[d].data(), thmin[d].size() * sizeof(float));
     }
     e = hipMalloc(&c.geom_block, bytes);
     if (e != hipSuccess) { delete ctx; return MLS_E_NOMEM; }
@@ -191,6 +219,12 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
         a.centres = reinterpret_cast<const double *>(base + off_c[d]);
         a.width_c = reinterpret_cast<const float *>(base + off_wc[d]);
         a.width_f = reinterpret_cast<const float *>(base + off_wf[d]);
+        a.tile_hmin = reinterpret_cast<const float *>(base + off_th[d]);
+    }
+    if (hipMalloc((void **)&c.d_grid, sizeof(Grid)) != hipSuccess ||
+        hipMemcpy(c.d_grid, &c.g, sizeof(Grid), hipMemcpyHostToDevice) != hipSuccess) {
+        mls_ctx_destroy(ctx);
+        return MLS_E_NOMEM;
     }
     if (hipMalloc((void **)&c.err, sizeof(ErrWord)) != hipSuccess ||
         hipMalloc((void **)&c.stats, sizeof(DevStats)) != hipSuccess ||
@@ -208,6 +242,7 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
     if (hipMalloc((void **)&c.tile_count, nt * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void **)&c.tile_off, (nt + 1) * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void **)&c.tile_cursor, nt * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void **)&c.tile_active, nt * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void **)&c.block_sums, (nb + 1) * sizeof(uint32_t)) != hipSuccess) {
         mls_ctx_destroy(ctx);
         return MLS_E_NOMEM;
@@ -223,6 +258,7 @@ void mls_ctx_destroy(mls_ctx *ctx)
     Ctx &c = ctx->c;
     hipDeviceSynchronize();
     hipFree(c.geom_block);
+    hipFree(c.d_grid);
     hipFree(c.err);
     hipFree(c.stats);
     hipFree(c.tables);
@@ -230,6 +266,7 @@ void mls_ctx_destroy(mls_ctx *ctx)
     hipFree(c.tile_count);
     hipFree(c.tile_off);
     hipFree(c.tile_cursor);
+    hipFree(c.tile_active);
     hipFree(c.block_sums);
     hipFree(c.entries);
     hipFree(c.work);

@@ -15,35 +15,20 @@ namespace {
 
 constexpr int kBlock = 256;
 
-struct SetGeo {      // one (axis, staggering type) node set of a marker
-    AxisGeo g;
-    float w[3];
-    Moments<float> m;
-};
-
-__device__ __forceinline__ void set_weights(const Weight &W, SetGeo &sg)
-{
-    float m0 = 0.f, m1 = 0.f, m2 = 0.f;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        float w = weight1(W, sg.g.s[a]);
-        sg.w[a] = w;
-        m0 += w;
-        m1 += w * sg.g.s[a];
-        m2 += w * sg.g.s[a] * sg.g.s[a];
-    }
-    sg.m = {m0, m1, m2};
-}
-
 // FP64 re-solve of one (marker, component): recompute the offsets, weights
-// and moments in FP64 from the position.  Returns false if A is singular.
-__device__ bool solve_fp64(const Grid &g, const Weight &W, int c, const double pos[3], double phi[27])
+// and moments in FP64 from the position and store Phi (out points at the
+// marker's first support node, consecutive nodes kLanes floats apart).
+// Returns false if A is singular.
+__device__ __forceinline__ bool solve_fp64(const Grid &g, const Weight &W, int c, double px, double py, double pz,
+                                           float *out)
 {
     double s[3][3], w[3][3];
     Moments<double> m[3];
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-        axis_offsets_d(g.ax[d], d == c, pos[d], s[d]);
+        axis_offsets_d(g.ax[d], d == c, d == 0 ? px : (d == 1 ? py : pz), s[d]);
         double m0 = 0, m1 = 0, m2 = 0;
+#pragma unroll
         for (int a = 0; a < 3; ++a) {
             w[d][a] = weight1_d(W, s[d][a]);
             m0 += w[d][a]; m1 += w[d][a] * s[d][a]; m2 += w[d][a] * s[d][a] * s[d][a];
@@ -52,92 +37,112 @@ __device__ bool solve_fp64(const Grid &g, const Weight &W, int c, const double p
     }
     double A[10], L[10], gam[4];
     assemble(m[0], m[1], m[2], A);
-    if (!cholesky4(A, L)) return false;
-    const double e0[4] = {1.0, 0.0, 0.0, 0.0};
-    chol_solve(L, e0, gam);
-    for (int k = 0; k < kNe; ++k) {
-        int a = k % 3, b = (k / 3) % 3, cc = k / 9;
-        double W3 = w[0][a] * w[1][b] * w[2][cc];
-        phi[k] = W3 * (gam[0] + gam[1] * s[0][a] + gam[2] * s[1][b] + gam[3] * s[2][cc]);
+    const bool ok = cholesky4(A, L);
+    if (ok) {
+        const double e0[4] = {1.0, 0.0, 0.0, 0.0};
+        chol_solve(L, e0, gam);
     }
-    return true;
+#pragma unroll 1
+    for (int k = 0; k < kNe; ++k) {
+        const int a = k % 3, b = (k / 3) % 3, cc = k / 9;
+        const double W3 = w[0][a] * w[1][b] * w[2][cc];
+        out[k * kLanes] = ok ? (float)(W3 * (gam[0] + gam[1] * s[0][a] + gam[2] * s[1][b] + gam[3] * s[2][cc]))
+                             : __builtin_nanf("");
+    }
+    return ok;
 }
 
-__global__ void __launch_bounds__(kBlock)
-k_build_exact(const Grid g, const Weight W, float tau, int64_t n,
+__device__ __forceinline__ void mark_failed(ErrWord *err, int64_t l, double px, double py, double pz,
+                                            uint32_t *hout, float *out, uint8_t *rout)
+{
+    raise_error(err, l, isfinite(px) && isfinite(py) && isfinite(pz) ? MLS_E_SUPPORT : MLS_E_NONFINITE);
+    *hout = 0xffffffffu;
+#pragma unroll 1
+    for (int k = 0; k < kNe; ++k) out[k * kLanes] = __builtin_nanf("");
+    if (rout) *rout = 0;
+}
+
+// Work split of the build kernels: a block holds kGroups groups of 64
+// consecutive markers; each group is handled by three wavefronts, one per
+// velocity component, so a wavefront stores 64 consecutive floats per
+// support node and the component is uniform across it.
+constexpr int kGroups = 2;
+constexpr int kBuildBlock = 3 * 64 * kGroups;
+
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+__global__ void __launch_bounds__(kBuildBlock)
+k_build_exact(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n,
               const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
               uint32_t *__restrict__ home, float *__restrict__ phi, uint8_t *__restrict__ route,
               ErrWord *err, DevStats *st)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const Grid &g = *gp;
+    const int wave = wave_id(), lane = threadIdx.x & 63;
+    const int c = wave % 3;
+    const int grp = wave / 3;
+    const int64_t gstride = (int64_t)gridDim.x * kGroups * 64;
     unsigned long long routed = 0;
     float kmax = 0.f;
-    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n; l += stride) {
-        const double pos[3] = {(double)x[l], (double)y[l], (double)z[l]};
-        SetGeo sg[3][2];   // [axis][is_face]
-        bool ok = true;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                ok = ok && axis_geo(g.ax[d], t, pos[d], sg[d][t].g);
-            }
-        }
+    for (int64_t base = ((int64_t)blockIdx.x * kGroups + grp) * 64; base < n; base += gstride) {
+        const int64_t l = base + lane;
+        if (l >= n) continue;
+        // this wavefront's contiguous slice of the outputs (wave-uniform base)
+        float *out = phi + ((((base >> 6) * 3 + c) * kNe) << 6) + lane;
+        uint32_t *hout = home + (((base >> 6) * 3 + c) << 6) + lane;
+        uint8_t *rout = route ? route + (((base >> 6) * 3 + c) << 6) + lane : nullptr;
+        const double px = (double)x[l], py = (double)y[l], pz = (double)z[l];
+        AxisGeo G[3];
+        bool ok = axis_geo(g.ax[0], c == 0, px, G[0]);
+        ok = ok && axis_geo(g.ax[1], c == 1, py, G[1]);
+        ok = ok && axis_geo(g.ax[2], c == 2, pz, G[2]);
         if (!ok) {
-            raise_error(err, l, isfinite(pos[0]) && isfinite(pos[1]) && isfinite(pos[2]) ? MLS_E_SUPPORT
-                                                                                       : MLS_E_NONFINITE);
-            for (int c = 0; c < 3; ++c) {
-                home[(int64_t)c * n + l] = 0xffffffffu;
-                for (int k = 0; k < kNe; ++k) phi[((int64_t)c * kNe + k) * n + l] = __builtin_nanf("");
-                if (route) route[(int64_t)c * n + l] = 0;
-            }
+            mark_failed(err, l, px, py, pz, hout, out, rout);
             continue;
         }
+        *hout = pack_home(G[0].ih, G[1].ih, G[2].ih);
+        float w[3][3];
+        Moments<float> m[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            set_weights(W, sg[d][0]);
-            set_weights(W, sg[d][1]);
-        }
+            float m0 = 0.f, m1 = 0.f, m2 = 0.f;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const SetGeo &X = sg[0][c == 0], &Y = sg[1][c == 1], &Z = sg[2][c == 2];
-            home[(int64_t)c * n + l] = pack_home(X.g.ih, Y.g.ih, Z.g.ih);
-            float A[10], L[10], gam[4];
-            assemble(X.m, Y.m, Z.m, A);
-            bool fp32_ok = cholesky4(A, L);
-            float kap = 0.f;
-            if (fp32_ok) {
-                kap = cond1_and_gamma(A, L, gam);
-                fp32_ok = kap <= tau && isfinite(kap);
-                kmax = fmaxf(kmax, isfinite(kap) ? kap : 3.0e38f);
+            for (int a = 0; a < 3; ++a) {
+                const float wa = weight1(W, G[d].s[a]);
+                w[d][a] = wa;
+                m0 += wa;
+                m1 += wa * G[d].s[a];
+                m2 += wa * G[d].s[a] * G[d].s[a];
             }
-            float *out = phi + (int64_t)c * kNe * n + l;
-            if (fp32_ok) {
+            m[d] = {m0, m1, m2};
+        }
+        float A[10], L[10], gam[4];
+        assemble(m[0], m[1], m[2], A);
+        bool fp32_ok = cholesky4(A, L);
+        if (fp32_ok) {
+            const float kap = cond_bound_and_gamma(A, L, gam);
+            fp32_ok = kap <= tau && isfinite(kap);
+            kmax = fmaxf(kmax, isfinite(kap) ? kap : 3.0e38f);
+        }
+        if (fp32_ok) {
 #pragma unroll
-                for (int cz = 0; cz < 3; ++cz) {
+            for (int cz = 0; cz < 3; ++cz) {
 #pragma unroll
-                    for (int by = 0; by < 3; ++by) {
-                        const float wyz = Y.w[by] * Z.w[cz];
-                        const float pyz = gam[0] + gam[2] * Y.g.s[by] + gam[3] * Z.g.s[cz];
+                for (int by = 0; by < 3; ++by) {
+                    const float wyz = w[1][by] * w[2][cz];
+                    const float pyz = gam[0] + gam[2] * G[1].s[by] + gam[3] * G[2].s[cz];
 #pragma unroll
-                        for (int ax = 0; ax < 3; ++ax) {
-                            const int k = ax + 3 * by + 9 * cz;
-                            out[(int64_t)k * n] = X.w[ax] * wyz * (pyz + gam[1] * X.g.s[ax]);
-                        }
+                    for (int ax = 0; ax < 3; ++ax) {
+                        const int k = ax + 3 * by + 9 * cz;
+                        out[k * kLanes] = w[0][ax] * wyz * (pyz + gam[1] * G[0].s[ax]);
                     }
                 }
-                if (route) route[(int64_t)c * n + l] = 0;
-            } else {
-                double ph[27];
-                ++routed;
-                if (!solve_fp64(g, W, c, pos, ph)) {
-                    raise_error(err, l, MLS_E_SINGULAR);
-                    for (int k = 0; k < kNe; ++k) out[(int64_t)k * n] = __builtin_nanf("");
-                } else {
-                    for (int k = 0; k < kNe; ++k) out[(int64_t)k * n] = (float)ph[k];
-                }
-                if (route) route[(int64_t)c * n + l] = 1;
             }
+            if (rout) *rout = 0;
+        } else {
+            ++routed;
+            if (!solve_fp64(g, W, c, px, py, pz, out)) raise_error(err, l, MLS_E_SINGULAR);
+            if (rout) *rout = 1;
         }
     }
     // one atomic per wavefront for the statistics
@@ -145,7 +150,7 @@ k_build_exact(const Grid g, const Weight W, float tau, int64_t n,
     for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
     float km = kmax;
     for (int off = 32; off > 0; off >>= 1) km = fmaxf(km, __shfl_xor(km, off));
-    if ((threadIdx.x & 63) == 0) {
+    if (lane == 0) {
         if (tot) atomicAdd(&st->fp64_solves, tot);
         if (km > 0.f) atomicMax(&st->kappa_max_bits, __float_as_uint(km));
     }
@@ -156,7 +161,7 @@ k_build_exact(const Grid g, const Weight W, float tau, int64_t n,
 // Shepard blend of one component from its table.  xi: in-cell offsets,
 // geo: table's normalised home control volume [lo, hi) per axis.
 __device__ __forceinline__ void shepard(const float *__restrict__ tab, const float *__restrict__ geo,
-                                        int nsub, const float xi[3], float *__restrict__ out, int64_t n)
+                                        int nsub, const float xi[3], float *__restrict__ out)
 {
     int j0[3];
     float t0[3], step[3];
@@ -215,51 +220,46 @@ __device__ __forceinline__ void shepard(const float *__restrict__ tab, const flo
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int k = 4 * q + e;
-            if (k < kNe) out[(int64_t)k * n] = vals[e];
+            if (k < kNe) out[k * kLanes] = vals[e];
         }
     }
 }
 
-__global__ void __launch_bounds__(kBlock)
-k_build_fast(const Grid g, const FastTables T, int64_t n,
+__global__ void __launch_bounds__(kBuildBlock)
+k_build_fast(const Grid *__restrict__ gp, const FastTables T, int64_t n,
              const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
              uint32_t *__restrict__ home, float *__restrict__ phi, uint8_t *__restrict__ route, ErrWord *err)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const Grid &g = *gp;
+    const int wave = wave_id(), lane = threadIdx.x & 63;
+    const int c = wave % 3;
+    const int grp = wave / 3;
+    const int64_t gstride = (int64_t)gridDim.x * kGroups * 64;
     const int64_t rows = (int64_t)T.n_sub * T.n_sub * T.n_sub;
-    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n; l += stride) {
-        const double pos[3] = {(double)x[l], (double)y[l], (double)z[l]};
-        AxisGeo ag[3][2];
-        bool ok = true;
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-#pragma unroll
-            for (int t = 0; t < 2; ++t) ok = ok && axis_geo(g.ax[d], t, pos[d], ag[d][t]);
+    for (int64_t base = ((int64_t)blockIdx.x * kGroups + grp) * 64; base < n; base += gstride) {
+        const int64_t l = base + lane;
+        if (l >= n) continue;
+        float *out = phi + ((((base >> 6) * 3 + c) * kNe) << 6) + lane;
+        uint32_t *hout = home + (((base >> 6) * 3 + c) << 6) + lane;
+        uint8_t *rout = route ? route + (((base >> 6) * 3 + c) << 6) + lane : nullptr;
+        const double px = (double)x[l], py = (double)y[l], pz = (double)z[l];
+        AxisGeo G[3];
+        bool ok = axis_geo(g.ax[0], c == 0, px, G[0]);
+        ok = ok && axis_geo(g.ax[1], c == 1, py, G[1]);
+        ok = ok && axis_geo(g.ax[2], c == 2, pz, G[2]);
         if (!ok) {
-            raise_error(err, l, isfinite(pos[0]) && isfinite(pos[1]) && isfinite(pos[2]) ? MLS_E_SUPPORT
-                                                                                       : MLS_E_NONFINITE);
-            for (int c = 0; c < 3; ++c) {
-                home[(int64_t)c * n + l] = 0xffffffffu;
-                for (int k = 0; k < kNe; ++k) phi[((int64_t)c * kNe + k) * n + l] = __builtin_nanf("");
-                if (route) route[(int64_t)c * n + l] = 0;
-            }
+            mark_failed(err, l, px, py, pz, hout, out, rout);
             continue;
         }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const AxisGeo &X = ag[0][c == 0], &Y = ag[1][c == 1], &Z = ag[2][c == 2];
-            home[(int64_t)c * n + l] = pack_home(X.ih, Y.ih, Z.ih);
-            int t = 0;
-            if (T.stretched_axis >= 0) {
-                const int d = T.stretched_axis;
-                const int ih = d == 0 ? X.ih : (d == 1 ? Y.ih : Z.ih);
-                t = T.first[c == d] + ih;
-            }
-            const float xi[3] = {X.xi, Y.xi, Z.xi};
-            shepard(T.tab + (int64_t)t * rows * kTableStride, T.geo + (int64_t)t * 6, T.n_sub, xi,
-                    phi + (int64_t)c * kNe * n + l, n);
-            if (route) route[(int64_t)c * n + l] = 0;
+        *hout = pack_home(G[0].ih, G[1].ih, G[2].ih);
+        int t = 0;
+        if (T.stretched_axis >= 0) {
+            const int d = T.stretched_axis;
+            t = T.first[c == d] + G[d].ih;
         }
+        const float xi[3] = {G[0].xi, G[1].xi, G[2].xi};
+        shepard(T.tab + (int64_t)t * rows * kTableStride, T.geo + (int64_t)t * 6, T.n_sub, xi, out);
+        if (rout) *rout = 0;
     }
 }
 
@@ -313,6 +313,14 @@ k_table_build(const Weight W, int64_t count, int nsub, const double *__restrict_
     }
 }
 
+int build_grid(int64_t n, int cu)
+{
+    int64_t b = (n + kGroups * 64 - 1) / (kGroups * 64);
+    const int64_t cap = (int64_t)cu * 16;
+    if (b > cap) b = cap;
+    return (int)(b < 1 ? 1 : b);
+}
+
 int grid_for(int64_t work, int cu)
 {
     int64_t b = (work + kBlock - 1) / kBlock;
@@ -328,7 +336,7 @@ hipError_t launch_build_exact(const Ctx &c, int64_t n, const float *x, const flo
 {
     if (n == 0) return hipSuccess;
     const float tau = (float)(c.opts.kappa_tau > 3.0e38 ? 3.0e38 : c.opts.kappa_tau);
-    hipLaunchKernelGGL(k_build_exact, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.g, c.w, tau, n,
+    hipLaunchKernelGGL(k_build_exact, dim3(build_grid(n, c.cu_count)), dim3(kBuildBlock), 0, s, c.d_grid, c.w, tau, n,
                        x, y, z, home, phi, route, c.err, c.stats);
     return hipGetLastError();
 }
@@ -337,7 +345,7 @@ hipError_t launch_build_fast(const Ctx &c, int64_t n, const float *x, const floa
                              uint32_t *home, float *phi, uint8_t *route, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_build_fast, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.g, fast_tables(c), n,
+    hipLaunchKernelGGL(k_build_fast, dim3(build_grid(n, c.cu_count)), dim3(kBuildBlock), 0, s, c.d_grid, fast_tables(c), n,
                        x, y, z, home, phi, route, c.err);
     return hipGetLastError();
 }

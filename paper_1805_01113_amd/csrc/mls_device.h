@@ -23,6 +23,20 @@ __device__ __forceinline__ void raise_error(ErrWord *err, int64_t marker, int st
 // Kept free of fused multiply-adds so that the coordinates are the plain
 // IEEE results of their definitions.
 #pragma clang fp contract(off)
+// Face / centre coordinate of wrapped index i in [0, n] / [0, n-1].  On an
+// axis whose stored coordinates equal f0 + i h (faces) and f0 + (i + 1/2) h
+// (centres) bit for bit -- checked on the host -- they are recomputed here,
+// which spares the locate step its dependent memory loads.
+__device__ __forceinline__ double fval(const Axis &a, int i)
+{
+    return a.exact ? a.f0 + (double)i * a.h : a.faces[i];
+}
+
+__device__ __forceinline__ double cval(const Axis &a, int i)
+{
+    return a.exact ? a.f0 + ((double)i + 0.5) * a.h : a.centres[i];
+}
+
 __device__ __forceinline__ double face_x(const Axis &a, int i)
 {
     double shift = 0.0;
@@ -30,7 +44,7 @@ __device__ __forceinline__ double face_x(const Axis &a, int i)
         if (i < 0) { i += a.n; shift = -1.0; }
         else if (i >= a.n) { i -= a.n; shift = 1.0; }
     }
-    return a.faces[i] + shift * a.L;
+    return fval(a, i) + shift * a.L;
 }
 
 __device__ __forceinline__ double centre_x(const Axis &a, int i)
@@ -40,7 +54,7 @@ __device__ __forceinline__ double centre_x(const Axis &a, int i)
         if (i < 0) { i += a.n; shift = -1.0; }
         else if (i >= a.n) { i -= a.n; shift = 1.0; }
     }
-    return a.centres[i] + shift * a.L;
+    return cval(a, i) + shift * a.L;
 }
 
 __device__ __forceinline__ double node_x(const Axis &a, int is_face, int i)
@@ -48,9 +62,11 @@ __device__ __forceinline__ double node_x(const Axis &a, int is_face, int i)
     return is_face ? face_x(a, i) : centre_x(a, i);
 }
 
-// Periodic wrap of x into [f0, f0 + L).
+// Periodic wrap of x into [f0, f0 + L).  With f0 = 0 a coordinate already in
+// [0, L) gives t = floor(x / L) = 0 exactly, so it is returned unchanged.
 __device__ __forceinline__ double wrap_x(const Axis &a, double x)
 {
+    if (a.f0 == 0.0 && x >= 0.0 && x < a.L) return x;
     double t = floor((x - a.f0) / a.L);
     double X = x - t * a.L;
     if (X >= a.f0 + a.L) X -= a.L;
@@ -70,16 +86,16 @@ __device__ __forceinline__ bool locate(const Axis &a, int is_face, double x, int
         X = wrap_x(a, x);
     } else {
         X = x;
-        if (!(X >= a.faces[0] && X <= a.faces[n])) return false;
+        if (!(X >= fval(a, 0) && X <= fval(a, n))) return false;
     }
     int i;
     if (!is_face) {
-        if (X >= a.faces[n]) return false;
+        if (X >= fval(a, n)) return false;
         if (a.uniform) {
             i = (int)floor((X - a.f0) * a.inv_h);
             i = min(max(i, 0), n - 1);
-            while (i > 0 && X < a.faces[i]) --i;
-            while (i < n - 1 && X >= a.faces[i + 1]) ++i;
+            while (i > 0 && X < fval(a, i)) --i;
+            while (i < n - 1 && X >= fval(a, i + 1)) ++i;
         } else {
             int lo = 0, hi = n;   // faces[lo] <= X < faces[hi]
             while (hi - lo > 1) {
@@ -89,16 +105,16 @@ __device__ __forceinline__ bool locate(const Axis &a, int is_face, double x, int
             i = lo;
         }
     } else {
-        if (X < a.centres[0]) {
+        if (X < cval(a, 0)) {
             i = 0;
-        } else if (X >= a.centres[n - 1]) {
+        } else if (X >= cval(a, n - 1)) {
             i = n;
         } else if (a.uniform) {
             // centres[i-1] <= X < centres[i], i in [1, n-1]
             i = (int)floor((X - a.f0) * a.inv_h + 0.5);
             i = min(max(i, 1), n - 1);
-            while (i > 1 && X < a.centres[i - 1]) --i;
-            while (i < n - 1 && X >= a.centres[i]) ++i;
+            while (i > 1 && X < cval(a, i - 1)) --i;
+            while (i < n - 1 && X >= cval(a, i)) ++i;
         } else {
             int lo = 0, hi = n - 1;   // centres[lo] <= X < centres[hi]
             while (hi - lo > 1) {
@@ -123,14 +139,23 @@ __device__ __forceinline__ bool axis_geo(const Axis &a, int is_face, double x, A
     int ih;
     double X;
     if (!locate(a, is_face, x, ih, X)) return false;
-    double xm = node_x(a, is_face, ih - 1);
-    double x0 = node_x(a, is_face, ih);
-    double xp = node_x(a, is_face, ih + 1);
-    double H = 0.5 * (xp - xm);
-    g.s[0] = (float)((xm - X) / H);
-    g.s[1] = (float)((x0 - X) / H);
-    g.s[2] = (float)((xp - X) / H);
-    g.xi = (float)((X - x0) / H);
+    const double x0 = node_x(a, is_face, ih);
+    if (a.uniform) {
+        // neighbours one spacing away; H = h
+        const double d0 = (x0 - X) * a.inv_h;
+        g.s[0] = (float)(d0 - 1.0);
+        g.s[1] = (float)d0;
+        g.s[2] = (float)(d0 + 1.0);
+        g.xi = (float)(-d0);
+    } else {
+        const double xm = node_x(a, is_face, ih - 1);
+        const double xp = node_x(a, is_face, ih + 1);
+        const double rH = 2.0 / (xp - xm);   // 1 / H, H = half the support width
+        g.s[0] = (float)((xm - X) * rH);
+        g.s[1] = (float)((x0 - X) * rH);
+        g.s[2] = (float)((xp - X) * rH);
+        g.xi = (float)((X - x0) * rH);
+    }
     g.ih = (a.periodic && ih >= a.n) ? ih - a.n : ih;
     return true;
 }
@@ -157,7 +182,7 @@ __device__ __forceinline__ float weight1(const Weight &w, float s)
 {
     if (w.kind == MLS_W_CONST) return 1.0f;
     float t = s * w.inv_eps;
-    float g = expf(-t * t);
+    float g = __expf(-t * t);
     if (w.kind == MLS_W_GAUSS) return g;
     return fmaxf(g - w.cut, 0.0f);
 }
@@ -200,25 +225,28 @@ __device__ __forceinline__ void assemble(const Moments<T> mx, const Moments<T> m
 // Cholesky factor of the symmetric 4x4 A (10 entries).  Returns false if A is
 // not numerically positive definite.  L stored row-wise lower: l00 l10 l11
 // l20 l21 l22 l30 l31 l32 l33; the diagonal holds 1/l_ii.
+__device__ __forceinline__ float rsqrt_t(float v) { return rsqrtf(v); }
+__device__ __forceinline__ double rsqrt_t(double v) { return 1.0 / sqrt(v); }
+
 template <typename T>
 __device__ __forceinline__ bool cholesky4(const T A[10], T L[10])
 {
     T d0 = A[0];
     if (!(d0 > T(0))) return false;
-    T l00 = sqrt(d0), r0 = T(1) / l00;
+    T r0 = rsqrt_t(d0);
     T l10 = A[1] * r0, l20 = A[2] * r0, l30 = A[3] * r0;
     T d1 = A[4] - l10 * l10;
     if (!(d1 > T(0))) return false;
-    T l11 = sqrt(d1), r1 = T(1) / l11;
+    T r1 = rsqrt_t(d1);
     T l21 = (A[5] - l20 * l10) * r1;
     T l31 = (A[6] - l30 * l10) * r1;
     T d2 = A[7] - l20 * l20 - l21 * l21;
     if (!(d2 > T(0))) return false;
-    T l22 = sqrt(d2), r2 = T(1) / l22;
+    T r2 = rsqrt_t(d2);
     T l32 = (A[8] - l30 * l20 - l31 * l21) * r2;
     T d3 = A[9] - l30 * l30 - l31 * l31 - l32 * l32;
     if (!(d3 > T(0))) return false;
-    T r3 = T(1) / sqrt(d3);
+    T r3 = rsqrt_t(d3);
     L[0] = r0; L[1] = l10; L[2] = r1; L[3] = l20; L[4] = l21; L[5] = r2;
     L[6] = l30; L[7] = l31; L[8] = l32; L[9] = r3;
     return true;
@@ -238,25 +266,46 @@ __device__ __forceinline__ void chol_solve(const T L[10], const T b[4], T x[4])
     x[0] = (y0 - L[1] * x[1] - L[3] * x[2] - L[6] * x[3]) * L[0];
 }
 
-// 1-norm condition number estimate ||A||_1 ||A^-1||_1 (exact for 4x4: all
-// four columns of the inverse are formed).  gamma receives A^-1 e_0.
+// gamma = A^-1 e_0 and an upper bound of the 2-norm condition number,
+// kappa_2(A) <= ||A||_F ||L^-1||_F^2 (A^-1 = L^-T L^-1), from the explicit
+// inverse M = L^-1 of the Cholesky factor.
 template <typename T>
-__device__ __forceinline__ T cond1_and_gamma(const T A[10], const T L[10], T gamma[4])
+__device__ __forceinline__ T cond_bound_and_gamma(const T A[10], const T L[10], T gamma[4])
 {
-    const T full[16] = {A[0], A[1], A[2], A[3], A[1], A[4], A[5], A[6],
-                        A[2], A[5], A[7], A[8], A[3], A[6], A[8], A[9]};
-    T na = T(0), ni = T(0);
-    for (int j = 0; j < 4; ++j) {
-        T sa = fabs(full[0 * 4 + j]) + fabs(full[1 * 4 + j]) + fabs(full[2 * 4 + j]) + fabs(full[3 * 4 + j]);
-        na = sa > na ? sa : na;
-        T e[4] = {T(j == 0), T(j == 1), T(j == 2), T(j == 3)};
-        T col[4];
-        chol_solve(L, e, col);
-        if (j == 0) { gamma[0] = col[0]; gamma[1] = col[1]; gamma[2] = col[2]; gamma[3] = col[3]; }
-        T si = fabs(col[0]) + fabs(col[1]) + fabs(col[2]) + fabs(col[3]);
-        ni = si > ni ? si : ni;
-    }
-    return na * ni;
+    // M = L^-1 (lower triangular), column by column
+    const T m00 = L[0];
+    const T m11 = L[2], m10 = -L[1] * m00 * m11;
+    const T m22 = L[5], m21 = -L[4] * m11 * m22, m20 = -(L[3] * m00 + L[4] * m10) * m22;
+    const T m33 = L[9];
+    const T m32 = -L[8] * m22 * m33;
+    const T m31 = -(L[7] * m11 + L[8] * m21) * m33;
+    const T m30 = -(L[6] * m00 + L[7] * m10 + L[8] * m20) * m33;
+    // gamma = M^T (M e_0)
+    gamma[0] = m00 * m00 + m10 * m10 + m20 * m20 + m30 * m30;
+    gamma[1] = m11 * m10 + m21 * m20 + m31 * m30;
+    gamma[2] = m22 * m20 + m32 * m30;
+    gamma[3] = m33 * m30;
+    const T mf = m00 * m00 + m10 * m10 + m11 * m11 + m20 * m20 + m21 * m21 + m22 * m22 + m30 * m30 +
+                 m31 * m31 + m32 * m32 + m33 * m33;
+    const T af = A[0] * A[0] + A[4] * A[4] + A[7] * A[7] + A[9] * A[9] +
+                 T(2) * (A[1] * A[1] + A[2] * A[2] + A[3] * A[3] + A[5] * A[5] + A[6] * A[6] + A[8] * A[8]);
+    return sqrt(af) * mf;
+}
+
+// Blocked marker layout of the shape functions, home indices and route
+// flags: markers are grouped in blocks of 64 (one wavefront); inside a block
+// the 64 values of one (component, support node) are consecutive.  So a
+// wavefront building one component of 64 markers writes one contiguous
+// 27 x 256-byte stretch, and a lane's consecutive support nodes are 64
+// floats apart.
+constexpr int kLanes = 64;
+__device__ __forceinline__ int64_t phi_at(int64_t l, int c)
+{
+    return ((((l >> 6) * 3 + c) * kNe) << 6) + (l & 63);   // + k * kLanes for node k
+}
+__device__ __forceinline__ int64_t home_at(int64_t l, int c)
+{
+    return (((l >> 6) * 3 + c) << 6) + (l & 63);
 }
 
 __device__ __forceinline__ uint32_t pack_home(int i, int j, int k)

@@ -27,6 +27,8 @@ struct Axis {
     int32_t periodic;   // 1 = periodic
     int32_t uniform;    // 1 = all cell widths bitwise equal
     int32_t tile;       // tile edge (nodes) of the spreading grid along this axis
+    int32_t exact;      // 1: faces[i] == f0 + i*h and centres[i] == f0 + (i+0.5)*h bit for bit
+    double h;           // L / n (exactly-uniform axes)
     double f0;          // faces[0]
     double L;           // faces[n] - faces[0]
     double inv_h;       // n / L: only used to guess the home node
@@ -34,6 +36,7 @@ struct Axis {
     const double *centres;  // n, 0.5 * (f[i] + f[i+1])
     const float *width_c;   // n     control-volume widths of centre nodes
     const float *width_f;   // n + 1 control-volume widths of face nodes
+    const float *tile_hmin; // ntile: smallest control-volume width near each tile (spreading bound)
 };
 
 struct Weight {
@@ -79,6 +82,7 @@ struct FastTables {
 struct Ctx {
     int device = 0;
     Grid g{};
+    Grid *d_grid = nullptr;       // device copy of g read by the kernels
     Weight w{};
     mls_opts opts{};
     std::vector<double> h_faces[3];
@@ -99,9 +103,10 @@ struct Ctx {
     uint32_t *tile_count = nullptr;    // ntiles
     uint32_t *tile_off = nullptr;      // ntiles + 1
     uint32_t *tile_cursor = nullptr;   // ntiles
+    uint32_t *tile_active = nullptr;   // ntiles: non-empty tiles per XCD slab
     uint32_t *block_sums = nullptr;    // scan partials
     uint32_t *entries = nullptr;       // 8 * cap_markers
-    uint32_t *work = nullptr;          // persistent-kernel work counter(s)
+    uint32_t *work = nullptr;          // [0..7] active-list sizes, [8..15] cursors
     int64_t last_entries_hint = 0;
     int cu_count = 256;
     // time step

@@ -28,16 +28,17 @@ __device__ __forceinline__ int64_t field_index(const Grid &g, int c, int i, int 
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_interp(const Grid g, int64_t n, const uint32_t *__restrict__ home, const float *__restrict__ phi,
+k_interp(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home, const float *__restrict__ phi,
          const float *__restrict__ u, const float *__restrict__ v, const float *__restrict__ w,
          float *__restrict__ U, float *__restrict__ V, float *__restrict__ W, ErrWord *err)
 {
+    const Grid &g = *gp;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n; l += stride) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const float *q = c == 0 ? u : (c == 1 ? v : w);
-            const uint32_t h = home[(int64_t)c * n + l];
+            const uint32_t h = home[home_at(l, c)];
             int i, j, k;
             unpack_home(h, i, j, k);
             float *out = c == 0 ? U : (c == 1 ? V : W);
@@ -53,12 +54,12 @@ k_interp(const Grid g, int64_t n, const uint32_t *__restrict__ home, const float
                 oy[a] = (int64_t)nb_index(j, a - 1, g.dims[c][1], g.ax[1].periodic) * g.dims[c][0];
                 oz[a] = (int64_t)nb_index(k, a - 1, g.dims[c][2], g.ax[2].periodic) * g.dims[c][0] * g.dims[c][1];
             }
-            const float *p = phi + (int64_t)c * kNe * n + l;
+            const float *p = phi + phi_at(l, c);
             float acc = 0.f;
 #pragma unroll
             for (int kk = 0; kk < kNe; ++kk) {
                 const int a = kk % 3, b = (kk / 3) % 3, cz = kk / 9;
-                acc += p[(int64_t)kk * n] * q[oz[cz] + oy[b] + ox[a]];
+                acc += p[kk * kLanes] * q[oz[cz] + oy[b] + ox[a]];
             }
             out[l] = acc;
         }
@@ -92,40 +93,66 @@ __device__ __forceinline__ int axis_tiles(const Grid &g, int d, int cell, int fa
     return cnt;
 }
 
+// Binning of markers into tiles.  Lanes of a wavefront that hit the same tile
+// are combined into one atomic (the leader adds the count, the others take
+// consecutive slots after it in lane order), so a tile's entry list consists
+// of runs of consecutive marker indices and the accumulation kernel reads the
+// shape functions of a run with coalesced loads.
 template <bool FILL>
 __global__ void __launch_bounds__(kBlock)
-k_bin(const Grid g, int64_t n, const uint32_t *__restrict__ home, uint32_t *__restrict__ count,
+k_bin(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home, uint32_t *__restrict__ count,
       uint32_t *__restrict__ cursor, uint32_t *__restrict__ entries, ErrWord *err)
 {
+    const Grid &g = *gp;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long lower = (1ull << lane) - 1ull;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n; l += stride) {
-        int hc[3][3];
-        bool valid = true;
+    // the loop bound is wave-uniform so that the ballots below see the whole wave
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
+        const int64_t l = base + lane;
+        int nt = 0;
+        int64_t tl[8];
+        if (l < n) {
+            int hc[3][3];
+            bool valid = true;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            unpack_home(home[(int64_t)c * n + l], hc[c][0], hc[c][1], hc[c][2]);
-            valid = valid && home_ok(g, c, hc[c][0], hc[c][1], hc[c][2]);
-        }
-        if (!valid) {           // a marker without a valid support contributes nothing
-            if (!FILL) raise_error(err, l, MLS_E_SUPPORT);
-            continue;
-        }
-        int tx[2], ty[2], tz[2];
-        // centre-staggered home on axis d comes from component (d+1)%3
-        const int nx = axis_tiles(g, 0, hc[1][0], hc[0][0], tx);
-        const int ny = axis_tiles(g, 1, hc[2][1], hc[1][1], ty);
-        const int nz = axis_tiles(g, 2, hc[0][2], hc[2][2], tz);
-        for (int a = 0; a < nz; ++a)
-            for (int b = 0; b < ny; ++b)
-                for (int cc = 0; cc < nx; ++cc) {
-                    const int64_t t = ((int64_t)tz[a] * g.ntile[1] + ty[b]) * g.ntile[0] + tx[cc];
-                    if (!FILL) {
-                        atomicAdd(&count[t], 1u);
-                    } else {
-                        const uint32_t pos = atomicAdd(&cursor[t], 1u);
-                        entries[pos] = (uint32_t)l;
-                    }
+            for (int c = 0; c < 3; ++c) {
+                unpack_home(home[home_at(l, c)], hc[c][0], hc[c][1], hc[c][2]);
+                valid = valid && home_ok(g, c, hc[c][0], hc[c][1], hc[c][2]);
+            }
+            if (valid) {
+                int tx[2], ty[2], tz[2];
+                // centre-staggered home on axis d comes from component (d+1)%3
+                const int nx = axis_tiles(g, 0, hc[1][0], hc[0][0], tx);
+                const int ny = axis_tiles(g, 1, hc[2][1], hc[1][1], ty);
+                const int nz = axis_tiles(g, 2, hc[0][2], hc[2][2], tz);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int a = q >> 2, b = (q >> 1) & 1, cc = q & 1;
+                    const bool use = a < nz && b < ny && cc < nx;
+                    tl[q] = use ? ((int64_t)tz[a] * g.ntile[1] + ty[b]) * g.ntile[0] + tx[cc] : -1;
                 }
+                nt = 8;
+            } else if (!FILL) {
+                raise_error(err, l, MLS_E_SUPPORT);   // contributes nothing
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t t = nt ? tl[q] : -1;
+            unsigned long long pending = __ballot(t >= 0);
+            while (pending) {
+                const int leader = __ffsll((long long)pending) - 1;
+                const int64_t tlead = __shfl(t, leader);
+                const unsigned long long mask = __ballot(t == tlead) & pending;
+                uint32_t pos = 0;
+                if (lane == leader)
+                    pos = atomicAdd(FILL ? &cursor[tlead] : &count[tlead], (uint32_t)__popcll(mask));
+                pos = __shfl(pos, leader);
+                if (FILL && ((mask >> lane) & 1ull)) entries[pos + __popcll(mask & lower)] = (uint32_t)l;
+                pending &= ~mask;
+            }
+        }
     }
 }
 
@@ -215,7 +242,34 @@ __global__ void __launch_bounds__(kBlock) k_scan_final(const uint32_t *__restric
     }
     const int64_t first = base + (int64_t)threadIdx.x * per;
     if (first <= nt - 1 && nt - 1 < first + per) off[nt] = run;   // the owner of the last tile
-    if (blockIdx.x == 0 && threadIdx.x == 0) *work = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < 16) work[threadIdx.x] = 0u;   // active-list sizes and cursors
+}
+
+// Non-empty tiles, listed per XCD slab: the tiles are split into 8 contiguous
+// slabs (one per XCD); work[x] counts the non-empty tiles of slab x and
+// active[x * chunk + i] lists them.
+__global__ void __launch_bounds__(kBlock)
+k_active_tiles(const uint32_t *__restrict__ count, int64_t nt, uint32_t *__restrict__ active, uint32_t *work)
+{
+    const int lane = threadIdx.x & 63;
+    const unsigned long long lower = (1ull << lane) - 1ull;
+    const int64_t chunk = (nt + 7) >> 3;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < nt; base += stride) {
+        const int64_t t = base + lane;
+        const int x = (t < nt && count[t] > 0u) ? (int)(t / chunk) : -1;
+        unsigned long long pending = __ballot(x >= 0);
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const int xl = __shfl(x, leader);
+            const unsigned long long mask = __ballot(x == xl) & pending;
+            uint32_t pos = 0;
+            if (lane == leader) pos = atomicAdd(&work[xl], (uint32_t)__popcll(mask));
+            pos = __shfl(pos, leader);
+            if ((mask >> lane) & 1ull) active[(int64_t)xl * chunk + pos + __popcll(mask & lower)] = (uint32_t)t;
+            pending &= ~mask;
+        }
+    }
 }
 
 // ---- spreading: per-tile fixed-point accumulation ------------------------------
@@ -228,25 +282,42 @@ __device__ __forceinline__ float width_of(const Axis &a, int is_face, int i)
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_spread_tiles(const Grid g, int64_t n, const uint32_t *__restrict__ home, const float *__restrict__ phi,
+k_spread_tiles(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home, const float *__restrict__ phi,
                const float *__restrict__ area, const float *__restrict__ Fx, const float *__restrict__ Fy,
                const float *__restrict__ Fz, float *__restrict__ fx, float *__restrict__ fy,
                float *__restrict__ fz, const uint32_t *__restrict__ off, const uint32_t *__restrict__ entries,
-               uint32_t *work, double inv_hmin2, ErrWord *err)
+               const uint32_t *__restrict__ active, uint32_t *work, ErrWord *err)
 {
+    const Grid &g = *gp;
     __shared__ unsigned long long acc[kTileNodes];
     __shared__ float red[3][kBlock / 64];
-    __shared__ int64_t tile_sh;
     const int tsx = g.ax[0].tile, tsy = g.ax[1].tile, tsz = g.ax[2].tile;
     const int tnodes = tsx * tsy * tsz;
+    const Axis &AX = g.ax[0], &AY = g.ax[1], &AZ = g.ax[2];
+    // XCD-aware dynamic assignment: workgroups are dispatched round-robin over
+    // the 8 XCDs, so blockIdx % 8 names the XCD.  Each XCD first takes the
+    // non-empty tiles of its own slab (tiles sharing markers then share that
+    // XCD's L2), then helps the other slabs.
+    __shared__ int64_t tile_sh;
+    const int xcd = blockIdx.x & 7;
+    const int64_t chunk = (g.ntiles + 7) >> 3;
+    int src = xcd, rounds = 0;
     for (;;) {
-        if (threadIdx.x == 0) tile_sh = (int64_t)atomicAdd(work, 1u);
+        if (threadIdx.x == 0) {
+            int64_t t = -1;
+            while (rounds < 8) {
+                const uint32_t i = atomicAdd(&work[8 + src], 1u);
+                if (i < work[src]) { t = active[(int64_t)src * chunk + i]; break; }
+                src = (src + 1) & 7;
+                ++rounds;
+            }
+            tile_sh = t;
+        }
         __syncthreads();
         const int64_t t = tile_sh;
         __syncthreads();
-        if (t >= g.ntiles) break;
+        if (t < 0) break;
         const uint32_t beg = off[t], end = off[t + 1];
-        if (beg == end) continue;
         const int tx = (int)(t % g.ntile[0]);
         const int ty = (int)((t / g.ntile[0]) % g.ntile[1]);
         const int tz = (int)(t / ((int64_t)g.ntile[0] * g.ntile[1]));
@@ -271,59 +342,78 @@ k_spread_tiles(const Grid g, int64_t n, const uint32_t *__restrict__ home, const
         float M[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) M[c] = fmaxf(fmaxf(red[c][0], red[c][1]), fmaxf(red[c][2], red[c][3]));
-        // contributions per node <= number of entries; scale so that
-        // count * bound * 2^S < 2^62
-        const int kbits = 33 - __clz((int)(end - beg) | 1);   // > log2(count)
+        // c_l <= A_l / h^2 for a shape function with sum phi dV close to dV,
+        // h the smallest control-volume width near the tile; with |phi| <= 2
+        // every contribution |c_l phi_k F_l| stays below bound = 8 M / h^2.
+        const float hloc = fminf(fminf(AX.tile_hmin[tx], AY.tile_hmin[ty]), AZ.tile_hmin[tz]);
+        const double inv_h2 = 1.0 / ((double)hloc * (double)hloc);
 #pragma unroll 1
         for (int c = 0; c < 3; ++c) {
-            const double bound = 8.0 * (double)M[c] * inv_hmin2;   // |c_l phi_k F_l| limit
-            if (!(bound > 0.0)) continue;                          // nothing to add for this component
+            const double bound = 8.0 * (double)M[c] * inv_h2;
+            if (!(bound > 0.0) || !(bound < 1e300)) {   // nothing to add, or a non-finite force
+                if (!(bound >= 0.0) || bound >= 1e300)
+                    for (uint32_t e = beg + threadIdx.x; e < end; e += blockDim.x) raise_error(err, entries[e], MLS_E_RANGE);
+                continue;
+            }
             int ebits;
-            frexp(bound, &ebits);                                  // bound < 2^ebits
-            const int S = 61 - ebits - kbits;
-            const double scale = ldexp(1.0, S);
+            frexp(bound, &ebits);                      // bound < 2^ebits
+            // each scaled contribution stays below 2^30: it converts to int32
+            // exactly enough (quantum 2^-30 of the bound) and sums in int64
+            const int S = 30 - ebits;
             for (int q = threadIdx.x; q < tnodes; q += blockDim.x) acc[q] = 0ull;
             __syncthreads();
             const float *F = c == 0 ? Fx : (c == 1 ? Fy : Fz);
-            const Axis &AX = g.ax[0], &AY = g.ax[1], &AZ = g.ax[2];
+            const float scale_f = ldexpf(1.0f, S);
+            const float lim = 1073741824.0f;            // 2^30
             for (uint32_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
                 const uint32_t m = entries[e];
                 int hi, hj, hk;
-                unpack_home(home[(int64_t)c * n + m], hi, hj, hk);
+                unpack_home(home[home_at(m, c)], hi, hj, hk);
                 int ix[3], iy[3], iz[3];
-                float wx[3], wy[3], wz[3];
+                bool inx[3], iny[3], inz[3];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     ix[a] = nb_index(hi, a - 1, g.dims[c][0], AX.periodic);
                     iy[a] = nb_index(hj, a - 1, g.dims[c][1], AY.periodic);
                     iz[a] = nb_index(hk, a - 1, g.dims[c][2], AZ.periodic);
+                    inx[a] = (unsigned)(ix[a] - x0) < (unsigned)tsx;
+                    iny[a] = (unsigned)(iy[a] - y0) < (unsigned)tsy;
+                    inz[a] = (unsigned)(iz[a] - z0) < (unsigned)tsz;
+                }
+                // this component's support may miss the tile (the entry list is
+                // the union over components): then nothing is read
+                if (!((inx[0] || inx[1] || inx[2]) && (iny[0] || iny[1] || iny[2]) && (inz[0] || inz[1] || inz[2])))
+                    continue;
+                float wx[3], wy[3], wz[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
                     wx[a] = width_of(AX, c == 0, ix[a]);
                     wy[a] = width_of(AY, c == 1, iy[a]);
                     wz[a] = width_of(AZ, c == 2, iz[a]);
                 }
-                const float *p = phi + (int64_t)c * kNe * n + m;
+                const float *p = phi + phi_at(m, c);
                 float ph[kNe];
                 float hl = 0.f, den = 0.f;
 #pragma unroll
                 for (int k = 0; k < kNe; ++k) {
                     const int a = k % 3, b = (k / 3) % 3, cz = k / 9;
-                    ph[k] = p[(int64_t)k * n];
+                    ph[k] = p[k * kLanes];
                     hl += ph[k] * (wx[a] + wy[b] + wz[cz]);
                     den += ph[k] * (wx[a] * wy[b] * wz[cz]);
                 }
-                hl *= (1.0f / 3.0f);
-                // c_l F_l = A_l h_l F_l / sum_k phi_k dV_k   (eq. 8)
-                const double val = (double)area[m] * (double)hl * (double)F[m] / (double)den;
+                // c_l F_l = A_l h_l F_l / sum_k phi_k dV_k   (eq. 8), pre-scaled
+                const float vsc = area[m] * (hl * (1.0f / 3.0f)) * F[m] / den * scale_f;
                 bool range_ok = true;
 #pragma unroll
                 for (int k = 0; k < kNe; ++k) {
                     const int a = k % 3, b = (k / 3) % 3, cz = k / 9;
-                    const int lx = ix[a] - x0, ly = iy[b] - y0, lz = iz[cz] - z0;
-                    if ((unsigned)lx < (unsigned)tsx && (unsigned)ly < (unsigned)tsy && (unsigned)lz < (unsigned)tsz) {
-                        const double v = val * (double)ph[k];
-                        range_ok = range_ok && (fabs(v) <= bound);
-                        const long long qv = __double2ll_rn(v * scale);
-                        atomicAdd(&acc[(lz * tsy + ly) * tsx + lx], (unsigned long long)qv);
+                    if (inx[a] && iny[b] && inz[cz]) {
+                        float vs = ph[k] * vsc;
+                        range_ok = range_ok && (fabsf(vs) < lim);
+                        vs = fminf(fmaxf(vs, -lim), lim);
+                        const long long qv = (long long)(int)rintf(vs);
+                        const int li = ((iz[cz] - z0) * tsy + (iy[b] - y0)) * tsx + (ix[a] - x0);
+                        atomicAdd(&acc[li], (unsigned long long)qv);
                     }
                 }
                 if (!range_ok) raise_error(err, m, MLS_E_RANGE);
@@ -360,7 +450,7 @@ hipError_t launch_interp(const Ctx &c, int64_t n, const uint32_t *home, const fl
                          float *U, float *V, float *W, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_interp, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.g, n, home, phi,
+    hipLaunchKernelGGL(k_interp, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, home, phi,
                        u, v, w, U, V, W, c.err);
     return hipGetLastError();
 }
@@ -374,20 +464,21 @@ hipError_t launch_spread(Ctx &c, int64_t n, const uint32_t *home, const float *p
     const int64_t nb = (nt + kScanChunk - 1) / kScanChunk;
     TimedLaunch* tb = new TimedLaunch(c, MLS_K_SPREAD_BIN, s);
     hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(nt, c.cu_count)), dim3(kBlock), 0, s, c.tile_count, nt);
-    hipLaunchKernelGGL(k_bin<false>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.g, n, home,
+    hipLaunchKernelGGL(k_bin<false>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, home,
                        c.tile_count, c.tile_cursor, c.entries, c.err);
     hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)nb), dim3(kBlock), 0, s, c.tile_count, nt, c.block_sums);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, c.block_sums, nb);
     hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kBlock), 0, s, c.tile_count, nt, c.block_sums,
                        c.tile_off, c.tile_cursor, c.work);
-    hipLaunchKernelGGL(k_bin<true>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.g, n, home,
+    hipLaunchKernelGGL(k_bin<true>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, home,
                        c.tile_count, c.tile_cursor, c.entries, c.err);
+    hipLaunchKernelGGL(k_active_tiles, dim3(grid_for(nt, c.cu_count)), dim3(kBlock), 0, s, c.tile_count, nt,
+                       c.tile_active, c.work);
     delete tb;
-    const double inv_hmin2 = 1.0 / (c.g.h_min * c.g.h_min);
-    const int persist = c.cu_count * 4;
+    const int persist = ((c.cu_count * 4) + 7) & ~7;   // a multiple of the 8 XCDs
     TimedLaunch tt(c, MLS_K_SPREAD_TILES, s);
-    hipLaunchKernelGGL(k_spread_tiles, dim3(persist), dim3(kBlock), 0, s, c.g, n, home, phi, area, Fx, Fy, Fz,
-                       fx, fy, fz, c.tile_off, c.entries, c.work, inv_hmin2, c.err);
+    hipLaunchKernelGGL(k_spread_tiles, dim3(persist), dim3(kBlock), 0, s, c.d_grid, n, home, phi, area, Fx, Fy, Fz,
+                       fx, fy, fz, c.tile_off, c.entries, c.tile_active, c.work, c.err);
     return hipGetLastError();
 }
 

@@ -192,24 +192,25 @@ class Context:
         for t, nm in ((x, "x"), (y, "y"), (z, "z")):
             _check_dev(t, torch.float32, n, nm)
         dev = x.device
+        m = npad(n)
         if home is None:
-            home = torch.empty(3 * n, dtype=torch.int32, device=dev)
+            home = torch.empty(3 * m, dtype=torch.int32, device=dev)
         if phi is None:
-            phi = torch.empty(3 * 27 * n, dtype=torch.float32, device=dev)
-        _check_dev(home, torch.int32, 3 * n, "home")
-        _check_dev(phi, torch.float32, 81 * n, "phi")
+            phi = torch.empty(81 * m, dtype=torch.float32, device=dev)
+        _check_dev(home, torch.int32, 3 * m, "home")
+        _check_dev(phi, torch.float32, 81 * m, "phi")
         if route is not None:
-            _check_dev(route, torch.uint8, 3 * n, "route")
+            _check_dev(route, torch.uint8, 3 * m, "route")
         st = self._lib.mls_build(self.h, n, _ptr(x), _ptr(y), _ptr(z), int(method), _ptr(home), _ptr(phi),
                                  _ptr(route), _stream(stream))
         self._raise(st, "mls_build")
         return home, phi, route
 
-    def interp(self, home, phi, u, v, w, out=None, stream=None):
+    def interp(self, home, phi, u, v, w, n, out=None, stream=None):
+        """U [3, n] = Phi^T q (eq. 6) for the n markers of home/phi."""
         import torch
-        n = home.numel() // 3
-        _check_dev(home, torch.int32, 3 * n, "home")
-        _check_dev(phi, torch.float32, 81 * n, "phi")
+        _check_dev(home, torch.int32, 3 * npad(n), "home")
+        _check_dev(phi, torch.float32, 81 * npad(n), "phi")
         for c, q in enumerate((u, v, w)):
             _check_dev(q, torch.float32, int(np.prod(self.shape(c))), "field %d" % c)
         if out is None:
@@ -223,9 +224,9 @@ class Context:
     def spread(self, home, phi, area, F, fields, stream=None):
         """Adds the eq. 7-8 forcing of marker forces F [3, n] into fields (u, v, w grids)."""
         import torch
-        n = home.numel() // 3
-        _check_dev(home, torch.int32, 3 * n, "home")
-        _check_dev(phi, torch.float32, 81 * n, "phi")
+        n = area.numel()
+        _check_dev(home, torch.int32, 3 * npad(n), "home")
+        _check_dev(phi, torch.float32, 81 * npad(n), "phi")
         _check_dev(area, torch.float32, n, "area")
         _check_dev(F, torch.float32, 3 * n, "F")
         for c, q in enumerate(fields):
@@ -282,9 +283,9 @@ class StepBuffers:
         self.y = torch.empty_like(y0)
         self.z = torch.empty_like(z0)
         self.vb = vb
-        self.home = torch.empty(3 * n, dtype=torch.int32, device=dev)
-        self.phi = torch.empty(81 * n, dtype=torch.float32, device=dev)
-        self.route = torch.zeros(3 * n, dtype=torch.uint8, device=dev) if route else None
+        self.home = torch.empty(3 * npad(n), dtype=torch.int32, device=dev)
+        self.phi = torch.empty(81 * npad(n), dtype=torch.float32, device=dev)
+        self.route = torch.zeros(3 * npad(n), dtype=torch.uint8, device=dev) if route else None
         self.fields = fields
         self.forcing = forcing
         self.U = torch.empty((3, n), dtype=torch.float32, device=dev)
@@ -359,7 +360,29 @@ def timing_get(ctx: "Context", reset=True):
     return {K_NAMES[i]: (t.ms[i], t.launches[i]) for i in range(len(K_NAMES)) if t.launches[i] > 0}
 
 
-def unpack_home(home: np.ndarray, n: int) -> np.ndarray:
-    """Packed home [3*n] (uint32 bits) -> [3, n, 3] int (component, marker, axis)."""
-    h = np.asarray(home).astype(np.int64).reshape(3, n) & 0xFFFFFFFF
+def npad(n: int) -> int:
+    """Marker count rounded up to the 64-marker blocks of the phi/home layout."""
+    return (int(n) + 63) // 64 * 64
+
+
+def unblock(a, n: int, per: int = 1):
+    """Blocked layout [npad/64][3][per][64] -> [3, n, per] (numpy or torch)."""
+    m = npad(n)
+    if hasattr(a, "permute"):
+        return a.reshape(m // 64, 3, per, 64).permute(1, 0, 3, 2).reshape(3, m, per)[:, :n]
+    return np.asarray(a).reshape(m // 64, 3, per, 64).transpose(1, 0, 3, 2).reshape(3, m, per)[:, :n]
+
+
+def unpack_phi(phi, n: int):
+    """phi (81 * npad) -> [3, n, 27] (component, marker, support node)."""
+    return unblock(phi, n, 27)
+
+
+def unpack_route(route, n: int):
+    return unblock(route, n, 1)[:, :, 0]
+
+
+def unpack_home(home, n: int) -> np.ndarray:
+    """Packed home (3 * npad, uint32 bits) -> [3, n, 3] int (component, marker, axis)."""
+    h = np.asarray(unblock(np.asarray(home), n, 1)[:, :, 0]).astype(np.int64) & 0xFFFFFFFF
     return np.stack([h & 0x7FF, (h >> 11) & 0x7FF, h >> 22], axis=-1)

@@ -233,7 +233,7 @@ def fourier_modes(r: np.random.Generator, n_modes: int, kmax: int = 4):
     return np.array(ks, dtype=np.float64), a, th
 
 
-def fourier_field(grid: GridSpec, comp: int, modes, lengths, device="cpu", out=None, slab=64):
+def fourier_field(grid: GridSpec, comp: int, modes, lengths, device="cpu", out=None, slab=256):
     """q(x) = sum_m a_m cos(2 pi k_m . x / L + theta_m) sampled in FP64 at the
     component's nodes, stored FP32 [z][y][x].  Uses torch (CPU or GPU) so the
     large grids can be filled on the device in z-slabs."""

@@ -36,12 +36,12 @@ def gpu_build(ctx, x, y, z, method=0, route=False):
     from paper_1805_01113_amd import mls
     xd, yd, zd = to_dev(x), to_dev(y), to_dev(z)
     n = len(x)
-    r = torch.zeros(3 * n, dtype=torch.uint8, device="cuda") if route else None
+    r = torch.zeros(3 * mls.npad(n), dtype=torch.uint8, device="cuda") if route else None
     home, phi, r = ctx.build(xd, yd, zd, method=method, route=r)
     ctx.sync()
     h = mls.unpack_home(home.cpu().numpy().view(np.uint32), n)      # [3, n, 3]
-    p = phi.cpu().numpy().reshape(3, 27, n).transpose(0, 2, 1)      # [3, n, 27]
-    return home, phi, h, p, (r.cpu().numpy().reshape(3, n) if route else None)
+    p = mls.unpack_phi(phi.cpu().numpy(), n)                        # [3, n, 27]
+    return home, phi, h, p, (mls.unpack_route(r.cpu().numpy(), n) if route else None)
 
 
 def compare_build(orc, grid, ctx, x, y, z, method=0, nsub=9, label="", kind=0):

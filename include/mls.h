@@ -107,6 +107,8 @@ typedef struct {
                              volume, boundaries included (default 9 -> 729) */
     double fallback_tol;  /* learned: consistency residual above which the
                              marker falls back to exact MLS (default 1e-4) */
+    int32_t spread_tile;  /* edge (cells) of the spreading tiles: 4, 8 or 16
+                             (0 = default 8) */
 } mls_opts;
 
 typedef struct {
@@ -126,8 +128,8 @@ const char *mls_version(void);
  * coordinates and control-volume widths, and sizes the spreading tiles.
  * weight/opts may be NULL for the defaults.  Returns MLS_E_ARG for a grid
  * that is not increasing, has fewer than 3 cells on an axis, exceeds the
- * packed-index limits, has more than one non-uniform axis, or a periodic axis
- * whose cell count is neither <= 16 nor a multiple of 4. */
+ * packed-index limits, or has a periodic axis longer than 16 cells whose cell
+ * count has no divisor between 4 and 16 (the spreading tiles). */
 mls_status mls_ctx_create(mls_ctx **ctx, const mls_grid *grid, const mls_weight *weight,
                           const mls_opts *opts);
 void mls_ctx_destroy(mls_ctx *ctx);
@@ -171,9 +173,12 @@ mls_status mls_interp(mls_ctx *ctx, int64_t n, const uint32_t *home, const float
  *   c_l = dV_l / sum_k phi_k dV_k,            f_k += c_l phi_k F_l,
  * with dx_k, dy_k, dz_k the control-volume widths of support node k on the
  * component's grid and dV_k = dx_k dy_k dz_k.  area = A_l (device FP32, n).
- * The result is bitwise reproducible: markers are binned by tiles of the
- * forcing grid and each tile sums its contributions in 64-bit fixed point,
- * whose sum does not depend on order.  A contribution larger than the
+ * The result is bitwise reproducible and independent of the marker order:
+ * markers are binned (counting sort) by the tile of the forcing grid that
+ * holds their cell; a tile sums its markers' contributions in 64-bit fixed
+ * point in a box covering the tile and its one-node halo; tiles are coloured
+ * 2x2x2 so that boxes of one colour never overlap, and the eight colours add
+ * their boxes into the field one after another.  A contribution larger than the
  * fixed-point bound (|c_l phi_k F_l| > 8 max|A_l F_l| / h_min^2, which a
  * shape function with |phi| <= 2 and sum phi dV close to dV never reaches)
  * raises MLS_E_RANGE. */

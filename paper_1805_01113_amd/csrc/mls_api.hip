@@ -96,14 +96,20 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
         for (int i = 0; i <= n && a.exact; ++i) a.exact = (f[i] == a.f0 + (double)i * a.h);
         for (int i = 0; i < n && a.exact; ++i) a.exact = (c.h_centres[d][i] == a.f0 + ((double)i + 0.5) * a.h);
         if (!bitwise) { ++nonuniform; c.stretched_axis = d; }
+        // spreading tiles: a periodic axis longer than kMaxTile cells is cut
+        // into equal tiles (a divisor of n between 4 and 16, the requested
+        // edge if it divides n); a shorter one is a single tile
+        const int want = (opts && opts->spread_tile) ? opts->spread_tile : 8;
+        if (want != 4 && want != 8 && want != 16) { delete ctx; return MLS_E_ARG; }
         if (a.periodic) {
+            a.tile = 0;
             if (n <= kMaxTile) a.tile = n;
-            else if (n % 16 == 0) a.tile = 16;
-            else if (n % 8 == 0) a.tile = 8;
-            else if (n % 4 == 0) a.tile = 4;
-            else { delete ctx; return MLS_E_ARG; }
+            else if (n % want == 0) a.tile = want;
+            for (int t = kMaxTile; t >= 4 && !a.tile; --t)
+                if (n % t == 0) a.tile = t;
+            if (!a.tile) { delete ctx; return MLS_E_ARG; }
         } else {
-            a.tile = kMaxTile;
+            a.tile = want;
         }
     }
     if (nonuniform > 1) c.stretched_axis = -2;   // fast-MLS unavailable (more than one stretched axis)
@@ -145,9 +151,35 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
         const Axis &a = c.g.ax[d];
         const int nn = a.periodic ? a.n : a.n + 1;
         c.g.ntile[d] = (nn + a.tile - 1) / a.tile;
+        c.g.box[d] = (a.periodic && c.g.ntile[d] == 1) ? a.n : a.tile + 3;
         nt *= c.g.ntile[d];
     }
     c.g.ntiles = nt;
+    if ((int64_t)c.g.box[0] * c.g.box[1] * c.g.box[2] * 8 > 60 * 1024) { delete ctx; return MLS_E_ARG; }
+    // tile colours: tiles whose boxes may overlap get different colours.  Along
+    // an axis the colour is the parity of the tile index; an odd number of
+    // periodic tiles gives the last tile a third colour.
+    {
+        int64_t cnt[3][3];
+        for (int d = 0; d < 3; ++d) {
+            const int m = c.g.ntile[d];
+            const bool periodic = c.g.ax[d].periodic != 0;
+            c.g.ncol[d] = m == 1 ? 1 : ((periodic && (m & 1)) ? 3 : 2);
+            if (c.g.ncol[d] == 1) { cnt[0][d] = 1; cnt[1][d] = 0; cnt[2][d] = 0; }
+            else if (c.g.ncol[d] == 2) { cnt[0][d] = (m + 1) / 2; cnt[1][d] = m / 2; cnt[2][d] = 0; }
+            else { cnt[0][d] = (m - 1) / 2; cnt[1][d] = (m - 1) / 2; cnt[2][d] = 1; }
+        }
+        uint32_t base = 0;
+        for (int cz = 0; cz < c.g.ncol[2]; ++cz)
+            for (int cy = 0; cy < c.g.ncol[1]; ++cy)
+                for (int cx = 0; cx < c.g.ncol[0]; ++cx) {
+                    const int col = cx + c.g.ncol[0] * (cy + c.g.ncol[1] * cz);
+                    const int64_t k = cnt[cx][0] * cnt[cy][1] * cnt[cz][2];
+                    c.colour_tiles[col] = k;
+                    c.g.colour_base[col] = base;
+                    base += (uint32_t)k;
+                }
+    }
     // smallest control-volume width within two nodes of each tile, per axis
     std::vector<float> thmin[3];
     for (int d = 0; d < 3; ++d) {
@@ -155,7 +187,7 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
         thmin[d].resize(c.g.ntile[d]);
         for (int t = 0; t < c.g.ntile[d]; ++t) {
             double m = std::numeric_limits<double>::infinity();
-            for (int i = t * a.tile - 2; i <= (t + 1) * a.tile + 1; ++i) {
+            for (int i = t * a.tile - 3; i <= (t + 1) * a.tile + 3; ++i) {
                 int ic = i, jf = i;
                 if (a.periodic) {
                     ic = ((i % a.n) + a.n) % a.n;
@@ -181,7 +213,8 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
     c.opts.n_sub = 9;
     c.opts.fallback_tol = 1e-4;
     if (opts) {
-        if (!(opts->kappa_tau >= 0.0) || opts->n_sub < 2 || opts->n_sub > 65 || !(opts->fallback_tol >= 0.0)) {
+        if (!(opts->kappa_tau >= 0.0) || opts->n_sub < 2 || opts->n_sub > 65 || !(opts->fallback_tol >= 0.0) ||
+            (opts->spread_tile != 0 && opts->spread_tile != 4 && opts->spread_tile != 8 && opts->spread_tile != 16)) {
             delete ctx;
             return MLS_E_ARG;
         }

@@ -52,7 +52,10 @@ struct Grid {
     Axis ax[3];
     int32_t dims[3][3];   // dims[c][d]: nodes of component c along axis d
     int32_t ntile[3];     // tiles per axis (spreading)
+    int32_t box[3];       // LDS box edge per axis: tile + 3 (whole axis for a single periodic tile)
+    int32_t ncol[3];      // tile colours per axis: 1 (one tile), 2 (even count or walls), 3 (odd periodic count)
     int64_t ntiles;       // product
+    uint32_t colour_base[27]; // first slot of each tile colour in the active-tile list
     double h_min;         // smallest node spacing over all axes and components
 };
 
@@ -106,8 +109,9 @@ struct Ctx {
     uint32_t *tile_active = nullptr;   // ntiles: non-empty tiles per XCD slab
     uint32_t *block_sums = nullptr;    // scan partials
     uint32_t *entries = nullptr;       // 8 * cap_markers
-    uint32_t *work = nullptr;          // [0..7] active-list sizes, [8..15] cursors
-    int64_t last_entries_hint = 0;
+    uint32_t *work = nullptr;          // [0..26] active-list sizes per colour, [32..58] cursors
+    int64_t colour_tiles[27] = {};   // tiles of each colour
+    int spread_blocks_per_cu = 8;
     int cu_count = 256;
     // time step
     unsigned long long *step_ctr = nullptr;

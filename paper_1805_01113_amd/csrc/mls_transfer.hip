@@ -67,37 +67,38 @@ k_interp(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ ho
 }
 
 // ---- spreading: tile binning -------------------------------------------------
+//
+// Every marker belongs to exactly one tile of the grid: the tile holding its
+// cell (the home of a centre-staggered component on each axis).  A tile's
+// markers spread into an LDS box that covers the tile plus the one-node halo
+// of their supports (tile + 3 nodes per axis).  Tiles are coloured 2x2x2 by
+// the parity of their indices; boxes of tiles of one colour never overlap, so
+// a colour's tiles add their boxes into the field with plain read-modify-
+// writes, and the eight colours run one after another.  Each node thus
+// receives its additions in the fixed colour order, and inside a box the
+// contributions are summed in 64-bit fixed point, whose sum does not depend on
+// the order of the markers: the result is bitwise reproducible.
 
-// Distinct tiles along one axis touched by the union of the three
-// components' supports of a marker.  cell: home of a centre-staggered
-// component on this axis; face: home of the face-staggered one (cell or
-// cell + 1).  Writes up to 2 tile indices, returns the count.
-__device__ __forceinline__ int axis_tiles(const Grid &g, int d, int cell, int face, int t[2])
+__device__ __forceinline__ int64_t marker_tile(const Grid &g, const uint32_t *__restrict__ home, int64_t l,
+                                               bool &valid)
 {
-    const Axis &a = g.ax[d];
-    const int nn = a.periodic ? a.n : a.n + 1;   // node count covering all components
-    int lo = cell - 1;
-    int hi = cell + 1;
-    const int cell1 = a.periodic ? (cell + 1 == a.n ? 0 : cell + 1) : cell + 1;
-    if (face == cell1) hi = cell + 2;
-    int cnt = 0;
-    for (int i = lo; i <= hi; ++i) {
-        int w = i;
-        if (a.periodic) w = w < 0 ? w + nn : (w >= nn ? w - nn : w);
-        if (w < 0 || w >= nn) continue;
-        const int tile = w / a.tile;
-        bool seen = false;
-        for (int q = 0; q < cnt; ++q) seen = seen || (t[q] == tile);
-        if (!seen && cnt < 2) t[cnt++] = tile;
+    int hc[3][3];
+    valid = true;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        unpack_home(home[home_at(l, c)], hc[c][0], hc[c][1], hc[c][2]);
+        valid = valid && home_ok(g, c, hc[c][0], hc[c][1], hc[c][2]);
     }
-    return cnt;
+    // the cell on axis d is the home of component (d + 1) % 3 (centre-staggered on d)
+    const int tx = hc[1][0] / g.ax[0].tile;
+    const int ty = hc[2][1] / g.ax[1].tile;
+    const int tz = hc[0][2] / g.ax[2].tile;
+    return ((int64_t)tz * g.ntile[1] + ty) * g.ntile[0] + tx;
 }
 
-// Binning of markers into tiles.  Lanes of a wavefront that hit the same tile
-// are combined into one atomic (the leader adds the count, the others take
-// consecutive slots after it in lane order), so a tile's entry list consists
-// of runs of consecutive marker indices and the accumulation kernel reads the
-// shape functions of a run with coalesced loads.
+// Lanes of a wavefront that hit the same tile are combined into one atomic:
+// the leader adds the count and the others take consecutive slots in lane
+// order, so a tile's marker list is made of runs of consecutive markers.
 template <bool FILL>
 __global__ void __launch_bounds__(kBlock)
 k_bin(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home, uint32_t *__restrict__ count,
@@ -107,51 +108,26 @@ k_bin(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home,
     const int lane = threadIdx.x & 63;
     const unsigned long long lower = (1ull << lane) - 1ull;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    // the loop bound is wave-uniform so that the ballots below see the whole wave
+    // the loop bound is wave-uniform so that the ballots see the whole wave
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
         const int64_t l = base + lane;
-        int nt = 0;
-        int64_t tl[8];
+        int64_t t = -1;
         if (l < n) {
-            int hc[3][3];
-            bool valid = true;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                unpack_home(home[home_at(l, c)], hc[c][0], hc[c][1], hc[c][2]);
-                valid = valid && home_ok(g, c, hc[c][0], hc[c][1], hc[c][2]);
-            }
-            if (valid) {
-                int tx[2], ty[2], tz[2];
-                // centre-staggered home on axis d comes from component (d+1)%3
-                const int nx = axis_tiles(g, 0, hc[1][0], hc[0][0], tx);
-                const int ny = axis_tiles(g, 1, hc[2][1], hc[1][1], ty);
-                const int nz = axis_tiles(g, 2, hc[0][2], hc[2][2], tz);
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int a = q >> 2, b = (q >> 1) & 1, cc = q & 1;
-                    const bool use = a < nz && b < ny && cc < nx;
-                    tl[q] = use ? ((int64_t)tz[a] * g.ntile[1] + ty[b]) * g.ntile[0] + tx[cc] : -1;
-                }
-                nt = 8;
-            } else if (!FILL) {
-                raise_error(err, l, MLS_E_SUPPORT);   // contributes nothing
-            }
+            bool valid;
+            const int64_t tt = marker_tile(g, home, l, valid);
+            if (valid) t = tt;
+            else if (!FILL) raise_error(err, l, MLS_E_SUPPORT);   // contributes nothing
         }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int64_t t = nt ? tl[q] : -1;
-            unsigned long long pending = __ballot(t >= 0);
-            while (pending) {
-                const int leader = __ffsll((long long)pending) - 1;
-                const int64_t tlead = __shfl(t, leader);
-                const unsigned long long mask = __ballot(t == tlead) & pending;
-                uint32_t pos = 0;
-                if (lane == leader)
-                    pos = atomicAdd(FILL ? &cursor[tlead] : &count[tlead], (uint32_t)__popcll(mask));
-                pos = __shfl(pos, leader);
-                if (FILL && ((mask >> lane) & 1ull)) entries[pos + __popcll(mask & lower)] = (uint32_t)l;
-                pending &= ~mask;
-            }
+        unsigned long long pending = __ballot(t >= 0);
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const int64_t tlead = __shfl(t, leader);
+            const unsigned long long mask = __ballot(t == tlead) & pending;
+            uint32_t pos = 0;
+            if (lane == leader) pos = atomicAdd(FILL ? &cursor[tlead] : &count[tlead], (uint32_t)__popcll(mask));
+            pos = __shfl(pos, leader);
+            if (FILL && ((mask >> lane) & 1ull)) entries[pos + __popcll(mask & lower)] = (uint32_t)l;
+            pending &= ~mask;
         }
     }
 }
@@ -242,31 +218,46 @@ __global__ void __launch_bounds__(kBlock) k_scan_final(const uint32_t *__restric
     }
     const int64_t first = base + (int64_t)threadIdx.x * per;
     if (first <= nt - 1 && nt - 1 < first + per) off[nt] = run;   // the owner of the last tile
-    if (blockIdx.x == 0 && threadIdx.x < 16) work[threadIdx.x] = 0u;   // active-list sizes and cursors
+    if (blockIdx.x == 0 && threadIdx.x < 64) work[threadIdx.x] = 0u;   // colour list sizes and cursors
 }
 
-// Non-empty tiles, listed per XCD slab: the tiles are split into 8 contiguous
-// slabs (one per XCD); work[x] counts the non-empty tiles of slab x and
-// active[x * chunk + i] lists them.
-__global__ void __launch_bounds__(kBlock)
-k_active_tiles(const uint32_t *__restrict__ count, int64_t nt, uint32_t *__restrict__ active, uint32_t *work)
+__device__ __forceinline__ int axis_colour(const Grid &g, int d, int t)
 {
+    const int k = g.ncol[d];
+    return k == 1 ? 0 : ((k == 3 && t == g.ntile[d] - 1) ? 2 : (t & 1));
+}
+
+__device__ __forceinline__ int tile_colour(const Grid &g, int64_t t)
+{
+    const int tx = (int)(t % g.ntile[0]);
+    const int ty = (int)((t / g.ntile[0]) % g.ntile[1]);
+    const int tz = (int)(t / ((int64_t)g.ntile[0] * g.ntile[1]));
+    return axis_colour(g, 0, tx) + g.ncol[0] * (axis_colour(g, 1, ty) + g.ncol[1] * axis_colour(g, 2, tz));
+}
+
+// Non-empty tiles listed per colour: work[col] counts them and
+// active[colour_base[col] + i] lists them.
+__global__ void __launch_bounds__(kBlock)
+k_active_tiles(const Grid *__restrict__ gp, const uint32_t *__restrict__ count, uint32_t *__restrict__ active,
+               uint32_t *work)
+{
+    const Grid &g = *gp;
     const int lane = threadIdx.x & 63;
     const unsigned long long lower = (1ull << lane) - 1ull;
-    const int64_t chunk = (nt + 7) >> 3;
+    const int64_t nt = g.ntiles;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < nt; base += stride) {
         const int64_t t = base + lane;
-        const int x = (t < nt && count[t] > 0u) ? (int)(t / chunk) : -1;
-        unsigned long long pending = __ballot(x >= 0);
+        const int col = (t < nt && count[t] > 0u) ? tile_colour(g, t) : -1;
+        unsigned long long pending = __ballot(col >= 0);
         while (pending) {
             const int leader = __ffsll((long long)pending) - 1;
-            const int xl = __shfl(x, leader);
-            const unsigned long long mask = __ballot(x == xl) & pending;
+            const int cl = __shfl(col, leader);
+            const unsigned long long mask = __ballot(col == cl) & pending;
             uint32_t pos = 0;
-            if (lane == leader) pos = atomicAdd(&work[xl], (uint32_t)__popcll(mask));
+            if (lane == leader) pos = atomicAdd(&work[cl], (uint32_t)__popcll(mask));
             pos = __shfl(pos, leader);
-            if ((mask >> lane) & 1ull) active[(int64_t)xl * chunk + pos + __popcll(mask & lower)] = (uint32_t)t;
+            if ((mask >> lane) & 1ull) active[g.colour_base[cl] + pos + __popcll(mask & lower)] = (uint32_t)t;
             pending &= ~mask;
         }
     }
@@ -274,44 +265,41 @@ k_active_tiles(const uint32_t *__restrict__ count, int64_t nt, uint32_t *__restr
 
 // ---- spreading: per-tile fixed-point accumulation ------------------------------
 
-constexpr int kTileNodes = kMaxTile * kMaxTile * kMaxTile;   // 4096
-
 __device__ __forceinline__ float width_of(const Axis &a, int is_face, int i)
 {
     return is_face ? a.width_f[i] : a.width_c[i];
 }
 
+// Box-local index of node i (wrapped) on axis a for a box starting at node b0.
+__device__ __forceinline__ int box_local(const Axis &a, int ntile, int nodes, int b0, int i)
+{
+    if (a.periodic && ntile == 1) return i;            // the box is the whole (short) axis
+    int l = i - b0;
+    if (a.periodic) l = l < 0 ? l + nodes : (l >= nodes ? l - nodes : l);
+    return l;
+}
+
 __global__ void __launch_bounds__(kBlock)
-k_spread_tiles(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home, const float *__restrict__ phi,
-               const float *__restrict__ area, const float *__restrict__ Fx, const float *__restrict__ Fy,
-               const float *__restrict__ Fz, float *__restrict__ fx, float *__restrict__ fy,
-               float *__restrict__ fz, const uint32_t *__restrict__ off, const uint32_t *__restrict__ entries,
-               const uint32_t *__restrict__ active, uint32_t *work, ErrWord *err)
+k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32_t *__restrict__ home,
+                const float *__restrict__ phi, const float *__restrict__ area, const float *__restrict__ Fx,
+                const float *__restrict__ Fy, const float *__restrict__ Fz, float *__restrict__ fx,
+                float *__restrict__ fy, float *__restrict__ fz, const uint32_t *__restrict__ off,
+                const uint32_t *__restrict__ entries, const uint32_t *__restrict__ active, uint32_t *work,
+                ErrWord *err)
 {
     const Grid &g = *gp;
-    __shared__ unsigned long long acc[kTileNodes];
+    extern __shared__ unsigned long long acc[];
     __shared__ float red[3][kBlock / 64];
-    const int tsx = g.ax[0].tile, tsy = g.ax[1].tile, tsz = g.ax[2].tile;
-    const int tnodes = tsx * tsy * tsz;
-    const Axis &AX = g.ax[0], &AY = g.ax[1], &AZ = g.ax[2];
-    // XCD-aware dynamic assignment: workgroups are dispatched round-robin over
-    // the 8 XCDs, so blockIdx % 8 names the XCD.  Each XCD first takes the
-    // non-empty tiles of its own slab (tiles sharing markers then share that
-    // XCD's L2), then helps the other slabs.
     __shared__ int64_t tile_sh;
-    const int xcd = blockIdx.x & 7;
-    const int64_t chunk = (g.ntiles + 7) >> 3;
-    int src = xcd, rounds = 0;
+    const Axis &AX = g.ax[0], &AY = g.ax[1], &AZ = g.ax[2];
+    const int bx = g.box[0], by = g.box[1], bz = g.box[2];
+    const int bnodes = bx * by * bz;
+    const uint32_t nact = work[colour];
+    const uint32_t abase = g.colour_base[colour];
     for (;;) {
         if (threadIdx.x == 0) {
-            int64_t t = -1;
-            while (rounds < 8) {
-                const uint32_t i = atomicAdd(&work[8 + src], 1u);
-                if (i < work[src]) { t = active[(int64_t)src * chunk + i]; break; }
-                src = (src + 1) & 7;
-                ++rounds;
-            }
-            tile_sh = t;
+            const uint32_t i = atomicAdd(&work[32 + colour], 1u);
+            tile_sh = i < nact ? (int64_t)active[abase + i] : -1;
         }
         __syncthreads();
         const int64_t t = tile_sh;
@@ -321,7 +309,10 @@ k_spread_tiles(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restric
         const int tx = (int)(t % g.ntile[0]);
         const int ty = (int)((t / g.ntile[0]) % g.ntile[1]);
         const int tz = (int)(t / ((int64_t)g.ntile[0] * g.ntile[1]));
-        const int x0 = tx * tsx, y0 = ty * tsy, z0 = tz * tsz;
+        // box origin: one node below the tile (a single-tile periodic axis keeps the whole axis)
+        const int b0x = (AX.periodic && g.ntile[0] == 1) ? 0 : tx * AX.tile - 1;
+        const int b0y = (AY.periodic && g.ntile[1] == 1) ? 0 : ty * AY.tile - 1;
+        const int b0z = (AZ.periodic && g.ntile[2] == 1) ? 0 : tz * AZ.tile - 1;
 
         // largest |A_l F_l| per component among the tile's markers
         float mx[3] = {0.f, 0.f, 0.f};
@@ -357,41 +348,41 @@ k_spread_tiles(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restric
             }
             int ebits;
             frexp(bound, &ebits);                      // bound < 2^ebits
-            // each scaled contribution stays below 2^30: it converts to int32
-            // exactly enough (quantum 2^-30 of the bound) and sums in int64
+            // a scaled contribution stays below 2^30 (converted to int32, summed
+            // in int64); its quantum is 2^-30 of the bound
             const int S = 30 - ebits;
-            for (int q = threadIdx.x; q < tnodes; q += blockDim.x) acc[q] = 0ull;
+            for (int q = threadIdx.x; q < bnodes; q += blockDim.x) acc[q] = 0ull;
             __syncthreads();
             const float *F = c == 0 ? Fx : (c == 1 ? Fy : Fz);
             const float scale_f = ldexpf(1.0f, S);
             const float lim = 1073741824.0f;            // 2^30
+            const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
             for (uint32_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
                 const uint32_t m = entries[e];
                 int hi, hj, hk;
                 unpack_home(home[home_at(m, c)], hi, hj, hk);
-                int ix[3], iy[3], iz[3];
-                bool inx[3], iny[3], inz[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    ix[a] = nb_index(hi, a - 1, g.dims[c][0], AX.periodic);
-                    iy[a] = nb_index(hj, a - 1, g.dims[c][1], AY.periodic);
-                    iz[a] = nb_index(hk, a - 1, g.dims[c][2], AZ.periodic);
-                    inx[a] = (unsigned)(ix[a] - x0) < (unsigned)tsx;
-                    iny[a] = (unsigned)(iy[a] - y0) < (unsigned)tsy;
-                    inz[a] = (unsigned)(iz[a] - z0) < (unsigned)tsz;
-                }
-                // this component's support may miss the tile (the entry list is
-                // the union over components): then nothing is read
-                if (!((inx[0] || inx[1] || inx[2]) && (iny[0] || iny[1] || iny[2]) && (inz[0] || inz[1] || inz[2])))
-                    continue;
-                float wx[3], wy[3], wz[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    wx[a] = width_of(AX, c == 0, ix[a]);
-                    wy[a] = width_of(AY, c == 1, iy[a]);
-                    wz[a] = width_of(AZ, c == 2, iz[a]);
-                }
                 const float *p = phi + phi_at(m, c);
+                int ix[3], iy[3], iz[3];
+                float wx[3], wy[3], wz[3];
+                bool inbox = true;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const int gx = nb_index(hi, a - 1, nxc, AX.periodic);
+                    const int gy = nb_index(hj, a - 1, nyc, AY.periodic);
+                    const int gz = nb_index(hk, a - 1, nzc, AZ.periodic);
+                    wx[a] = width_of(AX, c == 0, gx);
+                    wy[a] = width_of(AY, c == 1, gy);
+                    wz[a] = width_of(AZ, c == 2, gz);
+                    ix[a] = box_local(AX, g.ntile[0], nxc, b0x, gx);
+                    iy[a] = box_local(AY, g.ntile[1], nyc, b0y, gy);
+                    iz[a] = box_local(AZ, g.ntile[2], nzc, b0z, gz);
+                    inbox = inbox && (unsigned)ix[a] < (unsigned)bx && (unsigned)iy[a] < (unsigned)by &&
+                            (unsigned)iz[a] < (unsigned)bz;
+                }
+                if (!inbox) {           // cannot happen for a home written by the build
+                    raise_error(err, m, MLS_E_SUPPORT);
+                    continue;
+                }
                 float ph[kNe];
                 float hl = 0.f, den = 0.f;
 #pragma unroll
@@ -407,26 +398,27 @@ k_spread_tiles(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restric
 #pragma unroll
                 for (int k = 0; k < kNe; ++k) {
                     const int a = k % 3, b = (k / 3) % 3, cz = k / 9;
-                    if (inx[a] && iny[b] && inz[cz]) {
-                        float vs = ph[k] * vsc;
-                        range_ok = range_ok && (fabsf(vs) < lim);
-                        vs = fminf(fmaxf(vs, -lim), lim);
-                        const long long qv = (long long)(int)rintf(vs);
-                        const int li = ((iz[cz] - z0) * tsy + (iy[b] - y0)) * tsx + (ix[a] - x0);
-                        atomicAdd(&acc[li], (unsigned long long)qv);
-                    }
+                    float vs = ph[k] * vsc;
+                    range_ok = range_ok && (fabsf(vs) < lim);
+                    vs = fminf(fmaxf(vs, -lim), lim);
+                    const long long qv = (long long)(int)rintf(vs);
+                    atomicAdd(&acc[(iz[cz] * by + iy[b]) * bx + ix[a]], (unsigned long long)qv);
                 }
                 if (!range_ok) raise_error(err, m, MLS_E_RANGE);
             }
             __syncthreads();
             float *f = c == 0 ? fx : (c == 1 ? fy : fz);
             const double inv_scale = ldexp(1.0, -S);
-            for (int q = threadIdx.x; q < tnodes; q += blockDim.x) {
+            for (int q = threadIdx.x; q < bnodes; q += blockDim.x) {
                 const long long sv = (long long)acc[q];
                 if (sv == 0) continue;
-                const int lx = q % tsx, ly = (q / tsx) % tsy, lz = q / (tsx * tsy);
-                const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-                if (gx >= g.dims[c][0] || gy >= g.dims[c][1] || gz >= g.dims[c][2]) continue;
+                const int lx = q % bx, ly = (q / bx) % by, lz = q / (bx * by);
+                int gx = b0x + lx, gy = b0y + ly, gz = b0z + lz;
+                if (AX.periodic) gx = gx < 0 ? gx + nxc : (gx >= nxc ? gx - nxc : gx);
+                if (AY.periodic) gy = gy < 0 ? gy + nyc : (gy >= nyc ? gy - nyc : gy);
+                if (AZ.periodic) gz = gz < 0 ? gz + nzc : (gz >= nzc ? gz - nzc : gz);
+                if ((unsigned)gx >= (unsigned)nxc || (unsigned)gy >= (unsigned)nyc || (unsigned)gz >= (unsigned)nzc)
+                    continue;
                 const int64_t idx = field_index(g, c, gx, gy, gz);
                 f[idx] = f[idx] + (float)((double)sv * inv_scale);
             }
@@ -462,23 +454,28 @@ hipError_t launch_spread(Ctx &c, int64_t n, const uint32_t *home, const float *p
     if (n == 0) return hipSuccess;
     const int64_t nt = c.g.ntiles;
     const int64_t nb = (nt + kScanChunk - 1) / kScanChunk;
-    TimedLaunch* tb = new TimedLaunch(c, MLS_K_SPREAD_BIN, s);
-    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(nt, c.cu_count)), dim3(kBlock), 0, s, c.tile_count, nt);
-    hipLaunchKernelGGL(k_bin<false>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, home,
-                       c.tile_count, c.tile_cursor, c.entries, c.err);
-    hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)nb), dim3(kBlock), 0, s, c.tile_count, nt, c.block_sums);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, c.block_sums, nb);
-    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kBlock), 0, s, c.tile_count, nt, c.block_sums,
-                       c.tile_off, c.tile_cursor, c.work);
-    hipLaunchKernelGGL(k_bin<true>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, home,
-                       c.tile_count, c.tile_cursor, c.entries, c.err);
-    hipLaunchKernelGGL(k_active_tiles, dim3(grid_for(nt, c.cu_count)), dim3(kBlock), 0, s, c.tile_count, nt,
-                       c.tile_active, c.work);
-    delete tb;
-    const int persist = ((c.cu_count * 4) + 7) & ~7;   // a multiple of the 8 XCDs
+    {
+        TimedLaunch tb(c, MLS_K_SPREAD_BIN, s);
+        hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(nt, c.cu_count)), dim3(kBlock), 0, s, c.tile_count, nt);
+        hipLaunchKernelGGL(k_bin<false>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, home,
+                           c.tile_count, c.tile_cursor, c.entries, c.err);
+        hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)nb), dim3(kBlock), 0, s, c.tile_count, nt, c.block_sums);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, c.block_sums, nb);
+        hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kBlock), 0, s, c.tile_count, nt, c.block_sums,
+                           c.tile_off, c.tile_cursor, c.work);
+        hipLaunchKernelGGL(k_bin<true>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, home,
+                           c.tile_count, c.tile_cursor, c.entries, c.err);
+        hipLaunchKernelGGL(k_active_tiles, dim3(grid_for(nt, c.cu_count)), dim3(kBlock), 0, s, c.d_grid,
+                           c.tile_count, c.tile_active, c.work);
+    }
+    const size_t lds = (size_t)c.g.box[0] * c.g.box[1] * c.g.box[2] * sizeof(unsigned long long);
+    const int persist = c.cu_count * c.spread_blocks_per_cu;
     TimedLaunch tt(c, MLS_K_SPREAD_TILES, s);
-    hipLaunchKernelGGL(k_spread_tiles, dim3(persist), dim3(kBlock), 0, s, c.d_grid, n, home, phi, area, Fx, Fy, Fz,
-                       fx, fy, fz, c.tile_off, c.entries, c.tile_active, c.work, c.err);
+    for (int col = 0; col < 27; ++col) {
+        if (c.colour_tiles[col] == 0) continue;
+        hipLaunchKernelGGL(k_spread_colour, dim3(persist), dim3(kBlock), lds, s, c.d_grid, col, n, home, phi, area,
+                           Fx, Fy, Fz, fx, fy, fz, c.tile_off, c.entries, c.tile_active, c.work, c.err);
+    }
     return hipGetLastError();
 }
 

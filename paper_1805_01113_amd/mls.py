@@ -40,7 +40,8 @@ class _Weight(ctypes.Structure):
 
 
 class _Opts(ctypes.Structure):
-    _fields_ = [("kappa_tau", ctypes.c_double), ("n_sub", ctypes.c_int32), ("fallback_tol", ctypes.c_double)]
+    _fields_ = [("kappa_tau", ctypes.c_double), ("n_sub", ctypes.c_int32), ("fallback_tol", ctypes.c_double),
+                ("spread_tile", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -136,7 +137,7 @@ class Context:
 
     def __init__(self, faces: Sequence[np.ndarray], periodic: Sequence[bool], kind: int = W_GAUSS_SHIFTED,
                  eps: float = 1.0, radius: float = 1.5, kappa_tau: float = 1e6, n_sub: int = 9,
-                 fallback_tol: float = 1e-4):
+                 fallback_tol: float = 1e-4, spread_tile: int = 0):
         L = load()
         self._lib = L
         self.faces = [np.ascontiguousarray(f, dtype=np.float64) for f in faces]
@@ -148,7 +149,7 @@ class Context:
             g.periodic[d] = 1 if self.periodic[d] else 0
             g.faces[d] = self.faces[d].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         w = _Weight(kind, eps, radius)
-        o = _Opts(kappa_tau, n_sub, fallback_tol)
+        o = _Opts(kappa_tau, n_sub, fallback_tol, spread_tile)
         self.n_sub = n_sub
         h = ctypes.c_void_p()
         st = L.mls_ctx_create(ctypes.byref(h), ctypes.byref(g), ctypes.byref(w), ctypes.byref(o))

@@ -101,6 +101,29 @@ def test_ragged_periodic_32(orc, torch_cuda, kind):
                 kw=dict(kind=kind))
 
 
+@pytest.mark.parametrize("dims,tile", [((24, 40, 12), 8), ((48, 20, 36), 16), ((36, 28, 44), 4)])
+def test_uneven_grid_tiles(orc, torch_cuda, dims, tile):
+    """Non-power-of-two periodic grids: odd tile counts (three tile colours),
+    single-tile axes and every tile edge."""
+    gs = W.GridSpec([W.uniform_faces(n) for n in dims], [True] * 3)
+    r = np.random.default_rng(sum(dims))
+    n = 2000
+    x, y, z = [r.uniform(-0.2, 1.2, n).astype(np.float32) for _ in range(3)]
+    area = r.uniform(0.2, 1.0, n).astype(np.float32) / 900
+    F = r.normal(size=(3, n)).astype(np.float32)
+    fields = [r.normal(size=gs.shape(c)).astype(np.float32) for c in range(3)]
+    _full_check(orc, torch_cuda, gs, x, y, z, area, F, fields, label="grid%s tile%d" % (dims, tile),
+                kw=dict(spread_tile=tile))
+
+
+def test_grid_rejected_without_tile_divisor(torch_cuda):
+    """A periodic axis of 17 cells has no tile edge between 4 and 16."""
+    from paper_1805_01113_amd import mls
+    gs = W.GridSpec([W.uniform_faces(17), W.uniform_faces(16), W.uniform_faces(16)], [True] * 3)
+    with pytest.raises(mls.MLSError):
+        _ctx(gs)
+
+
 def _stretched(nxy=48, nz=72, n_bodies=12, seed=4):
     wl = W.stretched_channel(n_bodies=n_bodies, nxy=nxy, nz=nz, cfg_id=100 + seed)
     return wl

@@ -107,8 +107,9 @@ typedef struct {
                              volume, boundaries included (default 9 -> 729) */
     double fallback_tol;  /* learned: consistency residual above which the
                              marker falls back to exact MLS (default 1e-4) */
-    int32_t spread_tile;  /* edge (cells) of the spreading tiles: 4, 8 or 16
-                             (0 = default 8) */
+    int32_t spread_tile;  /* edge (cells) of the spreading tiles on axes longer
+                             than 16 cells, 4..12 (0 = default 8); a periodic
+                             axis uses a divisor of its length */
 } mls_opts;
 
 typedef struct {
@@ -129,7 +130,7 @@ const char *mls_version(void);
  * weight/opts may be NULL for the defaults.  Returns MLS_E_ARG for a grid
  * that is not increasing, has fewer than 3 cells on an axis, exceeds the
  * packed-index limits, or has a periodic axis longer than 16 cells whose cell
- * count has no divisor between 4 and 16 (the spreading tiles). */
+ * count has no divisor between 4 and 12 (the spreading tiles). */
 mls_status mls_ctx_create(mls_ctx **ctx, const mls_grid *grid, const mls_weight *weight,
                           const mls_opts *opts);
 void mls_ctx_destroy(mls_ctx *ctx);

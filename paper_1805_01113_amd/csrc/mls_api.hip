@@ -100,12 +100,12 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
         // into equal tiles (a divisor of n between 4 and 16, the requested
         // edge if it divides n); a shorter one is a single tile
         const int want = (opts && opts->spread_tile) ? opts->spread_tile : 8;
-        if (want != 4 && want != 8 && want != 16) { delete ctx; return MLS_E_ARG; }
+        if (want < 4 || want > kMaxBoxTile) { delete ctx; return MLS_E_ARG; }
         if (a.periodic) {
             a.tile = 0;
             if (n <= kMaxTile) a.tile = n;
             else if (n % want == 0) a.tile = want;
-            for (int t = kMaxTile; t >= 4 && !a.tile; --t)
+            for (int t = kMaxBoxTile; t >= 4 && !a.tile; --t)
                 if (n % t == 0) a.tile = t;
             if (!a.tile) { delete ctx; return MLS_E_ARG; }
         } else {
@@ -155,7 +155,10 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
         nt *= c.g.ntile[d];
     }
     c.g.ntiles = nt;
-    if ((int64_t)c.g.box[0] * c.g.box[1] * c.g.box[2] * 8 > 60 * 1024) { delete ctx; return MLS_E_ARG; }
+    // three fixed-point boxes (one per component) must fit the LDS of a workgroup
+    const int64_t lds = (int64_t)3 * c.g.box[0] * c.g.box[1] * c.g.box[2] * 8;
+    if (lds > 160 * 1024) { delete ctx; return MLS_E_ARG; }
+    c.spread_blocks_per_cu = std::max(1, std::min(8, (int)((160 * 1024) / (lds + 512))));
     // tile colours: tiles whose boxes may overlap get different colours.  Along
     // an axis the colour is the parity of the tile index; an odd number of
     // periodic tiles gives the last tile a third colour.
@@ -214,7 +217,7 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
     c.opts.fallback_tol = 1e-4;
     if (opts) {
         if (!(opts->kappa_tau >= 0.0) || opts->n_sub < 2 || opts->n_sub > 65 || !(opts->fallback_tol >= 0.0) ||
-            (opts->spread_tile != 0 && opts->spread_tile != 4 && opts->spread_tile != 8 && opts->spread_tile != 16)) {
+            (opts->spread_tile != 0 && (opts->spread_tile < 4 || opts->spread_tile > kMaxBoxTile))) {
             delete ctx;
             return MLS_E_ARG;
         }
@@ -261,7 +264,7 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
     }
     if (hipMalloc((void **)&c.err, sizeof(ErrWord)) != hipSuccess ||
         hipMalloc((void **)&c.stats, sizeof(DevStats)) != hipSuccess ||
-        hipMalloc((void **)&c.work, 64 * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void **)&c.work, 128 * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void **)&c.step_ctr, sizeof(unsigned long long)) != hipSuccess) {
         mls_ctx_destroy(ctx);
         return MLS_E_NOMEM;
@@ -269,10 +272,11 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
     const unsigned long long none = kNoError;
     hipMemcpy(c.err, &none, sizeof(none), hipMemcpyHostToDevice);
     hipMemset(c.stats, 0, sizeof(DevStats));
-    hipMemset(c.work, 0, 64 * sizeof(uint32_t));
+    hipMemset(c.work, 0, 128 * sizeof(uint32_t));
     hipMemset(c.step_ctr, 0, sizeof(unsigned long long));
     const int64_t nb = (nt + 2047) / 2048;
-    if (hipMalloc((void **)&c.tile_count, nt * sizeof(uint32_t)) != hipSuccess ||
+    if (hipMalloc((void **)&c.block_fmax, (size_t)3 * c.cu_count * 32 * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void **)&c.tile_count, nt * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void **)&c.tile_off, (nt + 1) * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void **)&c.tile_cursor, nt * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void **)&c.tile_active, nt * sizeof(uint32_t)) != hipSuccess ||
@@ -302,6 +306,7 @@ void mls_ctx_destroy(mls_ctx *ctx)
     hipFree(c.tile_active);
     hipFree(c.block_sums);
     hipFree(c.entries);
+    hipFree(c.block_fmax);
     hipFree(c.work);
     hipFree(c.step_ctr);
     for (hipEvent_t ev : c.ev_pool) hipEventDestroy(ev);
@@ -318,7 +323,7 @@ mls_status mls_reserve(mls_ctx *ctx, int64_t n)
     hipFree(c.entries);
     c.entries = nullptr;
     c.cap_markers = 0;
-    hipError_t e = hipMalloc((void **)&c.entries, (size_t)8 * (size_t)n * sizeof(uint32_t));
+    hipError_t e = hipMalloc((void **)&c.entries, (size_t)n * sizeof(uint32_t));
     if (e != hipSuccess) return hip_fail(ctx, e, "spread scratch");
     c.cap_markers = n;
     return MLS_OK;

@@ -17,7 +17,8 @@ namespace mls {
 
 constexpr int kNe = 27;           // 3x3x3 support nodes
 constexpr int kTableStride = 28;  // table row: 27 values + 1 pad (16-byte rows)
-constexpr int kMaxTile = 16;      // largest tile edge of the spreading grid
+constexpr int kMaxTile = 16;      // a periodic axis of up to this many cells is one spreading tile
+constexpr int kMaxBoxTile = 12;   // largest tile edge cut from a longer axis (three int64 boxes in LDS)
 constexpr int kPackI = 11, kPackJ = 11;  // home packing i | j << 11 | k << 22
 constexpr uint32_t kMaskI = (1u << kPackI) - 1, kMaskJ = (1u << kPackJ) - 1;
 
@@ -108,8 +109,10 @@ struct Ctx {
     uint32_t *tile_cursor = nullptr;   // ntiles
     uint32_t *tile_active = nullptr;   // ntiles: non-empty tiles per XCD slab
     uint32_t *block_sums = nullptr;    // scan partials
-    uint32_t *entries = nullptr;       // 8 * cap_markers
-    uint32_t *work = nullptr;          // [0..26] active-list sizes per colour, [32..58] cursors
+    uint32_t *entries = nullptr;       // cap_markers: markers sorted by tile
+    uint32_t *block_fmax = nullptr;    // per-block force maxima of the counting pass (3 per block)
+    uint32_t *work = nullptr;          // [0..26] active-list sizes per colour, [32..58] cursors,
+                                       // [64..66] max |A F| per component (FP32 bits)
     int64_t colour_tiles[27] = {};   // tiles of each colour
     int spread_blocks_per_cu = 8;
     int cu_count = 256;

@@ -99,13 +99,19 @@ __device__ __forceinline__ int64_t marker_tile(const Grid &g, const uint32_t *__
 // Lanes of a wavefront that hit the same tile are combined into one atomic:
 // the leader adds the count and the others take consecutive slots in lane
 // order, so a tile's marker list is made of runs of consecutive markers.
+// The counting pass also records max_l |A_l F_l| per component (FP32 bits,
+// positive floats order as unsigned integers), the scale of the fixed-point
+// spreading sums.
 template <bool FILL>
 __global__ void __launch_bounds__(kBlock)
 k_bin(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home, uint32_t *__restrict__ count,
-      uint32_t *__restrict__ cursor, uint32_t *__restrict__ entries, ErrWord *err)
+      uint32_t *__restrict__ cursor, uint32_t *__restrict__ entries, ErrWord *err,
+      const float *__restrict__ area, const float *__restrict__ Fx, const float *__restrict__ Fy,
+      const float *__restrict__ Fz, uint32_t *__restrict__ fmax_bits)
 {
     const Grid &g = *gp;
     const int lane = threadIdx.x & 63;
+    float mx[3] = {0.f, 0.f, 0.f};
     const unsigned long long lower = (1ull << lane) - 1ull;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     // the loop bound is wave-uniform so that the ballots see the whole wave
@@ -117,6 +123,15 @@ k_bin(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home,
             const int64_t tt = marker_tile(g, home, l, valid);
             if (valid) t = tt;
             else if (!FILL) raise_error(err, l, MLS_E_SUPPORT);   // contributes nothing
+            if (!FILL && valid) {
+                const float a = fabsf(area[l]);
+                // a non-finite force is caught here: fmaxf would drop a NaN
+                const float f0 = a * fabsf(Fx[l]), f1 = a * fabsf(Fy[l]), f2 = a * fabsf(Fz[l]);
+                if (!(f0 <= 3.0e38f && f1 <= 3.0e38f && f2 <= 3.0e38f)) raise_error(err, l, MLS_E_RANGE);
+                mx[0] = fmaxf(mx[0], f0);
+                mx[1] = fmaxf(mx[1], f1);
+                mx[2] = fmaxf(mx[2], f2);
+            }
         }
         unsigned long long pending = __ballot(t >= 0);
         while (pending) {
@@ -128,6 +143,22 @@ k_bin(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home,
             pos = __shfl(pos, leader);
             if (FILL && ((mask >> lane) & 1ull)) entries[pos + __popcll(mask & lower)] = (uint32_t)l;
             pending &= ~mask;
+        }
+    }
+    if (!FILL) {
+        // block maximum -> fmax_bits[3 * blockIdx + c]; the scan reduces them
+        __shared__ float bm[3][kBlock / 64];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float v = mx[c];
+            for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+            if (lane == 0) bm[c][threadIdx.x >> 6] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            const int c = threadIdx.x;
+            fmax_bits[3 * blockIdx.x + c] =
+                __float_as_uint(fmaxf(fmaxf(bm[c][0], bm[c][1]), fmaxf(bm[c][2], bm[c][3])));
         }
     }
 }
@@ -175,9 +206,26 @@ __global__ void __launch_bounds__(kBlock) k_scan_partials(const uint32_t *__rest
     if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
-__global__ void __launch_bounds__(kBlock) k_scan_top(uint32_t *__restrict__ partial, int64_t nb)
+__global__ void __launch_bounds__(kBlock) k_scan_top(uint32_t *__restrict__ partial, int64_t nb,
+                                                     const uint32_t *__restrict__ bmax, int nbmax,
+                                                     uint32_t *__restrict__ fmax_bits)
 {
     __shared__ uint32_t sh[4];
+    // maximum of the per-block force maxima of the counting pass (positive
+    // floats order as unsigned integers)
+    {
+        uint32_t m[3] = {0u, 0u, 0u};
+        for (int i = threadIdx.x; i < nbmax; i += blockDim.x)
+            for (int c = 0; c < 3; ++c) m[c] = max(m[c], bmax[3 * i + c]);
+        for (int c = 0; c < 3; ++c) {
+            uint32_t v = m[c];
+            for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
+            if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+            __syncthreads();
+            if (threadIdx.x == 0) fmax_bits[c] = max(max(sh[0], sh[1]), max(sh[2], sh[3]));
+            __syncthreads();
+        }
+    }
     uint32_t carry = 0;
     for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
         const int64_t i = b0 + threadIdx.x;
@@ -285,25 +333,27 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                 const float *__restrict__ Fy, const float *__restrict__ Fz, float *__restrict__ fx,
                 float *__restrict__ fy, float *__restrict__ fz, const uint32_t *__restrict__ off,
                 const uint32_t *__restrict__ entries, const uint32_t *__restrict__ active, uint32_t *work,
-                ErrWord *err)
+                const uint32_t *__restrict__ fmax_bits, ErrWord *err)
 {
     const Grid &g = *gp;
-    extern __shared__ unsigned long long acc[];
-    __shared__ float red[3][kBlock / 64];
+    extern __shared__ unsigned long long acc[];     // three boxes, one per component
     __shared__ int64_t tile_sh;
     const Axis &AX = g.ax[0], &AY = g.ax[1], &AZ = g.ax[2];
     const int bx = g.box[0], by = g.box[1], bz = g.box[2];
     const int bnodes = bx * by * bz;
     const uint32_t nact = work[colour];
     const uint32_t abase = g.colour_base[colour];
+    float Mf[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Mf[c] = __uint_as_float(fmax_bits[c]);
     for (;;) {
         if (threadIdx.x == 0) {
             const uint32_t i = atomicAdd(&work[32 + colour], 1u);
             tile_sh = i < nact ? (int64_t)active[abase + i] : -1;
         }
+        for (int q = threadIdx.x; q < 3 * bnodes; q += blockDim.x) acc[q] = 0ull;
         __syncthreads();
         const int64_t t = tile_sh;
-        __syncthreads();
         if (t < 0) break;
         const uint32_t beg = off[t], end = off[t + 1];
         const int tx = (int)(t % g.ntile[0]);
@@ -313,52 +363,31 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
         const int b0x = (AX.periodic && g.ntile[0] == 1) ? 0 : tx * AX.tile - 1;
         const int b0y = (AY.periodic && g.ntile[1] == 1) ? 0 : ty * AY.tile - 1;
         const int b0z = (AZ.periodic && g.ntile[2] == 1) ? 0 : tz * AZ.tile - 1;
-
-        // largest |A_l F_l| per component among the tile's markers
-        float mx[3] = {0.f, 0.f, 0.f};
-        for (uint32_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
-            const uint32_t m = entries[e];
-            const float a = fabsf(area[m]);
-            mx[0] = fmaxf(mx[0], a * fabsf(Fx[m]));
-            mx[1] = fmaxf(mx[1], a * fabsf(Fy[m]));
-            mx[2] = fmaxf(mx[2], a * fabsf(Fz[m]));
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float v = mx[c];
-            for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-            if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = v;
-        }
-        __syncthreads();
-        float M[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) M[c] = fmaxf(fmaxf(red[c][0], red[c][1]), fmaxf(red[c][2], red[c][3]));
-        // c_l <= A_l / h^2 for a shape function with sum phi dV close to dV,
-        // h the smallest control-volume width near the tile; with |phi| <= 2
-        // every contribution |c_l phi_k F_l| stays below bound = 8 M / h^2.
+        // c_l <= A_l / h^2 for a shape function with sum phi dV close to dV, h
+        // the smallest control-volume width near the tile; with |phi| <= 2 every
+        // contribution |c_l phi_k F_l| stays below bound = 8 max|A F| / h^2.
+        // A scaled contribution stays below 2^30 (converted to int32 and summed
+        // in int64); its quantum is 2^-30 of the bound.
         const float hloc = fminf(fminf(AX.tile_hmin[tx], AY.tile_hmin[ty]), AZ.tile_hmin[tz]);
         const double inv_h2 = 1.0 / ((double)hloc * (double)hloc);
-#pragma unroll 1
+        int S[3];
+        float scale_f[3];
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const double bound = 8.0 * (double)M[c] * inv_h2;
-            if (!(bound > 0.0) || !(bound < 1e300)) {   // nothing to add, or a non-finite force
-                if (!(bound >= 0.0) || bound >= 1e300)
-                    for (uint32_t e = beg + threadIdx.x; e < end; e += blockDim.x) raise_error(err, entries[e], MLS_E_RANGE);
-                continue;
-            }
-            int ebits;
-            frexp(bound, &ebits);                      // bound < 2^ebits
-            // a scaled contribution stays below 2^30 (converted to int32, summed
-            // in int64); its quantum is 2^-30 of the bound
-            const int S = 30 - ebits;
-            for (int q = threadIdx.x; q < bnodes; q += blockDim.x) acc[q] = 0ull;
-            __syncthreads();
-            const float *F = c == 0 ? Fx : (c == 1 ? Fy : Fz);
-            const float scale_f = ldexpf(1.0f, S);
-            const float lim = 1073741824.0f;            // 2^30
-            const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
-            for (uint32_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
-                const uint32_t m = entries[e];
+            const double bound = 8.0 * (double)Mf[c] * inv_h2;
+            int ebits = 0;
+            if (bound > 0.0 && bound < 1e300) frexp(bound, &ebits);   // bound < 2^ebits
+            S[c] = 30 - ebits;
+            scale_f[c] = (bound > 0.0 && bound < 1e300) ? ldexpf(1.0f, S[c]) : 0.0f;
+        }
+        const float lim = 1073741824.0f;            // 2^30
+        for (uint32_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
+            const uint32_t m = entries[e];
+            const float am = area[m];
+            bool range_ok = true;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
                 int hi, hj, hk;
                 unpack_home(home[home_at(m, c)], hi, hj, hk);
                 const float *p = phi + phi_at(m, c);
@@ -380,7 +409,7 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                             (unsigned)iz[a] < (unsigned)bz;
                 }
                 if (!inbox) {           // cannot happen for a home written by the build
-                    raise_error(err, m, MLS_E_SUPPORT);
+                    range_ok = false;
                     continue;
                 }
                 float ph[kNe];
@@ -392,9 +421,10 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                     hl += ph[k] * (wx[a] + wy[b] + wz[cz]);
                     den += ph[k] * (wx[a] * wy[b] * wz[cz]);
                 }
+                const float Fm = c == 0 ? Fx[m] : (c == 1 ? Fy[m] : Fz[m]);
                 // c_l F_l = A_l h_l F_l / sum_k phi_k dV_k   (eq. 8), pre-scaled
-                const float vsc = area[m] * (hl * (1.0f / 3.0f)) * F[m] / den * scale_f;
-                bool range_ok = true;
+                const float vsc = am * (hl * (1.0f / 3.0f)) * Fm / den * scale_f[c];
+                unsigned long long *box = acc + c * bnodes;
 #pragma unroll
                 for (int k = 0; k < kNe; ++k) {
                     const int a = k % 3, b = (k / 3) % 3, cz = k / 9;
@@ -402,28 +432,47 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                     range_ok = range_ok && (fabsf(vs) < lim);
                     vs = fminf(fmaxf(vs, -lim), lim);
                     const long long qv = (long long)(int)rintf(vs);
-                    atomicAdd(&acc[(iz[cz] * by + iy[b]) * bx + ix[a]], (unsigned long long)qv);
+                    if (qv != 0) atomicAdd(&box[(iz[cz] * by + iy[b]) * bx + ix[a]], (unsigned long long)qv);
                 }
-                if (!range_ok) raise_error(err, m, MLS_E_RANGE);
             }
-            __syncthreads();
-            float *f = c == 0 ? fx : (c == 1 ? fy : fz);
-            const double inv_scale = ldexp(1.0, -S);
-            for (int q = threadIdx.x; q < bnodes; q += blockDim.x) {
+            if (!range_ok) raise_error(err, m, MLS_E_RANGE);
+        }
+        __syncthreads();
+        // flush: the box nodes of a thread are read in batches of kFlush before
+        // any is written back, so their loads overlap
+        constexpr int kFlush = 8;
+        for (int q0 = threadIdx.x; q0 < 3 * bnodes; q0 += kFlush * blockDim.x) {
+            float *dst[kFlush];
+            float add[kFlush];
+            float old[kFlush];
+#pragma unroll
+            for (int u = 0; u < kFlush; ++u) {
+                dst[u] = nullptr;
+                add[u] = 0.f;
+                const int q = q0 + u * blockDim.x;
+                if (q >= 3 * bnodes) continue;
                 const long long sv = (long long)acc[q];
                 if (sv == 0) continue;
-                const int lx = q % bx, ly = (q / bx) % by, lz = q / (bx * by);
+                const int c = q / bnodes, r = q - c * bnodes;
+                const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
+                const int lx = r % bx, ly = (r / bx) % by, lz = r / (bx * by);
                 int gx = b0x + lx, gy = b0y + ly, gz = b0z + lz;
                 if (AX.periodic) gx = gx < 0 ? gx + nxc : (gx >= nxc ? gx - nxc : gx);
                 if (AY.periodic) gy = gy < 0 ? gy + nyc : (gy >= nyc ? gy - nyc : gy);
                 if (AZ.periodic) gz = gz < 0 ? gz + nzc : (gz >= nzc ? gz - nzc : gz);
                 if ((unsigned)gx >= (unsigned)nxc || (unsigned)gy >= (unsigned)nyc || (unsigned)gz >= (unsigned)nzc)
                     continue;
-                const int64_t idx = field_index(g, c, gx, gy, gz);
-                f[idx] = f[idx] + (float)((double)sv * inv_scale);
+                float *f = c == 0 ? fx : (c == 1 ? fy : fz);
+                dst[u] = f + field_index(g, c, gx, gy, gz);
+                add[u] = (float)((double)sv * ldexp(1.0, -S[c]));
             }
-            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kFlush; ++u) old[u] = dst[u] ? *dst[u] : 0.f;
+#pragma unroll
+            for (int u = 0; u < kFlush; ++u)
+                if (dst[u]) *dst[u] = old[u] + add[u];
         }
+        __syncthreads();
     }
 }
 
@@ -457,24 +506,32 @@ hipError_t launch_spread(Ctx &c, int64_t n, const uint32_t *home, const float *p
     {
         TimedLaunch tb(c, MLS_K_SPREAD_BIN, s);
         hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(nt, c.cu_count)), dim3(kBlock), 0, s, c.tile_count, nt);
-        hipLaunchKernelGGL(k_bin<false>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, home,
-                           c.tile_count, c.tile_cursor, c.entries, c.err);
+        const int gbin = grid_for(n, c.cu_count);
+        hipLaunchKernelGGL(k_bin<false>, dim3(gbin), dim3(kBlock), 0, s, c.d_grid, n, home,
+                           c.tile_count, c.tile_cursor, c.entries, c.err, area, Fx, Fy, Fz, c.block_fmax);
         hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)nb), dim3(kBlock), 0, s, c.tile_count, nt, c.block_sums);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, c.block_sums, nb);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, c.block_sums, nb, c.block_fmax, gbin,
+                           c.work + 64);
         hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kBlock), 0, s, c.tile_count, nt, c.block_sums,
                            c.tile_off, c.tile_cursor, c.work);
         hipLaunchKernelGGL(k_bin<true>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, home,
-                           c.tile_count, c.tile_cursor, c.entries, c.err);
+                           c.tile_count, c.tile_cursor, c.entries, c.err, area, Fx, Fy, Fz, c.work + 64);
         hipLaunchKernelGGL(k_active_tiles, dim3(grid_for(nt, c.cu_count)), dim3(kBlock), 0, s, c.d_grid,
                            c.tile_count, c.tile_active, c.work);
     }
-    const size_t lds = (size_t)c.g.box[0] * c.g.box[1] * c.g.box[2] * sizeof(unsigned long long);
+    const size_t lds = (size_t)3 * c.g.box[0] * c.g.box[1] * c.g.box[2] * sizeof(unsigned long long);
     const int persist = c.cu_count * c.spread_blocks_per_cu;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_spread_colour, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+    }
     TimedLaunch tt(c, MLS_K_SPREAD_TILES, s);
     for (int col = 0; col < 27; ++col) {
         if (c.colour_tiles[col] == 0) continue;
         hipLaunchKernelGGL(k_spread_colour, dim3(persist), dim3(kBlock), lds, s, c.d_grid, col, n, home, phi, area,
-                           Fx, Fy, Fz, fx, fy, fz, c.tile_off, c.entries, c.tile_active, c.work, c.err);
+                           Fx, Fy, Fz, fx, fy, fz, c.tile_off, c.entries, c.tile_active, c.work, c.work + 64,
+                           c.err);
     }
     return hipGetLastError();
 }

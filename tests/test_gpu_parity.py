@@ -101,7 +101,7 @@ def test_ragged_periodic_32(orc, torch_cuda, kind):
                 kw=dict(kind=kind))
 
 
-@pytest.mark.parametrize("dims,tile", [((24, 40, 12), 8), ((48, 20, 36), 16), ((36, 28, 44), 4)])
+@pytest.mark.parametrize("dims,tile", [((24, 40, 12), 8), ((48, 20, 36), 12), ((36, 28, 44), 4)])
 def test_uneven_grid_tiles(orc, torch_cuda, dims, tile):
     """Non-power-of-two periodic grids: odd tile counts (three tile colours),
     single-tile axes and every tile edge."""
@@ -117,7 +117,7 @@ def test_uneven_grid_tiles(orc, torch_cuda, dims, tile):
 
 
 def test_grid_rejected_without_tile_divisor(torch_cuda):
-    """A periodic axis of 17 cells has no tile edge between 4 and 16."""
+    """A periodic axis of 17 cells has no tile edge between 4 and 12."""
     from paper_1805_01113_amd import mls
     gs = W.GridSpec([W.uniform_faces(17), W.uniform_faces(16), W.uniform_faces(16)], [True] * 3)
     with pytest.raises(mls.MLSError):

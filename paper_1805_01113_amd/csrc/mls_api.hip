@@ -172,15 +172,16 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
             else if (c.g.ncol[d] == 2) { cnt[0][d] = (m + 1) / 2; cnt[1][d] = m / 2; cnt[2][d] = 0; }
             else { cnt[0][d] = (m - 1) / 2; cnt[1][d] = (m - 1) / 2; cnt[2][d] = 1; }
         }
-        uint32_t base = 0;
+        for (int k = 0; k < 3; ++k)
+            for (int d = 0; d < 3; ++d) c.g.ncol_tiles[k][d] = (int32_t)cnt[k][d];
+        int64_t base = 0;
         for (int cz = 0; cz < c.g.ncol[2]; ++cz)
             for (int cy = 0; cy < c.g.ncol[1]; ++cy)
                 for (int cx = 0; cx < c.g.ncol[0]; ++cx) {
                     const int col = cx + c.g.ncol[0] * (cy + c.g.ncol[1] * cz);
-                    const int64_t k = cnt[cx][0] * cnt[cy][1] * cnt[cz][2];
-                    c.colour_tiles[col] = k;
+                    c.colour_tiles[col] = cnt[cx][0] * cnt[cy][1] * cnt[cz][2];
                     c.g.colour_base[col] = base;
-                    base += (uint32_t)k;
+                    base += c.colour_tiles[col];
                 }
     }
     // smallest control-volume width within two nodes of each tile, per axis

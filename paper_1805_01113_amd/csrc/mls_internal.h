@@ -56,7 +56,8 @@ struct Grid {
     int32_t box[3];       // LDS box edge per axis: tile + 3 (whole axis for a single periodic tile)
     int32_t ncol[3];      // tile colours per axis: 1 (one tile), 2 (even count or walls), 3 (odd periodic count)
     int64_t ntiles;       // product
-    uint32_t colour_base[27]; // first slot of each tile colour in the active-tile list
+    int32_t ncol_tiles[3][3]; // [axis colour][axis]: tiles of that colour along the axis
+    int64_t colour_base[27];  // first slot of each colour in the active-tile list
     double h_min;         // smallest node spacing over all axes and components
 };
 
@@ -107,7 +108,7 @@ struct Ctx {
     uint32_t *tile_count = nullptr;    // ntiles
     uint32_t *tile_off = nullptr;      // ntiles + 1
     uint32_t *tile_cursor = nullptr;   // ntiles
-    uint32_t *tile_active = nullptr;   // ntiles: non-empty tiles per XCD slab
+    uint32_t *tile_active = nullptr;   // ntiles: non-empty tiles, grouped by colour
     uint32_t *block_sums = nullptr;    // scan partials
     uint32_t *entries = nullptr;       // cap_markers: markers sorted by tile
     uint32_t *block_fmax = nullptr;    // per-block force maxima of the counting pass (3 per block)

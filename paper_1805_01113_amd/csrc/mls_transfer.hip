@@ -275,40 +275,39 @@ __device__ __forceinline__ int axis_colour(const Grid &g, int d, int t)
     return k == 1 ? 0 : ((k == 3 && t == g.ntile[d] - 1) ? 2 : (t & 1));
 }
 
-__device__ __forceinline__ int tile_colour(const Grid &g, int64_t t)
-{
-    const int tx = (int)(t % g.ntile[0]);
-    const int ty = (int)((t / g.ntile[0]) % g.ntile[1]);
-    const int tz = (int)(t / ((int64_t)g.ntile[0] * g.ntile[1]));
-    return axis_colour(g, 0, tx) + g.ncol[0] * (axis_colour(g, 1, ty) + g.ncol[1] * axis_colour(g, 2, tz));
-}
-
 // Non-empty tiles listed per colour: work[col] counts them and
-// active[colour_base[col] + i] lists them.
+// active[colour_base[col] + i] lists them.  A block gathers its 2048 tiles
+// per colour in LDS and takes its slots with one atomic per colour.
+constexpr int kActiveChunk = 2048;
 __global__ void __launch_bounds__(kBlock)
-k_active_tiles(const Grid *__restrict__ gp, const uint32_t *__restrict__ count, uint32_t *__restrict__ active,
+k_active_tiles(const Grid *__restrict__ gp, const uint32_t *__restrict__ off, uint32_t *__restrict__ active,
                uint32_t *work)
 {
     const Grid &g = *gp;
-    const int lane = threadIdx.x & 63;
-    const unsigned long long lower = (1ull << lane) - 1ull;
-    const int64_t nt = g.ntiles;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < nt; base += stride) {
-        const int64_t t = base + lane;
-        const int col = (t < nt && count[t] > 0u) ? tile_colour(g, t) : -1;
-        unsigned long long pending = __ballot(col >= 0);
-        while (pending) {
-            const int leader = __ffsll((long long)pending) - 1;
-            const int cl = __shfl(col, leader);
-            const unsigned long long mask = __ballot(col == cl) & pending;
-            uint32_t pos = 0;
-            if (lane == leader) pos = atomicAdd(&work[cl], (uint32_t)__popcll(mask));
-            pos = __shfl(pos, leader);
-            if ((mask >> lane) & 1ull) active[g.colour_base[cl] + pos + __popcll(mask & lower)] = (uint32_t)t;
-            pending &= ~mask;
+    __shared__ uint32_t lcount[27], lbase[27];
+    if (threadIdx.x < 27) lcount[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t t0 = (int64_t)blockIdx.x * kActiveChunk + (int64_t)threadIdx.x * (kActiveChunk / kBlock);
+    int col[kActiveChunk / kBlock];
+    uint32_t pos[kActiveChunk / kBlock];
+#pragma unroll
+    for (int q = 0; q < kActiveChunk / kBlock; ++q) {
+        const int64_t t = t0 + q;
+        col[q] = -1;
+        if (t < g.ntiles && off[t + 1] > off[t]) {
+            const int tx = (int)(t % g.ntile[0]);
+            const int ty = (int)((t / g.ntile[0]) % g.ntile[1]);
+            const int tz = (int)(t / ((int64_t)g.ntile[0] * g.ntile[1]));
+            col[q] = axis_colour(g, 0, tx) + g.ncol[0] * (axis_colour(g, 1, ty) + g.ncol[1] * axis_colour(g, 2, tz));
+            pos[q] = atomicAdd(&lcount[col[q]], 1u);
         }
     }
+    __syncthreads();
+    if (threadIdx.x < 27) lbase[threadIdx.x] = lcount[threadIdx.x] ? atomicAdd(&work[threadIdx.x], lcount[threadIdx.x]) : 0u;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kActiveChunk / kBlock; ++q)
+        if (col[q] >= 0) active[g.colour_base[col[q]] + lbase[col[q]] + pos[q]] = (uint32_t)(t0 + q);
 }
 
 // ---- spreading: per-tile fixed-point accumulation ------------------------------
@@ -337,15 +336,15 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
 {
     const Grid &g = *gp;
     extern __shared__ unsigned long long acc[];     // three boxes, one per component
-    __shared__ int64_t tile_sh;
     const Axis &AX = g.ax[0], &AY = g.ax[1], &AZ = g.ax[2];
     const int bx = g.box[0], by = g.box[1], bz = g.box[2];
     const int bnodes = bx * by * bz;
-    const uint32_t nact = work[colour];
-    const uint32_t abase = g.colour_base[colour];
     float Mf[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) Mf[c] = __uint_as_float(fmax_bits[c]);
+    const uint32_t nact = work[colour];
+    const int64_t abase = g.colour_base[colour];
+    __shared__ int64_t tile_sh;
     for (;;) {
         if (threadIdx.x == 0) {
             const uint32_t i = atomicAdd(&work[32 + colour], 1u);
@@ -516,8 +515,8 @@ hipError_t launch_spread(Ctx &c, int64_t n, const uint32_t *home, const float *p
                            c.tile_off, c.tile_cursor, c.work);
         hipLaunchKernelGGL(k_bin<true>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, home,
                            c.tile_count, c.tile_cursor, c.entries, c.err, area, Fx, Fy, Fz, c.work + 64);
-        hipLaunchKernelGGL(k_active_tiles, dim3(grid_for(nt, c.cu_count)), dim3(kBlock), 0, s, c.d_grid,
-                           c.tile_count, c.tile_active, c.work);
+        hipLaunchKernelGGL(k_active_tiles, dim3((unsigned)((nt + kActiveChunk - 1) / kActiveChunk)), dim3(kBlock), 0,
+                           s, c.d_grid, c.tile_off, c.tile_active, c.work);
     }
     const size_t lds = (size_t)3 * c.g.box[0] * c.g.box[1] * c.g.box[2] * sizeof(unsigned long long);
     const int persist = c.cu_count * c.spread_blocks_per_cu;

@@ -105,8 +105,10 @@ typedef struct {
                              0 routes every solve to FP64) */
     int32_t n_sub;        /* fast-MLS sub-nodes per axis of the home control
                              volume, boundaries included (default 9 -> 729) */
-    double fallback_tol;  /* learned: consistency residual above which the
-                             marker falls back to exact MLS (default 1e-4) */
+    double fallback_tol;  /* learned: a marker keeps the network's shape
+                             functions only if its consistency residual is
+                             below this, else it falls back to exact MLS
+                             (default 1e-4; 0 sends every marker to exact) */
     int32_t spread_tile;  /* edge (cells) of the spreading tiles on axes longer
                              than 16 cells, 4..12 (0 = default 8); a periodic
                              axis uses a divisor of its length */
@@ -155,7 +157,12 @@ mls_status mls_reserve(mls_ctx *ctx, int64_t n_markers);
  * table on a uniform grid, one per plane and staggering type along a
  * stretched axis, Sec. 2 last paragraph) and blends the 8 corners of the
  * enclosing sub-cell with inverse-square-distance (Shepard) weights, eq. 9-10.
- * MLS_LEARNED requires a loaded network (mls_mlp_load).  Markers whose
+ * MLS_LEARNED evaluates the loaded network (mls_mlp_load) and keeps its
+ * output where the residual max(|sum_k phi_k - 1|, max_d |sum_k phi_k s_dk|)
+ * (partition of unity and reproduction of linear fields, the consistency
+ * conditions of MLS with a linear basis; s_dk the offset of node k from the
+ * marker along d in units of H_d) is below opts.fallback_tol, and builds the
+ * other markers with exact MLS (route bit 2).  Markers whose
  * support leaves a wall axis get NaN phi and raise MLS_E_SUPPORT. */
 mls_status mls_build(mls_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
                      int32_t method, uint32_t *home, float *phi, uint8_t *route, void *stream);
@@ -281,6 +288,61 @@ typedef struct {
 } mls_timing;
 mls_status mls_timing_enable(mls_ctx *ctx, int32_t on);
 mls_status mls_timing_get(mls_ctx *ctx, mls_timing *out, int32_t reset);
+
+/* ---- learned surrogate (an addition to the paper's method) ----------------
+ * A network 6 -> 128 -> 128 -> 27 maps the features of a (marker, component)
+ * support -- xi_d = (X - X_0)/H_d (in-cell offset, H_d = half the support
+ * width on axis d) and rho_d = (X_{+1} - X_0)/(X_0 - X_{-1}) (spacing ratio),
+ * d = x, y, z, which fix the exact shape function of eq. 3-6 -- to its 27
+ * shape-function values:
+ *   u = (feat - shift) * scale,  h1 = gelu(u W1 + b1),  h2 = gelu(h1 W2 + b2),
+ *   phi = h2 W3 + b3,            gelu(z) = z Phi(z) (Phi: standard normal CDF).
+ * Parameters are one FP32 vector of MLS_MLP_PARAMS floats: W1 [6][128], b1
+ * [128], W2 [128][128], b2 [128], W3 [128][27], b3 [27], each W stored
+ * [input][output] row-major; the input normalisation is norm[12] = shift[6],
+ * scale[6].  Matrix products run on the matrix cores in split BF16 (each FP32
+ * operand as a high plus a low BF16 part, three products accumulated in FP32).
+ * Training minimises
+ *   L = mean_{b,k} (phi_bk - t_bk)^2
+ *       + mu mean_b [(sum_k phi_bk - 1)^2 + sum_d (sum_k phi_bk s_dk)^2]
+ * with Adam (beta1 0.9, beta2 0.999, eps 1e-8). */
+#define MLS_MLP_PARAMS 20891
+
+/* Load parameters and normalisation (HOST pointers, copied) and reset the
+ * Adam state.  MLS_E_ARG on a non-finite value. */
+mls_status mls_mlp_load(mls_ctx *ctx, const float *params, const float *norm);
+
+/* Copy the current parameters (MLS_MLP_PARAMS floats) and normalisation (12)
+ * to HOST memory (either may be NULL); synchronises the device. */
+mls_status mls_mlp_get(mls_ctx *ctx, float *params, float *norm);
+
+/* Features of n markers (device x, y, z): feat[(c n + l) 6 + q] (device FP32,
+ * 3 n rows of 6) for component c = 0, 1, 2; a row whose support leaves the
+ * grid is NaN and raises MLS_E_SUPPORT. */
+mls_status mls_features(mls_ctx *ctx, int64_t n, const float *x, const float *y, const float *z, float *feat,
+                        void *stream);
+
+/* Network output out[b][27] (device FP32) for a batch of m entries taken
+ * from the feature rows feat[rows][6] (device FP32): entry b is row idx[b]
+ * if idx (device int64, m entries) is not NULL, else row b (then m <= rows).
+ * An idx entry outside [0, rows) raises MLS_E_ARG on the device (mls_sync
+ * reports it) and reads row 0. */
+mls_status mls_mlp_forward(mls_ctx *ctx, int64_t m, const float *feat, int64_t rows, const int64_t *idx,
+                           float *out, void *stream);
+
+/* Loss L (above) and its gradient dL/dparams of a batch of m >= 1 entries,
+ * rows chosen as in mls_mlp_forward from feat [rows][6] and target
+ * [rows][27] (device FP32); grad: device MLS_MLP_PARAMS floats in the
+ * parameter layout, loss: device float.  Every reduction runs in a fixed
+ * order, so equal inputs give equal results bit for bit. */
+mls_status mls_mlp_grad(mls_ctx *ctx, int64_t m, const float *feat, const float *target, int64_t rows,
+                        const int64_t *idx, float mu, float *grad, float *loss, void *stream);
+
+/* One Adam step with learning rate lr on the gradient of the batch as in
+ * mls_mlp_grad; loss (device float) may be NULL.  A later MLS_LEARNED build
+ * uses the updated parameters. */
+mls_status mls_mlp_train_step(mls_ctx *ctx, int64_t m, const float *feat, const float *target, int64_t rows,
+                              const int64_t *idx, float mu, float lr, float *loss, void *stream);
 
 #ifdef __cplusplus
 }

@@ -310,6 +310,7 @@ void mls_ctx_destroy(mls_ctx *ctx)
     hipFree(c.block_fmax);
     hipFree(c.work);
     hipFree(c.step_ctr);
+    mlp_free(c);
     for (hipEvent_t ev : c.ev_pool) hipEventDestroy(ev);
     delete ctx;
 }
@@ -381,6 +382,12 @@ mls_status mls_build(mls_ctx *ctx, int64_t n, const float *x, const float *y, co
         if (st != MLS_OK) return st;
         TimedLaunch t(c, MLS_K_BUILD_FAST, s);
         e = launch_build_fast(c, n, x, y, z, home, phi, route, s);
+        break;
+    }
+    case MLS_LEARNED: {
+        if (!c.mlp.loaded) return fail(ctx, MLS_E_ARG, "MLS_LEARNED needs a network (mls_mlp_load)");
+        TimedLaunch t(c, MLS_K_BUILD_LEARNED, s);
+        e = launch_build_learned(c, n, x, y, z, home, phi, route, s);
         break;
     }
     default:
@@ -495,6 +502,109 @@ mls_status mls_fast_tables(mls_ctx *ctx, float *dst, int64_t *count, int32_t *ro
         hipError_t e = hipMemcpyAsync(dst, c.tables, bytes, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return hip_fail(ctx, e, "table copy");
     }
+    return MLS_OK;
+}
+
+// ---- learned surrogate --------------------------------------------------------
+
+mls_status mls_mlp_load(mls_ctx *ctx, const float *params, const float *norm)
+{
+    if (!ctx || !params || !norm) return MLS_E_ARG;
+    Ctx &c = ctx->c;
+    for (int i = 0; i < kMlpParams; ++i)
+        if (!std::isfinite(params[i])) return fail(ctx, MLS_E_ARG, "non-finite network parameter %d", i);
+    for (int i = 0; i < 12; ++i)
+        if (!std::isfinite(norm[i])) return fail(ctx, MLS_E_ARG, "non-finite input normalisation %d", i);
+    hipError_t e = mlp_alloc(c);
+    if (e != hipSuccess) return hip_fail(ctx, e, "network allocation");
+    if (hipDeviceSynchronize() != hipSuccess) return MLS_E_HIP;
+    Mlp &net = c.mlp;
+    e = hipMemcpy(net.params, params, kMlpParams * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(net.norm, norm, 12 * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(net.m1, 0, 2 * (size_t)kMlpParams * sizeof(float));
+    if (e != hipSuccess) return hip_fail(ctx, e, "network upload");
+    memcpy(net.h_norm, norm, sizeof(net.h_norm));
+    net.adam_step = 0;
+    net.version += 1;
+    net.loaded = true;
+    return MLS_OK;
+}
+
+mls_status mls_mlp_get(mls_ctx *ctx, float *params, float *norm)
+{
+    if (!ctx) return MLS_E_ARG;
+    Ctx &c = ctx->c;
+    if (!c.mlp.loaded) return fail(ctx, MLS_E_ARG, "no network loaded");
+    if (hipDeviceSynchronize() != hipSuccess) return MLS_E_HIP;
+    if (params && hipMemcpy(params, c.mlp.params, kMlpParams * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+        return MLS_E_HIP;
+    if (norm) memcpy(norm, c.mlp.h_norm, sizeof(c.mlp.h_norm));
+    return MLS_OK;
+}
+
+mls_status mls_features(mls_ctx *ctx, int64_t n, const float *x, const float *y, const float *z, float *feat,
+                        void *stream)
+{
+    if (!ctx) return MLS_E_ARG;
+    if (n < 0 || n > (int64_t)0x1fffffff) return fail(ctx, MLS_E_ARG, "bad marker count");
+    if (n > 0 && (!x || !y || !z || !feat)) return fail(ctx, MLS_E_ARG, "null array");
+    hipError_t e = launch_features(ctx->c, n, x, y, z, feat, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(ctx, e, "features launch");
+    return MLS_OK;
+}
+
+static mls_status mlp_batch_check(mls_ctx *ctx, int64_t m, const float *feat, int64_t rows, const int64_t *idx)
+{
+    Ctx &c = ctx->c;
+    if (!c.mlp.loaded) return fail(ctx, MLS_E_ARG, "no network loaded");
+    if (m < 0 || m > ((int64_t)1 << 26)) return fail(ctx, MLS_E_ARG, "bad batch size %lld", (long long)m);
+    if (m > 0 && !feat) return fail(ctx, MLS_E_ARG, "null array");
+    if (rows < 0 || (!idx && m > rows)) return fail(ctx, MLS_E_ARG, "batch of %lld rows from %lld", (long long)m,
+                                                    (long long)rows);
+    hipError_t e = mlp_reserve(c, m);
+    if (e != hipSuccess) return hip_fail(ctx, e, "training scratch");
+    return MLS_OK;
+}
+
+mls_status mls_mlp_forward(mls_ctx *ctx, int64_t m, const float *feat, int64_t rows, const int64_t *idx, float *out,
+                           void *stream)
+{
+    if (!ctx) return MLS_E_ARG;
+    mls_status st = mlp_batch_check(ctx, m, feat, rows, idx);
+    if (st != MLS_OK) return st;
+    if (m > 0 && !out) return fail(ctx, MLS_E_ARG, "null array");
+    hipError_t e = mlp_forward_batch(ctx->c, m, feat, rows, idx, out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(ctx, e, "network forward");
+    return MLS_OK;
+}
+
+mls_status mls_mlp_grad(mls_ctx *ctx, int64_t m, const float *feat, const float *target, int64_t rows,
+                        const int64_t *idx, float mu, float *grad, float *loss, void *stream)
+{
+    if (!ctx) return MLS_E_ARG;
+    mls_status st = mlp_batch_check(ctx, m, feat, rows, idx);
+    if (st != MLS_OK) return st;
+    if (m < 1 || !target || !grad || !loss) return fail(ctx, MLS_E_ARG, "null array or empty batch");
+    if (!(mu >= 0.0f) || !std::isfinite(mu)) return fail(ctx, MLS_E_ARG, "bad mu");
+    hipError_t e = mlp_grad_batch(ctx->c, m, feat, target, rows, idx, mu, grad, loss, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(ctx, e, "network gradient");
+    return MLS_OK;
+}
+
+mls_status mls_mlp_train_step(mls_ctx *ctx, int64_t m, const float *feat, const float *target, int64_t rows,
+                              const int64_t *idx, float mu, float lr, float *loss, void *stream)
+{
+    if (!ctx) return MLS_E_ARG;
+    mls_status st = mlp_batch_check(ctx, m, feat, rows, idx);
+    if (st != MLS_OK) return st;
+    if (m < 1 || !target) return fail(ctx, MLS_E_ARG, "null array or empty batch");
+    if (!(mu >= 0.0f) || !std::isfinite(mu) || !(lr >= 0.0f) || !std::isfinite(lr))
+        return fail(ctx, MLS_E_ARG, "bad mu or learning rate");
+    Ctx &c = ctx->c;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = mlp_grad_batch(c, m, feat, target, rows, idx, mu, c.mlp.grad, loss ? loss : c.mlp.loss, s);
+    if (e == hipSuccess) e = mlp_adam(c, lr, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "training step");
     return MLS_OK;
 }
 

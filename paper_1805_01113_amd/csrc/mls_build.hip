@@ -7,60 +7,13 @@
 // 1-D moments, solves it in FP32 (FP64 if its condition number exceeds the
 // routing threshold) and writes the 27 shape-function values.  Stores are
 // SoA, so a wavefront writes 64 consecutive floats per (component, node).
-#include "mls_device.h"
+#include "mls_exact.h"
 
 namespace mls {
 
 namespace {
 
 constexpr int kBlock = 256;
-
-// FP64 re-solve of one (marker, component): recompute the offsets, weights
-// and moments in FP64 from the position and store Phi (out points at the
-// marker's first support node, consecutive nodes kLanes floats apart).
-// Returns false if A is singular.
-__device__ __forceinline__ bool solve_fp64(const Grid &g, const Weight &W, int c, double px, double py, double pz,
-                                           float *out)
-{
-    double s[3][3], w[3][3];
-    Moments<double> m[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        axis_offsets_d(g.ax[d], d == c, d == 0 ? px : (d == 1 ? py : pz), s[d]);
-        double m0 = 0, m1 = 0, m2 = 0;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            w[d][a] = weight1_d(W, s[d][a]);
-            m0 += w[d][a]; m1 += w[d][a] * s[d][a]; m2 += w[d][a] * s[d][a] * s[d][a];
-        }
-        m[d] = {m0, m1, m2};
-    }
-    double A[10], L[10], gam[4];
-    assemble(m[0], m[1], m[2], A);
-    const bool ok = cholesky4(A, L);
-    if (ok) {
-        const double e0[4] = {1.0, 0.0, 0.0, 0.0};
-        chol_solve(L, e0, gam);
-    }
-#pragma unroll 1
-    for (int k = 0; k < kNe; ++k) {
-        const int a = k % 3, b = (k / 3) % 3, cc = k / 9;
-        const double W3 = w[0][a] * w[1][b] * w[2][cc];
-        out[k * kLanes] = ok ? (float)(W3 * (gam[0] + gam[1] * s[0][a] + gam[2] * s[1][b] + gam[3] * s[2][cc]))
-                             : __builtin_nanf("");
-    }
-    return ok;
-}
-
-__device__ __forceinline__ void mark_failed(ErrWord *err, int64_t l, double px, double py, double pz,
-                                            uint32_t *hout, float *out, uint8_t *rout)
-{
-    raise_error(err, l, isfinite(px) && isfinite(py) && isfinite(pz) ? MLS_E_SUPPORT : MLS_E_NONFINITE);
-    *hout = 0xffffffffu;
-#pragma unroll 1
-    for (int k = 0; k < kNe; ++k) out[k * kLanes] = __builtin_nanf("");
-    if (rout) *rout = 0;
-}
 
 // Work split of the build kernels: a block holds kGroups groups of 64
 // consecutive markers; each group is handled by three wavefronts, one per
@@ -101,49 +54,7 @@ k_build_exact(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n,
             continue;
         }
         *hout = pack_home(G[0].ih, G[1].ih, G[2].ih);
-        float w[3][3];
-        Moments<float> m[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            float m0 = 0.f, m1 = 0.f, m2 = 0.f;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const float wa = weight1(W, G[d].s[a]);
-                w[d][a] = wa;
-                m0 += wa;
-                m1 += wa * G[d].s[a];
-                m2 += wa * G[d].s[a] * G[d].s[a];
-            }
-            m[d] = {m0, m1, m2};
-        }
-        float A[10], L[10], gam[4];
-        assemble(m[0], m[1], m[2], A);
-        bool fp32_ok = cholesky4(A, L);
-        if (fp32_ok) {
-            const float kap = cond_bound_and_gamma(A, L, gam);
-            fp32_ok = kap <= tau && isfinite(kap);
-            kmax = fmaxf(kmax, isfinite(kap) ? kap : 3.0e38f);
-        }
-        if (fp32_ok) {
-#pragma unroll
-            for (int cz = 0; cz < 3; ++cz) {
-#pragma unroll
-                for (int by = 0; by < 3; ++by) {
-                    const float wyz = w[1][by] * w[2][cz];
-                    const float pyz = gam[0] + gam[2] * G[1].s[by] + gam[3] * G[2].s[cz];
-#pragma unroll
-                    for (int ax = 0; ax < 3; ++ax) {
-                        const int k = ax + 3 * by + 9 * cz;
-                        out[k * kLanes] = w[0][ax] * wyz * (pyz + gam[1] * G[0].s[ax]);
-                    }
-                }
-            }
-            if (rout) *rout = 0;
-        } else {
-            ++routed;
-            if (!solve_fp64(g, W, c, px, py, pz, out)) raise_error(err, l, MLS_E_SINGULAR);
-            if (rout) *rout = 1;
-        }
+        exact_from_geo(g, W, tau, c, l, px, py, pz, G, out, rout, 0, err, routed, kmax);
     }
     // one atomic per wavefront for the statistics
     unsigned long long tot = routed;

@@ -11,6 +11,7 @@ struct AxisGeo {
     int32_t ih;      // wrapped home node index
     float s[3];      // (X_a - X)/H for a = -1, 0, +1
     float xi;        // (X - X_0)/H
+    float rho;       // (X_{+1} - X_0)/(X_0 - X_{-1}): 1 on a uniform axis
 };
 
 __device__ __forceinline__ void raise_error(ErrWord *err, int64_t marker, int status)
@@ -147,6 +148,7 @@ __device__ __forceinline__ bool axis_geo(const Axis &a, int is_face, double x, A
         g.s[1] = (float)d0;
         g.s[2] = (float)(d0 + 1.0);
         g.xi = (float)(-d0);
+        g.rho = 1.0f;
     } else {
         const double xm = node_x(a, is_face, ih - 1);
         const double xp = node_x(a, is_face, ih + 1);
@@ -155,6 +157,7 @@ __device__ __forceinline__ bool axis_geo(const Axis &a, int is_face, double x, A
         g.s[1] = (float)((x0 - X) * rH);
         g.s[2] = (float)((xp - X) * rH);
         g.xi = (float)((X - x0) * rH);
+        g.rho = (float)((xp - x0) / (x0 - xm));
     }
     g.ih = (a.periodic && ih >= a.n) ? ih - a.n : ih;
     return true;

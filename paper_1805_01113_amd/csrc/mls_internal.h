@@ -84,6 +84,41 @@ struct FastTables {
     int32_t first[2];        // first table index of centre / face staggering
 };
 
+// Learned surrogate: 6 -> 128 -> 128 -> 27 GELU network.  The FP32 parameter
+// vector is W1 [6][128], b1 [128], W2 [128][128], b2 [128], W3 [128][27],
+// b3 [27] (weights stored [input][output]); norm = shift[6], scale[6].
+constexpr int kMlpIn = 6, kMlpHidden = 128, kMlpOut = 27;
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kMlpIn * kMlpHidden;
+constexpr int kOffW2 = kOffB1 + kMlpHidden;
+constexpr int kOffB2 = kOffW2 + kMlpHidden * kMlpHidden;
+constexpr int kOffW3 = kOffB2 + kMlpHidden;
+constexpr int kOffB3 = kOffW3 + kMlpHidden * kMlpOut;
+constexpr int kMlpParams = kOffB3 + kMlpOut;   // 20891
+// Inference image of the network (built from the FP32 parameters): the
+// matrix-core operands of every (layer, 32-row output tile, 16-wide k block)
+// as split BF16 (high part, low part), 64 lanes x 8 values each, followed by
+// the FP32 biases (b1, b2, b3 padded to 32) and norm.
+constexpr int kMlpSlots = 4 + 4 * 8 + 8;                       // layer 1, 2, 3
+constexpr int kMlpImageOps = kMlpSlots * 2 * 64;               // 16-byte operand words
+constexpr int kMlpImageFloats = 2 * kMlpHidden + 32 + 12;      // biases + norm
+constexpr size_t kMlpImageBytes = (size_t)kMlpImageOps * 16 + kMlpImageFloats * sizeof(float);
+
+struct Mlp {
+    bool loaded = false;
+    float *params = nullptr;   // kMlpParams (FP32 master copy)
+    float *grad = nullptr;     // kMlpParams
+    float *m1 = nullptr, *m2 = nullptr;   // Adam moments
+    float *norm = nullptr;     // 12
+    void *image = nullptr;     // kMlpImageBytes
+    float *loss = nullptr;     // 1 (device)
+    float h_norm[12] = {};
+    int64_t version = 0, image_version = -1;
+    int64_t adam_step = 0;
+    float *scratch = nullptr;  // training activations
+    int64_t cap_batch = 0;
+};
+
 struct Ctx {
     int device = 0;
     Grid g{};
@@ -117,6 +152,8 @@ struct Ctx {
     int64_t colour_tiles[27] = {};   // tiles of each colour
     int spread_blocks_per_cu = 8;
     int cu_count = 256;
+    // learned surrogate
+    Mlp mlp;
     // time step
     unsigned long long *step_ctr = nullptr;
     // per-kernel timing
@@ -144,6 +181,8 @@ hipError_t launch_build_exact(const Ctx &c, int64_t n, const float *x, const flo
                               uint32_t *home, float *phi, uint8_t *route, hipStream_t s);
 hipError_t launch_build_fast(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
                              uint32_t *home, float *phi, uint8_t *route, hipStream_t s);
+hipError_t launch_build_learned(Ctx &c, int64_t n, const float *x, const float *y, const float *z,
+                                uint32_t *home, float *phi, uint8_t *route, hipStream_t s);
 hipError_t launch_table_build(const Ctx &c, hipStream_t s);
 hipError_t launch_interp(const Ctx &c, int64_t n, const uint32_t *home, const float *phi,
                          const float *u, const float *v, const float *w,
@@ -159,6 +198,19 @@ hipError_t launch_force(const Ctx &c, int64_t n, const float *vb, const float *U
 hipError_t launch_step_advance(const Ctx &c, hipStream_t s);
 
 FastTables fast_tables(const Ctx &c);
+
+// learned surrogate (training and feature kernels)
+hipError_t mlp_alloc(Ctx &c);
+void mlp_free(Ctx &c);
+hipError_t mlp_reserve(Ctx &c, int64_t batch);
+hipError_t mlp_pack(Ctx &c, hipStream_t s);
+hipError_t launch_features(const Ctx &c, int64_t n, const float *x, const float *y, const float *z, float *feat,
+                           hipStream_t s);
+hipError_t mlp_forward_batch(Ctx &c, int64_t m, const float *feat, int64_t rows, const int64_t *idx, float *y,
+                             hipStream_t s);
+hipError_t mlp_grad_batch(Ctx &c, int64_t m, const float *feat, const float *target, int64_t rows,
+                          const int64_t *idx, float mu, float *grad, float *loss, hipStream_t s);
+hipError_t mlp_adam(Ctx &c, float lr, hipStream_t s);
 
 }  // namespace mls
 

@@ -61,6 +61,8 @@ class _StepBuf(ctypes.Structure):
         "fx", "fy", "fz")]
 
 
+MLP_PARAMS = 20891   # 6*128 + 128 + 128*128 + 128 + 128*27 + 27
+
 K_NAMES = ["build_exact", "build_fast", "build_learned", "interp", "spread_bin", "spread_tiles", "jitter", "force"]
 
 
@@ -104,7 +106,14 @@ def load(path: str = LIB_PATH, need_torch: bool = True):
     L.mls_graph_destroy.restype = None
     L.mls_timing_enable.argtypes = [P, I32]
     L.mls_timing_get.argtypes = [P, ctypes.POINTER(_Timing), I32]
-    for name in ("mls_ctx_create", "mls_reserve", "mls_build", "mls_interp", "mls_spread", "mls_sync",
+    L.mls_mlp_load.argtypes = [P, P, P]
+    L.mls_mlp_get.argtypes = [P, P, P]
+    L.mls_features.argtypes = [P, I64, P, P, P, P, P]
+    L.mls_mlp_forward.argtypes = [P, I64, P, I64, P, P, P]
+    L.mls_mlp_grad.argtypes = [P, I64, P, P, I64, P, ctypes.c_float, P, P, P]
+    L.mls_mlp_train_step.argtypes = [P, I64, P, P, I64, P, ctypes.c_float, ctypes.c_float, P, P]
+    for name in ("mls_mlp_load", "mls_mlp_get", "mls_features", "mls_mlp_forward", "mls_mlp_grad",
+                 "mls_mlp_train_step","mls_ctx_create", "mls_reserve", "mls_build", "mls_interp", "mls_spread", "mls_sync",
                  "mls_stats_get", "mls_stats_reset", "mls_fast_tables", "mls_step", "mls_step_counter_set",
                  "mls_graph_create", "mls_graph_launch", "mls_timing_enable", "mls_timing_get"):
         getattr(L, name).restype = ctypes.c_int
@@ -269,6 +278,77 @@ class Context:
                                        _stream(stream))
         self._raise(st, "mls_fast_tables")
         return buf[:, :, :27], (first[0], first[1]), ax.value
+
+    # ---- learned surrogate ---------------------------------------------------
+    def mlp_load(self, params: np.ndarray, norm: np.ndarray):
+        """Load the network (MLP_PARAMS FP32 parameters, norm = shift[6], scale[6])."""
+        p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        q = np.ascontiguousarray(norm, dtype=np.float32).ravel()
+        if p.size != MLP_PARAMS or q.size != 12:
+            raise ValueError("need %d parameters and 12 normalisation values" % MLP_PARAMS)
+        self._raise(self._lib.mls_mlp_load(self.h, p.ctypes.data, q.ctypes.data), "mls_mlp_load")
+
+    def mlp_get(self):
+        p = np.empty(MLP_PARAMS, dtype=np.float32)
+        q = np.empty(12, dtype=np.float32)
+        self._raise(self._lib.mls_mlp_get(self.h, p.ctypes.data, q.ctypes.data), "mls_mlp_get")
+        return p, q
+
+    def features(self, x, y, z, out=None, stream=None):
+        """Features [3, n, 6] (xi_x, xi_y, xi_z, rho_x, rho_y, rho_z per component)."""
+        import torch
+        n = x.numel()
+        for t, nm in ((x, "x"), (y, "y"), (z, "z")):
+            _check_dev(t, torch.float32, n, nm)
+        if out is None:
+            out = torch.empty((3, n, 6), dtype=torch.float32, device=x.device)
+        _check_dev(out, torch.float32, 18 * n, "out")
+        self._raise(self._lib.mls_features(self.h, n, _ptr(x), _ptr(y), _ptr(z), _ptr(out), _stream(stream)),
+                    "mls_features")
+        return out
+
+    def _rows(self, feat, idx):
+        import torch
+        if feat.dim() != 2 or feat.shape[1] != 6:
+            feat = feat.reshape(-1, 6)
+        _check_dev(feat, torch.float32, feat.shape[0] * 6, "feat")
+        if idx is not None:
+            _check_dev(idx, torch.int64, idx.numel(), "idx")
+            return feat, idx.numel(), feat.shape[0]
+        return feat, feat.shape[0], feat.shape[0]
+
+    def mlp_forward(self, feat, idx=None, out=None, stream=None):
+        """Network output [m, 27] for feature rows feat[idx] (or all rows)."""
+        import torch
+        feat, m, rows = self._rows(feat, idx)
+        if out is None:
+            out = torch.empty((m, 27), dtype=torch.float32, device=feat.device)
+        _check_dev(out, torch.float32, 27 * m, "out")
+        self._raise(self._lib.mls_mlp_forward(self.h, m, _ptr(feat), rows, _ptr(idx), _ptr(out), _stream(stream)),
+                    "mls_mlp_forward")
+        return out
+
+    def mlp_grad(self, feat, target, mu=1.0, idx=None, stream=None):
+        """(loss, gradient) of a batch; both device tensors."""
+        import torch
+        feat, m, rows = self._rows(feat, idx)
+        target = target.reshape(-1, 27)
+        _check_dev(target, torch.float32, rows * 27, "target")
+        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=feat.device)
+        loss = torch.empty(1, dtype=torch.float32, device=feat.device)
+        self._raise(self._lib.mls_mlp_grad(self.h, m, _ptr(feat), _ptr(target), rows, _ptr(idx), float(mu),
+                                           _ptr(grad), _ptr(loss), _stream(stream)), "mls_mlp_grad")
+        return loss, grad
+
+    def mlp_train_step(self, feat, target, lr, mu=1.0, idx=None, loss=None, stream=None):
+        import torch
+        feat, m, rows = self._rows(feat, idx)
+        target = target.reshape(-1, 27)
+        _check_dev(target, torch.float32, rows * 27, "target")
+        if loss is not None:
+            _check_dev(loss, torch.float32, 1, "loss")
+        self._raise(self._lib.mls_mlp_train_step(self.h, m, _ptr(feat), _ptr(target), rows, _ptr(idx), float(mu),
+                                                 float(lr), _ptr(loss), _stream(stream)), "mls_mlp_train_step")
 
 
 class StepBuffers:

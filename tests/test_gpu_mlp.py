@@ -1,0 +1,274 @@
+"""GPU tests of the learned surrogate: features, the network's forward pass
+and gradient (HIP training kernels) against the FP64 oracle on identical
+FP32 parameters, the fused learned build against both, and the exact-MLS
+gate (threshold 0 gives the exact build bit for bit; a threshold between the
+residuals splits the markers as the oracle's residuals say).
+
+Tolerances (split-BF16 products: each FP32 operand as a high plus a low BF16
+part, three products accumulated in FP32, about 2^-17 relative per product,
+amplified by cancellation in 128-term sums and by three layers):
+network outputs 2e-4 normwise relative, gradients 1e-3 per parameter block,
+fused kernel vs batched training forward 2e-5.
+"""
+import numpy as np
+import pytest
+
+from parity import normwise, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+FWD_TOL = 2e-4
+GRAD_TOL = 1e-3
+FUSED_TOL = 2e-5
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1805_01113_amd import mls
+    mls.load()
+    return torch
+
+
+def _grid(nxy=32, nz=48, beta=2.5, lz=1.5):
+    from paper_1805_01113_amd import workloads as W
+    return W.GridSpec([W.uniform_faces(nxy), W.uniform_faces(nxy), W.tanh_faces(nz, lz, beta)],
+                      [True, True, False])
+
+
+def _markers(gs, n, seed):
+    r = np.random.default_rng(seed)
+    fz = gs.faces[2]
+    x = r.uniform(0.0, 1.0, n).astype(np.float32)
+    y = r.uniform(0.0, 1.0, n).astype(np.float32)
+    z = r.uniform(fz[2], fz[-3], n).astype(np.float32)
+    return x, y, z
+
+
+def _params(seed=3):
+    """Oracle-initialised network with non-zero biases and normalisation."""
+    from oracle import mlp as M
+    r = np.random.default_rng(seed + 100)
+    p = M.init_params(seed)
+    p.b1 = r.normal(0, 0.3, 128)
+    p.b2 = r.normal(0, 0.3, 128)
+    p.b3 = r.normal(0, 0.05, 27)
+    p.shift = np.array([0.0, 0.0, 0.0, 1.0, 1.0, 1.0])
+    p.scale = np.array([3.4, 3.4, 3.4, 1.0, 1.0, 40.0])
+    flat = p.flat().astype(np.float32)
+    norm = np.concatenate([p.shift, p.scale]).astype(np.float32)
+    # the oracle sees exactly the FP32 values the GPU holds
+    q = M.Params.unflat(flat.astype(np.float64), norm[:6].astype(np.float64), norm[6:].astype(np.float64))
+    return flat, norm, q
+
+
+def _ctx(gs, **kw):
+    from paper_1805_01113_amd import mls
+    return mls.Context(gs.faces, gs.periodic, **kw)
+
+
+def test_features_match_oracle(orc, torch_cuda):
+    gs = _grid()
+    x, y, z = _markers(gs, 3000, 11)
+    ctx = _ctx(gs)
+    f = ctx.features(to_dev(x), to_dev(y), to_dev(z))
+    ctx.sync()
+    f = f.cpu().numpy()
+    g = orc.Grid(gs.faces, gs.periodic)
+    for c in range(3):
+        ref = orc.build_exact(g, c, x, y, z)
+        exi = np.abs(f[c, :, :3] - ref["xi"]).max()
+        erho = np.abs(f[c, :, 3:] - ref["rho"]).max()
+        say("features comp %d: |xi| err %.2e  |rho| err %.2e" % (c, exi, erho))
+        # FP32 rounding of the FP64 values (|xi| <= 1, rho near 1)
+        assert exi <= 2.0 ** -23 and erho <= 2.0 ** -22
+
+
+def _rows(ctx, gs, n, seed):
+    x, y, z = _markers(gs, n, seed)
+    f = ctx.features(to_dev(x), to_dev(y), to_dev(z))
+    ctx.sync()
+    return (x, y, z), f
+
+
+def test_forward_matches_oracle(torch_cuda):
+    from oracle import mlp as M
+    gs = _grid()
+    ctx = _ctx(gs)
+    flat, norm, q = _params()
+    ctx.mlp_load(flat, norm)
+    _, f = _rows(ctx, gs, 2500, 12)
+    rows = f.reshape(-1, 6)
+    y = ctx.mlp_forward(rows)
+    ctx.sync()
+    ref, _ = M.forward(q, rows.cpu().numpy().astype(np.float64))
+    e = normwise(y.cpu().numpy(), ref)
+    say("network forward (batched kernels) normwise rel err %.2e" % e)
+    assert e <= FWD_TOL
+    # gathered rows give the same outputs bit for bit
+    idx = torch_cuda.randperm(rows.shape[0], device="cuda")[:1000]
+    yi = ctx.mlp_forward(rows, idx=idx)
+    ctx.sync()
+    assert torch_cuda.equal(yi, y[idx])
+
+
+def test_gradient_matches_oracle(orc, torch_cuda):
+    from oracle import mlp as M
+    gs = _grid()
+    ctx = _ctx(gs)
+    flat, norm, q = _params(5)
+    ctx.mlp_load(flat, norm)
+    (x, y, z), f = _rows(ctx, gs, 1500, 13)
+    g = orc.Grid(gs.faces, gs.periodic)
+    target = np.stack([orc.build_exact(g, c, x, y, z)["phi"] for c in range(3)]).astype(np.float32)
+    rows = f.reshape(-1, 6)
+    tg = to_dev(target.reshape(-1, 27))
+    for mu in (0.0, 1.0):
+        loss, grad = ctx.mlp_grad(rows, tg, mu=mu)
+        ctx.sync()
+        L, G = M.loss_and_grad(q, rows.cpu().numpy().astype(np.float64), target.reshape(-1, 27).astype(np.float64),
+                               mu=mu)
+        gg = grad.cpu().numpy()
+        el = abs(float(loss.item()) - L) / abs(L)
+        say("mu %.1f loss gpu %.6e oracle %.6e rel err %.2e" % (mu, loss.item(), L, el))
+        assert el <= GRAD_TOL
+        offs = np.cumsum([0, 768, 128, 16384, 128, 3456, 27])
+        for name, a, b in zip(("W1", "b1", "W2", "b2", "W3", "b3"), offs[:-1], offs[1:]):
+            e = normwise(gg[a:b], G[a:b])
+            say("mu %.1f grad %s normwise rel err %.2e" % (mu, name, e))
+            assert e <= GRAD_TOL, name
+    # a gathered batch equals the same rows passed contiguously, bit for bit
+    idx = torch_cuda.randperm(rows.shape[0], device="cuda")[:3000]
+    l1, g1 = ctx.mlp_grad(rows, tg, mu=1.0, idx=idx)
+    l2, g2 = ctx.mlp_grad(rows[idx].contiguous(), tg[idx].contiguous(), mu=1.0)
+    ctx.sync()
+    assert torch_cuda.equal(g1, g2) and torch_cuda.equal(l1, l2)
+
+
+def test_learned_build_accept_all(orc, torch_cuda):
+    """Gate wide open: the fused kernel's phi is the network's output."""
+    from oracle import mlp as M
+    from paper_1805_01113_amd import mls
+    gs = _grid()
+    ctx = _ctx(gs, fallback_tol=1e30)
+    flat, norm, q = _params(7)
+    ctx.mlp_load(flat, norm)
+    n = 2000 + 37     # ragged last block
+    x, y, z = _markers(gs, n, 14)
+    f = ctx.features(to_dev(x), to_dev(y), to_dev(z))
+    route = torch_cuda.zeros(3 * mls.npad(n), dtype=torch_cuda.uint8, device="cuda")
+    home, phi, route = ctx.build(to_dev(x), to_dev(y), to_dev(z), method=mls.MLS_LEARNED, route=route)
+    ctx.sync()
+    p = mls.unpack_phi(phi.cpu().numpy(), n)
+    r = mls.unpack_route(route.cpu().numpy(), n)
+    assert np.all(r == 2)
+    yb = ctx.mlp_forward(f.reshape(-1, 6)).cpu().numpy().reshape(3, n, 27)
+    e_b = normwise(p, yb)
+    ref, _ = M.forward(q, f.reshape(-1, 6).cpu().numpy().astype(np.float64))
+    e_o = normwise(p, ref.reshape(3, n, 27))
+    say("fused learned build vs batched forward %.2e, vs oracle %.2e" % (e_b, e_o))
+    assert e_b <= FUSED_TOL and e_o <= FWD_TOL
+    # home indices are the exact build's
+    h = mls.unpack_home(home.cpu().numpy().view(np.uint32), n)
+    g = orc.Grid(gs.faces, gs.periodic)
+    for c in range(3):
+        assert np.array_equal(h[c], orc.build_exact(g, c, x, y, z)["home"])
+    st = ctx.stats()
+    assert st["learned"] == 3 * n and st["fallbacks"] == 0
+
+
+def test_gate_zero_is_exact(torch_cuda):
+    """Threshold 0: every marker falls back, the result is the exact build bit for bit."""
+    from paper_1805_01113_amd import mls
+    gs = _grid()
+    ctx = _ctx(gs, fallback_tol=0.0)
+    flat, norm, _ = _params(8)
+    ctx.mlp_load(flat, norm)
+    n = 1500 + 5
+    x, y, z = [to_dev(a) for a in _markers(gs, n, 15)]
+    route = torch_cuda.zeros(3 * mls.npad(n), dtype=torch_cuda.uint8, device="cuda")
+    h1, p1, route = ctx.build(x, y, z, method=mls.MLS_LEARNED, route=route)
+    ctx.sync()
+    st = ctx.stats()
+    ctx.stats_reset()
+    h0, p0, _ = ctx.build(x, y, z, method=mls.MLS_EXACT)
+    ctx.sync()
+    a = mls.unpack_phi(p1.cpu().numpy(), n)
+    b = mls.unpack_phi(p0.cpu().numpy(), n)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    assert np.array_equal(mls.unpack_home(h1.cpu().numpy().view(np.uint32), n),
+                          mls.unpack_home(h0.cpu().numpy().view(np.uint32), n))
+    r = mls.unpack_route(route.cpu().numpy(), n)
+    assert np.all((r & 6) == 4)
+    assert st["fallbacks"] == 3 * n and st["learned"] == 0
+
+
+def test_gate_splits_by_residual(torch_cuda):
+    """Threshold at the median residual: markers well below it keep the
+    network's output, markers well above it get the exact build."""
+    from oracle import mlp as M
+    from paper_1805_01113_amd import mls
+    gs = _grid()
+    flat, norm, q = _params(9)
+    probe = _ctx(gs)
+    n = 3000
+    x, y, z = _markers(gs, n, 16)
+    f = probe.features(to_dev(x), to_dev(y), to_dev(z)).cpu().numpy().reshape(-1, 6).astype(np.float64)
+    ref, _ = M.forward(q, f)
+    r0, r1 = M.residuals(ref, f)
+    res = np.maximum(r0, r1).reshape(3, n)
+    tol = float(np.median(res))
+    ctx = _ctx(gs, fallback_tol=tol)
+    ctx.mlp_load(flat, norm)
+    route = torch_cuda.zeros(3 * mls.npad(n), dtype=torch_cuda.uint8, device="cuda")
+    xd, yd, zd = to_dev(x), to_dev(y), to_dev(z)
+    _, p1, route = ctx.build(xd, yd, zd, method=mls.MLS_LEARNED, route=route)
+    _, p0, _ = ctx.build(xd, yd, zd, method=mls.MLS_EXACT)
+    ctx.sync()
+    a = mls.unpack_phi(p1.cpu().numpy(), n)
+    b = mls.unpack_phi(p0.cpu().numpy(), n)
+    r = mls.unpack_route(route.cpu().numpy(), n)
+    learned = (r & 2) != 0
+    fell = (r & 4) != 0
+    assert np.all(learned ^ fell)
+    assert np.all(learned[res < 0.5 * tol]) and np.all(fell[res > 2.0 * tol])
+    assert np.array_equal(a[fell].view(np.uint32), b[fell].view(np.uint32))
+    e = normwise(a[learned], ref.reshape(3, n, 27)[learned])
+    say("gate at %.3e: %d learned, %d exact; learned vs oracle %.2e" % (tol, learned.sum(), fell.sum(), e))
+    assert e <= FWD_TOL
+
+
+def test_training_reduces_loss_and_is_reproducible(torch_cuda):
+    """A short run of the GPU trainer lowers the loss on held-out rows, and
+    two runs from the same start give the same parameters bit for bit."""
+    from paper_1805_01113_amd import mls
+    gs = _grid()
+    ctx = _ctx(gs)
+    flat, norm, _ = _params(10)
+    (x, y, z), f = _rows(ctx, gs, 6000, 17)
+    _, phi, _ = ctx.build(to_dev(x), to_dev(y), to_dev(z), method=mls.MLS_EXACT)
+    ctx.sync()
+    target = mls.unpack_phi(phi, 6000).reshape(-1, 27).contiguous()
+    rows = f.reshape(-1, 6)
+    train, held = slice(0, 15000), slice(15000, 18000)
+
+    def run(steps):
+        ctx.mlp_load(flat, norm)
+        gen = torch_cuda.Generator(device="cuda")
+        gen.manual_seed(0)
+        for _ in range(steps):
+            idx = torch_cuda.randint(0, 15000, (1024,), device="cuda", generator=gen)
+            ctx.mlp_train_step(rows[train], target[train], lr=1e-3, mu=1.0, idx=idx)
+        p, _ = ctx.mlp_get()
+        return p
+
+    ctx.mlp_load(flat, norm)
+    l0, _ = ctx.mlp_grad(rows[held].contiguous(), target[held].contiguous(), mu=1.0)
+    p1 = run(400)
+    l1, _ = ctx.mlp_grad(rows[held].contiguous(), target[held].contiguous(), mu=1.0)
+    ctx.sync()
+    say("held-out loss: %.3e -> %.3e after 400 steps" % (l0.item(), l1.item()))
+    assert l1.item() < 0.2 * l0.item()
+    p2 = run(400)
+    assert np.array_equal(p1.view(np.uint32), p2.view(np.uint32))

@@ -103,14 +103,116 @@ def cpu_baseline(wl, fields_dev, target_s):
                       "3 components, FP64; build %.1fs interp %.1fs spread %.1fs" % (m2, wl.n, *parts)}
 
 
+METHODS = {"exact": 0, "fast": 1, "learned": 2}
+
+
+def load_network(ctx, path):
+    """Load the trained surrogate into ctx; None if no checkpoint is available."""
+    from paper_1805_01113_amd import train_mlp
+    path = path or train_mlp.DEFAULT_WEIGHTS
+    if not os.path.exists(path):
+        log("no surrogate checkpoint at %s: learned method skipped" % path)
+        return None
+    p, q, meta = train_mlp.load_weights(path)
+    ctx.mlp_load(p, q)
+    return {"path": os.path.relpath(path, ROOT), "trained": meta["config"], "held_out": meta["end"]}
+
+
+def per_body_rate(torch, ctx, wl, bufs, fields, forcing, x0, y0, z0, area, method, jitter, seed, stream, sub):
+    """markers/s of one mls_step per body (a host loop over bodies), same kernels."""
+    import ctypes
+    from paper_1805_01113_amd import mls
+    offs = wl.body_offsets
+    torch.cuda.synchronize()
+    t_a = time.perf_counter()
+    for b in range(sub):
+        s, e = int(offs[b]), int(offs[b + 1])
+        sb = mls._StepBuf()
+        sb.n = e - s
+        for key, t in (("x0", x0), ("y0", y0), ("z0", z0), ("x", bufs.x), ("y", bufs.y), ("z", bufs.z),
+                       ("area", area)):
+            setattr(sb, key, t.data_ptr() + 4 * s)
+        sb.home = bufs.home.data_ptr()
+        sb.phi = bufs.phi.data_ptr()
+        sb.U = bufs.U.data_ptr()
+        sb.F = bufs.F.data_ptr()
+        sb.u, sb.v, sb.w = [f.data_ptr() for f in fields]
+        sb.fx, sb.fy, sb.fz = [f.data_ptr() for f in forcing]
+        d = mls._desc(method, 1.0, jitter, seed)
+        st = ctx._lib.mls_step(ctx.h, ctypes.byref(d), ctypes.byref(sb), stream.cuda_stream)
+        assert st == 0
+    torch.cuda.synchronize()
+    t_b = time.perf_counter()
+    ctx.sync()
+    return int(offs[sub]) / (t_b - t_a)
+
+
+def compare_methods(torch, ctx, wl, bufs, fields, forcing, x0, y0, z0, area, jitter, seed, args, ms_main,
+                    main_method):
+    """{per-body, batched} x {exact, fast, learned}: markers/s, and the
+    interpolated velocity of each method against exact MLS on the same
+    jittered positions (normwise: max |U - U_exact| / max |U_exact|)."""
+    from paper_1805_01113_amd import mls
+    stream = torch.cuda.current_stream()
+    n = wl.n
+    names = ["exact", "fast"] + (["learned"] if ctx.mlp_loaded else [])
+    sub = int(min(len(wl.body_offsets) - 1, 2000))
+    # reference velocities: exact MLS at a fixed jitter counter
+    probe_step = 1 << 20
+    ref = None
+    out = {}
+    for name in names:
+        m = METHODS[name]
+        mls.step_counter_set(ctx, probe_step)
+        ctx.stats_reset()
+        mls.step(ctx, bufs, method=m, dt=1.0, jitter=jitter, seed=seed)
+        ctx.sync()
+        st = ctx.stats()
+        U = bufs.U.clone()
+        if ref is None:
+            ref = U
+        err = float((U - ref).abs().max().item() / ref.abs().max().item())
+        row = {"interp_err_vs_exact": err}
+        if m == mls.MLS_LEARNED:
+            tot = st["learned"] + st["fallbacks"]
+            row["fallback_rate"] = st["fallbacks"] / max(1, tot)
+            row["network_kept"] = st["learned"]
+        if m == main_method:
+            ms = ms_main
+        else:
+            g2 = mls.StepGraph(ctx, bufs, method=m, dt=1.0, jitter=jitter, seed=seed)
+            g2.launch(args.warmup)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            g2.launch(args.steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ctx.sync()
+            ms = e0.elapsed_time(e1) / max(args.steps, 1)
+            g2.close()
+        row["batched"] = {"ms_per_step": round(ms, 4), "markers_per_s": round(n / (ms * 1e-3), 1)}
+        rate = per_body_rate(torch, ctx, wl, bufs, fields, forcing, x0, y0, z0, area, m, jitter, seed, stream, sub)
+        row["per_body"] = {"markers_per_s": round(rate, 1), "bodies_timed": sub}
+        log("%s: batched %.3f ms/step (%.3e markers/s), per-body %.3e markers/s, interp err vs exact %.2e%s"
+            % (name, ms, n / (ms * 1e-3), rate, err,
+               (", fallback rate %.4f" % row["fallback_rate"]) if "fallback_rate" in row else ""))
+        out[name] = row
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="uneven", choices=["uneven", "ellipsoids", "stretched", "sphere"])
-    ap.add_argument("--method", default="exact", choices=["exact", "fast"])
+    ap.add_argument("--method", default="exact", choices=["exact", "fast", "learned"])
+    ap.add_argument("--weights", default=None, help="surrogate checkpoint (default: the packaged one)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (JSON lines)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the eager / per-body / fast comparisons")
     ap.add_argument("--copy-gib", type=float, default=0.0,
@@ -154,10 +256,21 @@ def main():
     torch.cuda.synchronize()
     log("fields ready (%.1f GB velocity + %.1f GB forcing)" % (sum(f.numel() for f in fields) * 4e-9,
                                                                  sum(f.numel() for f in forcing) * 4e-9))
-    method = mls.MLS_EXACT if args.method == "exact" else mls.MLS_FAST
+    method = METHODS[args.method]
     ctx = mls.Context(wl.grid.faces, wl.grid.periodic)
     ctx.reserve(n)
+    net_meta = load_network(ctx, args.weights)
+    if method == mls.MLS_LEARNED and net_meta is None:
+        raise SystemExit("--method learned needs the surrogate checkpoint")
     bufs = mls.StepBuffers(ctx, x0, y0, z0, area, fields, forcing)
+    tune = None
+    if not args.no_tune:
+        t_a = time.time()
+        tune = ctx.autotune(bufs, method=method, cache_path=args.tune_cache)
+        for f in forcing:
+            f.zero_()
+        torch.cuda.synchronize()
+        log("autotune (%.1fs): %s" % (time.time() - t_a, json.dumps(tune)))
     jitter = 0.1 * h_min
     seed = 20180503
     graph = mls.StepGraph(ctx, bufs, method=method, dt=1.0, jitter=jitter, seed=seed)
@@ -198,7 +311,9 @@ def main():
         "jitter": 24.0,
         "build_exact": 12 + 12 + 324.0,
         "build_fast": 12 + 12 + 324.0,
+        "build_learned": 12 + 12 + 324.0,
         "interp": 12 + 324 + 12 + 4.0 * t_per,
+        "build_interp": 12 + 12 + 324 + 4.0 * t_per + 12 + 12,
         "force": 24.0,
         "spread_tiles": 12 + 324 + 12 + 4 + 8.0 * t_per,
         "spread_bin": 0.0,
@@ -216,57 +331,14 @@ def main():
             "frac": round(dom[1]["GBs"] / HBM_PEAK_GBS, 4), "traffic": None,
             "alg_bytes_per_marker": round(alg[dom[0]], 1), "markers_per_launch": n}
 
-    extra = {"ms_per_step_eager": round(ms_eager, 4), "kernels": kernels,
+    extra = {"ms_per_step_eager": round(ms_eager, 4), "kernels": kernels, "autotune": tune,
              "touched_nodes_per_marker": round(t_per, 3),
              "step_alg_bytes_per_marker": round(step_bytes / n, 1),
              "step_hbm_frac": round(step_bytes / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     if not args.no_extra:
-        # per-body launches (what a loop over bodies would do), one step
-        offs = wl.body_offsets
-        nb = len(offs) - 1
-        sub = int(min(nb, 2000))
-        torch.cuda.synchronize()
-        t_a = time.perf_counter()
-        for b in range(sub):
-            s, e = int(offs[b]), int(offs[b + 1])
-            sb = mls._StepBuf()
-            sb.n = e - s
-            for key, t, w in (("x0", x0, 1), ("y0", y0, 1), ("z0", z0, 1), ("x", bufs.x, 1), ("y", bufs.y, 1),
-                              ("z", bufs.z, 1), ("area", area, 1)):
-                setattr(sb, key, t.data_ptr() + 4 * s)
-            sb.home = bufs.home.data_ptr()
-            sb.phi = bufs.phi.data_ptr()
-            sb.U = bufs.U.data_ptr()
-            sb.F = bufs.F.data_ptr()
-            sb.u, sb.v, sb.w = [f.data_ptr() for f in fields]
-            sb.fx, sb.fy, sb.fz = [f.data_ptr() for f in forcing]
-            d = mls._desc(method, 1.0, jitter, seed)
-            import ctypes
-            st = ctx._lib.mls_step(ctx.h, ctypes.byref(d), ctypes.byref(sb), stream.cuda_stream)
-            assert st == 0
-        torch.cuda.synchronize()
-        t_b = time.perf_counter()
-        ctx.sync()
-        per_body_rate = int(offs[sub]) / (t_b - t_a)
-        extra["per_body_launches"] = {"markers_per_s": round(per_body_rate, 1), "bodies_timed": sub,
-                                      "note": "one mls_step per body (host loop), same kernels"}
-        log("per-body: %.3e markers/s over %d bodies" % (per_body_rate, sub))
-        # the other build method through the same graph path
-        other = mls.MLS_FAST if method == mls.MLS_EXACT else mls.MLS_EXACT
-        g2 = mls.StepGraph(ctx, bufs, method=other, dt=1.0, jitter=jitter, seed=seed)
-        g2.launch(args.warmup)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        g2.launch(args.steps)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ctx.sync()
-        ms2 = e0.elapsed_time(e1) / max(args.steps, 1)
-        extra["graph_" + ("fast" if other == mls.MLS_FAST else "exact")] = {
-            "ms_per_step": round(ms2, 4), "markers_per_s": round(n / (ms2 * 1e-3), 1)}
-        log("graph %s: %.3f ms/step" % ("fast" if other == mls.MLS_FAST else "exact", ms2))
-        g2.close()
+        extra["methods"] = compare_methods(torch, ctx, wl, bufs, fields, forcing, x0, y0, z0, area, jitter, seed,
+                                           args, ms_graph, method)
 
     cpu = None
     if not args.no_cpu:
@@ -294,6 +366,8 @@ def main():
         "cpu_baseline": cpu,
         "extra": extra,
     }
+    if net_meta is not None:
+        extra["surrogate"] = net_meta
     print(json.dumps(out), flush=True)
     graph.close()
     ctx.close()

@@ -232,7 +232,9 @@ mls_status mls_fast_tables(mls_ctx *ctx, float *dst, int64_t *count, int32_t *ro
  *   force    F = (V_b - U) / dt, the direct forcing of Sec. 2 (V_b = 0 if NULL);
  *   spread   f += c_l phi F (eq. 7-8);
  * and then increments the context's device step counter, which the jitter
- * of the next step reads.  All buffers are caller-owned device arrays:
+ * of the next step reads.  With MLS_EXACT the build, interpolation and
+ * forcing run as one kernel (the interpolation uses the shape functions in
+ * registers, phi is not read back); home, phi, U and F are written as above.  All buffers are caller-owned device arrays:
  * x0,y0,z0 [n] (read), x,y,z [n] (written by jitter), area [n], vb [3][n] or
  * NULL, home, phi and route (or NULL) in the blocked layout above, U [3][n], F [3][n],
  * the velocity fields u,v,w and the forcing fields fx,fy,fz. */
@@ -280,7 +282,9 @@ void mls_graph_destroy(mls_graph *graph);
  * synchronises and returns the summed milliseconds and launch counts. */
 enum {
     MLS_K_BUILD_EXACT = 0, MLS_K_BUILD_FAST = 1, MLS_K_BUILD_LEARNED = 2, MLS_K_INTERP = 3,
-    MLS_K_SPREAD_BIN = 4, MLS_K_SPREAD_TILES = 5, MLS_K_JITTER = 6, MLS_K_FORCE = 7, MLS_K_COUNT = 16
+    MLS_K_SPREAD_BIN = 4, MLS_K_SPREAD_TILES = 5, MLS_K_JITTER = 6, MLS_K_FORCE = 7,
+    MLS_K_BUILD_INTERP = 8,  /* exact build fused with interpolation and forcing (mls_step, MLS_EXACT) */
+    MLS_K_COUNT = 16
 };
 typedef struct {
     double ms[MLS_K_COUNT];
@@ -288,6 +292,46 @@ typedef struct {
 } mls_timing;
 mls_status mls_timing_enable(mls_ctx *ctx, int32_t on);
 mls_status mls_timing_get(mls_ctx *ctx, mls_timing *out, int32_t reset);
+
+/* ---- launch shapes and the autotuner (an addition to the paper's method) ---
+ * spread_tile: edge of the spreading tiles (4..12, as mls_opts.spread_tile);
+ * *_blocks_per_cu (1..64): resident workgroups per compute unit of the
+ * spreading tile launches (bounded further by the LDS of a tile's boxes), of
+ * the exact / fast build and of the interpolation. */
+typedef struct {
+    int32_t spread_tile;
+    int32_t spread_blocks_per_cu;
+    int32_t build_blocks_per_cu;
+    int32_t interp_blocks_per_cu;
+} mls_tune;
+
+typedef struct {
+    mls_tune best;           /* the shapes now applied */
+    double ms_build;         /* their time per call (ms) of each phase */
+    double ms_interp;
+    double ms_spread;        /* binning and tiles */
+    int32_t from_cache;      /* 1: taken from the cache file, nothing timed */
+    int32_t candidates;      /* shapes timed */
+} mls_tune_report;
+
+mls_status mls_tune_get(mls_ctx *ctx, mls_tune *out);
+
+/* Apply launch shapes.  A new spread_tile re-cuts the spreading tiles
+ * (capture step graphs after this call).  MLS_E_ARG for a value out of range
+ * or a tile edge the grid does not allow (the previous shapes stay). */
+mls_status mls_tune_set(mls_ctx *ctx, const mls_tune *in);
+
+/* Time candidate launch shapes of the build (method), the interpolation and
+ * the spreading on the caller's step buffers (n, x0, y0, z0, area, vb, home,
+ * phi, u, v, w, U, F, fx, fy, fz as for mls_step; markers at x0), keep the
+ * fastest of each phase and apply them.  cache_path (may be NULL) names a
+ * JSON-lines file: an entry whose key (device architecture, compute units,
+ * grid, periodic flags, stretched axis, method, floor(log2 n)) matches is
+ * applied without timing; otherwise the result is appended.  home, phi, U and
+ * F are overwritten and the forcing fields receive the contributions of the
+ * timed spreading calls (zero them afterwards).  Synchronises `stream`. */
+mls_status mls_autotune(mls_ctx *ctx, int32_t method, const mls_step_buffers *buf, const char *cache_path,
+                        mls_tune_report *out, void *stream);
 
 /* ---- learned surrogate (an addition to the paper's method) ----------------
  * A network 6 -> 128 -> 128 -> 27 maps the features of a (marker, component)

@@ -44,6 +44,117 @@ int32_t comp_nodes(const Axis &a, int c, int d)
 
 }  // namespace
 
+// Spreading tiles for the requested edge: a periodic axis of at most kMaxTile
+// cells is one tile; a longer one is cut into equal tiles (the requested edge
+// if it divides the axis, else its largest divisor between 4 and
+// kMaxBoxTile; none -> MLS_E_ARG); a wall axis uses the requested edge.
+// Derives the LDS boxes, the tile colours and the per-tile smallest control
+// volume width, (re)allocates the per-tile scratch and uploads the grid.
+// On error the previous tiling is kept.
+mls_status mls::setup_tiles(Ctx &c, int want)
+{
+    if (want < 4 || want > kMaxBoxTile) return MLS_E_ARG;
+    Grid g = c.g;
+    for (int d = 0; d < 3; ++d) {
+        Axis &a = g.ax[d];
+        const int n = a.n;
+        if (a.periodic) {
+            a.tile = 0;
+            if (n <= kMaxTile) a.tile = n;
+            else if (n % want == 0) a.tile = want;
+            for (int t = kMaxBoxTile; t >= 4 && !a.tile; --t)
+                if (n % t == 0) a.tile = t;
+            if (!a.tile) return MLS_E_ARG;
+        } else {
+            a.tile = want;
+        }
+    }
+    int64_t nt = 1;
+    for (int d = 0; d < 3; ++d) {
+        const Axis &a = g.ax[d];
+        const int nn = a.periodic ? a.n : a.n + 1;
+        g.ntile[d] = (nn + a.tile - 1) / a.tile;
+        g.box[d] = (a.periodic && g.ntile[d] == 1) ? a.n : a.tile + 3;
+        nt *= g.ntile[d];
+    }
+    g.ntiles = nt;
+    // three fixed-point boxes (one per component) must fit the LDS of a workgroup
+    const int64_t lds = (int64_t)3 * g.box[0] * g.box[1] * g.box[2] * 8;
+    if (lds > 160 * 1024) return MLS_E_ARG;
+    // tile colours: tiles whose boxes may overlap get different colours.  Along
+    // an axis the colour is the parity of the tile index; an odd number of
+    // periodic tiles gives the last tile a third colour.
+    int64_t colour_tiles[27] = {};
+    {
+        int64_t cnt[3][3];
+        for (int d = 0; d < 3; ++d) {
+            const int m = g.ntile[d];
+            const bool periodic = g.ax[d].periodic != 0;
+            g.ncol[d] = m == 1 ? 1 : ((periodic && (m & 1)) ? 3 : 2);
+            if (g.ncol[d] == 1) { cnt[0][d] = 1; cnt[1][d] = 0; cnt[2][d] = 0; }
+            else if (g.ncol[d] == 2) { cnt[0][d] = (m + 1) / 2; cnt[1][d] = m / 2; cnt[2][d] = 0; }
+            else { cnt[0][d] = (m - 1) / 2; cnt[1][d] = (m - 1) / 2; cnt[2][d] = 1; }
+        }
+        for (int k = 0; k < 3; ++k)
+            for (int d = 0; d < 3; ++d) g.ncol_tiles[k][d] = (int32_t)cnt[k][d];
+        for (int k = 0; k < 27; ++k) g.colour_base[k] = 0;
+        int64_t base = 0;
+        for (int cz = 0; cz < g.ncol[2]; ++cz)
+            for (int cy = 0; cy < g.ncol[1]; ++cy)
+                for (int cx = 0; cx < g.ncol[0]; ++cx) {
+                    const int col = cx + g.ncol[0] * (cy + g.ncol[1] * cz);
+                    colour_tiles[col] = cnt[cx][0] * cnt[cy][1] * cnt[cz][2];
+                    g.colour_base[col] = base;
+                    base += colour_tiles[col];
+                }
+    }
+    // smallest control-volume width within three nodes of each tile, per axis
+    std::vector<float> thmin;
+    size_t off[3];
+    for (int d = 0; d < 3; ++d) {
+        const Axis &a = g.ax[d];
+        off[d] = thmin.size();
+        for (int t = 0; t < g.ntile[d]; ++t) {
+            double m = std::numeric_limits<double>::infinity();
+            for (int i = t * a.tile - 3; i <= (t + 1) * a.tile + 3; ++i) {
+                int ic = i;
+                if (a.periodic) ic = ((i % a.n) + a.n) % a.n;
+                if (ic >= 0 && ic < (int)c.h_wc[d].size()) m = std::min(m, (double)c.h_wc[d][ic]);
+                if (ic >= 0 && ic < (int)c.h_wf[d].size()) m = std::min(m, (double)c.h_wf[d][ic]);
+            }
+            thmin.push_back((float)m);
+        }
+    }
+    // device scratch for the new tiling
+    const int64_t nb = (nt + 2047) / 2048;
+    float *th = nullptr;
+    uint32_t *tcount = nullptr, *toff = nullptr, *tcur = nullptr, *tact = nullptr, *bsum = nullptr;
+    bool ok = hipMalloc((void **)&th, thmin.size() * sizeof(float)) == hipSuccess &&
+              hipMalloc((void **)&tcount, nt * sizeof(uint32_t)) == hipSuccess &&
+              hipMalloc((void **)&toff, (nt + 1) * sizeof(uint32_t)) == hipSuccess &&
+              hipMalloc((void **)&tcur, nt * sizeof(uint32_t)) == hipSuccess &&
+              hipMalloc((void **)&tact, nt * sizeof(uint32_t)) == hipSuccess &&
+              hipMalloc((void **)&bsum, (nb + 1) * sizeof(uint32_t)) == hipSuccess;
+    ok = ok && hipMemcpy(th, thmin.data(), thmin.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
+    for (int d = 0; d < 3; ++d) g.ax[d].tile_hmin = th + off[d];
+    ok = ok && hipDeviceSynchronize() == hipSuccess &&
+         hipMemcpy(c.d_grid, &g, sizeof(Grid), hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        hipFree(th); hipFree(tcount); hipFree(toff); hipFree(tcur); hipFree(tact); hipFree(bsum);
+        hipMemcpy(c.d_grid, &c.g, sizeof(Grid), hipMemcpyHostToDevice);
+        return MLS_E_NOMEM;
+    }
+    hipFree(c.tile_hmin_block); hipFree(c.tile_count); hipFree(c.tile_off); hipFree(c.tile_cursor);
+    hipFree(c.tile_active); hipFree(c.block_sums);
+    c.tile_hmin_block = th;
+    c.tile_count = tcount; c.tile_off = toff; c.tile_cursor = tcur; c.tile_active = tact; c.block_sums = bsum;
+    c.g = g;
+    for (int k = 0; k < 27; ++k) c.colour_tiles[k] = colour_tiles[k];
+    c.spread_blocks_per_cu = std::max(1, std::min(c.spread_blocks_per_cu_req, (int)((160 * 1024) / (lds + 512))));
+    c.opts.spread_tile = want;
+    return MLS_OK;
+}
+
 extern "C" {
 
 const char *mls_version(void) { return "mls_hip 0.1.0 (gfx950)"; }
@@ -96,21 +207,6 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
         for (int i = 0; i <= n && a.exact; ++i) a.exact = (f[i] == a.f0 + (double)i * a.h);
         for (int i = 0; i < n && a.exact; ++i) a.exact = (c.h_centres[d][i] == a.f0 + ((double)i + 0.5) * a.h);
         if (!bitwise) { ++nonuniform; c.stretched_axis = d; }
-        // spreading tiles: a periodic axis longer than kMaxTile cells is cut
-        // into equal tiles (a divisor of n between 4 and 16, the requested
-        // edge if it divides n); a shorter one is a single tile
-        const int want = (opts && opts->spread_tile) ? opts->spread_tile : 8;
-        if (want < 4 || want > kMaxBoxTile) { delete ctx; return MLS_E_ARG; }
-        if (a.periodic) {
-            a.tile = 0;
-            if (n <= kMaxTile) a.tile = n;
-            else if (n % want == 0) a.tile = want;
-            for (int t = kMaxBoxTile; t >= 4 && !a.tile; --t)
-                if (n % t == 0) a.tile = t;
-            if (!a.tile) { delete ctx; return MLS_E_ARG; }
-        } else {
-            a.tile = want;
-        }
     }
     if (nonuniform > 1) c.stretched_axis = -2;   // fast-MLS unavailable (more than one stretched axis)
     for (int cc = 0; cc < 3; ++cc)
@@ -146,63 +242,12 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
         }
     }
     c.g.h_min = hmin;
-    int64_t nt = 1;
     for (int d = 0; d < 3; ++d) {
-        const Axis &a = c.g.ax[d];
-        const int nn = a.periodic ? a.n : a.n + 1;
-        c.g.ntile[d] = (nn + a.tile - 1) / a.tile;
-        c.g.box[d] = (a.periodic && c.g.ntile[d] == 1) ? a.n : a.tile + 3;
-        nt *= c.g.ntile[d];
+        c.h_wc[d] = wc[d];
+        c.h_wf[d] = wf[d];
     }
-    c.g.ntiles = nt;
-    // three fixed-point boxes (one per component) must fit the LDS of a workgroup
-    const int64_t lds = (int64_t)3 * c.g.box[0] * c.g.box[1] * c.g.box[2] * 8;
-    if (lds > 160 * 1024) { delete ctx; return MLS_E_ARG; }
-    c.spread_blocks_per_cu = std::max(1, std::min(8, (int)((160 * 1024) / (lds + 512))));
-    // tile colours: tiles whose boxes may overlap get different colours.  Along
-    // an axis the colour is the parity of the tile index; an odd number of
-    // periodic tiles gives the last tile a third colour.
-    {
-        int64_t cnt[3][3];
-        for (int d = 0; d < 3; ++d) {
-            const int m = c.g.ntile[d];
-            const bool periodic = c.g.ax[d].periodic != 0;
-            c.g.ncol[d] = m == 1 ? 1 : ((periodic && (m & 1)) ? 3 : 2);
-            if (c.g.ncol[d] == 1) { cnt[0][d] = 1; cnt[1][d] = 0; cnt[2][d] = 0; }
-            else if (c.g.ncol[d] == 2) { cnt[0][d] = (m + 1) / 2; cnt[1][d] = m / 2; cnt[2][d] = 0; }
-            else { cnt[0][d] = (m - 1) / 2; cnt[1][d] = (m - 1) / 2; cnt[2][d] = 1; }
-        }
-        for (int k = 0; k < 3; ++k)
-            for (int d = 0; d < 3; ++d) c.g.ncol_tiles[k][d] = (int32_t)cnt[k][d];
-        int64_t base = 0;
-        for (int cz = 0; cz < c.g.ncol[2]; ++cz)
-            for (int cy = 0; cy < c.g.ncol[1]; ++cy)
-                for (int cx = 0; cx < c.g.ncol[0]; ++cx) {
-                    const int col = cx + c.g.ncol[0] * (cy + c.g.ncol[1] * cz);
-                    c.colour_tiles[col] = cnt[cx][0] * cnt[cy][1] * cnt[cz][2];
-                    c.g.colour_base[col] = base;
-                    base += c.colour_tiles[col];
-                }
-    }
-    // smallest control-volume width within two nodes of each tile, per axis
-    std::vector<float> thmin[3];
-    for (int d = 0; d < 3; ++d) {
-        const Axis &a = c.g.ax[d];
-        thmin[d].resize(c.g.ntile[d]);
-        for (int t = 0; t < c.g.ntile[d]; ++t) {
-            double m = std::numeric_limits<double>::infinity();
-            for (int i = t * a.tile - 3; i <= (t + 1) * a.tile + 3; ++i) {
-                int ic = i, jf = i;
-                if (a.periodic) {
-                    ic = ((i % a.n) + a.n) % a.n;
-                    jf = ic;
-                }
-                if (ic >= 0 && ic < (int)wc[d].size()) m = std::min(m, (double)wc[d][ic]);
-                if (jf >= 0 && jf < (int)wf[d].size()) m = std::min(m, (double)wf[d][jf]);
-            }
-            thmin[d][t] = (float)m;
-        }
-    }
+    const int want_tile = (opts && opts->spread_tile) ? opts->spread_tile : 8;
+    if (want_tile < 4 || want_tile > kMaxBoxTile) { delete ctx; return MLS_E_ARG; }
 
     // ---- weight and options ----
     mls_weight wdef = {MLS_W_GAUSS_SHIFTED, 1.0, 1.5};
@@ -235,15 +280,12 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
         off_wc[d] = take(wc[d].size() * sizeof(float));
         off_wf[d] = take(wf[d].size() * sizeof(float));
     }
-    size_t off_th[3];
-    for (int d = 0; d < 3; ++d) off_th[d] = take(thmin[d].size() * sizeof(float));
     std::vector<unsigned char> blob(bytes, 0);
     for (int d = 0; d < 3; ++d) {
         memcpy(&blob[off_f[d]], c.h_faces[d].data(), c.h_faces[d].size() * sizeof(double));
         memcpy(&blob[off_c[d]], c.h_centres[d].data(), c.h_centres[d].size() * sizeof(double));
         memcpy(&blob[off_wc[d]], wc[d].data(), wc[d].size() * sizeof(float));
         memcpy(&blob[off_wf[d]], wf[d].data(), wf[d].size() * sizeof(float));
-        memcpy(&blob[off_th[d]], thmin[d].data(), thmin[d].size() * sizeof(float));
     }
     e = hipMalloc(&c.geom_block, bytes);
     if (e != hipSuccess) { delete ctx; return MLS_E_NOMEM; }
@@ -256,7 +298,6 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
         a.centres = reinterpret_cast<const double *>(base + off_c[d]);
         a.width_c = reinterpret_cast<const float *>(base + off_wc[d]);
         a.width_f = reinterpret_cast<const float *>(base + off_wf[d]);
-        a.tile_hmin = reinterpret_cast<const float *>(base + off_th[d]);
     }
     if (hipMalloc((void **)&c.d_grid, sizeof(Grid)) != hipSuccess ||
         hipMemcpy(c.d_grid, &c.g, sizeof(Grid), hipMemcpyHostToDevice) != hipSuccess) {
@@ -275,16 +316,12 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
     hipMemset(c.stats, 0, sizeof(DevStats));
     hipMemset(c.work, 0, 128 * sizeof(uint32_t));
     hipMemset(c.step_ctr, 0, sizeof(unsigned long long));
-    const int64_t nb = (nt + 2047) / 2048;
-    if (hipMalloc((void **)&c.block_fmax, (size_t)3 * c.cu_count * 32 * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc((void **)&c.tile_count, nt * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc((void **)&c.tile_off, (nt + 1) * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc((void **)&c.tile_cursor, nt * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc((void **)&c.tile_active, nt * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc((void **)&c.block_sums, (nb + 1) * sizeof(uint32_t)) != hipSuccess) {
+    if (hipMalloc((void **)&c.block_fmax, (size_t)3 * c.cu_count * 32 * sizeof(uint32_t)) != hipSuccess) {
         mls_ctx_destroy(ctx);
         return MLS_E_NOMEM;
     }
+    const mls_status ts = setup_tiles(c, want_tile);
+    if (ts != MLS_OK) { mls_ctx_destroy(ctx); return ts; }
     if (hipDeviceSynchronize() != hipSuccess) { mls_ctx_destroy(ctx); return MLS_E_HIP; }
     *out = ctx;
     return MLS_OK;
@@ -308,6 +345,7 @@ void mls_ctx_destroy(mls_ctx *ctx)
     hipFree(c.block_sums);
     hipFree(c.entries);
     hipFree(c.block_fmax);
+    hipFree(c.tile_hmin_block);
     hipFree(c.work);
     hipFree(c.step_ctr);
     mlp_free(c);

@@ -54,9 +54,77 @@ k_build_exact(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n,
             continue;
         }
         *hout = pack_home(G[0].ih, G[1].ih, G[2].ih);
-        exact_from_geo(g, W, tau, c, l, px, py, pz, G, out, rout, 0, err, routed, kmax);
+        float ph[kNe];
+        exact_from_geo(g, W, tau, c, l, px, py, pz, G, out, rout, 0, err, routed, kmax, ph);
     }
     // one atomic per wavefront for the statistics
+    unsigned long long tot = routed;
+    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+    float km = kmax;
+    for (int off = 32; off > 0; off >>= 1) km = fmaxf(km, __shfl_xor(km, off));
+    if (lane == 0) {
+        if (tot) atomicAdd(&st->fp64_solves, tot);
+        if (km > 0.f) atomicMax(&st->kappa_max_bits, __float_as_uint(km));
+    }
+}
+
+// Exact build fused with the interpolation (eq. 6) and the direct forcing of
+// a time step: after a lane has the shape function of its (marker,
+// component) it gathers the 27 support values of that component's velocity
+// and writes U and F = (V_b - U) / dt next to home and phi, so that phi is not
+// read back.  The FP64 route reads its own stored values back.
+__global__ void __launch_bounds__(kBuildBlock)
+k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n, const float *__restrict__ x,
+               const float *__restrict__ y, const float *__restrict__ z, uint32_t *__restrict__ home,
+               float *__restrict__ phi, uint8_t *__restrict__ route, const float *__restrict__ u,
+               const float *__restrict__ v, const float *__restrict__ w, const float *__restrict__ vb, float inv_dt,
+               float *__restrict__ U, float *__restrict__ F, ErrWord *err, DevStats *st)
+{
+    const Grid &g = *gp;
+    const int wave = wave_id(), lane = threadIdx.x & 63;
+    const int c = wave % 3;
+    const int grp = wave / 3;
+    const int64_t gstride = (int64_t)gridDim.x * kGroups * 64;
+    const float *q = c == 0 ? u : (c == 1 ? v : w);
+    const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
+    unsigned long long routed = 0;
+    float kmax = 0.f;
+    for (int64_t base = ((int64_t)blockIdx.x * kGroups + grp) * 64; base < n; base += gstride) {
+        const int64_t l = base + lane;
+        if (l >= n) continue;
+        float *out = phi + ((((base >> 6) * 3 + c) * kNe) << 6) + lane;
+        uint32_t *hout = home + (((base >> 6) * 3 + c) << 6) + lane;
+        uint8_t *rout = route ? route + (((base >> 6) * 3 + c) << 6) + lane : nullptr;
+        const double px = (double)x[l], py = (double)y[l], pz = (double)z[l];
+        AxisGeo G[3];
+        bool ok = axis_geo(g.ax[0], c == 0, px, G[0]);
+        ok = ok && axis_geo(g.ax[1], c == 1, py, G[1]);
+        ok = ok && axis_geo(g.ax[2], c == 2, pz, G[2]);
+        if (!ok) {
+            mark_failed(err, l, px, py, pz, hout, out, rout);
+            U[c * n + l] = __builtin_nanf("");
+            F[c * n + l] = __builtin_nanf("");
+            continue;
+        }
+        *hout = pack_home(G[0].ih, G[1].ih, G[2].ih);
+        float ph[kNe];
+        if (!exact_from_geo(g, W, tau, c, l, px, py, pz, G, out, rout, 0, err, routed, kmax, ph)) {
+#pragma unroll
+            for (int k = 0; k < kNe; ++k) ph[k] = out[k * kLanes];
+        }
+        int64_t ox[3], oy[3], oz[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            ox[a] = nb_index(G[0].ih, a - 1, nxc, g.ax[0].periodic);
+            oy[a] = (int64_t)nb_index(G[1].ih, a - 1, nyc, g.ax[1].periodic) * nxc;
+            oz[a] = (int64_t)nb_index(G[2].ih, a - 1, nzc, g.ax[2].periodic) * nxc * nyc;
+        }
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < kNe; ++k) acc += ph[k] * q[oz[k / 9] + oy[(k / 3) % 3] + ox[k % 3]];
+        U[c * n + l] = acc;
+        F[c * n + l] = ((vb ? vb[c * n + l] : 0.0f) - acc) * inv_dt;
+    }
     unsigned long long tot = routed;
     for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
     float km = kmax;
@@ -224,10 +292,12 @@ k_table_build(const Weight W, int64_t count, int nsub, const double *__restrict_
     }
 }
 
-int build_grid(int64_t n, int cu)
+// Workgroups of a build launch: one per kGroups x 64 markers, at most
+// blocks_per_cu per compute unit (the rest is covered by the grid stride).
+int build_grid(int64_t n, int cu, int blocks_per_cu)
 {
     int64_t b = (n + kGroups * 64 - 1) / (kGroups * 64);
-    const int64_t cap = (int64_t)cu * 16;
+    const int64_t cap = (int64_t)cu * blocks_per_cu;
     if (b > cap) b = cap;
     return (int)(b < 1 ? 1 : b);
 }
@@ -247,8 +317,20 @@ hipError_t launch_build_exact(const Ctx &c, int64_t n, const float *x, const flo
 {
     if (n == 0) return hipSuccess;
     const float tau = (float)(c.opts.kappa_tau > 3.0e38 ? 3.0e38 : c.opts.kappa_tau);
-    hipLaunchKernelGGL(k_build_exact, dim3(build_grid(n, c.cu_count)), dim3(kBuildBlock), 0, s, c.d_grid, c.w, tau, n,
+    hipLaunchKernelGGL(k_build_exact, dim3(build_grid(n, c.cu_count, c.build_blocks_per_cu)), dim3(kBuildBlock), 0, s, c.d_grid, c.w, tau, n,
                        x, y, z, home, phi, route, c.err, c.stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_interp(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
+                               uint32_t *home, float *phi, uint8_t *route, const float *u, const float *v,
+                               const float *w, const float *vb, float dt, float *U, float *F, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const float tau = (float)(c.opts.kappa_tau > 3.0e38 ? 3.0e38 : c.opts.kappa_tau);
+    hipLaunchKernelGGL(k_build_interp, dim3(build_grid(n, c.cu_count, c.build_blocks_per_cu)), dim3(kBuildBlock), 0,
+                       s, c.d_grid, c.w, tau, n, x, y, z, home, phi, route, u, v, w, vb, 1.0f / dt, U, F, c.err,
+                       c.stats);
     return hipGetLastError();
 }
 
@@ -256,7 +338,7 @@ hipError_t launch_build_fast(const Ctx &c, int64_t n, const float *x, const floa
                              uint32_t *home, float *phi, uint8_t *route, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_build_fast, dim3(build_grid(n, c.cu_count)), dim3(kBuildBlock), 0, s, c.d_grid, fast_tables(c), n,
+    hipLaunchKernelGGL(k_build_fast, dim3(build_grid(n, c.cu_count, c.build_blocks_per_cu)), dim3(kBuildBlock), 0, s, c.d_grid, fast_tables(c), n,
                        x, y, z, home, phi, route, c.err);
     return hipGetLastError();
 }

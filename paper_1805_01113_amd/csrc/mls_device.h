@@ -338,6 +338,12 @@ __device__ __forceinline__ bool home_ok(const Grid &g, int c, int i, int j, int 
     return true;
 }
 
+// Offset of node (i, j, k) in component c's field ([z][y][x], C order).
+__device__ __forceinline__ int64_t field_index(const Grid &g, int c, int i, int j, int k)
+{
+    return ((int64_t)k * g.dims[c][1] + j) * g.dims[c][0] + i;
+}
+
 // Wrapped neighbour index along an axis (periodic) or plain (wall axis: the
 // support check guarantees it is in range).
 __device__ __forceinline__ int nb_index(int i, int a, int n, int periodic)

@@ -56,14 +56,13 @@ __device__ __forceinline__ void mark_failed(ErrWord *err, int64_t l, double px, 
     if (rout) *rout = 0;
 }
 
-// Shape functions of component c from the support geometry G of a located
-// marker (out: the marker's first support node, nodes kLanes floats apart).
-// route_bits is stored with bit 0 set when the solve went to FP64; routed and
-// kmax accumulate the lane's statistics.
-__device__ __forceinline__ void exact_from_geo(const Grid &g, const Weight &W, float tau, int c, int64_t l,
-                                               double px, double py, double pz, const AxisGeo G[3], float *out,
-                                               uint8_t *rout, uint8_t route_bits, ErrWord *err,
-                                               unsigned long long &routed, float &kmax)
+// FP32 exact shape functions of one (marker, component) from its support
+// geometry G: 1-D weights and moments, the 10 moment-matrix entries, Cholesky
+// and the condition bound.  Returns false (ph undefined) when the bound
+// exceeds tau or A is not numerically positive definite: the caller then
+// solves in FP64.  kmax accumulates the largest bound seen.
+__device__ __forceinline__ bool exact_fp32(const Weight &W, float tau, const AxisGeo G[3], float ph[kNe],
+                                           float &kmax)
 {
     float w[3][3];
     Moments<float> m[3];
@@ -82,32 +81,46 @@ __device__ __forceinline__ void exact_from_geo(const Grid &g, const Weight &W, f
     }
     float A[10], L[10], gam[4];
     assemble(m[0], m[1], m[2], A);
-    bool fp32_ok = cholesky4(A, L);
-    if (fp32_ok) {
+    bool ok = cholesky4(A, L);
+    if (ok) {
         const float kap = cond_bound_and_gamma(A, L, gam);
-        fp32_ok = kap <= tau && isfinite(kap);
+        ok = kap <= tau && isfinite(kap);
         kmax = fmaxf(kmax, isfinite(kap) ? kap : 3.0e38f);
     }
-    if (fp32_ok) {
+    if (!ok) return false;
 #pragma unroll
-        for (int cz = 0; cz < 3; ++cz) {
+    for (int cz = 0; cz < 3; ++cz) {
 #pragma unroll
-            for (int by = 0; by < 3; ++by) {
-                const float wyz = w[1][by] * w[2][cz];
-                const float pyz = gam[0] + gam[2] * G[1].s[by] + gam[3] * G[2].s[cz];
+        for (int by = 0; by < 3; ++by) {
+            const float wyz = w[1][by] * w[2][cz];
+            const float pyz = gam[0] + gam[2] * G[1].s[by] + gam[3] * G[2].s[cz];
 #pragma unroll
-                for (int ax = 0; ax < 3; ++ax) {
-                    const int k = ax + 3 * by + 9 * cz;
-                    out[k * kLanes] = w[0][ax] * wyz * (pyz + gam[1] * G[0].s[ax]);
-                }
-            }
+            for (int ax = 0; ax < 3; ++ax) ph[ax + 3 * by + 9 * cz] = w[0][ax] * wyz * (pyz + gam[1] * G[0].s[ax]);
         }
-        if (rout) *rout = route_bits;
-    } else {
-        ++routed;
-        if (!solve_fp64(g, W, c, px, py, pz, out)) raise_error(err, l, MLS_E_SINGULAR);
-        if (rout) *rout = route_bits | 1;
     }
+    return true;
+}
+
+// Shape functions of component c from the support geometry G of a located
+// marker, stored at out (the marker's first support node, nodes kLanes floats
+// apart).  route_bits is stored with bit 0 set when the solve went to FP64;
+// routed and kmax accumulate the lane's statistics.  Returns true if the FP32
+// solve was used (then ph holds the values).
+__device__ __forceinline__ bool exact_from_geo(const Grid &g, const Weight &W, float tau, int c, int64_t l,
+                                               double px, double py, double pz, const AxisGeo G[3], float *out,
+                                               uint8_t *rout, uint8_t route_bits, ErrWord *err,
+                                               unsigned long long &routed, float &kmax, float ph[kNe])
+{
+    if (exact_fp32(W, tau, G, ph, kmax)) {
+#pragma unroll
+        for (int k = 0; k < kNe; ++k) out[k * kLanes] = ph[k];
+        if (rout) *rout = route_bits;
+        return true;
+    }
+    ++routed;
+    if (!solve_fp64(g, W, c, px, py, pz, out)) raise_error(err, l, MLS_E_SINGULAR);
+    if (rout) *rout = route_bits | 1;
+    return false;
 }
 
 }  // namespace mls

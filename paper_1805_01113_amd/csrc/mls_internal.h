@@ -127,6 +127,7 @@ struct Ctx {
     mls_opts opts{};
     std::vector<double> h_faces[3];
     std::vector<double> h_centres[3];
+    std::vector<float> h_wc[3], h_wf[3];   // control-volume widths of centre / face nodes
     std::string last_error;
     // device allocations owned by the context
     void *geom_block = nullptr;   // faces, centres, widths
@@ -150,7 +151,12 @@ struct Ctx {
     uint32_t *work = nullptr;          // [0..26] active-list sizes per colour, [32..58] cursors,
                                        // [64..66] max |A F| per component (FP32 bits)
     int64_t colour_tiles[27] = {};   // tiles of each colour
-    int spread_blocks_per_cu = 8;
+    float *tile_hmin_block = nullptr;  // per-tile smallest control-volume width (all axes)
+    // launch shapes (autotuned): resident workgroups per compute unit
+    int spread_blocks_per_cu = 8;      // effective (bounded by the LDS of the tile boxes)
+    int spread_blocks_per_cu_req = 8;  // requested
+    int build_blocks_per_cu = 16;
+    int interp_blocks_per_cu = 32;
     int cu_count = 256;
     // learned surrogate
     Mlp mlp;
@@ -181,6 +187,9 @@ hipError_t launch_build_exact(const Ctx &c, int64_t n, const float *x, const flo
                               uint32_t *home, float *phi, uint8_t *route, hipStream_t s);
 hipError_t launch_build_fast(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
                              uint32_t *home, float *phi, uint8_t *route, hipStream_t s);
+hipError_t launch_build_interp(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
+                               uint32_t *home, float *phi, uint8_t *route, const float *u, const float *v,
+                               const float *w, const float *vb, float dt, float *U, float *F, hipStream_t s);
 hipError_t launch_build_learned(Ctx &c, int64_t n, const float *x, const float *y, const float *z,
                                 uint32_t *home, float *phi, uint8_t *route, hipStream_t s);
 hipError_t launch_table_build(const Ctx &c, hipStream_t s);
@@ -198,6 +207,9 @@ hipError_t launch_force(const Ctx &c, int64_t n, const float *vb, const float *U
 hipError_t launch_step_advance(const Ctx &c, hipStream_t s);
 
 FastTables fast_tables(const Ctx &c);
+
+// (Re)cut the spreading tiles for edge `want` (see mls_ctx_create).
+mls_status setup_tiles(Ctx &c, int want);
 
 // learned surrogate (training and feature kernels)
 hipError_t mlp_alloc(Ctx &c);

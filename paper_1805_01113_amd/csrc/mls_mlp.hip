@@ -520,8 +520,9 @@ k_build_learned(const Grid *__restrict__ gp, const Weight W, float tau, float to
             axis_geo(g.ax[0], c == 0, px, G[0]);
             axis_geo(g.ax[1], c == 1, py, G[1]);
             axis_geo(g.ax[2], c == 2, pz, G[2]);
+            float ph[kNe];
             exact_from_geo(g, W, tau, c, l, px, py, pz, G, out + lane, rout ? rout + lane : nullptr, 4, err, routed,
-                           kmax);
+                           kmax, ph);
         }
     }
     unsigned long long tot = routed;

@@ -145,11 +145,27 @@ mls_status mls_step(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buff
         if (e != hipSuccess) return MLS_E_HIP;
         bx = b->x; by = b->y; bz = b->z;
     }
-    mls_status st = mls_build(ctx, n, bx, by, bz, desc->method, b->home, b->phi, b->route, stream);
+    mls_status st = MLS_OK;
+    hipError_t e;
+    if (desc->method == MLS_EXACT) {
+        // exact MLS: the build writes U and F as well, so phi is not read
+        // back for the interpolation
+        st = mls_reserve(ctx, n);
+        if (st != MLS_OK) return st;
+        {
+            TimedLaunch t(c, MLS_K_BUILD_INTERP, s);
+            e = launch_build_interp(c, n, bx, by, bz, b->home, b->phi, b->route, b->u, b->v, b->w, b->vb, desc->dt,
+                                    b->U, b->F, s);
+        }
+        if (e != hipSuccess) return MLS_E_HIP;
+        e = launch_spread(c, n, b->home, b->phi, b->area, b->F, b->F + n, b->F + 2 * n, b->fx, b->fy, b->fz, s);
+        if (e != hipSuccess) return MLS_E_HIP;
+        return launch_step_advance(c, s) == hipSuccess ? MLS_OK : MLS_E_HIP;
+    }
+    st = mls_build(ctx, n, bx, by, bz, desc->method, b->home, b->phi, b->route, stream);
     if (st != MLS_OK) return st;
     st = mls_interp(ctx, n, b->home, b->phi, b->u, b->v, b->w, b->U, b->U + n, b->U + 2 * n, stream);
     if (st != MLS_OK) return st;
-    hipError_t e;
     {
         TimedLaunch t(c, MLS_K_FORCE, s);
         e = launch_force(c, n, b->vb, b->U, desc->dt, b->F, s);

@@ -22,11 +22,6 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__device__ __forceinline__ int64_t field_index(const Grid &g, int c, int i, int j, int k)
-{
-    return ((int64_t)k * g.dims[c][1] + j) * g.dims[c][0] + i;
-}
-
 __global__ void __launch_bounds__(kBlock)
 k_interp(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home, const float *__restrict__ phi,
          const float *__restrict__ u, const float *__restrict__ v, const float *__restrict__ w,
@@ -388,8 +383,11 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
             for (int c = 0; c < 3; ++c) {
                 const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
                 int hi, hj, hk;
+                float ph[kNe];
                 unpack_home(home[home_at(m, c)], hi, hj, hk);
                 const float *p = phi + phi_at(m, c);
+#pragma unroll
+                for (int k = 0; k < kNe; ++k) ph[k] = p[k * kLanes];
                 int ix[3], iy[3], iz[3];
                 float wx[3], wy[3], wz[3];
                 bool inbox = true;
@@ -411,12 +409,10 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                     range_ok = false;
                     continue;
                 }
-                float ph[kNe];
                 float hl = 0.f, den = 0.f;
 #pragma unroll
                 for (int k = 0; k < kNe; ++k) {
                     const int a = k % 3, b = (k / 3) % 3, cz = k / 9;
-                    ph[k] = p[k * kLanes];
                     hl += ph[k] * (wx[a] + wy[b] + wz[cz]);
                     den += ph[k] * (wx[a] * wy[b] * wz[cz]);
                 }
@@ -490,7 +486,9 @@ hipError_t launch_interp(const Ctx &c, int64_t n, const uint32_t *home, const fl
                          float *U, float *V, float *W, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_interp, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, home, phi,
+    int64_t blocks = (n + kBlock - 1) / kBlock;
+    blocks = std::min(blocks, (int64_t)c.cu_count * c.interp_blocks_per_cu);
+    hipLaunchKernelGGL(k_interp, dim3((unsigned)blocks), dim3(kBlock), 0, s, c.d_grid, n, home, phi,
                        u, v, w, U, V, W, c.err);
     return hipGetLastError();
 }

@@ -63,7 +63,18 @@ class _StepBuf(ctypes.Structure):
 
 MLP_PARAMS = 20891   # 6*128 + 128 + 128*128 + 128 + 128*27 + 27
 
-K_NAMES = ["build_exact", "build_fast", "build_learned", "interp", "spread_bin", "spread_tiles", "jitter", "force"]
+class _Tune(ctypes.Structure):
+    _fields_ = [("spread_tile", ctypes.c_int32), ("spread_blocks_per_cu", ctypes.c_int32),
+                ("build_blocks_per_cu", ctypes.c_int32), ("interp_blocks_per_cu", ctypes.c_int32)]
+
+
+class _TuneReport(ctypes.Structure):
+    _fields_ = [("best", _Tune), ("ms_build", ctypes.c_double), ("ms_interp", ctypes.c_double),
+                ("ms_spread", ctypes.c_double), ("from_cache", ctypes.c_int32), ("candidates", ctypes.c_int32)]
+
+
+K_NAMES = ["build_exact", "build_fast", "build_learned", "interp", "spread_bin", "spread_tiles", "jitter", "force",
+           "build_interp"]
 
 
 class _Timing(ctypes.Structure):
@@ -106,13 +117,16 @@ def load(path: str = LIB_PATH, need_torch: bool = True):
     L.mls_graph_destroy.restype = None
     L.mls_timing_enable.argtypes = [P, I32]
     L.mls_timing_get.argtypes = [P, ctypes.POINTER(_Timing), I32]
+    L.mls_tune_get.argtypes = [P, ctypes.POINTER(_Tune)]
+    L.mls_tune_set.argtypes = [P, ctypes.POINTER(_Tune)]
+    L.mls_autotune.argtypes = [P, I32, ctypes.POINTER(_StepBuf), ctypes.c_char_p, ctypes.POINTER(_TuneReport), P]
     L.mls_mlp_load.argtypes = [P, P, P]
     L.mls_mlp_get.argtypes = [P, P, P]
     L.mls_features.argtypes = [P, I64, P, P, P, P, P]
     L.mls_mlp_forward.argtypes = [P, I64, P, I64, P, P, P]
     L.mls_mlp_grad.argtypes = [P, I64, P, P, I64, P, ctypes.c_float, P, P, P]
     L.mls_mlp_train_step.argtypes = [P, I64, P, P, I64, P, ctypes.c_float, ctypes.c_float, P, P]
-    for name in ("mls_mlp_load", "mls_mlp_get", "mls_features", "mls_mlp_forward", "mls_mlp_grad",
+    for name in ("mls_tune_get", "mls_tune_set", "mls_autotune", "mls_mlp_load", "mls_mlp_get", "mls_features", "mls_mlp_forward", "mls_mlp_grad",
                  "mls_mlp_train_step","mls_ctx_create", "mls_reserve", "mls_build", "mls_interp", "mls_spread", "mls_sync",
                  "mls_stats_get", "mls_stats_reset", "mls_fast_tables", "mls_step", "mls_step_counter_set",
                  "mls_graph_create", "mls_graph_launch", "mls_timing_enable", "mls_timing_get"):
@@ -160,6 +174,7 @@ class Context:
         w = _Weight(kind, eps, radius)
         o = _Opts(kappa_tau, n_sub, fallback_tol, spread_tile)
         self.n_sub = n_sub
+        self.mlp_loaded = False
         h = ctypes.c_void_p()
         st = L.mls_ctx_create(ctypes.byref(h), ctypes.byref(g), ctypes.byref(w), ctypes.byref(o))
         if st != 0:
@@ -279,6 +294,31 @@ class Context:
         self._raise(st, "mls_fast_tables")
         return buf[:, :, :27], (first[0], first[1]), ax.value
 
+    # ---- launch shapes ---------------------------------------------------------
+    def tune_get(self):
+        t = _Tune()
+        self._raise(self._lib.mls_tune_get(self.h, ctypes.byref(t)), "mls_tune_get")
+        return {k: getattr(t, k) for k, _ in _Tune._fields_}
+
+    def tune_set(self, **shape):
+        cur = self.tune_get()
+        cur.update(shape)
+        t = _Tune(**cur)
+        self._raise(self._lib.mls_tune_set(self.h, ctypes.byref(t)), "mls_tune_set")
+
+    def autotune(self, bufs: "StepBuffers", method=MLS_EXACT, cache_path=None, stream=None):
+        """Time launch shapes on the step buffers and apply the fastest
+        (mls_autotune); returns the report as a dict."""
+        r = _TuneReport()
+        b = bufs.struct()
+        cp = None if cache_path is None else os.fsencode(cache_path)
+        self._raise(self._lib.mls_autotune(self.h, int(method), ctypes.byref(b), cp, ctypes.byref(r),
+                                           _stream(stream)), "mls_autotune")
+        out = {k: getattr(r.best, k) for k, _ in _Tune._fields_}
+        out.update(ms_build=r.ms_build, ms_interp=r.ms_interp, ms_spread=r.ms_spread,
+                   from_cache=bool(r.from_cache), candidates=r.candidates)
+        return out
+
     # ---- learned surrogate ---------------------------------------------------
     def mlp_load(self, params: np.ndarray, norm: np.ndarray):
         """Load the network (MLP_PARAMS FP32 parameters, norm = shift[6], scale[6])."""
@@ -287,6 +327,7 @@ class Context:
         if p.size != MLP_PARAMS or q.size != 12:
             raise ValueError("need %d parameters and 12 normalisation values" % MLP_PARAMS)
         self._raise(self._lib.mls_mlp_load(self.h, p.ctypes.data, q.ctypes.data), "mls_mlp_load")
+        self.mlp_loaded = True
 
     def mlp_get(self):
         p = np.empty(MLP_PARAMS, dtype=np.float32)

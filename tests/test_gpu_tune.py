@@ -1,0 +1,85 @@
+"""GPU tests of the launch-shape autotuner: a first call times candidates and
+writes the cache, a second call applies the cached shapes without timing,
+and the transfer stays within 1e-5 of the oracle under every spreading tile
+edge the grid allows (re-cut in place)."""
+import numpy as np
+import pytest
+
+from parity import F_TOL, PHI_TOL, normwise, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1805_01113_amd import mls
+    mls.load()
+    return torch
+
+
+def _spread_vs_oracle(orc, torch, ctx, gs, x, y, z, area, F, label):
+    from paper_1805_01113_amd import mls
+    n = len(x)
+    home, phi, _ = ctx.build(to_dev(x), to_dev(y), to_dev(z), method=mls.MLS_EXACT)
+    fo = [torch.zeros(gs.shape(c), dtype=torch.float32, device="cuda") for c in range(3)]
+    ctx.spread(home, phi, to_dev(area), to_dev(F), fo)
+    ctx.sync()
+    g = orc.Grid(gs.faces, gs.periodic)
+    p = mls.unpack_phi(phi.cpu().numpy(), n)
+    errs = []
+    for c in range(3):
+        ref = orc.build_exact(g, c, x, y, z)
+        assert normwise(p[c], ref["phi"]) <= PHI_TOL
+        fref, _ = orc.spread(g, c, ref["home"], ref["phi"], area, F[c])
+        errs.append(normwise(fo[c].cpu().numpy(), fref))
+    say("%s spread normwise rel err %s" % (label, ["%.2e" % e for e in errs]))
+    assert max(errs) <= F_TOL
+
+
+def test_autotune_then_cache(orc, torch_cuda, tmp_path):
+    from paper_1805_01113_amd import mls
+    from paper_1805_01113_amd import workloads as W
+    torch = torch_cuda
+    wl = W.single_sphere(n=64, subdiv=4)
+    ctx = mls.Context(wl.grid.faces, wl.grid.periodic)
+    x0, y0, z0, area = [torch.from_numpy(a).cuda() for a in (wl.x, wl.y, wl.z, wl.area)]
+    fields = wl.fields("cuda")
+    forcing = [torch.zeros(wl.grid.shape(c), dtype=torch.float32, device="cuda") for c in range(3)]
+    bufs = mls.StepBuffers(ctx, x0, y0, z0, area, fields, forcing)
+    cache = str(tmp_path / "tune.jsonl")
+    r1 = ctx.autotune(bufs, method=mls.MLS_EXACT, cache_path=cache)
+    say("autotune: %s" % r1)
+    assert not r1["from_cache"] and r1["candidates"] >= 8
+    assert 4 <= r1["spread_tile"] <= 12
+    assert ctx.tune_get()["spread_tile"] == r1["spread_tile"]
+    with open(cache) as f:
+        assert len(f.read().strip().splitlines()) == 1
+    r2 = ctx.autotune(bufs, method=mls.MLS_EXACT, cache_path=cache)
+    assert r2["from_cache"] and r2["candidates"] == 0
+    for k in ("spread_tile", "spread_blocks_per_cu", "build_blocks_per_cu", "interp_blocks_per_cu"):
+        assert r2[k] == r1[k]
+    # the tuned context still computes the transfer of the oracle
+    _spread_vs_oracle(orc, torch, ctx, wl.grid, wl.x, wl.y, wl.z, wl.area, wl.force, "tuned")
+
+
+def test_every_tile_edge_matches_oracle(orc, torch_cuda):
+    from paper_1805_01113_amd import mls
+    from paper_1805_01113_amd import workloads as W
+    gs = W.GridSpec([W.uniform_faces(48), W.uniform_faces(48), W.uniform_faces(48)], [True, True, True])
+    r = np.random.default_rng(5)
+    n = 4000
+    x, y, z = [r.uniform(0, 1, n).astype(np.float32) for _ in range(3)]
+    area = r.uniform(0.5, 1.5, n).astype(np.float32) / 48 ** 2
+    F = r.normal(size=(3, n)).astype(np.float32)
+    ctx = mls.Context(gs.faces, gs.periodic)
+    for tile in (4, 6, 8, 12):
+        ctx.tune_set(spread_tile=tile, spread_blocks_per_cu=4)
+        assert ctx.tune_get()["spread_tile"] == tile
+        _spread_vs_oracle(orc, torch_cuda, ctx, gs, x, y, z, area, F, "tile %d" % tile)
+    with pytest.raises(mls.MLSError):
+        ctx.tune_set(spread_tile=13)
+    with pytest.raises(mls.MLSError):
+        ctx.tune_set(build_blocks_per_cu=0)
+    assert ctx.tune_get()["spread_tile"] == 12

@@ -232,9 +232,14 @@ mls_status mls_fast_tables(mls_ctx *ctx, float *dst, int64_t *count, int32_t *ro
  *   force    F = (V_b - U) / dt, the direct forcing of Sec. 2 (V_b = 0 if NULL);
  *   spread   f += c_l phi F (eq. 7-8);
  * and then increments the context's device step counter, which the jitter
- * of the next step reads.  With MLS_EXACT the build, interpolation and
- * forcing run as one kernel (the interpolation uses the shape functions in
- * registers, phi is not read back); home, phi, U and F are written as above.  All buffers are caller-owned device arrays:
+ * of the next step reads.  With MLS_EXACT the step works in spreading-tile
+ * order: markers are binned by the tile of their cell, the build,
+ * interpolation and forcing run as one kernel (phi is not read back), and row
+ * p of the blocked home / phi / route layout holds marker order[p] (see
+ * mls_step_order), so that the tiles read their rows contiguously; U and F
+ * stay indexed by marker.  Markers whose support leaves the grid come last.
+ * The order of the markers inside a tile may differ between runs; U, F and
+ * the forcing do not.  With MLS_FAST and MLS_LEARNED rows are in marker order.  All buffers are caller-owned device arrays:
  * x0,y0,z0 [n] (read), x,y,z [n] (written by jitter), area [n], vb [3][n] or
  * NULL, home, phi and route (or NULL) in the blocked layout above, U [3][n], F [3][n],
  * the velocity fields u,v,w and the forcing fields fx,fy,fz. */
@@ -262,6 +267,11 @@ typedef struct {
 
 /* Enqueue one step.  Reserves scratch on first use for n markers. */
 mls_status mls_step(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buffers *buf, void *stream);
+
+/* Copy the row order of the last MLS_EXACT step of n markers into order
+ * (device, n uint32): row p of its home / phi / route holds marker order[p].
+ * MLS_E_ARG if the last exact step had a different marker count. */
+mls_status mls_step_order(mls_ctx *ctx, uint32_t *order, int64_t n, void *stream);
 
 /* Set the device step counter read by the jitter (enqueued on stream). */
 mls_status mls_step_counter_set(mls_ctx *ctx, uint64_t step, void *stream);

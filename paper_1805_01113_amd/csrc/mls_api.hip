@@ -126,13 +126,15 @@ mls_status mls::setup_tiles(Ctx &c, int want)
         }
     }
     // device scratch for the new tiling
-    const int64_t nb = (nt + 2047) / 2048;
+    // one extra bucket (index nt) collects markers without a valid support
+    // when the step bins markers from their positions
+    const int64_t nb = (nt + 1 + 2047) / 2048;
     float *th = nullptr;
     uint32_t *tcount = nullptr, *toff = nullptr, *tcur = nullptr, *tact = nullptr, *bsum = nullptr;
     bool ok = hipMalloc((void **)&th, thmin.size() * sizeof(float)) == hipSuccess &&
-              hipMalloc((void **)&tcount, nt * sizeof(uint32_t)) == hipSuccess &&
-              hipMalloc((void **)&toff, (nt + 1) * sizeof(uint32_t)) == hipSuccess &&
-              hipMalloc((void **)&tcur, nt * sizeof(uint32_t)) == hipSuccess &&
+              hipMalloc((void **)&tcount, (nt + 1) * sizeof(uint32_t)) == hipSuccess &&
+              hipMalloc((void **)&toff, (nt + 2) * sizeof(uint32_t)) == hipSuccess &&
+              hipMalloc((void **)&tcur, (nt + 1) * sizeof(uint32_t)) == hipSuccess &&
               hipMalloc((void **)&tact, nt * sizeof(uint32_t)) == hipSuccess &&
               hipMalloc((void **)&bsum, (nb + 1) * sizeof(uint32_t)) == hipSuccess;
     ok = ok && hipMemcpy(th, thmin.data(), thmin.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
@@ -316,7 +318,7 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
     hipMemset(c.stats, 0, sizeof(DevStats));
     hipMemset(c.work, 0, 128 * sizeof(uint32_t));
     hipMemset(c.step_ctr, 0, sizeof(unsigned long long));
-    if (hipMalloc((void **)&c.block_fmax, (size_t)3 * c.cu_count * 32 * sizeof(uint32_t)) != hipSuccess) {
+    if (hipMalloc((void **)&c.block_fmax, (size_t)3 * c.cu_count * kMaxBlocksPerCu * sizeof(uint32_t)) != hipSuccess) {
         mls_ctx_destroy(ctx);
         return MLS_E_NOMEM;
     }

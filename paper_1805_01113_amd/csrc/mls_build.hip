@@ -37,14 +37,24 @@ k_build_exact(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n,
     const int64_t gstride = (int64_t)gridDim.x * kGroups * 64;
     unsigned long long routed = 0;
     float kmax = 0.f;
-    for (int64_t base = ((int64_t)blockIdx.x * kGroups + grp) * 64; base < n; base += gstride) {
+    // the next item's coordinates are loaded one iteration ahead
+    int64_t base = ((int64_t)blockIdx.x * kGroups + grp) * 64;
+    float nx = 0.f, ny = 0.f, nz = 0.f;
+    if (base + lane < n) { nx = x[base + lane]; ny = y[base + lane]; nz = z[base + lane]; }
+    for (; base < n; base += gstride) {
         const int64_t l = base + lane;
+        const float cx = nx, cy = ny, cz = nz;
+        if (base + gstride + lane < n) {
+            nx = x[base + gstride + lane];
+            ny = y[base + gstride + lane];
+            nz = z[base + gstride + lane];
+        }
         if (l >= n) continue;
         // this wavefront's contiguous slice of the outputs (wave-uniform base)
         float *out = phi + ((((base >> 6) * 3 + c) * kNe) << 6) + lane;
         uint32_t *hout = home + (((base >> 6) * 3 + c) << 6) + lane;
         uint8_t *rout = route ? route + (((base >> 6) * 3 + c) << 6) + lane : nullptr;
-        const double px = (double)x[l], py = (double)y[l], pz = (double)z[l];
+        const double px = (double)cx, py = (double)cy, pz = (double)cz;
         AxisGeo G[3];
         bool ok = axis_geo(g.ax[0], c == 0, px, G[0]);
         ok = ok && axis_geo(g.ax[1], c == 1, py, G[1]);
@@ -69,16 +79,20 @@ k_build_exact(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n,
 }
 
 // Exact build fused with the interpolation (eq. 6) and the direct forcing of
-// a time step: after a lane has the shape function of its (marker,
-// component) it gathers the 27 support values of that component's velocity
-// and writes U and F = (V_b - U) / dt next to home and phi, so that phi is not
-// read back.  The FP64 route reads its own stored values back.
+// a time step, over the markers in spreading-tile order: row p of the
+// blocked home / phi / route layout belongs to marker m = order[p].  After a
+// lane has the shape function of its (marker, component) it gathers the 27
+// support values of that component's velocity and writes U[c][m] and
+// F[c][m] = (V_b - U) / dt, so phi is not read back (the FP64 route reads its
+// own stored values).  Each workgroup also records max |A_m F_m| per component
+// in block_fmax[3 blockIdx + c], the scale of the spreading sums.
 __global__ void __launch_bounds__(kBuildBlock)
-k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n, const float *__restrict__ x,
-               const float *__restrict__ y, const float *__restrict__ z, uint32_t *__restrict__ home,
-               float *__restrict__ phi, uint8_t *__restrict__ route, const float *__restrict__ u,
-               const float *__restrict__ v, const float *__restrict__ w, const float *__restrict__ vb, float inv_dt,
-               float *__restrict__ U, float *__restrict__ F, ErrWord *err, DevStats *st)
+k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n, const uint32_t *__restrict__ order,
+               const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
+               uint32_t *__restrict__ home, float *__restrict__ phi, uint8_t *__restrict__ route,
+               const float *__restrict__ u, const float *__restrict__ v, const float *__restrict__ w,
+               const float *__restrict__ vb, const float *__restrict__ area, float inv_dt, float *__restrict__ U,
+               float *__restrict__ F, uint32_t *__restrict__ block_fmax, ErrWord *err, DevStats *st)
 {
     const Grid &g = *gp;
     const int wave = wave_id(), lane = threadIdx.x & 63;
@@ -88,30 +102,41 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
     const float *q = c == 0 ? u : (c == 1 ? v : w);
     const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
     unsigned long long routed = 0;
-    float kmax = 0.f;
-    for (int64_t base = ((int64_t)blockIdx.x * kGroups + grp) * 64; base < n; base += gstride) {
-        const int64_t l = base + lane;
-        if (l >= n) continue;
+    float kmax = 0.f, fmx = 0.f;
+    // the next item's marker and coordinates are loaded one iteration ahead
+    int64_t base = ((int64_t)blockIdx.x * kGroups + grp) * 64;
+    uint32_t nm = 0;
+    float nx = 0.f, ny = 0.f, nz = 0.f;
+    if (base + lane < n) {
+        nm = order[base + lane];
+        nx = x[nm]; ny = y[nm]; nz = z[nm];
+    }
+    for (; base < n; base += gstride) {
+        const int64_t p = base + lane;
+        const int64_t m = nm;
+        const float cx = nx, cy = ny, cz = nz;
+        if (base + gstride + lane < n) {
+            nm = order[base + gstride + lane];
+            nx = x[nm]; ny = y[nm]; nz = z[nm];
+        }
+        if (p >= n) continue;
         float *out = phi + ((((base >> 6) * 3 + c) * kNe) << 6) + lane;
         uint32_t *hout = home + (((base >> 6) * 3 + c) << 6) + lane;
         uint8_t *rout = route ? route + (((base >> 6) * 3 + c) << 6) + lane : nullptr;
-        const double px = (double)x[l], py = (double)y[l], pz = (double)z[l];
+        const double px = (double)cx, py = (double)cy, pz = (double)cz;
         AxisGeo G[3];
         bool ok = axis_geo(g.ax[0], c == 0, px, G[0]);
         ok = ok && axis_geo(g.ax[1], c == 1, py, G[1]);
         ok = ok && axis_geo(g.ax[2], c == 2, pz, G[2]);
         if (!ok) {
-            mark_failed(err, l, px, py, pz, hout, out, rout);
-            U[c * n + l] = __builtin_nanf("");
-            F[c * n + l] = __builtin_nanf("");
+            mark_failed(err, m, px, py, pz, hout, out, rout);
+            U[c * n + m] = __builtin_nanf("");
+            F[c * n + m] = __builtin_nanf("");
             continue;
         }
         *hout = pack_home(G[0].ih, G[1].ih, G[2].ih);
-        float ph[kNe];
-        if (!exact_from_geo(g, W, tau, c, l, px, py, pz, G, out, rout, 0, err, routed, kmax, ph)) {
-#pragma unroll
-            for (int k = 0; k < kNe; ++k) ph[k] = out[k * kLanes];
-        }
+        // the 27 field values are requested before the solve, which hides
+        // their latency
         int64_t ox[3], oy[3], oz[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -119,19 +144,40 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
             oy[a] = (int64_t)nb_index(G[1].ih, a - 1, nyc, g.ax[1].periodic) * nxc;
             oz[a] = (int64_t)nb_index(G[2].ih, a - 1, nzc, g.ax[2].periodic) * nxc * nyc;
         }
+        float qv[kNe];
+#pragma unroll
+        for (int k = 0; k < kNe; ++k) qv[k] = q[oz[k / 9] + oy[(k / 3) % 3] + ox[k % 3]];
+        float ph[kNe];
+        if (!exact_from_geo(g, W, tau, c, m, px, py, pz, G, out, rout, 0, err, routed, kmax, ph)) {
+#pragma unroll
+            for (int k = 0; k < kNe; ++k) ph[k] = out[k * kLanes];
+        }
         float acc = 0.f;
 #pragma unroll
-        for (int k = 0; k < kNe; ++k) acc += ph[k] * q[oz[k / 9] + oy[(k / 3) % 3] + ox[k % 3]];
-        U[c * n + l] = acc;
-        F[c * n + l] = ((vb ? vb[c * n + l] : 0.0f) - acc) * inv_dt;
+        for (int k = 0; k < kNe; ++k) acc += ph[k] * qv[k];
+        const float f = ((vb ? vb[c * n + m] : 0.0f) - acc) * inv_dt;
+        U[c * n + m] = acc;
+        F[c * n + m] = f;
+        const float af = fabsf(area[m]) * fabsf(f);
+        if (!(af <= 3.0e38f)) raise_error(err, m, MLS_E_RANGE);   // non-finite force (NaN fails too)
+        else fmx = fmaxf(fmx, af);
     }
     unsigned long long tot = routed;
     for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
     float km = kmax;
     for (int off = 32; off > 0; off >>= 1) km = fmaxf(km, __shfl_xor(km, off));
+    for (int off = 32; off > 0; off >>= 1) fmx = fmaxf(fmx, __shfl_xor(fmx, off));
+    __shared__ float bm[kBuildBlock / 64];
     if (lane == 0) {
         if (tot) atomicAdd(&st->fp64_solves, tot);
         if (km > 0.f) atomicMax(&st->kappa_max_bits, __float_as_uint(km));
+        bm[wave] = fmx;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        float v = 0.f;
+        for (int q2 = threadIdx.x; q2 < kBuildBlock / 64; q2 += 3) v = fmaxf(v, bm[q2]);
+        block_fmax[3 * blockIdx.x + threadIdx.x] = __float_as_uint(v);
     }
 }
 
@@ -215,13 +261,23 @@ k_build_fast(const Grid *__restrict__ gp, const FastTables T, int64_t n,
     const int grp = wave / 3;
     const int64_t gstride = (int64_t)gridDim.x * kGroups * 64;
     const int64_t rows = (int64_t)T.n_sub * T.n_sub * T.n_sub;
-    for (int64_t base = ((int64_t)blockIdx.x * kGroups + grp) * 64; base < n; base += gstride) {
+    // the next item's coordinates are loaded one iteration ahead
+    int64_t base = ((int64_t)blockIdx.x * kGroups + grp) * 64;
+    float nx = 0.f, ny = 0.f, nz = 0.f;
+    if (base + lane < n) { nx = x[base + lane]; ny = y[base + lane]; nz = z[base + lane]; }
+    for (; base < n; base += gstride) {
         const int64_t l = base + lane;
+        const float cx = nx, cy = ny, cz = nz;
+        if (base + gstride + lane < n) {
+            nx = x[base + gstride + lane];
+            ny = y[base + gstride + lane];
+            nz = z[base + gstride + lane];
+        }
         if (l >= n) continue;
         float *out = phi + ((((base >> 6) * 3 + c) * kNe) << 6) + lane;
         uint32_t *hout = home + (((base >> 6) * 3 + c) << 6) + lane;
         uint8_t *rout = route ? route + (((base >> 6) * 3 + c) << 6) + lane : nullptr;
-        const double px = (double)x[l], py = (double)y[l], pz = (double)z[l];
+        const double px = (double)cx, py = (double)cy, pz = (double)cz;
         AxisGeo G[3];
         bool ok = axis_geo(g.ax[0], c == 0, px, G[0]);
         ok = ok && axis_geo(g.ax[1], c == 1, py, G[1]);
@@ -302,6 +358,12 @@ int build_grid(int64_t n, int cu, int blocks_per_cu)
     return (int)(b < 1 ? 1 : b);
 }
 
+}  // namespace
+
+int build_blocks(const Ctx &c, int64_t n) { return build_grid(n, c.cu_count, c.build_blocks_per_cu); }
+
+namespace {
+
 int grid_for(int64_t work, int cu)
 {
     int64_t b = (work + kBlock - 1) / kBlock;
@@ -324,13 +386,14 @@ hipError_t launch_build_exact(const Ctx &c, int64_t n, const float *x, const flo
 
 hipError_t launch_build_interp(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
                                uint32_t *home, float *phi, uint8_t *route, const float *u, const float *v,
-                               const float *w, const float *vb, float dt, float *U, float *F, hipStream_t s)
+                               const float *w, const float *vb, const float *area, float dt, float *U, float *F,
+                               hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const float tau = (float)(c.opts.kappa_tau > 3.0e38 ? 3.0e38 : c.opts.kappa_tau);
     hipLaunchKernelGGL(k_build_interp, dim3(build_grid(n, c.cu_count, c.build_blocks_per_cu)), dim3(kBuildBlock), 0,
-                       s, c.d_grid, c.w, tau, n, x, y, z, home, phi, route, u, v, w, vb, 1.0f / dt, U, F, c.err,
-                       c.stats);
+                       s, c.d_grid, c.w, tau, n, c.entries, x, y, z, home, phi, route, u, v, w, vb, area, 1.0f / dt,
+                       U, F, c.block_fmax, c.err, c.stats);
     return hipGetLastError();
 }
 

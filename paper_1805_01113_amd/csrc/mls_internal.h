@@ -19,6 +19,7 @@ constexpr int kNe = 27;           // 3x3x3 support nodes
 constexpr int kTableStride = 28;  // table row: 27 values + 1 pad (16-byte rows)
 constexpr int kMaxTile = 16;      // a periodic axis of up to this many cells is one spreading tile
 constexpr int kMaxBoxTile = 12;   // largest tile edge cut from a longer axis (three int64 boxes in LDS)
+constexpr int kMaxBlocksPerCu = 64;   // largest tunable workgroups per compute unit of a launch
 constexpr int kPackI = 11, kPackJ = 11;  // home packing i | j << 11 | k << 22
 constexpr uint32_t kMaskI = (1u << kPackI) - 1, kMaskJ = (1u << kPackJ) - 1;
 
@@ -162,6 +163,7 @@ struct Ctx {
     Mlp mlp;
     // time step
     unsigned long long *step_ctr = nullptr;
+    int64_t step_sorted_n = -1;   // markers of the last exact step (its rows are in tile order)
     // per-kernel timing
     bool timing = false;
     bool capturing = false;
@@ -187,9 +189,6 @@ hipError_t launch_build_exact(const Ctx &c, int64_t n, const float *x, const flo
                               uint32_t *home, float *phi, uint8_t *route, hipStream_t s);
 hipError_t launch_build_fast(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
                              uint32_t *home, float *phi, uint8_t *route, hipStream_t s);
-hipError_t launch_build_interp(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
-                               uint32_t *home, float *phi, uint8_t *route, const float *u, const float *v,
-                               const float *w, const float *vb, float dt, float *U, float *F, hipStream_t s);
 hipError_t launch_build_learned(Ctx &c, int64_t n, const float *x, const float *y, const float *z,
                                 uint32_t *home, float *phi, uint8_t *route, hipStream_t s);
 hipError_t launch_table_build(const Ctx &c, hipStream_t s);
@@ -199,6 +198,21 @@ hipError_t launch_interp(const Ctx &c, int64_t n, const uint32_t *home, const fl
 hipError_t launch_spread(Ctx &c, int64_t n, const uint32_t *home, const float *phi,
                          const float *area, const float *Fx, const float *Fy, const float *Fz,
                          float *fx, float *fy, float *fz, hipStream_t s);
+
+// The exact time step in spreading-tile order: markers are binned by the tile
+// of their cell straight from their positions (entries = tile-sorted marker
+// indices, markers without a valid support last), the fused build writes row
+// p of home / phi for marker entries[p] together with U, F and per-block
+// force maxima, and the tile kernels read the rows of a tile contiguously.
+int build_blocks(const Ctx &c, int64_t n);   // workgroups of a build launch over n markers
+hipError_t launch_sort_positions(Ctx &c, int64_t n, const float *x, const float *y, const float *z, hipStream_t s);
+hipError_t launch_build_interp(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
+                               uint32_t *home, float *phi, uint8_t *route, const float *u, const float *v,
+                               const float *w, const float *vb, const float *area, float dt, float *U, float *F,
+                               hipStream_t s);
+hipError_t launch_spread_sorted(Ctx &c, int64_t n, const uint32_t *home, const float *phi, const float *area,
+                                const float *Fx, const float *Fy, const float *Fz, float *fx, float *fy, float *fz,
+                                hipStream_t s);
 
 hipError_t launch_jitter(const Ctx &c, int64_t n, const float *x0, const float *y0, const float *z0,
                          float *x, float *y, float *z, float amp, uint64_t seed, hipStream_t s);

@@ -148,18 +148,23 @@ mls_status mls_step(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buff
     mls_status st = MLS_OK;
     hipError_t e;
     if (desc->method == MLS_EXACT) {
-        // exact MLS: the build writes U and F as well, so phi is not read
-        // back for the interpolation
+        // exact MLS in spreading-tile order: bin the markers from their
+        // positions, build with interpolation and forcing fused (phi is not
+        // read back), spread reading each tile's rows contiguously
         st = mls_reserve(ctx, n);
         if (st != MLS_OK) return st;
+        e = launch_sort_positions(c, n, bx, by, bz, s);
+        if (e != hipSuccess) return MLS_E_HIP;
         {
             TimedLaunch t(c, MLS_K_BUILD_INTERP, s);
-            e = launch_build_interp(c, n, bx, by, bz, b->home, b->phi, b->route, b->u, b->v, b->w, b->vb, desc->dt,
-                                    b->U, b->F, s);
+            e = launch_build_interp(c, n, bx, by, bz, b->home, b->phi, b->route, b->u, b->v, b->w, b->vb, b->area,
+                                    desc->dt, b->U, b->F, s);
         }
         if (e != hipSuccess) return MLS_E_HIP;
-        e = launch_spread(c, n, b->home, b->phi, b->area, b->F, b->F + n, b->F + 2 * n, b->fx, b->fy, b->fz, s);
+        e = launch_spread_sorted(c, n, b->home, b->phi, b->area, b->F, b->F + n, b->F + 2 * n, b->fx, b->fy, b->fz,
+                                 s);
         if (e != hipSuccess) return MLS_E_HIP;
+        c.step_sorted_n = n;
         return launch_step_advance(c, s) == hipSuccess ? MLS_OK : MLS_E_HIP;
     }
     st = mls_build(ctx, n, bx, by, bz, desc->method, b->home, b->phi, b->route, stream);
@@ -174,6 +179,16 @@ mls_status mls_step(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buff
     st = mls_spread(ctx, n, b->home, b->phi, b->area, b->F, b->F + n, b->F + 2 * n, b->fx, b->fy, b->fz, stream);
     if (st != MLS_OK) return st;
     return launch_step_advance(c, s) == hipSuccess ? MLS_OK : MLS_E_HIP;
+}
+
+mls_status mls_step_order(mls_ctx *ctx, uint32_t *order, int64_t n, void *stream)
+{
+    if (!ctx || !order || n < 0) return MLS_E_ARG;
+    Ctx &c = ctx->c;
+    if (n != c.step_sorted_n) return MLS_E_ARG;
+    if (n == 0) return MLS_OK;
+    return hipMemcpyAsync(order, c.entries, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                          static_cast<hipStream_t>(stream)) == hipSuccess ? MLS_OK : MLS_E_HIP;
 }
 
 mls_status mls_step_counter_set(mls_ctx *ctx, uint64_t step, void *stream)

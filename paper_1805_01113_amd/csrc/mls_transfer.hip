@@ -158,6 +158,52 @@ k_bin(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home,
     }
 }
 
+// Binning straight from the marker positions (the exact time step): the
+// tile of the cell that holds the marker (centre-staggered home on each
+// axis); a marker whose cell support leaves a wall axis, or whose position is
+// not finite, goes to the extra bucket ntiles, after all tiles.
+template <bool FILL>
+__global__ void __launch_bounds__(kBlock)
+k_bin_pos(const Grid *__restrict__ gp, int64_t n, const float *__restrict__ x, const float *__restrict__ y,
+          const float *__restrict__ z, uint32_t *__restrict__ count, uint32_t *__restrict__ cursor,
+          uint32_t *__restrict__ entries)
+{
+    const Grid &g = *gp;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long lower = (1ull << lane) - 1ull;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
+        const int64_t l = base + lane;
+        int64_t t = -1;
+        if (l < n) {
+            const double p[3] = {(double)x[l], (double)y[l], (double)z[l]};
+            int cell[3];
+            bool ok = true;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                int ih = 0;
+                double X;
+                ok = ok && locate(g.ax[d], 0, p[d], ih, X);
+                cell[d] = ih;
+            }
+            t = ok ? ((int64_t)(cell[2] / g.ax[2].tile) * g.ntile[1] + cell[1] / g.ax[1].tile) * g.ntile[0] +
+                         cell[0] / g.ax[0].tile
+                   : g.ntiles;
+        }
+        unsigned long long pending = __ballot(t >= 0);
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const int64_t tlead = __shfl(t, leader);
+            const unsigned long long mask = __ballot(t == tlead) & pending;
+            uint32_t pos = 0;
+            if (lane == leader) pos = atomicAdd(FILL ? &cursor[tlead] : &count[tlead], (uint32_t)__popcll(mask));
+            pos = __shfl(pos, leader);
+            if (FILL && ((mask >> lane) & 1ull)) entries[pos + __popcll(mask & lower)] = (uint32_t)l;
+            pending &= ~mask;
+        }
+    }
+}
+
 __global__ void k_zero_u32(uint32_t *__restrict__ p, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -270,6 +316,14 @@ __device__ __forceinline__ int axis_colour(const Grid &g, int d, int t)
     return k == 1 ? 0 : ((k == 3 && t == g.ntile[d] - 1) ? 2 : (t & 1));
 }
 
+// One past the last slot of colour col in the active-tile list (the colours
+// in use are 0 .. ncol_x ncol_y ncol_z - 1, their slots consecutive).
+__device__ __forceinline__ int64_t colour_end(const Grid &g, int col)
+{
+    const int used = g.ncol[0] * g.ncol[1] * g.ncol[2];
+    return col + 1 < used ? g.colour_base[col + 1] : g.ntiles;
+}
+
 // Non-empty tiles listed per colour: work[col] counts them and
 // active[colour_base[col] + i] lists them.  A block gathers its 2048 tiles
 // per colour in LDS and takes its slots with one atomic per colour.
@@ -302,7 +356,10 @@ k_active_tiles(const Grid *__restrict__ gp, const uint32_t *__restrict__ off, ui
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kActiveChunk / kBlock; ++q)
-        if (col[q] >= 0) active[g.colour_base[col[q]] + lbase[col[q]] + pos[q]] = (uint32_t)(t0 + q);
+        if (col[q] >= 0) {
+            const int64_t slot = g.colour_base[col[q]] + lbase[col[q]] + pos[q];
+            if (slot < colour_end(g, col[q])) active[slot] = (uint32_t)(t0 + q);
+        }
 }
 
 // ---- spreading: per-tile fixed-point accumulation ------------------------------
@@ -321,6 +378,10 @@ __device__ __forceinline__ int box_local(const Axis &a, int ntile, int nodes, in
     return l;
 }
 
+// SORTED: row e of home / phi belongs to marker entries[e] (the exact time
+// step writes them in tile order), so a tile reads its rows contiguously;
+// otherwise home / phi are indexed by marker.
+template <bool SORTED>
 __global__ void __launch_bounds__(kBlock)
 k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32_t *__restrict__ home,
                 const float *__restrict__ phi, const float *__restrict__ area, const float *__restrict__ Fx,
@@ -337,13 +398,14 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
     float Mf[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) Mf[c] = __uint_as_float(fmax_bits[c]);
-    const uint32_t nact = work[colour];
     const int64_t abase = g.colour_base[colour];
+    const uint32_t nact = (uint32_t)min((int64_t)work[colour], colour_end(g, colour) - abase);
     __shared__ int64_t tile_sh;
     for (;;) {
         if (threadIdx.x == 0) {
             const uint32_t i = atomicAdd(&work[32 + colour], 1u);
-            tile_sh = i < nact ? (int64_t)active[abase + i] : -1;
+            const int64_t t = i < nact ? (int64_t)active[abase + i] : -1;
+            tile_sh = t < g.ntiles ? t : -1;
         }
         for (int q = threadIdx.x; q < 3 * bnodes; q += blockDim.x) acc[q] = 0ull;
         __syncthreads();
@@ -384,8 +446,9 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                 const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
                 int hi, hj, hk;
                 float ph[kNe];
-                unpack_home(home[home_at(m, c)], hi, hj, hk);
-                const float *p = phi + phi_at(m, c);
+                const int64_t row = SORTED ? (int64_t)e : (int64_t)m;
+                unpack_home(home[home_at(row, c)], hi, hj, hk);
+                const float *p = phi + phi_at(row, c);
 #pragma unroll
                 for (int k = 0; k < kNe; ++k) ph[k] = p[k * kLanes];
                 int ix[3], iy[3], iz[3];
@@ -481,6 +544,28 @@ int grid_for(int64_t work, int cu)
 
 }  // namespace
 
+template <bool SORTED>
+static hipError_t launch_tiles(Ctx &c, int64_t n, const uint32_t *home, const float *phi, const float *area,
+                               const float *Fx, const float *Fy, const float *Fz, float *fx, float *fy, float *fz,
+                               hipStream_t s)
+{
+    const size_t lds = (size_t)3 * c.g.box[0] * c.g.box[1] * c.g.box[2] * sizeof(unsigned long long);
+    const int persist = c.cu_count * c.spread_blocks_per_cu;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_spread_colour<SORTED>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    TimedLaunch tt(c, MLS_K_SPREAD_TILES, s);
+    for (int col = 0; col < 27; ++col) {
+        if (c.colour_tiles[col] == 0) continue;
+        hipLaunchKernelGGL(k_spread_colour<SORTED>, dim3(persist), dim3(kBlock), lds, s, c.d_grid, col, n, home, phi,
+                           area, Fx, Fy, Fz, fx, fy, fz, c.tile_off, c.entries, c.tile_active, c.work, c.work + 64,
+                           c.err);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_interp(const Ctx &c, int64_t n, const uint32_t *home, const float *phi,
                          const float *u, const float *v, const float *w,
                          float *U, float *V, float *W, hipStream_t s)
@@ -516,21 +601,45 @@ hipError_t launch_spread(Ctx &c, int64_t n, const uint32_t *home, const float *p
         hipLaunchKernelGGL(k_active_tiles, dim3((unsigned)((nt + kActiveChunk - 1) / kActiveChunk)), dim3(kBlock), 0,
                            s, c.d_grid, c.tile_off, c.tile_active, c.work);
     }
-    const size_t lds = (size_t)3 * c.g.box[0] * c.g.box[1] * c.g.box[2] * sizeof(unsigned long long);
-    const int persist = c.cu_count * c.spread_blocks_per_cu;
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_spread_colour, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    TimedLaunch tt(c, MLS_K_SPREAD_TILES, s);
-    for (int col = 0; col < 27; ++col) {
-        if (c.colour_tiles[col] == 0) continue;
-        hipLaunchKernelGGL(k_spread_colour, dim3(persist), dim3(kBlock), lds, s, c.d_grid, col, n, home, phi, area,
-                           Fx, Fy, Fz, fx, fy, fz, c.tile_off, c.entries, c.tile_active, c.work, c.work + 64,
-                           c.err);
-    }
+    return launch_tiles<false>(c, n, home, phi, area, Fx, Fy, Fz, fx, fy, fz, s);
+}
+
+hipError_t launch_sort_positions(Ctx &c, int64_t n, const float *x, const float *y, const float *z, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const int64_t nt = c.g.ntiles + 1;   // tiles and the bucket of markers without a valid support
+    const int64_t nb = (nt + kScanChunk - 1) / kScanChunk;
+    TimedLaunch tb(c, MLS_K_SPREAD_BIN, s);
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(nt, c.cu_count)), dim3(kBlock), 0, s, c.tile_count, nt);
+    hipLaunchKernelGGL(k_bin_pos<false>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, x, y, z,
+                       c.tile_count, c.tile_cursor, c.entries);
+    hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)nb), dim3(kBlock), 0, s, c.tile_count, nt, c.block_sums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, c.block_sums, nb, c.block_fmax, 0, c.work + 64);
+    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kBlock), 0, s, c.tile_count, nt, c.block_sums,
+                       c.tile_off, c.tile_cursor, c.work);
+    hipLaunchKernelGGL(k_bin_pos<true>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, x, y, z,
+                       c.tile_count, c.tile_cursor, c.entries);
     return hipGetLastError();
+}
+
+hipError_t launch_spread_sorted(Ctx &c, int64_t n, const uint32_t *home, const float *phi, const float *area,
+                                const float *Fx, const float *Fy, const float *Fz, float *fx, float *fy, float *fz,
+                                hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const int64_t nt = c.g.ntiles;
+    {
+        TimedLaunch tb(c, MLS_K_SPREAD_BIN, s);
+        // colour list sizes and tile cursors start at zero on every call (the
+        // call may follow another spreading of the same sort)
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBlock), 0, s, c.work, (int64_t)64);
+        // force bound from the build's per-block maxima (no scan: nb = 0)
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, c.block_sums, (int64_t)0, c.block_fmax,
+                           build_blocks(c, n), c.work + 64);
+        hipLaunchKernelGGL(k_active_tiles, dim3((unsigned)((nt + kActiveChunk - 1) / kActiveChunk)), dim3(kBlock), 0,
+                           s, c.d_grid, c.tile_off, c.tile_active, c.work);
+    }
+    return launch_tiles<true>(c, n, home, phi, area, Fx, Fy, Fz, fx, fy, fz, s);
 }
 
 }  // namespace mls

@@ -182,15 +182,22 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, const mls_step_buffers *b,
     c.timing = false;
     float *U = b->U, *V = b->U + n, *Wv = b->U + 2 * n;
     const float *F = b->F;
-    // the exact step runs the build fused with interpolation and forcing
+    // the exact step bins the markers and runs the build fused with
+    // interpolation and forcing, then spreads in tile order
+    const bool exact = method == MLS_EXACT;
     auto build = [&]() {
-        if (method != MLS_EXACT)
-            return mls_build(ctx, n, b->x0, b->y0, b->z0, method, b->home, b->phi, nullptr, stream);
-        return launch_build_interp(c, n, b->x0, b->y0, b->z0, b->home, b->phi, nullptr, b->u, b->v, b->w, b->vb,
-                                   1.0f, b->U, b->F, s) == hipSuccess ? MLS_OK : MLS_E_HIP;
+        if (!exact) return mls_build(ctx, n, b->x0, b->y0, b->z0, method, b->home, b->phi, nullptr, stream);
+        hipError_t e = launch_sort_positions(c, n, b->x0, b->y0, b->z0, s);
+        if (e == hipSuccess)
+            e = launch_build_interp(c, n, b->x0, b->y0, b->z0, b->home, b->phi, nullptr, b->u, b->v, b->w, b->vb,
+                                    b->area, 1.0f, b->U, b->F, s);
+        return e == hipSuccess ? MLS_OK : MLS_E_HIP;
     };
     auto interp = [&]() { return mls_interp(ctx, n, b->home, b->phi, b->u, b->v, b->w, U, V, Wv, stream); };
     auto spread = [&]() {
+        if (exact)
+            return launch_spread_sorted(c, n, b->home, b->phi, b->area, F, F + n, F + 2 * n, b->fx, b->fy, b->fz,
+                                        s) == hipSuccess ? MLS_OK : MLS_E_HIP;
         return mls_spread(ctx, n, b->home, b->phi, b->area, F, F + n, F + 2 * n, b->fx, b->fy, b->fz, stream);
     };
     bool ok = true;
@@ -223,8 +230,9 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, const mls_step_buffers *b,
         if (t < t_interp) { t_interp = t; best.interp_blocks_per_cu = v; }
     }
     c.interp_blocks_per_cu = best.interp_blocks_per_cu;
-    // forces F = (V_b - U) / 1 for the spreading candidates
-    if (ok) ok = launch_force(c, n, b->vb, b->U, 1.0f, b->F, s) == hipSuccess;
+    // forces F = (V_b - U) / 1 for the spreading candidates (the exact build
+    // writes them itself)
+    if (ok && !exact) ok = launch_force(c, n, b->vb, b->U, 1.0f, b->F, s) == hipSuccess;
     // spreading: tile edge x resident workgroups
     double t_spread = 1e30;
     const int tiles[] = {4, 6, 8, 10, 12};
@@ -236,6 +244,7 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, const mls_step_buffers *b,
         std::vector<int> shape = {c.g.ax[0].tile, c.g.ax[1].tile, c.g.ax[2].tile};
         if (std::find(seen.begin(), seen.end(), shape) != seen.end()) continue;
         seen.push_back(shape);
+        if (exact) ok = build() == MLS_OK;   // bin for this tiling (untimed)
         int last_eff = -1;
         for (int v : spcs) {
             const int64_t lds = (int64_t)3 * c.g.box[0] * c.g.box[1] * c.g.box[2] * 8;

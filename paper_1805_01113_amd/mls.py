@@ -111,6 +111,7 @@ def load(path: str = LIB_PATH, need_torch: bool = True):
                                   ctypes.POINTER(I32), ctypes.POINTER(I32), P]
     L.mls_step.argtypes = [P, ctypes.POINTER(_StepDesc), ctypes.POINTER(_StepBuf), P]
     L.mls_step_counter_set.argtypes = [P, ctypes.c_uint64, P]
+    L.mls_step_order.argtypes = [P, P, I64, P]
     L.mls_graph_create.argtypes = [P, ctypes.POINTER(_StepDesc), ctypes.POINTER(_StepBuf), ctypes.POINTER(P)]
     L.mls_graph_launch.argtypes = [P, I32, P]
     L.mls_graph_destroy.argtypes = [P]
@@ -128,7 +129,7 @@ def load(path: str = LIB_PATH, need_torch: bool = True):
     L.mls_mlp_train_step.argtypes = [P, I64, P, P, I64, P, ctypes.c_float, ctypes.c_float, P, P]
     for name in ("mls_tune_get", "mls_tune_set", "mls_autotune", "mls_mlp_load", "mls_mlp_get", "mls_features", "mls_mlp_forward", "mls_mlp_grad",
                  "mls_mlp_train_step","mls_ctx_create", "mls_reserve", "mls_build", "mls_interp", "mls_spread", "mls_sync",
-                 "mls_stats_get", "mls_stats_reset", "mls_fast_tables", "mls_step", "mls_step_counter_set",
+                 "mls_stats_get", "mls_stats_reset", "mls_fast_tables", "mls_step", "mls_step_counter_set", "mls_step_order",
                  "mls_graph_create", "mls_graph_launch", "mls_timing_enable", "mls_timing_get"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -438,6 +439,14 @@ def step(ctx: "Context", bufs: StepBuffers, method=MLS_EXACT, dt=1.0, jitter=0.0
     d = _desc(method, dt, jitter, seed)
     b = bufs.struct()
     ctx._raise(ctx._lib.mls_step(ctx.h, ctypes.byref(d), ctypes.byref(b), _stream(stream)), "mls_step")
+
+
+def step_order(ctx: "Context", n: int, stream=None):
+    """Row order of the last exact step: row p of its home / phi holds marker order[p]."""
+    import torch
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    ctx._raise(ctx._lib.mls_step_order(ctx.h, _ptr(out), int(n), _stream(stream)), "mls_step_order")
+    return out
 
 
 def step_counter_set(ctx: "Context", value: int, stream=None):

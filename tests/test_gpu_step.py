@@ -85,3 +85,38 @@ def test_graph_replays_match_eager():
     assert not np.array_equal(ref[0][0], ref[1][0])
     say("graph replays bitwise equal to eager steps (%d markers)" % wl.n)
     graph.close()
+
+
+def test_exact_step_rows_follow_the_reported_order(orc):
+    """The exact step writes row p of home / phi for marker order[p], grouped
+    by spreading tile; the rows equal the oracle's homes bit for bit and its
+    shape functions within 1e-5."""
+    import torch
+    from paper_1805_01113_amd import mls
+    wl = W.ellipsoids(n_bodies=40, n=128, cfg_id=302)
+    ctx, bufs = _setup(torch, wl)
+    n = wl.n
+    mls.step_counter_set(ctx, 3)
+    mls.step(ctx, bufs, method=mls.MLS_EXACT, dt=1.0, jitter=0.1 / 128, seed=1)
+    ctx.sync()
+    order = mls.step_order(ctx, n).cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(order), np.arange(n)), "order is not a permutation"
+    xj = [t.cpu().numpy() for t in (bufs.x, bufs.y, bufs.z)]
+    h = mls.unpack_home(bufs.home.cpu().numpy().view(np.uint32), n)
+    p = mls.unpack_phi(bufs.phi.cpu().numpy(), n)
+    g = orc.Grid(wl.grid.faces, wl.grid.periodic)
+    errs = []
+    for c in range(3):
+        ref = orc.build_exact(g, c, *xj)
+        assert np.array_equal(h[c], ref["home"][order]), "component %d homes" % c
+        errs.append(normwise(p[c], ref["phi"][order]))
+    # rows come grouped by tile: the tile of the cell of marker order[p] never decreases
+    tile = 8
+    cell = h[1][:, 0] // tile, h[2][:, 1] // tile, h[0][:, 2] // tile   # centre-staggered homes = cells
+    nt = 128 // tile
+    t = (cell[2] * nt + cell[1]) * nt + cell[0]
+    assert np.all(np.diff(t) >= 0)
+    say("exact step rows in tile order; phi err %s" % ["%.2e" % e for e in errs])
+    assert max(errs) <= PHI_TOL
+    with pytest.raises(mls.MLSError):
+        mls.step_order(ctx, n - 1)

@@ -38,7 +38,7 @@ k_build_exact(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n,
     unsigned long long routed = 0;
     float kmax = 0.f;
     // the next item's coordinates are loaded one iteration ahead
-    int64_t base = ((int64_t)blockIdx.x * kGroups + grp) * 64;
+    int64_t base = (xcd_block() * kGroups + grp) * 64;
     float nx = 0.f, ny = 0.f, nz = 0.f;
     if (base + lane < n) { nx = x[base + lane]; ny = y[base + lane]; nz = z[base + lane]; }
     for (; base < n; base += gstride) {
@@ -104,7 +104,7 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
     unsigned long long routed = 0;
     float kmax = 0.f, fmx = 0.f;
     // the next item's marker and coordinates are loaded one iteration ahead
-    int64_t base = ((int64_t)blockIdx.x * kGroups + grp) * 64;
+    int64_t base = (xcd_block() * kGroups + grp) * 64;
     uint32_t nm = 0;
     float nx = 0.f, ny = 0.f, nz = 0.f;
     if (base + lane < n) {
@@ -262,7 +262,7 @@ k_build_fast(const Grid *__restrict__ gp, const FastTables T, int64_t n,
     const int64_t gstride = (int64_t)gridDim.x * kGroups * 64;
     const int64_t rows = (int64_t)T.n_sub * T.n_sub * T.n_sub;
     // the next item's coordinates are loaded one iteration ahead
-    int64_t base = ((int64_t)blockIdx.x * kGroups + grp) * 64;
+    int64_t base = (xcd_block() * kGroups + grp) * 64;
     float nx = 0.f, ny = 0.f, nz = 0.f;
     if (base + lane < n) { nx = x[base + lane]; ny = y[base + lane]; nz = z[base + lane]; }
     for (; base < n; base += gstride) {
@@ -355,7 +355,7 @@ int build_grid(int64_t n, int cu, int blocks_per_cu)
     int64_t b = (n + kGroups * 64 - 1) / (kGroups * 64);
     const int64_t cap = (int64_t)cu * blocks_per_cu;
     if (b > cap) b = cap;
-    return (int)(b < 1 ? 1 : b);
+    return (int)round_up8(b < 1 ? 1 : b);   // a multiple of 8 for the XCD mapping
 }
 
 }  // namespace

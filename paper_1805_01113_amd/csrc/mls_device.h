@@ -338,6 +338,19 @@ __device__ __forceinline__ bool home_ok(const Grid &g, int c, int i, int j, int 
     return true;
 }
 
+// Workgroups are dispatched to the 8 XCDs of the chip round-robin
+// (workgroup b runs on XCD b % 8), and each XCD has its own L2.  For a grid
+// of nb workgroups (a multiple of 8) this index gives XCD x the contiguous
+// range [x nb / 8, (x + 1) nb / 8), so that neighbouring work items -- which
+// gather the same field lines -- share one L2.
+__device__ __forceinline__ int64_t xcd_block()
+{
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    return (int64_t)(b & 7) * (nb >> 3) + (b >> 3);
+}
+
+__host__ __device__ __forceinline__ int64_t round_up8(int64_t b) { return (b + 7) & ~(int64_t)7; }
+
 // Offset of node (i, j, k) in component c's field ([z][y][x], C order).
 __device__ __forceinline__ int64_t field_index(const Grid &g, int c, int i, int j, int k)
 {

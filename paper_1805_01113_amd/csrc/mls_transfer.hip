@@ -29,7 +29,7 @@ k_interp(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ ho
 {
     const Grid &g = *gp;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n; l += stride) {
+    for (int64_t l = xcd_block() * blockDim.x + threadIdx.x; l < n; l += stride) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const float *q = c == 0 ? u : (c == 1 ? v : w);
@@ -572,7 +572,7 @@ hipError_t launch_interp(const Ctx &c, int64_t n, const uint32_t *home, const fl
 {
     if (n == 0) return hipSuccess;
     int64_t blocks = (n + kBlock - 1) / kBlock;
-    blocks = std::min(blocks, (int64_t)c.cu_count * c.interp_blocks_per_cu);
+    blocks = round_up8(std::min(blocks, (int64_t)c.cu_count * c.interp_blocks_per_cu));
     hipLaunchKernelGGL(k_interp, dim3((unsigned)blocks), dim3(kBlock), 0, s, c.d_grid, n, home, phi,
                        u, v, w, U, V, W, c.err);
     return hipGetLastError();

@@ -32,6 +32,36 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def source_hash():
+    """SHA-256 over the HIP sources and headers of the library (the counter
+    summaries under profiles/ name the sources they were measured on)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1805_01113_amd", "csrc", "*"))) + \
+        [os.path.join(ROOT, "include", "mls.h")]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the rocprofv3 counter summary in
+    profiles/ (FETCH_SIZE and WRITE_SIZE scaled by the factors a plain device
+    copy reads for them), or None if there is none for the current sources."""
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_sha256") != source_hash() or d.get("workload") != workload:
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else int(k["traffic_bytes_per_launch"])
+
+
 def make_workload(name):
     from paper_1805_01113_amd import workloads as W
     if name == "uneven":
@@ -328,7 +358,7 @@ def main():
     step_bytes = sum(alg.get(k, 0.0) for k in kernels) * n
     log("eager: %.3f ms/step; kernels: %s" % (ms_eager, json.dumps(kernels)))
     roof = {"bound": "hbm", "kernel": dom[0], "achieved": dom[1]["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(dom[1]["GBs"] / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(dom[1]["GBs"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom[0], wl.name),
             "alg_bytes_per_marker": round(alg[dom[0]], 1), "markers_per_launch": n}
 
     extra = {"ms_per_step_eager": round(ms_eager, 4), "kernels": kernels, "autotune": tune,

@@ -110,7 +110,7 @@ typedef struct {
                              below this, else it falls back to exact MLS
                              (default 1e-4; 0 sends every marker to exact) */
     int32_t spread_tile;  /* edge (cells) of the spreading tiles on axes longer
-                             than 16 cells, 4..12 (0 = default 8); a periodic
+                             than 16 cells, 4..16 (0 = default 8); a periodic
                              axis uses a divisor of its length */
 } mls_opts;
 
@@ -132,7 +132,7 @@ const char *mls_version(void);
  * weight/opts may be NULL for the defaults.  Returns MLS_E_ARG for a grid
  * that is not increasing, has fewer than 3 cells on an axis, exceeds the
  * packed-index limits, or has a periodic axis longer than 16 cells whose cell
- * count has no divisor between 4 and 12 (the spreading tiles). */
+ * count has no divisor between 4 and 16 (the spreading tiles). */
 mls_status mls_ctx_create(mls_ctx **ctx, const mls_grid *grid, const mls_weight *weight,
                           const mls_opts *opts);
 void mls_ctx_destroy(mls_ctx *ctx);
@@ -184,9 +184,11 @@ mls_status mls_interp(mls_ctx *ctx, int64_t n, const uint32_t *home, const float
  * The result is bitwise reproducible and independent of the marker order:
  * markers are binned (counting sort) by the tile of the forcing grid that
  * holds their cell; a tile sums its markers' contributions in 64-bit fixed
- * point in a box covering the tile and its one-node halo; tiles are coloured
- * 2x2x2 so that boxes of one colour never overlap, and the eight colours add
- * their boxes into the field one after another.  A contribution larger than the
+ * point in a box covering the tile and its one-node halo (one component at a
+ * time); tiles are coloured by the parity of their index per axis (a third
+ * colour for the last tile of a periodic axis with an odd tile count) so that
+ * boxes of one colour never overlap, and the colours add their boxes into the
+ * field one after another.  A contribution larger than the
  * fixed-point bound (|c_l phi_k F_l| > 8 max|A_l F_l| / h_min^2, which a
  * shape function with |phi| <= 2 and sum phi dV close to dV never reaches)
  * raises MLS_E_RANGE. */
@@ -304,7 +306,7 @@ mls_status mls_timing_enable(mls_ctx *ctx, int32_t on);
 mls_status mls_timing_get(mls_ctx *ctx, mls_timing *out, int32_t reset);
 
 /* ---- launch shapes and the autotuner (an addition to the paper's method) ---
- * spread_tile: edge of the spreading tiles (4..12, as mls_opts.spread_tile);
+ * spread_tile: edge of the spreading tiles (4..16, as mls_opts.spread_tile);
  * *_blocks_per_cu (1..64): resident workgroups per compute unit of the
  * spreading tile launches (bounded further by the LDS of a tile's boxes), of
  * the exact / fast build and of the interpolation. */

@@ -78,8 +78,8 @@ mls_status mls::setup_tiles(Ctx &c, int want)
         nt *= g.ntile[d];
     }
     g.ntiles = nt;
-    // three fixed-point boxes (one per component) must fit the LDS of a workgroup
-    const int64_t lds = (int64_t)3 * g.box[0] * g.box[1] * g.box[2] * 8;
+    // the fixed-point box of one component must fit the LDS of a workgroup
+    const int64_t lds = (int64_t)g.box[0] * g.box[1] * g.box[2] * 8;
     if (lds > 160 * 1024) return MLS_E_ARG;
     // tile colours: tiles whose boxes may overlap get different colours.  Along
     // an axis the colour is the parity of the tile index; an odd number of

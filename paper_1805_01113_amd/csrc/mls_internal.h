@@ -18,7 +18,7 @@ namespace mls {
 constexpr int kNe = 27;           // 3x3x3 support nodes
 constexpr int kTableStride = 28;  // table row: 27 values + 1 pad (16-byte rows)
 constexpr int kMaxTile = 16;      // a periodic axis of up to this many cells is one spreading tile
-constexpr int kMaxBoxTile = 12;   // largest tile edge cut from a longer axis (three int64 boxes in LDS)
+constexpr int kMaxBoxTile = 16;   // largest tile edge cut from a longer axis (an int64 box of edge + 3 in LDS)
 constexpr int kMaxBlocksPerCu = 64;   // largest tunable workgroups per compute unit of a launch
 constexpr int kPackI = 11, kPackJ = 11;  // home packing i | j << 11 | k << 22
 constexpr uint32_t kMaskI = (1u << kPackI) - 1, kMaskJ = (1u << kPackJ) - 1;

@@ -66,10 +66,11 @@ k_interp(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ ho
 // Every marker belongs to exactly one tile of the grid: the tile holding its
 // cell (the home of a centre-staggered component on each axis).  A tile's
 // markers spread into an LDS box that covers the tile plus the one-node halo
-// of their supports (tile + 3 nodes per axis).  Tiles are coloured 2x2x2 by
-// the parity of their indices; boxes of tiles of one colour never overlap, so
-// a colour's tiles add their boxes into the field with plain read-modify-
-// writes, and the eight colours run one after another.  Each node thus
+// of their supports (tile + 3 nodes per axis).  Tiles are coloured by the
+// parity of their index per axis (a third colour for the last tile of a
+// periodic axis with an odd tile count); boxes of tiles of one colour never
+// overlap, so a colour's tiles add their boxes into the field with plain
+// read-modify-writes, and the colours run one after another.  Each node thus
 // receives its additions in the fixed colour order, and inside a box the
 // contributions are summed in 64-bit fixed point, whose sum does not depend on
 // the order of the markers: the result is bitwise reproducible.
@@ -391,13 +392,10 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                 const uint32_t *__restrict__ fmax_bits, ErrWord *err)
 {
     const Grid &g = *gp;
-    extern __shared__ unsigned long long acc[];     // three boxes, one per component
+    extern __shared__ unsigned long long acc[];     // the box of one component
     const Axis &AX = g.ax[0], &AY = g.ax[1], &AZ = g.ax[2];
     const int bx = g.box[0], by = g.box[1], bz = g.box[2];
     const int bnodes = bx * by * bz;
-    float Mf[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) Mf[c] = __uint_as_float(fmax_bits[c]);
     const int64_t abase = g.colour_base[colour];
     const uint32_t nact = (uint32_t)min((int64_t)work[colour], colour_end(g, colour) - abase);
     __shared__ int64_t tile_sh;
@@ -407,7 +405,6 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
             const int64_t t = i < nact ? (int64_t)active[abase + i] : -1;
             tile_sh = t < g.ntiles ? t : -1;
         }
-        for (int q = threadIdx.x; q < 3 * bnodes; q += blockDim.x) acc[q] = 0ull;
         __syncthreads();
         const int64_t t = tile_sh;
         if (t < 0) break;
@@ -419,36 +416,34 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
         const int b0x = (AX.periodic && g.ntile[0] == 1) ? 0 : tx * AX.tile - 1;
         const int b0y = (AY.periodic && g.ntile[1] == 1) ? 0 : ty * AY.tile - 1;
         const int b0z = (AZ.periodic && g.ntile[2] == 1) ? 0 : tz * AZ.tile - 1;
-        // c_l <= A_l / h^2 for a shape function with sum phi dV close to dV, h
-        // the smallest control-volume width near the tile; with |phi| <= 2 every
-        // contribution |c_l phi_k F_l| stays below bound = 8 max|A F| / h^2.
-        // A scaled contribution stays below 2^30 (converted to int32 and summed
-        // in int64); its quantum is 2^-30 of the bound.
         const float hloc = fminf(fminf(AX.tile_hmin[tx], AY.tile_hmin[ty]), AZ.tile_hmin[tz]);
         const double inv_h2 = 1.0 / ((double)hloc * (double)hloc);
-        int S[3];
-        float scale_f[3];
-#pragma unroll
+        // one component at a time: a third of the LDS per workgroup, so more
+        // workgroups fit a compute unit and tiles can be larger
+#pragma unroll 1
         for (int c = 0; c < 3; ++c) {
-            const double bound = 8.0 * (double)Mf[c] * inv_h2;
+            for (int q = threadIdx.x; q < bnodes; q += blockDim.x) acc[q] = 0ull;
+            // c_l <= A_l / h^2 for a shape function with sum phi dV close to dV, h
+            // the smallest control-volume width near the tile; with |phi| <= 2
+            // every contribution |c_l phi_k F_l| stays below bound = 8 max|A F| / h^2.
+            // A scaled contribution stays below 2^30 (converted to int32 and
+            // summed in int64); its quantum is 2^-30 of the bound.
+            const double bound = 8.0 * (double)__uint_as_float(fmax_bits[c]) * inv_h2;
             int ebits = 0;
             if (bound > 0.0 && bound < 1e300) frexp(bound, &ebits);   // bound < 2^ebits
-            S[c] = 30 - ebits;
-            scale_f[c] = (bound > 0.0 && bound < 1e300) ? ldexpf(1.0f, S[c]) : 0.0f;
-        }
-        const float lim = 1073741824.0f;            // 2^30
-        for (uint32_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
-            const uint32_t m = entries[e];
-            const float am = area[m];
-            bool range_ok = true;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
-                int hi, hj, hk;
-                float ph[kNe];
+            const int S = 30 - ebits;
+            const float scale_f = (bound > 0.0 && bound < 1e300) ? ldexpf(1.0f, S) : 0.0f;
+            const float lim = 1073741824.0f;            // 2^30
+            const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
+            const float *Fc = c == 0 ? Fx : (c == 1 ? Fy : Fz);
+            __syncthreads();
+            for (uint32_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
+                const uint32_t m = entries[e];
                 const int64_t row = SORTED ? (int64_t)e : (int64_t)m;
+                int hi, hj, hk;
                 unpack_home(home[home_at(row, c)], hi, hj, hk);
                 const float *p = phi + phi_at(row, c);
+                float ph[kNe];
 #pragma unroll
                 for (int k = 0; k < kNe; ++k) ph[k] = p[k * kLanes];
                 int ix[3], iy[3], iz[3];
@@ -469,7 +464,7 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                             (unsigned)iz[a] < (unsigned)bz;
                 }
                 if (!inbox) {           // cannot happen for a home written by the build
-                    range_ok = false;
+                    raise_error(err, m, MLS_E_RANGE);
                     continue;
                 }
                 float hl = 0.f, den = 0.f;
@@ -479,10 +474,9 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                     hl += ph[k] * (wx[a] + wy[b] + wz[cz]);
                     den += ph[k] * (wx[a] * wy[b] * wz[cz]);
                 }
-                const float Fm = c == 0 ? Fx[m] : (c == 1 ? Fy[m] : Fz[m]);
                 // c_l F_l = A_l h_l F_l / sum_k phi_k dV_k   (eq. 8), pre-scaled
-                const float vsc = am * (hl * (1.0f / 3.0f)) * Fm / den * scale_f[c];
-                unsigned long long *box = acc + c * bnodes;
+                const float vsc = area[m] * (hl * (1.0f / 3.0f)) * Fc[m] / den * scale_f;
+                bool range_ok = true;
 #pragma unroll
                 for (int k = 0; k < kNe; ++k) {
                     const int a = k % 3, b = (k / 3) % 3, cz = k / 9;
@@ -490,47 +484,47 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                     range_ok = range_ok && (fabsf(vs) < lim);
                     vs = fminf(fmaxf(vs, -lim), lim);
                     const long long qv = (long long)(int)rintf(vs);
-                    if (qv != 0) atomicAdd(&box[(iz[cz] * by + iy[b]) * bx + ix[a]], (unsigned long long)qv);
+                    if (qv != 0) atomicAdd(&acc[(iz[cz] * by + iy[b]) * bx + ix[a]], (unsigned long long)qv);
                 }
+                if (!range_ok) raise_error(err, m, MLS_E_RANGE);
             }
-            if (!range_ok) raise_error(err, m, MLS_E_RANGE);
-        }
-        __syncthreads();
-        // flush: the box nodes of a thread are read in batches of kFlush before
-        // any is written back, so their loads overlap
-        constexpr int kFlush = 8;
-        for (int q0 = threadIdx.x; q0 < 3 * bnodes; q0 += kFlush * blockDim.x) {
-            float *dst[kFlush];
-            float add[kFlush];
-            float old[kFlush];
+            __syncthreads();
+            // flush: the box nodes of a thread are read in batches of kFlush
+            // before any is written back, so their loads overlap
+            constexpr int kFlush = 8;
+            float *f = c == 0 ? fx : (c == 1 ? fy : fz);
+            const double qscale = ldexp(1.0, -S);
+            for (int q0 = threadIdx.x; q0 < bnodes; q0 += kFlush * blockDim.x) {
+                float *dst[kFlush];
+                float add[kFlush];
+                float old[kFlush];
 #pragma unroll
-            for (int u = 0; u < kFlush; ++u) {
-                dst[u] = nullptr;
-                add[u] = 0.f;
-                const int q = q0 + u * blockDim.x;
-                if (q >= 3 * bnodes) continue;
-                const long long sv = (long long)acc[q];
-                if (sv == 0) continue;
-                const int c = q / bnodes, r = q - c * bnodes;
-                const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
-                const int lx = r % bx, ly = (r / bx) % by, lz = r / (bx * by);
-                int gx = b0x + lx, gy = b0y + ly, gz = b0z + lz;
-                if (AX.periodic) gx = gx < 0 ? gx + nxc : (gx >= nxc ? gx - nxc : gx);
-                if (AY.periodic) gy = gy < 0 ? gy + nyc : (gy >= nyc ? gy - nyc : gy);
-                if (AZ.periodic) gz = gz < 0 ? gz + nzc : (gz >= nzc ? gz - nzc : gz);
-                if ((unsigned)gx >= (unsigned)nxc || (unsigned)gy >= (unsigned)nyc || (unsigned)gz >= (unsigned)nzc)
-                    continue;
-                float *f = c == 0 ? fx : (c == 1 ? fy : fz);
-                dst[u] = f + field_index(g, c, gx, gy, gz);
-                add[u] = (float)((double)sv * ldexp(1.0, -S[c]));
+                for (int u = 0; u < kFlush; ++u) {
+                    dst[u] = nullptr;
+                    add[u] = 0.f;
+                    const int q = q0 + u * blockDim.x;
+                    if (q >= bnodes) continue;
+                    const long long sv = (long long)acc[q];
+                    if (sv == 0) continue;
+                    const int lx = q % bx, ly = (q / bx) % by, lz = q / (bx * by);
+                    int gx = b0x + lx, gy = b0y + ly, gz = b0z + lz;
+                    if (AX.periodic) gx = gx < 0 ? gx + nxc : (gx >= nxc ? gx - nxc : gx);
+                    if (AY.periodic) gy = gy < 0 ? gy + nyc : (gy >= nyc ? gy - nyc : gy);
+                    if (AZ.periodic) gz = gz < 0 ? gz + nzc : (gz >= nzc ? gz - nzc : gz);
+                    if ((unsigned)gx >= (unsigned)nxc || (unsigned)gy >= (unsigned)nyc ||
+                        (unsigned)gz >= (unsigned)nzc)
+                        continue;
+                    dst[u] = f + field_index(g, c, gx, gy, gz);
+                    add[u] = (float)((double)sv * qscale);
+                }
+#pragma unroll
+                for (int u = 0; u < kFlush; ++u) old[u] = dst[u] ? *dst[u] : 0.f;
+#pragma unroll
+                for (int u = 0; u < kFlush; ++u)
+                    if (dst[u]) *dst[u] = old[u] + add[u];
             }
-#pragma unroll
-            for (int u = 0; u < kFlush; ++u) old[u] = dst[u] ? *dst[u] : 0.f;
-#pragma unroll
-            for (int u = 0; u < kFlush; ++u)
-                if (dst[u]) *dst[u] = old[u] + add[u];
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -549,7 +543,7 @@ static hipError_t launch_tiles(Ctx &c, int64_t n, const uint32_t *home, const fl
                                const float *Fx, const float *Fy, const float *Fz, float *fx, float *fy, float *fz,
                                hipStream_t s)
 {
-    const size_t lds = (size_t)3 * c.g.box[0] * c.g.box[1] * c.g.box[2] * sizeof(unsigned long long);
+    const size_t lds = (size_t)c.g.box[0] * c.g.box[1] * c.g.box[2] * sizeof(unsigned long long);
     const int persist = c.cu_count * c.spread_blocks_per_cu;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)k_spread_colour<SORTED>,

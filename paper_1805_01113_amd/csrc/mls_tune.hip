@@ -149,7 +149,7 @@ mls_status mls_tune_set(mls_ctx *ctx, const mls_tune *in)
         const mls_status st = setup_tiles(c, in->spread_tile);
         if (st != MLS_OK) return st;
     } else {
-        const int64_t lds = (int64_t)3 * c.g.box[0] * c.g.box[1] * c.g.box[2] * 8;
+        const int64_t lds = (int64_t)c.g.box[0] * c.g.box[1] * c.g.box[2] * 8;
         c.spread_blocks_per_cu = std::max(1, std::min(c.spread_blocks_per_cu_req, (int)((160 * 1024) / (lds + 512))));
     }
     return MLS_OK;
@@ -235,7 +235,7 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, const mls_step_buffers *b,
     if (ok && !exact) ok = launch_force(c, n, b->vb, b->U, 1.0f, b->F, s) == hipSuccess;
     // spreading: tile edge x resident workgroups
     double t_spread = 1e30;
-    const int tiles[] = {4, 6, 8, 10, 12};
+    const int tiles[] = {4, 6, 8, 10, 12, 16};
     const int spcs[] = {1, 2, 4, 8};
     std::vector<std::vector<int>> seen;
     for (int tile : tiles) {
@@ -247,7 +247,7 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, const mls_step_buffers *b,
         if (exact) ok = build() == MLS_OK;   // bin for this tiling (untimed)
         int last_eff = -1;
         for (int v : spcs) {
-            const int64_t lds = (int64_t)3 * c.g.box[0] * c.g.box[1] * c.g.box[2] * 8;
+            const int64_t lds = (int64_t)c.g.box[0] * c.g.box[1] * c.g.box[2] * 8;
             const int eff = std::max(1, std::min(v, (int)((160 * 1024) / (lds + 512))));
             if (eff == last_eff) continue;
             last_eff = eff;

@@ -74,12 +74,12 @@ def test_every_tile_edge_matches_oracle(orc, torch_cuda):
     area = r.uniform(0.5, 1.5, n).astype(np.float32) / 48 ** 2
     F = r.normal(size=(3, n)).astype(np.float32)
     ctx = mls.Context(gs.faces, gs.periodic)
-    for tile in (4, 6, 8, 12):
+    for tile in (4, 6, 8, 12, 16):
         ctx.tune_set(spread_tile=tile, spread_blocks_per_cu=4)
         assert ctx.tune_get()["spread_tile"] == tile
         _spread_vs_oracle(orc, torch_cuda, ctx, gs, x, y, z, area, F, "tile %d" % tile)
     with pytest.raises(mls.MLSError):
-        ctx.tune_set(spread_tile=13)
+        ctx.tune_set(spread_tile=17)
     with pytest.raises(mls.MLSError):
         ctx.tune_set(build_blocks_per_cu=0)
-    assert ctx.tune_get()["spread_tile"] == 12
+    assert ctx.tune_get()["spread_tile"] == 16

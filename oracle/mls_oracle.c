@@ -526,16 +526,56 @@ int orc_fast_shape(int dim, const double *xi, const double *cvlo, const double *
     return ORC_OK;
 }
 
+/* Trilinear variant of the fast-MLS lookup (the first "next" item beyond the
+ * paper's Shepard blend): the same enclosing sub-cell and table, blended with
+ * the multilinear weights of xi inside the sub-cell,
+ *   alpha_i = prod_d (t_d if corner i is at the upper sub-node along d else 1 - t_d),
+ * t_d = (xi_d - xs_lo,d) / (xs_hi,d - xs_lo,d).  The weights sum to one and
+ * reproduce xi itself, so the blend keeps the partition of unity and the
+ * exact reproduction of linear fields of the tabulated exact shape functions. */
+int orc_fast_shape_trilinear(int dim, const double *xi, const double *cvlo, const double *cvhi,
+                             int nsub, const double *table, double *phi)
+{
+    if ((dim != 2 && dim != 3) || nsub < 2) return ORC_E_ARG;
+    const int ne = dim == 2 ? 9 : 27;
+    const int nc = 1 << dim;
+    int j0[3];
+    double t[3];
+    for (int d = 0; d < dim; ++d) {
+        double u = (xi[d] - cvlo[d]) / (cvhi[d] - cvlo[d]) * (double)(nsub - 1);
+        int j = (int)floor(u);
+        if (j > nsub - 2) j = nsub - 2;
+        if (j < 0) j = 0;
+        j0[d] = j;
+        double xa = subnode(cvlo[d], cvhi[d], nsub, j), xb = subnode(cvlo[d], cvhi[d], nsub, j + 1);
+        t[d] = (xi[d] - xa) / (xb - xa);
+    }
+    for (int k = 0; k < ne; ++k) phi[k] = 0.0;
+    for (int i = 0; i < nc; ++i) {
+        double alpha = 1.0;
+        long idx = 0, stride = 1;
+        for (int d = 0; d < dim; ++d) {
+            int up = (i >> d) & 1;
+            alpha *= up ? t[d] : 1.0 - t[d];
+            idx += (j0[d] + up) * stride;
+            stride *= nsub;
+        }
+        for (int k = 0; k < ne; ++k) phi[k] += alpha * table[idx * ne + k];
+    }
+    return ORC_OK;
+}
+
 /* Per-marker fast-MLS build for component comp on the staggered grid.  The
  * table of a home node depends only on the support geometry; on a uniform
  * axis every cell has the same geometry, on a stretched axis each home index
  * has its own (the paper stores the extra shape functions of the cells along
  * the stretched direction).  Tables are computed here on demand, one per
  * distinct (home index along the non-uniform axes). */
-int orc_build_fast(const double *faces, const int32_t *n, const int32_t *periodic,
-                   int comp, int kind, double eps, double R, int nsub,
-                   long nm, const float *x, const float *y, const float *z,
-                   int32_t *home, double *phi, long *bad)
+/* blend 0: Shepard (eq. 9-10), 1: trilinear (orc_fast_shape_trilinear). */
+int orc_build_fast_blend(const double *faces, const int32_t *n, const int32_t *periodic,
+                         int comp, int kind, double eps, double R, int nsub, int blend,
+                         long nm, const float *x, const float *y, const float *z,
+                         int32_t *home, double *phi, long *bad)
 {
     grid3 g;
     grid_unpack(faces, n, periodic, &g);
@@ -587,13 +627,22 @@ int orc_build_fast(const double *faces, const int32_t *n, const int32_t *periodi
             rc = orc_fast_table(3, node, lo, hi, nsub, kind, eps, R, cache[key]);
             if (rc != ORC_OK) { free(cache[key]); cache[key] = NULL; if (first_bad < 0) { first_bad = l; first_rc = rc; } continue; }
         }
-        orc_fast_shape(3, xi, lo, hi, nsub, cache[key], phi + l * 27);
+        if (blend == 1) orc_fast_shape_trilinear(3, xi, lo, hi, nsub, cache[key], phi + l * 27);
+        else orc_fast_shape(3, xi, lo, hi, nsub, cache[key], phi + l * 27);
         for (int d = 0; d < 3; ++d) home[l * 3 + d] = (int32_t)h[d];
     }
     for (long k = 0; k < nkeys; ++k) free(cache[k]);
     free(cache);
     if (bad) *bad = first_bad;
     return first_rc;
+}
+
+int orc_build_fast(const double *faces, const int32_t *n, const int32_t *periodic,
+                   int comp, int kind, double eps, double R, int nsub,
+                   long nm, const float *x, const float *y, const float *z,
+                   int32_t *home, double *phi, long *bad)
+{
+    return orc_build_fast_blend(faces, n, periodic, comp, kind, eps, R, nsub, 0, nm, x, y, z, home, phi, bad);
 }
 
 /* Geometry of the normalised support of one home node, for table checks:

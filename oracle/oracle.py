@@ -63,6 +63,8 @@ def lib():
             L.orc_fast_table.argtypes = [i32, P, P, P, i32, i32, f64, f64, P]
             L.orc_fast_shape.argtypes = [i32, P, P, P, i32, P, P]
             L.orc_build_fast.argtypes = [P, P, P, i32, i32, f64, f64, i32, i64, P, P, P, P, P, P]
+            L.orc_fast_shape_trilinear.argtypes = [i32, P, P, P, i32, P, P]
+            L.orc_build_fast_blend.argtypes = [P, P, P, i32, i32, f64, f64, i32, i32, i64, P, P, P, P, P, P]
             L.orc_home_support.argtypes = [P, P, P, i32, P, P, P, P]
             L.orc_interp.argtypes = [P, P, P, i32, i64, P, P, P, P]
             L.orc_spread.argtypes = [P, P, P, i32, i64, P, P, P, P, P, P]
@@ -188,14 +190,19 @@ def fast_table(node, cvlo, cvhi, nsub, kind=W_GAUSS_SHIFTED, eps=1.0, R=1.5):
     return table
 
 
-def fast_shape(xi, cvlo, cvhi, nsub, table):
+BLEND_SHEPARD, BLEND_TRILINEAR = 0, 1
+
+
+def fast_shape(xi, cvlo, cvhi, nsub, table, blend=BLEND_SHEPARD):
+    """fast-MLS value at xi from a sub-node table: Shepard (eq. 9-10) or trilinear blend."""
     xi = np.ascontiguousarray(xi, dtype=np.float64)
     dim = xi.shape[0]
     cvlo = np.ascontiguousarray(cvlo, dtype=np.float64)
     cvhi = np.ascontiguousarray(cvhi, dtype=np.float64)
     table = np.ascontiguousarray(table, dtype=np.float64)
     phi = np.empty(3 ** dim)
-    lib().orc_fast_shape(dim, _p(xi), _p(cvlo), _p(cvhi), nsub, _p(table), _p(phi))
+    f = lib().orc_fast_shape_trilinear if blend == BLEND_TRILINEAR else lib().orc_fast_shape
+    f(dim, _p(xi), _p(cvlo), _p(cvhi), nsub, _p(table), _p(phi))
     return phi
 
 
@@ -208,14 +215,15 @@ def home_support(grid: Grid, comp, home):
     return node, lo, hi
 
 
-def build_fast(grid: Grid, comp, x, y, z, nsub=9, kind=W_GAUSS_SHIFTED, eps=1.0, R=1.5, check=True):
+def build_fast(grid: Grid, comp, x, y, z, nsub=9, kind=W_GAUSS_SHIFTED, eps=1.0, R=1.5, check=True,
+               blend=BLEND_SHEPARD):
     x, y, z = _markers(x, y, z)
     n = len(x)
     home = np.empty((n, 3), dtype=np.int32)
     phi = np.empty((n, 27))
     bad = ctypes.c_long(-1)
-    rc = lib().orc_build_fast(*grid.args(), comp, kind, eps, R, nsub, n, _p(x), _p(y), _p(z),
-                              _p(home), _p(phi), ctypes.byref(bad))
+    rc = lib().orc_build_fast_blend(*grid.args(), comp, kind, eps, R, nsub, blend, n, _p(x), _p(y), _p(z),
+                                    _p(home), _p(phi), ctypes.byref(bad))
     if rc != 0 and check:
         raise OracleError(rc, bad.value)
     return dict(home=home, phi=phi, rc=rc, bad=bad.value)

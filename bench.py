@@ -133,7 +133,7 @@ def cpu_baseline(wl, fields_dev, target_s):
                       "3 components, FP64; build %.1fs interp %.1fs spread %.1fs" % (m2, wl.n, *parts)}
 
 
-METHODS = {"exact": 0, "fast": 1, "learned": 2}
+METHODS = {"exact": 0, "fast": 1, "learned": 2, "fast_linear": 3}
 
 
 def load_network(ctx, path):
@@ -185,7 +185,7 @@ def compare_methods(torch, ctx, wl, bufs, fields, forcing, x0, y0, z0, area, jit
     from paper_1805_01113_amd import mls
     stream = torch.cuda.current_stream()
     n = wl.n
-    names = ["exact", "fast"] + (["learned"] if ctx.mlp_loaded else [])
+    names = ["exact", "fast", "fast_linear"] + (["learned"] if ctx.mlp_loaded else [])
     sub = int(min(len(wl.body_offsets) - 1, 2000))
     # reference velocities: exact MLS at a fixed jitter counter
     probe_step = 1 << 20
@@ -238,7 +238,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="uneven", choices=["uneven", "ellipsoids", "stretched", "sphere"])
-    ap.add_argument("--method", default="exact", choices=["exact", "fast", "learned"])
+    ap.add_argument("--method", default="exact", choices=["exact", "fast", "learned", "fast_linear"])
     ap.add_argument("--weights", default=None, help="surrogate checkpoint (default: the packaged one)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")

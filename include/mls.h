@@ -75,7 +75,8 @@ typedef enum {
 typedef enum {
     MLS_EXACT = 0,   /* eq. 3-6 per marker */
     MLS_FAST = 1,    /* eq. 9-10: Shepard blend of a sub-node table */
-    MLS_LEARNED = 2  /* MLP surrogate with exact-MLS fallback */
+    MLS_LEARNED = 2, /* MLP surrogate with exact-MLS fallback */
+    MLS_FAST_LINEAR = 3  /* the fast-MLS tables with a trilinear blend (beyond the paper) */
 } mls_method;
 
 /* The Eulerian grid as the paper states the problem (Sec. 2): per axis the
@@ -157,6 +158,10 @@ mls_status mls_reserve(mls_ctx *ctx, int64_t n_markers);
  * table on a uniform grid, one per plane and staggering type along a
  * stretched axis, Sec. 2 last paragraph) and blends the 8 corners of the
  * enclosing sub-cell with inverse-square-distance (Shepard) weights, eq. 9-10.
+ * MLS_FAST_LINEAR blends the same 8 rows with the multilinear weights of the
+ * marker inside the sub-cell; the weights sum to one and reproduce the
+ * position, so the tables' partition of unity and exact reproduction of
+ * linear fields carry over (second-order error in the sub-cell size).
  * MLS_LEARNED evaluates the loaded network (mls_mlp_load) and keeps its
  * output where the residual max(|sum_k phi_k - 1|, max_d |sum_k phi_k s_dk|)
  * (partition of unity and reproduction of linear fields, the consistency
@@ -241,7 +246,7 @@ mls_status mls_fast_tables(mls_ctx *ctx, float *dst, int64_t *count, int32_t *ro
  * mls_step_order), so that the tiles read their rows contiguously; U and F
  * stay indexed by marker.  Markers whose support leaves the grid come last.
  * The order of the markers inside a tile may differ between runs; U, F and
- * the forcing do not.  With MLS_FAST and MLS_LEARNED rows are in marker order.  All buffers are caller-owned device arrays:
+ * the forcing do not.  With the other methods rows are in marker order.  All buffers are caller-owned device arrays:
  * x0,y0,z0 [n] (read), x,y,z [n] (written by jitter), area [n], vb [3][n] or
  * NULL, home, phi and route (or NULL) in the blocked layout above, U [3][n], F [3][n],
  * the velocity fields u,v,w and the forcing fields fx,fy,fz. */

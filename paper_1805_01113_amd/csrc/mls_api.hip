@@ -417,11 +417,12 @@ mls_status mls_build(mls_ctx *ctx, int64_t n, const float *x, const float *y, co
         e = launch_build_exact(c, n, x, y, z, home, phi, route, s);
         break;
     }
-    case MLS_FAST: {
+    case MLS_FAST:
+    case MLS_FAST_LINEAR: {
         mls_status st = ensure_tables(ctx, s);
         if (st != MLS_OK) return st;
         TimedLaunch t(c, MLS_K_BUILD_FAST, s);
-        e = launch_build_fast(c, n, x, y, z, home, phi, route, s);
+        e = launch_build_fast(c, n, x, y, z, home, phi, route, s, method == MLS_FAST_LINEAR);
         break;
     }
     case MLS_LEARNED: {

@@ -250,6 +250,51 @@ __device__ __forceinline__ void shepard(const float *__restrict__ tab, const flo
     }
 }
 
+// Trilinear blend of the same table (the first "next" item beyond eq. 9-10):
+// the 8 corners of the enclosing sub-cell weighted by the multilinear
+// coordinates t_d of xi inside it.  The weights sum to one and reproduce xi,
+// so the exact tables' partition of unity and linear reproduction carry over.
+__device__ __forceinline__ void trilinear(const float *__restrict__ tab, const float *__restrict__ geo, int nsub,
+                                          const float xi[3], float *__restrict__ out)
+{
+    int j0[3];
+    float t[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const float lo = geo[2 * d], hi = geo[2 * d + 1];
+        const float step = (hi - lo) / (float)(nsub - 1);
+        int j = (int)floorf((xi[d] - lo) / (hi - lo) * (float)(nsub - 1));
+        j = min(max(j, 0), nsub - 2);
+        j0[d] = j;
+        t[d] = (xi[d] - (lo + (float)j * step)) / step;
+    }
+    float alpha[8];
+    const float *row[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        alpha[i] = ((i & 1) ? t[0] : 1.f - t[0]) * (((i >> 1) & 1) ? t[1] : 1.f - t[1]) *
+                   (((i >> 2) & 1) ? t[2] : 1.f - t[2]);
+        const int s = (j0[0] + (i & 1)) + nsub * ((j0[1] + ((i >> 1) & 1)) + nsub * (j0[2] + ((i >> 2) & 1)));
+        row[i] = tab + (int64_t)s * kTableStride;
+    }
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float4 v = *reinterpret_cast<const float4 *>(row[i] + 4 * q);
+            acc.x += alpha[i] * v.x; acc.y += alpha[i] * v.y; acc.z += alpha[i] * v.z; acc.w += alpha[i] * v.w;
+        }
+        const float vals[4] = {acc.x, acc.y, acc.z, acc.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = 4 * q + e;
+            if (k < kNe) out[k * kLanes] = vals[e];
+        }
+    }
+}
+
+template <bool TRILINEAR>
 __global__ void __launch_bounds__(kBuildBlock)
 k_build_fast(const Grid *__restrict__ gp, const FastTables T, int64_t n,
              const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
@@ -293,7 +338,8 @@ k_build_fast(const Grid *__restrict__ gp, const FastTables T, int64_t n,
             t = T.first[c == d] + G[d].ih;
         }
         const float xi[3] = {G[0].xi, G[1].xi, G[2].xi};
-        shepard(T.tab + (int64_t)t * rows * kTableStride, T.geo + (int64_t)t * 6, T.n_sub, xi, out);
+        if (TRILINEAR) trilinear(T.tab + (int64_t)t * rows * kTableStride, T.geo + (int64_t)t * 6, T.n_sub, xi, out);
+        else shepard(T.tab + (int64_t)t * rows * kTableStride, T.geo + (int64_t)t * 6, T.n_sub, xi, out);
         if (rout) *rout = 0;
     }
 }
@@ -398,11 +444,16 @@ hipError_t launch_build_interp(const Ctx &c, int64_t n, const float *x, const fl
 }
 
 hipError_t launch_build_fast(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
-                             uint32_t *home, float *phi, uint8_t *route, hipStream_t s)
+                             uint32_t *home, float *phi, uint8_t *route, hipStream_t s, bool trilinear_blend)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_build_fast, dim3(build_grid(n, c.cu_count, c.build_blocks_per_cu)), dim3(kBuildBlock), 0, s, c.d_grid, fast_tables(c), n,
-                       x, y, z, home, phi, route, c.err);
+    const dim3 grid(build_grid(n, c.cu_count, c.build_blocks_per_cu));
+    if (trilinear_blend)
+        hipLaunchKernelGGL(k_build_fast<true>, grid, dim3(kBuildBlock), 0, s, c.d_grid, fast_tables(c), n, x, y, z,
+                           home, phi, route, c.err);
+    else
+        hipLaunchKernelGGL(k_build_fast<false>, grid, dim3(kBuildBlock), 0, s, c.d_grid, fast_tables(c), n, x, y, z,
+                           home, phi, route, c.err);
     return hipGetLastError();
 }
 

@@ -188,7 +188,7 @@ struct TimedLaunch {
 hipError_t launch_build_exact(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
                               uint32_t *home, float *phi, uint8_t *route, hipStream_t s);
 hipError_t launch_build_fast(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
-                             uint32_t *home, float *phi, uint8_t *route, hipStream_t s);
+                             uint32_t *home, float *phi, uint8_t *route, hipStream_t s, bool trilinear_blend);
 hipError_t launch_build_learned(Ctx &c, int64_t n, const float *x, const float *y, const float *z,
                                 uint32_t *home, float *phi, uint8_t *route, hipStream_t s);
 hipError_t launch_table_build(const Ctx &c, hipStream_t s);

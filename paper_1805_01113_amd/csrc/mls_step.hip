@@ -209,7 +209,7 @@ mls_status mls_graph_create(mls_ctx *ctx, const mls_step_desc *desc, const mls_s
     if (st != MLS_OK) return st;
     hipStream_t cs;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return MLS_E_HIP;
-    if (desc->method == MLS_FAST) {
+    if (desc->method == MLS_FAST || desc->method == MLS_FAST_LINEAR) {
         st = mls_fast_tables(ctx, nullptr, nullptr, nullptr, nullptr, nullptr, cs);
         if (st != MLS_OK) { hipStreamDestroy(cs); return st; }
     }

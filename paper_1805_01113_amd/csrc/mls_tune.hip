@@ -164,7 +164,7 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, const mls_step_buffers *b,
     if (n < 1 || !b->x0 || !b->y0 || !b->z0 || !b->area || !b->home || !b->phi || !b->u || !b->v || !b->w || !b->U ||
         !b->F || !b->fx || !b->fy || !b->fz)
         return MLS_E_ARG;
-    if (method < MLS_EXACT || method > MLS_LEARNED || (method == MLS_LEARNED && !c.mlp.loaded)) return MLS_E_ARG;
+    if (method < MLS_EXACT || method > MLS_FAST_LINEAR || (method == MLS_LEARNED && !c.mlp.loaded)) return MLS_E_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     memset(out, 0, sizeof(*out));
     mls_tune cur;

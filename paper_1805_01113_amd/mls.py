@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmls_hip.so")
 
-MLS_EXACT, MLS_FAST, MLS_LEARNED = 0, 1, 2
+MLS_EXACT, MLS_FAST, MLS_LEARNED, MLS_FAST_LINEAR = 0, 1, 2, 3
 W_GAUSS_SHIFTED, W_GAUSS, W_CONST = 0, 1, 2
 STATUS = {0: "MLS_OK", -1: "MLS_E_ARG", -2: "MLS_E_SUPPORT", -3: "MLS_E_SINGULAR", -4: "MLS_E_NONFINITE",
           -5: "MLS_E_HIP", -6: "MLS_E_NOMEM", -7: "MLS_E_RANGE"}

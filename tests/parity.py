@@ -53,7 +53,8 @@ def compare_build(orc, grid, ctx, x, y, z, method=0, nsub=9, label="", kind=0):
         if method == 0:
             ref = orc.build_exact(grid, c, x, y, z, kind=kind)
         else:
-            ref = orc.build_fast(grid, c, x, y, z, nsub=nsub, kind=kind)
+            # method 1: Shepard blend (eq. 9-10); method 3: trilinear blend of the same tables
+            ref = orc.build_fast(grid, c, x, y, z, nsub=nsub, kind=kind, blend=1 if method == 3 else 0)
         assert np.array_equal(h[c], ref["home"]), "%s comp %d: home mismatch at %s" % (
             label, c, np.nonzero(np.any(h[c] != ref["home"], axis=1))[0][:10])
         e = normwise(p[c], ref["phi"])

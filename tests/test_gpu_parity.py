@@ -74,6 +74,13 @@ def test_single_sphere_64_fast(orc, torch_cuda):
                 label="sphere64 fast")
 
 
+def test_single_sphere_64_fast_trilinear(orc, torch_cuda):
+    wl = W.single_sphere()
+    fields = [f.numpy() for f in wl.fields("cpu")]
+    _full_check(orc, torch_cuda, wl.grid, wl.x, wl.y, wl.z, wl.area, wl.force, fields, method=3,
+                label="sphere64 fast trilinear")
+
+
 def _ragged_markers(n_grid, n, seed):
     r = np.random.default_rng(seed)
     x = r.uniform(-0.5, 1.5, n)
@@ -134,7 +141,7 @@ def test_stretched_exact_and_fast(orc, torch_cuda):
     fast-MLS tables."""
     wl = _stretched()
     fields = [f.numpy() for f in wl.fields("cpu")]
-    for method in (0, 1):
+    for method in (0, 1, 3):
         _full_check(orc, torch_cuda, wl.grid, wl.x, wl.y, wl.z, wl.area, wl.force, fields, method=method,
                     label="stretched m%d" % method)
 

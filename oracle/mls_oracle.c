@@ -783,3 +783,69 @@ int orc_axis_nodes(const double *faces, const int32_t *n, const int32_t *periodi
     for (long i = 0; i < m; ++i) X[i] = node_x(g.f[axis], g.n[axis], g.periodic[axis], axis == comp, i);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Coarse-grained collision detection (Sec. 5, the integer cell array coll). */
+/* ------------------------------------------------------------------------ */
+/* The cell of a marker is the Eulerian cell that contains it: along each
+ * axis the i with f[i] <= X < f[i+1], X being the wrapped coordinate on a
+ * periodic axis.  On a wall axis a coordinate outside [f[0], f[n]) has no
+ * cell (ORC_E_SUPPORT). */
+static int cell_axis(const double *f, int n, int periodic, double x, long *i_out)
+{
+    if (!isfinite(x)) return ORC_E_SUPPORT;
+    double X = periodic ? wrap_x(f, n, x) : x;
+    if (!(X >= f[0] && X < f[n])) return ORC_E_SUPPORT;
+    long lo = 0, hi = n;   /* f[lo] <= X < f[hi] */
+    while (hi - lo > 1) {
+        long mid = (lo + hi) / 2;
+        if (f[mid] <= X) lo = mid; else hi = mid;
+    }
+    *i_out = lo;
+    return ORC_OK;
+}
+
+/* The paper's two sweeps over the markers, in marker order.
+ *   coll, one int32 per cell (C order [z][y][x]), starts at 0 (cleared here).
+ *   Sweep 1: marker l of body b carries the id pid = b + 1.  If its cell
+ *   holds 0 the cell takes pid; if the cell then holds anything but pid it
+ *   becomes -1 (markers of more than one body share the cell).
+ *   Sweep 2: flag[l] = 1 where the cell of marker l holds -1 (a collision
+ *   force would be switched on for that marker), else 0.
+ * cell[l] receives the linear cell index of marker l.  Every marker is
+ * located before coll is touched: a marker without a cell returns
+ * ORC_E_SUPPORT, a body id outside [0, 2^31 - 2] ORC_E_ARG, with the first
+ * such marker in *bad. */
+int orc_collide(const double *faces, const int32_t *n, const int32_t *periodic,
+                long nm, const float *x, const float *y, const float *z, const int32_t *body,
+                int32_t *coll, long *cell, uint8_t *flag, long *bad)
+{
+    grid3 g;
+    grid_unpack(faces, n, periodic, &g);
+    *bad = -1;
+    const long ncell = (long)n[0] * n[1] * n[2];
+    for (long l = 0; l < nm; ++l) {
+        const double p[3] = {(double)x[l], (double)y[l], (double)z[l]};
+        long ic[3];
+        for (int d = 0; d < 3; ++d) {
+            if (cell_axis(g.f[d], g.n[d], g.periodic[d], p[d], &ic[d]) != ORC_OK) {
+                *bad = l;
+                return ORC_E_SUPPORT;
+            }
+        }
+        if (body[l] < 0 || body[l] > 2147483646) {
+            *bad = l;
+            return ORC_E_ARG;
+        }
+        cell[l] = (ic[2] * n[1] + ic[1]) * n[0] + ic[0];
+    }
+    for (long c = 0; c < ncell; ++c) coll[c] = 0;
+    for (long l = 0; l < nm; ++l) {
+        const int32_t pid = body[l] + 1;
+        int32_t *cv = &coll[cell[l]];
+        if (*cv == 0) *cv = pid;
+        if (*cv != pid) *cv = -1;
+    }
+    for (long l = 0; l < nm; ++l) flag[l] = coll[cell[l]] == -1 ? 1 : 0;
+    return ORC_OK;
+}

@@ -70,6 +70,7 @@ def lib():
             L.orc_spread.argtypes = [P, P, P, i32, i64, P, P, P, P, P, P]
             L.orc_node_volumes.argtypes = [P, P, P, i32, P]
             L.orc_axis_nodes.argtypes = [P, P, P, i32, i32, P]
+            L.orc_collide.argtypes = [P, P, P, i64, P, P, P, P, P, P, P, P]
             _lib = L
     return _lib
 
@@ -253,6 +254,27 @@ def spread(grid: Grid, comp, home, phi, area, F, f=None):
     cl = np.empty(n)
     lib().orc_spread(*grid.args(), comp, n, _p(home), _p(phi), _p(area), _p(F), _p(f), _p(cl))
     return f, cl
+
+
+def collide(grid: Grid, x, y, z, body, check=True):
+    """Coarse-grained collision detection (Sec. 5): returns dict(coll
+    [nz, ny, nx] int32 with 0 = empty cell, b + 1 = markers of body b only,
+    -1 = markers of several bodies; flag [N] uint8 = 1 where the marker's
+    cell holds -1; cell [N] linear cell index)."""
+    x, y, z = _markers(x, y, z)
+    body = np.ascontiguousarray(body, dtype=np.int32)
+    n = len(x)
+    assert len(body) == n
+    nx, ny, nz = (int(v) for v in grid.n)
+    coll = np.empty((nz, ny, nx), dtype=np.int32)
+    cell = np.empty(n, dtype=np.int64)
+    flag = np.empty(n, dtype=np.uint8)
+    bad = ctypes.c_long(-1)
+    rc = lib().orc_collide(*grid.args(), n, _p(x), _p(y), _p(z), _p(body), _p(coll), _p(cell), _p(flag),
+                           ctypes.byref(bad))
+    if rc != 0 and check:
+        raise OracleError(rc, bad.value)
+    return dict(coll=coll, flag=flag, cell=cell, rc=rc, bad=bad.value)
 
 
 # ---------------------------------------------------------------------------

@@ -359,6 +359,52 @@ def uneven_bodies(n_bodies: int = 10000, n: int = 1024, n_modes: int = 16, cfg_i
                    meta=dict(n_bodies=n_bodies, levels=lvl))
 
 
+def contact_pairs(n_pairs: int = 5000, n: int = 1024, n_modes: int = 16, cfg_id: int = 6,
+                  subdivs=(2, 3, 4), radii_h=(2.72, 5.31, 10.6), gap_h=(-1.5, 0.5)):
+    """Bodies in contact, for the collision detection of Sec. 5: n_pairs pairs
+    of spheres (subdivision and radius drawn as in uneven_bodies, l/h ~ 0.8)
+    whose surfaces are a gap U(gap_h) h apart along a random direction (a
+    negative gap overlaps), pairs placed without overlapping each other in a
+    periodic unit cube with a uniform n^3 grid.  Bodies 2p and 2p + 1 form
+    pair p; markers are stored body after body."""
+    h = 1.0 / n
+    g = GridSpec([uniform_faces(n)] * 3, [True] * 3)
+    rg = rng("geometry", cfg_id)
+    nb = 2 * n_pairs
+    lvl = rg.integers(0, len(subdivs), size=nb)
+    rad = np.array(radii_h)[lvl] * h
+    gap = rg.uniform(gap_h[0], gap_h[1], size=n_pairs) * h
+    u = rg.normal(size=(n_pairs, 3))
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    ra, rb = rad[0::2], rad[1::2]
+    bound = np.maximum(2 * ra, 2 * rb) + np.abs(gap)
+    mid = place_bodies(rng("placement", cfg_id), bound, np.zeros(3), np.ones(3), [True] * 3, 3 * h)
+    cen = np.empty((nb, 3))
+    cen[0::2] = mid - u * (ra + 0.5 * gap)[:, None]
+    cen[1::2] = mid + u * (rb + 0.5 * gap)[:, None]
+    rots = random_rotations(rng("rotation", cfg_id), nb)
+    counts = np.array([len(_ico(subdivs[i])[1]) for i in lvl])
+    offs = np.concatenate([[0], np.cumsum(counts)])
+    N = int(offs[-1])
+    pos = np.empty((N, 3)); area = np.empty(N); nrm = np.empty((N, 3))
+    for li, sd in enumerate(subdivs):
+        idx = np.nonzero(lvl == li)[0]
+        if len(idx) == 0:
+            continue
+        p, a, nr = surface_markers(sd, cen[idx], np.repeat(rad[idx][:, None], 3, axis=1), rots[idx])
+        nf = counts[idx[0]]
+        dst = (offs[idx][:, None] + np.arange(nf)[None, :]).reshape(-1)
+        pos[dst] = p; area[dst] = a; nrm[dst] = nr
+    return _finish("contact_%d_pairs_%d^3" % (n_pairs, n), g, [1.0] * 3, pos, area, nrm, offs, cfg_id, n_modes,
+                   meta=dict(n_bodies=nb, levels=lvl, gap=gap))
+
+
+def body_ids(offsets) -> np.ndarray:
+    """Body index of every marker from CSR body offsets (int32)."""
+    offsets = np.asarray(offsets, dtype=np.int64)
+    return np.repeat(np.arange(len(offsets) - 1, dtype=np.int32), np.diff(offsets))
+
+
 def stretched_channel(n_bodies: int = 2000, nxy: int = 512, nz: int = 768, lz: float = 1.5, beta: float = 2.5,
                       subdiv: int = 3, r_h: float = 5.31, n_modes: int = 16, cfg_id: int = 4):
     """Spheres (subdiv 3) in an nxy x nxy x nz box: x, y periodic uniform on

@@ -1,0 +1,224 @@
+"""Pins of the oracle's coarse-grained collision detection (Sec. 5).
+
+The oracle follows the paper's two sweeps over the markers in marker order.
+These tests check it against what the section states independently of that
+order: the three states of a cell (empty, one body, several bodies) written
+as sets, invariance under any marker order, the cell of a marker from the
+closed form floor(X n) on a uniform unit axis and from a linear scan of the
+faces on a stretched one, and geometric facts about bodies that are apart or
+overlap."""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1805_01113_amd import workloads as W
+
+
+def _uniform(n, periodic=(True, True, True)):
+    return orc.Grid([W.uniform_faces(n)] * 3, periodic)
+
+
+def _expected_by_sets(cells, body, shape):
+    """coll from the definition of its states: the set of bodies in a cell."""
+    occupants = {}
+    for c, b in zip(cells, body):
+        occupants.setdefault(int(c), set()).add(int(b))
+    coll = np.zeros(int(np.prod(shape)), dtype=np.int32)
+    for c, bs in occupants.items():
+        coll[c] = -1 if len(bs) > 1 else next(iter(bs)) + 1
+    return coll.reshape(shape)
+
+
+def _closed_form_cells(x, y, z, n):
+    """Cell of a marker on the periodic unit cube with n = 2^k cells per axis:
+    floor(X n) with X wrapped into [0, 1) (exact in FP64)."""
+    idx = []
+    for a in (x, y, z):
+        X = np.mod(np.asarray(a, dtype=np.float64), 1.0)
+        idx.append(np.floor(X * n).astype(np.int64))
+    return (idx[2] * n + idx[1]) * n + idx[0]
+
+
+def _clustered(rng, n_markers, n_bodies, n, n_hot):
+    """Markers of several bodies crowded into a few cells, plus stray ones."""
+    hot = rng.integers(0, n, size=(n_hot, 3))
+    pick = rng.integers(0, n_hot, size=n_markers)
+    pos = (hot[pick] + rng.uniform(0, 1, size=(n_markers, 3))) / n
+    stray = rng.uniform(0, 1, size=(n_markers // 4, 3))
+    pos = np.concatenate([pos, stray]).astype(np.float32)
+    body = rng.integers(0, n_bodies, size=len(pos)).astype(np.int32)
+    return pos[:, 0], pos[:, 1], pos[:, 2], body
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_states_match_set_definition(seed):
+    rng = np.random.default_rng(seed)
+    n = 16
+    g = _uniform(n)
+    x, y, z, body = _clustered(rng, 400, 5, n, 12)
+    r = orc.collide(g, x, y, z, body)
+    cells = _closed_form_cells(x, y, z, n)
+    np.testing.assert_array_equal(r["cell"], cells)
+    exp = _expected_by_sets(cells, body, (n, n, n))
+    np.testing.assert_array_equal(r["coll"], exp)
+    np.testing.assert_array_equal(r["flag"], (exp.reshape(-1)[cells] == -1).astype(np.uint8))
+    # the case is not trivial: all three states occur
+    assert (exp == -1).any() and (exp > 0).any() and (exp == 0).any()
+
+
+def test_marker_order_does_not_matter():
+    rng = np.random.default_rng(3)
+    n = 8
+    g = _uniform(n)
+    x, y, z, body = _clustered(rng, 200, 4, n, 6)
+    r0 = orc.collide(g, x, y, z, body)
+    for s in range(4):
+        p = np.random.default_rng(10 + s).permutation(len(x))
+        r = orc.collide(g, x[p], y[p], z[p], body[p])
+        np.testing.assert_array_equal(r["coll"], r0["coll"])
+        np.testing.assert_array_equal(r["flag"], r0["flag"][p])
+
+
+def test_three_bodies_in_one_cell():
+    """Three bodies reaching into one cell (the schematic case of the
+    section): that cell holds -1 and exactly the markers in it are flagged;
+    cells visited by one body hold that body's id."""
+    n = 8
+    g = _uniform(n)
+    h = 1.0 / n
+    shared = np.array([3, 4, 5]) * h
+    pts, body = [], []
+    for b in range(3):
+        pts.append(shared + (0.2 + 0.25 * b) * h)          # inside the shared cell
+        pts.append(shared + (0.5 + np.eye(3)[b]) * h)        # own neighbouring cell
+    pts = np.array(pts, dtype=np.float32)
+    body = np.array([0, 0, 1, 1, 2, 2], dtype=np.int32)
+    r = orc.collide(g, pts[:, 0], pts[:, 1], pts[:, 2], body)
+    assert r["coll"][5, 4, 3] == -1
+    assert r["coll"][5, 4, 4] == 1 and r["coll"][5, 5, 3] == 2 and r["coll"][6, 4, 3] == 3
+    np.testing.assert_array_equal(r["flag"], [1, 0, 1, 0, 1, 0])
+    assert (r["coll"] != 0).sum() == 4
+
+
+def test_one_body_never_collides():
+    wl = W.single_sphere(n=32, subdiv=3)
+    g = orc.Grid(wl.grid.faces, wl.grid.periodic)
+    body = np.zeros(wl.n, dtype=np.int32)
+    r = orc.collide(g, wl.x, wl.y, wl.z, body)
+    assert r["flag"].sum() == 0 and (r["coll"] == -1).sum() == 0
+    cells = _closed_form_cells(wl.x, wl.y, wl.z, 32)
+    assert (r["coll"] == 1).sum() == len(np.unique(cells))
+
+
+def _sphere_pair(centre_gap_h, n=64, subdiv=3, radius_h=5.31):
+    h = 1.0 / n
+    r = radius_h * h
+    c = np.array([[0.5 - r - 0.5 * centre_gap_h * h, 0.5, 0.5], [0.5 + r + 0.5 * centre_gap_h * h, 0.5, 0.5]])
+    pos, _, _ = W.surface_markers(subdiv, c, np.full((2, 3), r), np.stack([np.eye(3)] * 2))
+    nf = len(pos) // 2
+    body = np.repeat(np.arange(2, dtype=np.int32), nf)
+    p = pos.astype(np.float32)
+    return p, body, h
+
+
+def _nearest_other_body(p, body):
+    a, b = p[body == 0].astype(np.float64), p[body == 1].astype(np.float64)
+    d = np.sqrt(((a[:, None, :] - b[None, :, :]) ** 2).sum(-1))
+    return np.concatenate([d.min(axis=1), d.min(axis=0)])
+
+
+def test_bodies_apart_do_not_collide():
+    """Two spheres whose markers stay more than a cell diagonal apart cannot
+    share a cell."""
+    p, body, h = _sphere_pair(centre_gap_h=2.0)
+    assert _nearest_other_body(p, body).min() > np.sqrt(3.0) * h
+    r = orc.collide(_uniform(64), p[:, 0], p[:, 1], p[:, 2], body)
+    assert r["flag"].sum() == 0 and (r["coll"] == -1).sum() == 0
+
+
+def test_overlapping_bodies_collide_near_contact_only():
+    """Overlapping spheres: markers are flagged, and every flagged marker has
+    a marker of the other body within a cell diagonal (they share a cell)."""
+    p, body, h = _sphere_pair(centre_gap_h=-1.5)
+    r = orc.collide(_uniform(64), p[:, 0], p[:, 1], p[:, 2], body)
+    flagged = r["flag"].astype(bool)
+    assert flagged[body == 0].any() and flagged[body == 1].any()
+    near = _nearest_other_body(p, body)
+    order = np.concatenate([np.nonzero(body == 0)[0], np.nonzero(body == 1)[0]])
+    assert np.all(near[np.argsort(order)][flagged] <= np.sqrt(3.0) * h)
+    # flagged markers lie where the spheres meet (the plane x = 1/2)
+    assert np.abs(p[flagged, 0] - 0.5).max() < 2.0 * h
+
+
+def test_stretched_axis_cells_by_linear_scan():
+    fz = W.tanh_faces(24, 1.5, 2.5)
+    faces = [W.uniform_faces(8), W.uniform_faces(8), fz]
+    g = orc.Grid(faces, (True, True, False))
+    rng = np.random.default_rng(4)
+    n = 300
+    x = rng.uniform(-1, 2, n).astype(np.float32)
+    y = rng.uniform(0, 1, n).astype(np.float32)
+    z = rng.uniform(0, 1.5 * (1 - 1e-7), n).astype(np.float32)
+    body = rng.integers(0, 3, n).astype(np.int32)
+    r = orc.collide(g, x, y, z, body)
+    iz = np.array([max(i for i in range(24) if fz[i] <= float(v)) for v in z])
+    ix = np.floor(np.mod(x.astype(np.float64), 1.0) * 8).astype(int)
+    iy = np.floor(np.mod(y.astype(np.float64), 1.0) * 8).astype(int)
+    np.testing.assert_array_equal(r["cell"], (iz * 8 + iy) * 8 + ix)
+    np.testing.assert_array_equal(r["coll"], _expected_by_sets(r["cell"], body, (24, 8, 8)))
+
+
+def test_ties_go_to_the_upper_cell():
+    n = 64
+    g = _uniform(n)
+    i = np.arange(0, n, 7)
+    x = (i / n).astype(np.float32)
+    assert np.all(x.astype(np.float64) * n == i)
+    zeros = np.full(len(i), 0.5 / n, dtype=np.float32)
+    r = orc.collide(g, x, zeros, zeros, np.zeros(len(i), dtype=np.int32))
+    np.testing.assert_array_equal(r["cell"] % n, i)
+
+
+def test_errors_name_the_first_bad_marker():
+    g = orc.Grid([W.uniform_faces(8)] * 3, (True, True, False))
+    x = np.full(5, 0.5, dtype=np.float32)
+    z = np.array([0.5, 0.5, 1.0, -0.1, 0.5], dtype=np.float32)   # 1.0 is on the upper wall: outside
+    r = orc.collide(g, x, x, z, np.zeros(5, dtype=np.int32), check=False)
+    assert r["rc"] == orc.E_SUPPORT and r["bad"] == 2
+    body = np.array([0, 1, -1, 0, 0], dtype=np.int32)
+    r = orc.collide(g, x, x, np.full(5, 0.5, dtype=np.float32), body, check=False)
+    assert r["rc"] == -1 and r["bad"] == 2
+
+
+def test_every_small_configuration_of_two_markers():
+    """Brute force over every placement of two markers of two bodies on a 2^3
+    grid: they collide exactly when they share a cell."""
+    n = 2
+    g = _uniform(n)
+    centres = [((i + 0.5) / n, (j + 0.5) / n, (k + 0.5) / n) for i, j, k in itertools.product(range(n), repeat=3)]
+    for a, b in itertools.product(range(8), repeat=2):
+        p = np.array([centres[a], centres[b]], dtype=np.float32)
+        for bodies in ([0, 1], [0, 0]):
+            r = orc.collide(g, p[:, 0], p[:, 1], p[:, 2], np.array(bodies, dtype=np.int32))
+            hit = a == b and bodies[0] != bodies[1]
+            assert r["flag"].tolist() == ([1, 1] if hit else [0, 0])
+            assert (r["coll"] == -1).sum() == (1 if hit else 0)
+
+
+def test_contact_pairs_collide_within_pairs_only():
+    """The contact workload: pairs are placed 3h apart from each other, so a
+    cell shared by several bodies holds the two members of one pair, and
+    pairs that overlap (negative gap) are flagged."""
+    wl = W.contact_pairs(n_pairs=60, n=256)
+    body = W.body_ids(wl.body_offsets)
+    r = orc.collide(orc.Grid(wl.grid.faces, wl.grid.periodic), wl.x, wl.y, wl.z, body)
+    shared = {}
+    for c, b in zip(r["cell"], body):
+        shared.setdefault(int(c), set()).add(int(b))
+    multi = [bs for bs in shared.values() if len(bs) > 1]
+    assert multi and all(len(bs) == 2 and min(bs) % 2 == 0 and max(bs) == min(bs) + 1 for bs in multi)
+    gap = wl.meta["gap"] / (1.0 / 256)
+    hit_pairs = np.unique(body[r["flag"].astype(bool)] // 2)
+    assert set(np.nonzero(gap < -0.5)[0]) <= set(hit_pairs.tolist())

@@ -72,6 +72,8 @@ def make_workload(name):
         return W.stretched_channel()
     if name == "sphere":
         return W.single_sphere()
+    if name == "contact":
+        return W.contact_pairs()
     raise SystemExit("unknown workload %s" % name)
 
 
@@ -232,12 +234,56 @@ def compare_methods(torch, ctx, wl, bufs, fields, forcing, x0, y0, z0, area, jit
     return out
 
 
+def collision_cost(torch, ctx, wl, x, y, z, steps, ms_step):
+    """Coarse-grained collision detection on the step's markers: time of the
+    detection (cell ids + flags) and of the O(n) clear that readies the cell
+    array for the next step, against the step time."""
+    from paper_1805_01113_amd import mls
+    from paper_1805_01113_amd import workloads as W
+    n = wl.n
+    body = torch.from_numpy(W.body_ids(wl.body_offsets)).cuda()
+    coll = torch.zeros(ctx.cell_shape(), dtype=torch.int32, device="cuda")
+    flags = torch.empty(n, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    ctx.collide(x, y, z, body, coll, flags)
+    cells = int(torch.count_nonzero(coll))
+    shared = int((coll == -1).sum())
+    ctx.collide_clear(x, y, z, coll)
+    ctx.sync()
+    mls.timing_enable(ctx, True)
+    mls.timing_get(ctx, reset=True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        ctx.collide(x, y, z, body, coll, flags)
+        ctx.collide_clear(x, y, z, coll)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ctx.sync()
+    kt = mls.timing_get(ctx, reset=True)
+    mls.timing_enable(ctx, False)
+    ms = e0.elapsed_time(e1) / max(steps, 1)
+    flagged = int(flags.sum())
+    c = cells / n
+    alg = {"collide": 12 + 4 + 8 * c + 12 + 4 * c + 1, "collide_clear": 12 + 4 * c}
+    kern = {}
+    for k, (t, cnt) in kt.items():
+        avg = t / cnt
+        kern[k] = {"avg_ms": round(avg, 4), "alg_bytes_per_marker": round(alg[k], 2),
+                   "GBs": round(alg[k] * n / (avg * 1e-3) / 1e9, 1)}
+    del coll
+    return {"workload": wl.name, "ms_detect_and_clear": round(ms, 4), "markers_per_s": round(n / (ms * 1e-3), 1),
+            "overhead_vs_step": round(ms / ms_step, 4), "flagged_markers": flagged, "occupied_cells": cells,
+            "shared_cells": shared, "kernels": kern}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="uneven", choices=["uneven", "ellipsoids", "stretched", "sphere"])
+    ap.add_argument("--workload", default="uneven", choices=["uneven", "ellipsoids", "stretched", "sphere", "contact"])
     ap.add_argument("--method", default="exact", choices=["exact", "fast", "learned", "fast_linear"])
     ap.add_argument("--weights", default=None, help="surrogate checkpoint (default: the packaged one)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -369,6 +415,9 @@ def main():
     if not args.no_extra:
         extra["methods"] = compare_methods(torch, ctx, wl, bufs, fields, forcing, x0, y0, z0, area, jitter, seed,
                                            args, ms_graph, method)
+
+        extra["collision"] = collision_cost(torch, ctx, wl, x0, y0, z0, args.steps, ms_graph)
+        log("collision detection: %s" % json.dumps(extra["collision"]))
 
     cpu = None
     if not args.no_cpu:

@@ -201,6 +201,32 @@ mls_status mls_spread(mls_ctx *ctx, int64_t n, const uint32_t *home, const float
                       const float *area, const float *Fx, const float *Fy, const float *Fz,
                       float *fx, float *fy, float *fz, void *stream);
 
+/* Coarse-grained collision detection (Sec. 5, the integer cell array of its
+ * detection algorithm).  coll is a device int32 array with one entry per
+ * Eulerian cell, C order [z][y][x] over the n_z x n_y x n_x cells of the
+ * context's grid (cells, not velocity nodes), holding only zeros on entry (a
+ * fresh array, or one returned to zero by mls_collide_clear).  Marker l
+ * (device FP32 x, y, z) belongs to body body[l] (device int32,
+ * 0 <= body[l] <= 2^31 - 2) and lies in the cell with f[i] <= X < f[i+1]
+ * along each axis (X wrapped on a periodic axis).  On return a cell holds 0
+ * where no marker lies, body + 1 where markers of one body only lie and -1
+ * where markers of two or more bodies lie; if flags (device uint8 of n) is
+ * non-NULL, flags[l] = 1 where the cell of marker l holds -1 (the markers a
+ * collision force applies to), else 0.  The result is independent of marker
+ * order and scheduling, bit for bit.  Device errors (mls_sync, lowest marker
+ * first): a marker with a non-finite coordinate or outside a wall axis raises
+ * MLS_E_SUPPORT, a body id out of range MLS_E_ARG; such markers are left out
+ * and get flag 0.  Cost O(n): three cell lookups per marker, one
+ * compare-and-swap. */
+mls_status mls_collide(mls_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
+                       const int32_t *body, int32_t *coll, uint8_t *flags, void *stream);
+
+/* Returns to zero the entries of coll at the cells of the n markers at x, y, z
+ * (the positions given to mls_collide), so that the array can be reused
+ * without clearing every cell: O(n), not O(cells). */
+mls_status mls_collide_clear(mls_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
+                             int32_t *coll, void *stream);
+
 /* Synchronise `stream`, then report and clear the device error word.
  * Returns MLS_OK or the device error; *first_bad (if non-NULL) receives the
  * lowest offending marker index (or -1). */
@@ -301,6 +327,7 @@ enum {
     MLS_K_BUILD_EXACT = 0, MLS_K_BUILD_FAST = 1, MLS_K_BUILD_LEARNED = 2, MLS_K_INTERP = 3,
     MLS_K_SPREAD_BIN = 4, MLS_K_SPREAD_TILES = 5, MLS_K_JITTER = 6, MLS_K_FORCE = 7,
     MLS_K_BUILD_INTERP = 8,  /* exact build fused with interpolation and forcing (mls_step, MLS_EXACT) */
+    MLS_K_COLLIDE = 9, MLS_K_COLLIDE_CLEAR = 10,
     MLS_K_COUNT = 16
 };
 typedef struct {

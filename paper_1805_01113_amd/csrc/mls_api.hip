@@ -469,6 +469,36 @@ mls_status mls_spread(mls_ctx *ctx, int64_t n, const uint32_t *home, const float
     return MLS_OK;
 }
 
+mls_status mls_collide(mls_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
+                       const int32_t *body, int32_t *coll, uint8_t *flags, void *stream)
+{
+    if (!ctx) return MLS_E_ARG;
+    if (n < 0 || n > (int64_t)0x1fffffff) return fail(ctx, MLS_E_ARG, "bad marker count");
+    if (n > 0 && (!x || !y || !z || !body || !coll)) return fail(ctx, MLS_E_ARG, "null array");
+    hipError_t e;
+    {
+        TimedLaunch t(ctx->c, MLS_K_COLLIDE, static_cast<hipStream_t>(stream));
+        e = launch_collide(ctx->c, n, x, y, z, body, coll, flags, static_cast<hipStream_t>(stream));
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "collide launch");
+    return MLS_OK;
+}
+
+mls_status mls_collide_clear(mls_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
+                             int32_t *coll, void *stream)
+{
+    if (!ctx) return MLS_E_ARG;
+    if (n < 0 || n > (int64_t)0x1fffffff) return fail(ctx, MLS_E_ARG, "bad marker count");
+    if (n > 0 && (!x || !y || !z || !coll)) return fail(ctx, MLS_E_ARG, "null array");
+    hipError_t e;
+    {
+        TimedLaunch t(ctx->c, MLS_K_COLLIDE_CLEAR, static_cast<hipStream_t>(stream));
+        e = launch_collide_clear(ctx->c, n, x, y, z, coll, static_cast<hipStream_t>(stream));
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "collide clear launch");
+    return MLS_OK;
+}
+
 mls_status mls_sync(mls_ctx *ctx, void *stream, int64_t *first_bad)
 {
     if (first_bad) *first_bad = -1;

@@ -192,6 +192,10 @@ hipError_t launch_build_fast(const Ctx &c, int64_t n, const float *x, const floa
 hipError_t launch_build_learned(Ctx &c, int64_t n, const float *x, const float *y, const float *z,
                                 uint32_t *home, float *phi, uint8_t *route, hipStream_t s);
 hipError_t launch_table_build(const Ctx &c, hipStream_t s);
+hipError_t launch_collide(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
+                          const int32_t *body, int32_t *coll, uint8_t *flags, hipStream_t s);
+hipError_t launch_collide_clear(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
+                                int32_t *coll, hipStream_t s);
 hipError_t launch_interp(const Ctx &c, int64_t n, const uint32_t *home, const float *phi,
                          const float *u, const float *v, const float *w,
                          float *U, float *V, float *W, hipStream_t s);

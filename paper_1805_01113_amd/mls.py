@@ -16,6 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmls_hip.so")
 
 MLS_EXACT, MLS_FAST, MLS_LEARNED, MLS_FAST_LINEAR = 0, 1, 2, 3
+MLS_OK, MLS_E_ARG, MLS_E_SUPPORT, MLS_E_SINGULAR, MLS_E_NONFINITE, MLS_E_HIP, MLS_E_NOMEM, MLS_E_RANGE = \
+    0, -1, -2, -3, -4, -5, -6, -7
 W_GAUSS_SHIFTED, W_GAUSS, W_CONST = 0, 1, 2
 STATUS = {0: "MLS_OK", -1: "MLS_E_ARG", -2: "MLS_E_SUPPORT", -3: "MLS_E_SINGULAR", -4: "MLS_E_NONFINITE",
           -5: "MLS_E_HIP", -6: "MLS_E_NOMEM", -7: "MLS_E_RANGE"}
@@ -74,7 +76,7 @@ class _TuneReport(ctypes.Structure):
 
 
 K_NAMES = ["build_exact", "build_fast", "build_learned", "interp", "spread_bin", "spread_tiles", "jitter", "force",
-           "build_interp"]
+           "build_interp", "collide", "collide_clear"]
 
 
 class _Timing(ctypes.Structure):
@@ -102,6 +104,8 @@ def load(path: str = LIB_PATH, need_torch: bool = True):
     L.mls_build.argtypes = [P, I64, P, P, P, I32, P, P, P, P]
     L.mls_interp.argtypes = [P, I64, P, P, P, P, P, P, P, P, P]
     L.mls_spread.argtypes = [P, I64, P, P, P, P, P, P, P, P, P, P]
+    L.mls_collide.argtypes = [P, I64, P, P, P, P, P, P, P]
+    L.mls_collide_clear.argtypes = [P, I64, P, P, P, P, P]
     L.mls_sync.argtypes = [P, P, ctypes.POINTER(I64)]
     L.mls_last_error.argtypes = [P]
     L.mls_last_error.restype = ctypes.c_char_p
@@ -261,6 +265,39 @@ class Context:
                                   _ptr(F[2]), _ptr(fields[0]), _ptr(fields[1]), _ptr(fields[2]), _stream(stream))
         self._raise(st, "mls_spread")
         return fields
+
+    def cell_shape(self):
+        """Shape (z, y, x) of the cell array of collision detection."""
+        return tuple(int(v) for v in self.n[::-1])
+
+    def collide(self, x, y, z, body, coll, flags=None, stream=None):
+        """Coarse-grained collision detection (Sec. 5): enters the markers'
+        body ids into the zeroed int32 cell array coll (0 empty, body + 1 one
+        body, -1 several bodies) and, if given, sets flags [n] uint8 to 1 for
+        markers in a cell holding -1."""
+        import torch
+        n = x.numel()
+        for a, nm in ((x, "x"), (y, "y"), (z, "z")):
+            _check_dev(a, torch.float32, n, nm)
+        _check_dev(body, torch.int32, n, "body")
+        _check_dev(coll, torch.int32, int(np.prod(self.cell_shape())), "coll")
+        if flags is not None:
+            _check_dev(flags, torch.uint8, n, "flags")
+        st = self._lib.mls_collide(self.h, n, _ptr(x), _ptr(y), _ptr(z), _ptr(body), _ptr(coll), _ptr(flags),
+                                   _stream(stream))
+        self._raise(st, "mls_collide")
+        return coll, flags
+
+    def collide_clear(self, x, y, z, coll, stream=None):
+        """Returns the cells of the markers at x, y, z to zero."""
+        import torch
+        n = x.numel()
+        for a, nm in ((x, "x"), (y, "y"), (z, "z")):
+            _check_dev(a, torch.float32, n, nm)
+        _check_dev(coll, torch.int32, int(np.prod(self.cell_shape())), "coll")
+        st = self._lib.mls_collide_clear(self.h, n, _ptr(x), _ptr(y), _ptr(z), _ptr(coll), _stream(stream))
+        self._raise(st, "mls_collide_clear")
+        return coll
 
     def sync(self, stream=None, raise_on_error=True):
         bad = ctypes.c_int64(-1)

@@ -1,0 +1,148 @@
+"""GPU parity of coarse-grained collision detection (Sec. 5) against the
+oracle: the cell array and the marker flags must match bit for bit."""
+import numpy as np
+import pytest
+
+from parity import say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1805_01113_amd import mls
+    mls.load()
+    return torch
+
+
+def _gpu_collide(torch, ctx, x, y, z, body, coll=None):
+    xd, yd, zd = to_dev(x), to_dev(y), to_dev(z)
+    bd = torch.from_numpy(np.ascontiguousarray(body, dtype=np.int32)).cuda()
+    if coll is None:
+        coll = torch.zeros(ctx.cell_shape(), dtype=torch.int32, device="cuda")
+    flags = torch.empty(len(x), dtype=torch.uint8, device="cuda")
+    ctx.collide(xd, yd, zd, bd, coll, flags)
+    ctx.sync()
+    return coll, flags, (xd, yd, zd)
+
+
+def _compare(orc, torch, gs, x, y, z, body, label):
+    from paper_1805_01113_amd import mls
+    ctx = mls.Context(gs.faces, gs.periodic)
+    coll, flags, pos = _gpu_collide(torch, ctx, x, y, z, body)
+    ref = orc.collide(orc.Grid(gs.faces, gs.periodic), x, y, z, body)
+    np.testing.assert_array_equal(coll.cpu().numpy(), ref["coll"])
+    np.testing.assert_array_equal(flags.cpu().numpy(), ref["flag"])
+    say("%s: %d markers, %d flagged, %d shared cells, bit-exact" % (label, len(x), int(ref["flag"].sum()),
+                                                                    int((ref["coll"] == -1).sum())))
+    return ctx, coll, flags, pos, ref
+
+
+def _clustered(seed, n_markers, n_bodies, n, n_hot):
+    rng = np.random.default_rng(seed)
+    hot = rng.integers(0, n, size=(n_hot, 3))
+    pick = rng.integers(0, n_hot, size=n_markers)
+    pos = (hot[pick] + rng.uniform(0, 1, size=(n_markers, 3))) / n
+    pos = np.concatenate([pos, rng.uniform(-0.5, 1.5, size=(n_markers // 4, 3))]).astype(np.float32)
+    body = rng.integers(0, n_bodies, size=len(pos)).astype(np.int32)
+    return pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), body
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_clustered_markers_uniform_grid(orc, torch_cuda, seed):
+    from paper_1805_01113_amd import workloads as W
+    gs = W.GridSpec([W.uniform_faces(32)] * 3, [True] * 3)
+    x, y, z, body = _clustered(seed, 20000, 7, 32, 40)
+    _compare(orc, torch_cuda, gs, x, y, z, body, "clustered seed %d" % seed)
+
+
+def test_stretched_wall_grid(orc, torch_cuda):
+    from paper_1805_01113_amd import workloads as W
+    fz = W.tanh_faces(48, 1.5, 2.5)
+    gs = W.GridSpec([W.uniform_faces(40), W.uniform_faces(24), fz], [True, True, False])
+    rng = np.random.default_rng(8)
+    n = 30000
+    x = rng.uniform(-1, 2, n).astype(np.float32)
+    y = rng.uniform(0, 1, n).astype(np.float32)
+    z = rng.uniform(0.0, 1.5 * (1 - 1e-7), n).astype(np.float32)
+    z[:40] = fz[3:43].astype(np.float32)   # on or next to interior faces (FP32 rounding of the faces)
+    body = rng.integers(0, 4, n).astype(np.int32)
+    _compare(orc, torch_cuda, gs, x, y, z, body, "stretched walls")
+
+
+def test_contact_pairs_clear_and_reuse(orc, torch_cuda):
+    """The contact workload, then the O(n) clear returns the array to zero and
+    a second call on the same array (markers permuted) gives the same cells."""
+    from paper_1805_01113_amd import workloads as W
+    torch = torch_cuda
+    wl = W.contact_pairs(n_pairs=120, n=256)
+    body = W.body_ids(wl.body_offsets)
+    ctx, coll, flags, pos, ref = _compare(orc, torch, wl.grid, wl.x, wl.y, wl.z, body, "contact pairs")
+    assert ref["flag"].sum() > 0
+    ctx.collide_clear(*pos, coll)
+    ctx.sync()
+    assert int(torch.count_nonzero(coll)) == 0
+    p = np.random.default_rng(1).permutation(wl.n)
+    coll2, flags2, _ = _gpu_collide(torch, ctx, wl.x[p], wl.y[p], wl.z[p], body[p], coll=coll)
+    np.testing.assert_array_equal(coll2.cpu().numpy(), ref["coll"])
+    np.testing.assert_array_equal(flags2.cpu().numpy(), ref["flag"][p])
+
+
+def test_empty_and_single(orc, torch_cuda):
+    from paper_1805_01113_amd import mls
+    from paper_1805_01113_amd import workloads as W
+    torch = torch_cuda
+    gs = W.GridSpec([W.uniform_faces(8)] * 3, [True] * 3)
+    ctx = mls.Context(gs.faces, gs.periodic)
+    coll = torch.zeros(ctx.cell_shape(), dtype=torch.int32, device="cuda")
+    e = torch.empty(0, dtype=torch.float32, device="cuda")
+    ctx.collide(e, e, e, torch.empty(0, dtype=torch.int32, device="cuda"), coll,
+                torch.empty(0, dtype=torch.uint8, device="cuda"))
+    ctx.sync()
+    assert int(torch.count_nonzero(coll)) == 0
+    one = np.array([0.3], dtype=np.float32)
+    _compare(orc, torch, gs, one, one, one, np.array([41], dtype=np.int32), "single marker")
+
+
+def test_device_errors_name_lowest_marker(torch_cuda):
+    from paper_1805_01113_amd import mls
+    from paper_1805_01113_amd import workloads as W
+    torch = torch_cuda
+    gs = W.GridSpec([W.uniform_faces(8)] * 3, [True, True, False])
+    ctx = mls.Context(gs.faces, gs.periodic)
+    n = 2000
+    x = np.full(n, 0.5, dtype=np.float32)
+    z = x.copy()
+    z[1500] = 1.0      # on the upper wall: no cell
+    z[1700] = -0.25
+    body = np.zeros(n, dtype=np.int32)
+    body[1600] = -3
+    xd, zd = to_dev(x), to_dev(z)
+    coll = torch.zeros(ctx.cell_shape(), dtype=torch.int32, device="cuda")
+    flags = torch.empty(n, dtype=torch.uint8, device="cuda")
+    ctx.collide(xd, xd, zd, torch.from_numpy(body).cuda(), coll, flags)
+    st, bad = ctx.sync(raise_on_error=False)
+    assert st == mls.MLS_E_SUPPORT and bad == 1500
+    z[1500] = 0.5
+    z[1700] = 0.5
+    coll.zero_()
+    ctx.collide(xd, xd, to_dev(z), torch.from_numpy(body).cuda(), coll, flags)
+    st, bad = ctx.sync(raise_on_error=False)
+    assert st == mls.MLS_E_ARG and bad == 1600
+
+
+@pytest.mark.slow
+def test_contact_pairs_full_size(orc, torch_cuda):
+    """22.3 M markers of 10,000 bodies in contact pairs on 1024^3: the whole
+    cell array (1024^3 cells) and every flag against the oracle."""
+    from paper_1805_01113_amd import workloads as W
+    torch = torch_cuda
+    wl = W.contact_pairs()
+    body = W.body_ids(wl.body_offsets)
+    ctx, coll, flags, pos, ref = _compare(orc, torch, wl.grid, wl.x, wl.y, wl.z, body, "contact pairs full size")
+    ctx.collide_clear(*pos, coll)
+    ctx.sync()
+    assert int(torch.count_nonzero(coll)) == 0
+    ctx.close()

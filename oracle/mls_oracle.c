@@ -849,3 +849,131 @@ int orc_collide(const double *faces, const int32_t *n, const int32_t *periodic,
     for (long l = 0; l < nm; ++l) flag[l] = coll[cell[l]] == -1 ? 1 : 0;
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Adaptive Lagrangian mesh refinement (Sec. 4, Fig. 4, Table 1).            */
+/* ------------------------------------------------------------------------ */
+/* A base triangle V1 V2 V3 carries one marker at its centroid
+ * C = (V1 + V2 + V3)/3 (level 0).  The three refinement levels split it into
+ * sub-triangles and put one marker at each sub-triangle's centroid:
+ *   level 1: L1 = (V1 + V2)/2 splits it in two: (V1, L1, V3), (L1, V2, V3);
+ *   level 2: L2 = C splits it in three: (V1, V2, L2), (V2, V3, L2), (V3, V1, L2);
+ *   level 3: the edge midpoints L31 = (V1 + V2)/2, L32 = (V2 + V3)/2,
+ *            L33 = (V3 + V1)/2 split it in four: (V1, L31, L33), (L31, V2, L32),
+ *            (L33, L32, V3), (L31, L32, L33).
+ * So level L gives L + 1 markers per base triangle (Table 1: x2, x3, x4).
+ * Each marker carries its sub-triangle's flat area and unit normal (right-hand
+ * rule on the vertex order).
+ * Level of a triangle (the paper asks for a Lagrangian spacing no coarser than
+ * the local Eulerian one; the rule is this oracle's reading): l = mean edge
+ * length, h = mean of the three widths of the Eulerian cell containing C; a
+ * split into m sub-triangles shrinks the length scale by sqrt(m), so the level
+ * is the smallest L in 0..3 with l^2 <= ratio^2 h^2 (L + 1), else 3.  A
+ * forced level (0..3) applies to every triangle instead. */
+
+static void tri_sub(const double *A, const double *B, const double *C, double *cen, double *area, double *nrm)
+{
+    double e1[3], e2[3], cr[3];
+    for (int d = 0; d < 3; ++d) {
+        cen[d] = (A[d] + B[d] + C[d]) / 3.0;
+        e1[d] = B[d] - A[d];
+        e2[d] = C[d] - A[d];
+    }
+    cr[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    cr[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    cr[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    double len = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+    *area = 0.5 * len;
+    for (int d = 0; d < 3; ++d) nrm[d] = len > 0.0 ? cr[d] / len : 0.0;
+}
+
+/* Writes, for each base triangle t (vertex indices tri[3t..3t+2] into the
+ * FP32 vertex arrays), its level to tri_level[t] and its L + 1 markers, in
+ * triangle order and the sub-triangle order above, to x, y, z, area,
+ * normal[3 * m + d] (FP64) and parent[m] = t.  *count receives the marker
+ * total.  Errors: a vertex index outside [0, nvert) is ORC_E_ARG, a centroid
+ * outside a wall axis ORC_E_SUPPORT, with the triangle in *bad. */
+int orc_refine(const double *faces, const int32_t *n, const int32_t *periodic,
+               long ntri, const int32_t *tri, long nvert, const float *xv, const float *yv, const float *zv,
+               double ratio, int forced_level, double *x, double *y, double *z, double *area, double *normal,
+               int32_t *parent, uint8_t *tri_level, long *count, long *bad)
+{
+    grid3 g;
+    grid_unpack(faces, n, periodic, &g);
+    *bad = -1;
+    long m = 0;
+    for (long t = 0; t < ntri; ++t) {
+        double V[3][3];
+        for (int a = 0; a < 3; ++a) {
+            long iv = tri[3 * t + a];
+            if (iv < 0 || iv >= nvert) { *bad = t; return ORC_E_ARG; }
+            V[a][0] = xv[iv]; V[a][1] = yv[iv]; V[a][2] = zv[iv];
+        }
+        double C[3];
+        for (int d = 0; d < 3; ++d) C[d] = (V[0][d] + V[1][d] + V[2][d]) / 3.0;
+        int level = forced_level;
+        if (level < 0) {
+            double h = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                long ic;
+                if (cell_axis(g.f[d], g.n[d], g.periodic[d], C[d], &ic) != ORC_OK) { *bad = t; return ORC_E_SUPPORT; }
+                h += g.f[d][ic + 1] - g.f[d][ic];
+            }
+            h /= 3.0;
+            double l = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double *P = V[a], *Q = V[(a + 1) % 3];
+                l += sqrt((Q[0] - P[0]) * (Q[0] - P[0]) + (Q[1] - P[1]) * (Q[1] - P[1]) +
+                          (Q[2] - P[2]) * (Q[2] - P[2]));
+            }
+            l /= 3.0;
+            level = 3;
+            for (int L = 0; L <= 3; ++L) {
+                if (l * l <= ratio * ratio * h * h * (double)(L + 1)) { level = L; break; }
+            }
+        }
+        tri_level[t] = (uint8_t)level;
+        const double *V1 = V[0], *V2 = V[1], *V3 = V[2];
+        double sub[4][3][3];
+        int ns = level + 1;
+        double L1[3], L31[3], L32[3], L33[3];
+        for (int d = 0; d < 3; ++d) {
+            L1[d] = 0.5 * (V1[d] + V2[d]);
+            L31[d] = 0.5 * (V1[d] + V2[d]);
+            L32[d] = 0.5 * (V2[d] + V3[d]);
+            L33[d] = 0.5 * (V3[d] + V1[d]);
+        }
+        for (int d = 0; d < 3; ++d) {
+            switch (level) {
+            case 0:
+                sub[0][0][d] = V1[d]; sub[0][1][d] = V2[d]; sub[0][2][d] = V3[d];
+                break;
+            case 1:
+                sub[0][0][d] = V1[d]; sub[0][1][d] = L1[d]; sub[0][2][d] = V3[d];
+                sub[1][0][d] = L1[d]; sub[1][1][d] = V2[d]; sub[1][2][d] = V3[d];
+                break;
+            case 2:
+                sub[0][0][d] = V1[d]; sub[0][1][d] = V2[d]; sub[0][2][d] = C[d];
+                sub[1][0][d] = V2[d]; sub[1][1][d] = V3[d]; sub[1][2][d] = C[d];
+                sub[2][0][d] = V3[d]; sub[2][1][d] = V1[d]; sub[2][2][d] = C[d];
+                break;
+            default:
+                sub[0][0][d] = V1[d]; sub[0][1][d] = L31[d]; sub[0][2][d] = L33[d];
+                sub[1][0][d] = L31[d]; sub[1][1][d] = V2[d]; sub[1][2][d] = L32[d];
+                sub[2][0][d] = L33[d]; sub[2][1][d] = L32[d]; sub[2][2][d] = V3[d];
+                sub[3][0][d] = L31[d]; sub[3][1][d] = L32[d]; sub[3][2][d] = L33[d];
+                break;
+            }
+        }
+        for (int s = 0; s < ns; ++s, ++m) {
+            double cen[3], a, nr[3];
+            tri_sub(sub[s][0], sub[s][1], sub[s][2], cen, &a, nr);
+            x[m] = cen[0]; y[m] = cen[1]; z[m] = cen[2];
+            area[m] = a;
+            for (int d = 0; d < 3; ++d) normal[3 * m + d] = nr[d];
+            parent[m] = (int32_t)t;
+        }
+    }
+    *count = m;
+    return ORC_OK;
+}

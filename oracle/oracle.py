@@ -71,6 +71,7 @@ def lib():
             L.orc_node_volumes.argtypes = [P, P, P, i32, P]
             L.orc_axis_nodes.argtypes = [P, P, P, i32, i32, P]
             L.orc_collide.argtypes = [P, P, P, i64, P, P, P, P, P, P, P, P]
+            L.orc_refine.argtypes = [P, P, P, i64, P, i64, P, P, P, f64, i32, P, P, P, P, P, P, P, P, P]
             _lib = L
     return _lib
 
@@ -275,6 +276,31 @@ def collide(grid: Grid, x, y, z, body, check=True):
     if rc != 0 and check:
         raise OracleError(rc, bad.value)
     return dict(coll=coll, flag=flag, cell=cell, rc=rc, bad=bad.value)
+
+
+def refine(grid: Grid, tri, xv, yv, zv, ratio=1.0, level=-1, check=True):
+    """Adaptive Lagrangian mesh refinement (Sec. 4): returns dict(x, y, z,
+    area [M] FP64, normal [M, 3], parent [M] int32, level [T] uint8, count)
+    for the base triangles tri [T, 3] over FP32 vertices; level -1 chooses
+    each triangle's level from its size against the local cell size."""
+    tri = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
+    xv, yv, zv = _markers(xv, yv, zv)
+    T = tri.shape[0]
+    M = 4 * T
+    x, y, z, area = (np.empty(M) for _ in range(4))
+    normal = np.empty((M, 3))
+    parent = np.empty(M, dtype=np.int32)
+    lev = np.empty(T, dtype=np.uint8)
+    count = ctypes.c_long(0)
+    bad = ctypes.c_long(-1)
+    rc = lib().orc_refine(*grid.args(), T, _p(tri), len(xv), _p(xv), _p(yv), _p(zv), float(ratio), int(level),
+                          _p(x), _p(y), _p(z), _p(area), _p(normal), _p(parent), _p(lev), ctypes.byref(count),
+                          ctypes.byref(bad))
+    if rc != 0 and check:
+        raise OracleError(rc, bad.value)
+    m = count.value
+    return dict(x=x[:m], y=y[:m], z=z[:m], area=area[:m], normal=normal[:m], parent=parent[:m], level=lev,
+                count=m, rc=rc, bad=bad.value)
 
 
 # ---------------------------------------------------------------------------

@@ -164,6 +164,37 @@ def surface_markers(subdiv, centres, axes, rots, chunk=256):
     return pos, area, nrm
 
 
+def surface_mesh(subdiv, centres, axes, rots):
+    """Triangle meshes of bodies sharing one icosphere template (the base
+    Lagrangian meshes whose face centroids surface_markers returns): FP32
+    vertices [nb*nv, 3] and int32 triangles [nb*nf, 3] indexing them, body
+    after body, in the template's face order."""
+    V, F = _ico(subdiv)
+    nb = len(centres)
+    sv = V[None, :, :] * np.asarray(axes)[:, None, :]
+    Vb = np.einsum("bij,bvj->bvi", rots, sv) + np.asarray(centres)[:, None, :]
+    tri = (F[None, :, :] + (np.arange(nb) * len(V))[:, None, None]).reshape(-1, 3)
+    return Vb.reshape(-1, 3).astype(np.float32), tri.astype(np.int32)
+
+
+def body_mesh(wl):
+    """Base meshes of a workload's bodies (stored by the generators that keep
+    their geometry): (vertices [nv, 3] FP32, triangles [nt, 3] int32), the
+    triangles in the order of the workload's markers."""
+    m = wl.meta
+    if "centres" not in m:
+        raise ValueError("workload %s keeps no body geometry" % wl.name)
+    subdiv = np.asarray(m["subdivs"])
+    verts, tris, base = [], [], 0
+    # bodies are stored one after another; group runs of equal subdivision
+    for b0 in range(len(subdiv)):
+        v, t = surface_mesh(int(subdiv[b0]), m["centres"][b0:b0 + 1], m["axes"][b0:b0 + 1], m["rots"][b0:b0 + 1])
+        verts.append(v)
+        tris.append(t + base)
+        base += len(v)
+    return np.concatenate(verts), np.concatenate(tris)
+
+
 def place_bodies(r: np.random.Generator, radii, lo, hi, periodic, gap, max_tries=2000000):
     """Random non-overlapping placement: bounding spheres of radius R_i keep a
     periodic distance >= R_i + R_j + gap.  lo/hi bound the centres per axis.
@@ -305,9 +336,11 @@ def single_sphere(n: int = 64, subdiv: int = 4, radius: float = 0.1, n_modes: in
     U[0,1)^3, periodic unit cube with a uniform n^3 staggered grid."""
     g = GridSpec([uniform_faces(n)] * 3, [True] * 3)
     c = rng("placement", cfg_id).random((1, 3))
-    pos, area, nrm = surface_markers(subdiv, c, np.full((1, 3), radius), np.eye(3)[None])
+    axes = np.full((1, 3), radius)
+    pos, area, nrm = surface_markers(subdiv, c, axes, np.eye(3)[None])
     return _finish("single_sphere_%d^3_sub%d" % (n, subdiv), g, [1.0] * 3, pos, area, nrm,
-                   [0, len(area)], cfg_id, n_modes)
+                   [0, len(area)], cfg_id, n_modes,
+                   meta=dict(centres=c, axes=axes, rots=np.eye(3)[None], subdivs=np.array([subdiv])))
 
 
 def ellipsoids(n_bodies: int = 1000, n: int = 512, subdiv: int = 3, r0_h: float = 5.31,
@@ -356,7 +389,8 @@ def uneven_bodies(n_bodies: int = 10000, n: int = 1024, n_modes: int = 16, cfg_i
         dst = (offs[idx][:, None] + np.arange(nf)[None, :]).reshape(-1)
         pos[dst] = p; area[dst] = a; nrm[dst] = nr
     return _finish("uneven_%d_%d^3" % (n_bodies, n), g, [1.0] * 3, pos, area, nrm, offs, cfg_id, n_modes,
-                   meta=dict(n_bodies=n_bodies, levels=lvl))
+                   meta=dict(n_bodies=n_bodies, levels=lvl, centres=cen, axes=axes, rots=rots,
+                             subdivs=np.array(subdivs)[lvl]))
 
 
 def contact_pairs(n_pairs: int = 5000, n: int = 1024, n_modes: int = 16, cfg_id: int = 6,
@@ -423,7 +457,8 @@ def stretched_channel(n_bodies: int = 2000, nxy: int = 512, nz: int = 768, lz: f
     nf = len(_ico(subdiv)[1])
     offs = np.arange(n_bodies + 1) * nf
     dz = np.diff(fz)
+    geo = dict(centres=cen, axes=np.full((n_bodies, 3), r), rots=rots, subdivs=np.full(n_bodies, subdiv))
     return _finish("stretched_%d_%dx%dx%d_beta%.2f" % (n_bodies, nxy, nxy, nz, beta), g, [1.0, 1.0, lz],
                    pos, area, nrm, offs, cfg_id, n_modes,
                    meta=dict(n_bodies=n_bodies, dz_min=float(dz.min()), dz_max=float(dz.max()),
-                             dz_ratio=float(dz.min() / dz.max())))
+                             dz_ratio=float(dz.min() / dz.max()), **geo))

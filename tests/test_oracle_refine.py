@@ -1,0 +1,169 @@
+"""Pins of the oracle's adaptive Lagrangian mesh refinement (Sec. 4).
+
+Against what the paper prints and what geometry fixes: the marker counts of
+Table 1 (multiplicities 2, 3, 4 of levels 1-3), the refined positions of a
+unit triangle worked out by hand from Fig. 4, conservation of area and of the
+first moment of area by every split, sub-markers inside their triangle with
+the parent's normal, level 0 equal to the base markers of the workloads, and
+the level rule against closed forms on uniform and stretched grids."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1805_01113_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _rows(name):
+    out = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                out.append([float(v) for v in line.split()])
+    return out
+
+
+def _grid(n=16, periodic=True):
+    return orc.Grid([W.uniform_faces(n)] * 3, [periodic] * 3)
+
+
+def _strip(ntri):
+    """A strip of ntri triangles over two rows of vertices in the unit box."""
+    k = ntri // 2 + 2
+    xs = np.linspace(0.1, 0.9, k)
+    vx = np.concatenate([xs, xs]).astype(np.float32)
+    vy = np.concatenate([np.full(k, 0.4), np.full(k, 0.6)]).astype(np.float32)
+    vz = np.full(2 * k, 0.5, dtype=np.float32)
+    tris = []
+    for i in range(k - 1):
+        tris.append((i, i + 1, k + i))
+        tris.append((i + 1, k + i + 1, k + i))
+    return np.array(tris[:ntri], dtype=np.int32), vx, vy, vz
+
+
+def test_table1_marker_counts():
+    rows = _rows("table1_refinement_counts.txt")
+    assert len(rows) == 6
+    for we, base, refined in rows:
+        base, refined = int(base), int(refined)
+        if refined % base:
+            # the one row that is no multiple: read as 4 x base
+            assert (base, refined) == (162, 628)
+            refined = 4 * base
+        mult = refined // base
+        assert mult in (2, 3, 4)
+        tri, vx, vy, vz = _strip(base)
+        r = orc.refine(_grid(), tri, vx, vy, vz, level=mult - 1)
+        assert r["count"] == refined
+        assert np.all(r["level"] == mult - 1)
+        np.testing.assert_array_equal(np.bincount(r["parent"], minlength=base), np.full(base, mult))
+
+
+def test_fig4_unit_triangle():
+    rows = _rows("fig4_unit_triangle_refined.txt")
+    g = _grid()
+    for level in range(4):
+        exp = np.array([[xn / den, yn / den] for lv, xn, yn, den in rows if int(lv) == level])
+        r = orc.refine(g, [[0, 1, 2]], [0, 1, 0], [0, 0, 1], [0, 0, 0], level=level)
+        assert r["count"] == level + 1
+        np.testing.assert_allclose(np.stack([r["x"], r["y"]], axis=1), exp, rtol=0, atol=1e-15)
+        np.testing.assert_array_equal(r["z"], 0.0)
+        np.testing.assert_allclose(r["area"], 0.5 / (level + 1), rtol=1e-15)
+        np.testing.assert_allclose(r["normal"], np.tile([0.0, 0.0, 1.0], (level + 1, 1)), atol=1e-15)
+        assert np.all(r["parent"] == 0)
+
+
+@pytest.mark.parametrize("level", [0, 1, 2, 3])
+def test_splits_conserve_area_and_moment(level):
+    rng = np.random.default_rng(level)
+    T = 200
+    v = rng.uniform(0.2, 0.8, size=(3 * T, 3)).astype(np.float32)
+    tri = np.arange(3 * T, dtype=np.int32).reshape(T, 3)
+    r = orc.refine(_grid(), tri, v[:, 0], v[:, 1], v[:, 2], level=level)
+    m = level + 1
+    assert r["count"] == m * T
+    V = v.astype(np.float64)[tri]                        # [T, 3 vertices, 3]
+    C = V.mean(axis=1)
+    cr = np.cross(V[:, 1] - V[:, 0], V[:, 2] - V[:, 0])
+    A = 0.5 * np.linalg.norm(cr, axis=1)
+    nrm = cr / (2 * A[:, None])
+    a = r["area"].reshape(T, m)
+    P = np.stack([r["x"], r["y"], r["z"]], axis=1).reshape(T, m, 3)
+    np.testing.assert_allclose(a.sum(axis=1), A, rtol=1e-12)
+    np.testing.assert_allclose(a, np.repeat(A[:, None], m, axis=1) / m, rtol=1e-10)
+    np.testing.assert_allclose((a[:, :, None] * P).sum(axis=1) / A[:, None], C, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(r["normal"].reshape(T, m, 3), np.repeat(nrm[:, None], m, axis=1), atol=1e-10)
+    # every sub-marker lies strictly inside its base triangle (barycentric > 0)
+    for t in range(0, T, 17):
+        E = np.stack([V[t, 1] - V[t, 0], V[t, 2] - V[t, 0]], axis=1)
+        for s in range(m):
+            bc = np.linalg.lstsq(E, P[t, s] - V[t, 0], rcond=None)[0]
+            assert bc.min() > 0 and bc.sum() < 1
+
+
+def test_level_rule_on_uniform_grid():
+    """Equilateral triangles of edge l on a grid of spacing h: the level is the
+    smallest L with l <= ratio h sqrt(L + 1), at most 3."""
+    n = 64
+    h = 1.0 / n
+    g = _grid(n)
+    for ratio in (1.0, 0.8):
+        for lh in (0.5, 0.9, 1.2, 1.5, 1.8, 2.5):
+            l = lh * h
+            c = np.array([0.5 + 0.3 * h, 0.5 + 0.2 * h, 0.5 + 0.1 * h])
+            V = c + l * np.array([[-0.5, -np.sqrt(3) / 6, 0], [0.5, -np.sqrt(3) / 6, 0], [0, np.sqrt(3) / 3, 0]])
+            V = V.astype(np.float32)
+            r = orc.refine(g, [[0, 1, 2]], V[:, 0], V[:, 1], V[:, 2], ratio=ratio)
+            want = next((L for L in range(4) if lh <= ratio * np.sqrt(L + 1)), 3)
+            assert r["level"][0] == want, (ratio, lh)
+
+
+def test_level_follows_stretched_cells():
+    """One triangle moved along a tanh-stretched wall axis: its level equals
+    the rule applied to the cell widths found by a plain search of the faces,
+    and grows where the cells shrink."""
+    fz = W.tanh_faces(96, 1.5, 2.5)
+    faces = [W.uniform_faces(64), W.uniform_faces(64), fz]
+    g = orc.Grid(faces, (True, True, False))
+    base = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.2], [0.3, 1.0, -0.1]]) * (1.2 / 64)
+    levels, zs = [], np.linspace(0.02, 0.75, 60)
+    for zc in zs:
+        V = (base + [0.5, 0.5, zc]).astype(np.float32)
+        r = orc.refine(g, [[0, 1, 2]], V[:, 0], V[:, 1], V[:, 2])
+        Vd = V.astype(np.float64)
+        C = Vd.mean(axis=0)
+        h = np.mean([np.diff(faces[d])[np.searchsorted(faces[d], C[d], side="right") - 1] for d in range(3)])
+        l = np.mean([np.linalg.norm(Vd[(a + 1) % 3] - Vd[a]) for a in range(3)])
+        want = next((L for L in range(4) if l * l <= h * h * (L + 1)), 3)
+        assert r["level"][0] == want
+        levels.append(want)
+    assert levels[0] > levels[-1]            # finer cells at the wall, more markers
+    assert all(a >= b for a, b in zip(levels, levels[1:]))
+
+
+def test_level0_reproduces_base_markers():
+    wl = W.single_sphere(n=64, subdiv=3)
+    v, t = W.body_mesh(wl)
+    r = orc.refine(orc.Grid(wl.grid.faces, wl.grid.periodic), t, v[:, 0], v[:, 1], v[:, 2], level=0)
+    assert r["count"] == wl.n
+    np.testing.assert_allclose(np.stack([r["x"], r["y"], r["z"]], axis=1),
+                               np.stack([wl.x, wl.y, wl.z], axis=1), rtol=0, atol=2e-7)
+    # the workload's areas come from FP64 vertices, the mesh holds them rounded to
+    # FP32 (3e-8 at coordinates near 0.5, edges of 1e-2): about 1e-5 relative
+    np.testing.assert_allclose(r["area"], wl.area, rtol=2e-5)
+    # the template's vertex order is outward: the parent normals are the workload's outward normals
+    np.testing.assert_allclose(r["normal"], wl.normal, atol=1e-5)
+
+
+def test_errors_name_the_first_bad_triangle():
+    g = orc.Grid([W.uniform_faces(8)] * 3, (True, True, False))
+    vx = np.array([0.5, 0.6, 0.5, 0.5], dtype=np.float32)
+    vz = np.array([0.5, 0.5, 0.6, 1.2], dtype=np.float32)
+    r = orc.refine(g, [[0, 1, 2], [0, 1, 7], [0, 1, 3]], vx, vx, vz, check=False)
+    assert r["rc"] == -1 and r["bad"] == 1
+    r = orc.refine(g, [[0, 1, 2], [3, 3, 3]], vx, vx, vz, check=False)
+    assert r["rc"] == orc.E_SUPPORT and r["bad"] == 1

@@ -278,6 +278,36 @@ def collision_cost(torch, ctx, wl, x, y, z, steps, ms_step):
             "shared_cells": shared, "kernels": kern}
 
 
+def refinement_cost(torch, ctx, wl, steps):
+    """Adaptive Lagrangian refinement of the workload's base meshes (one
+    triangle per marker): time per call, markers out, level histogram."""
+    from paper_1805_01113_amd import mls
+    from paper_1805_01113_amd import workloads as W
+    v, t = W.body_mesh(wl)
+    tri = torch.from_numpy(t).cuda()
+    xv, yv, zv = (torch.from_numpy(np.ascontiguousarray(v[:, d])).cuda() for d in range(3))
+    r = ctx.refine(tri, xv, yv, zv)
+    ctx.sync()
+    m = r["count"]
+    hist = torch.bincount(r["level"].long(), minlength=4).tolist()
+    del r
+    mls.timing_enable(ctx, True)
+    mls.timing_get(ctx, reset=True)
+    for _ in range(steps):
+        ctx.refine(tri, xv, yv, zv, sync=False)
+    torch.cuda.synchronize()
+    ctx.sync()
+    kt = mls.timing_get(ctx, reset=True)
+    mls.timing_enable(ctx, False)
+    ms = kt["refine"][0] / kt["refine"][1]
+    T = len(t)
+    # per triangle, in each of the two passes: indices 12 B and 3 vertices
+    # 36 B; the level byte written once and read once; per marker 32 B written
+    alg = T * (2 * (12 + 36) + 2) + m * 32
+    return {"triangles": T, "markers_out": m, "levels": hist, "ms": round(ms, 4),
+            "triangles_per_s": round(T / (ms * 1e-3), 1), "alg_GBs": round(alg / (ms * 1e-3) / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -418,6 +448,9 @@ def main():
 
         extra["collision"] = collision_cost(torch, ctx, wl, x0, y0, z0, args.steps, ms_graph)
         log("collision detection: %s" % json.dumps(extra["collision"]))
+        if "centres" in wl.meta:
+            extra["refinement"] = refinement_cost(torch, ctx, wl, args.steps)
+            log("refinement: %s" % json.dumps(extra["refinement"]))
 
     cpu = None
     if not args.no_cpu:

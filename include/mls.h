@@ -227,6 +227,38 @@ mls_status mls_collide(mls_ctx *ctx, int64_t n, const float *x, const float *y, 
 mls_status mls_collide_clear(mls_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
                              int32_t *coll, void *stream);
 
+/* Adaptive Lagrangian mesh refinement (Sec. 4, Fig. 4, Table 1): markers
+ * for the interfacial condition generated from a base triangle mesh.
+ * tri (device int32 [ntri][3]) indexes the nvert vertices xv, yv, zv
+ * (device FP32).  Base triangle V1 V2 V3 gets a level L in 0..3 and L + 1
+ * markers, one at the centroid of each sub-triangle, with the sub-triangle's
+ * flat area and unit normal (right-hand rule on the vertex order):
+ *   L = 0: the triangle itself (marker at C = (V1 + V2 + V3)/3);
+ *   L = 1: split at L1 = (V1 + V2)/2 into (V1, L1, V3), (L1, V2, V3);
+ *   L = 2: split at C into (V1, V2, C), (V2, V3, C), (V3, V1, C);
+ *   L = 3: split at the edge midpoints L31 = (V1 + V2)/2, L32 = (V2 + V3)/2,
+ *          L33 = (V3 + V1)/2 into (V1, L31, L33), (L31, V2, L32),
+ *          (L33, L32, V3), (L31, L32, L33).
+ * level = -1 chooses per triangle the smallest L with
+ * l^2 <= ratio^2 h^2 (L + 1), at most 3, where l is the mean edge length and
+ * h the mean of the three widths of the Eulerian cell containing C (a split
+ * into L + 1 parts shrinks the length scale by sqrt(L + 1); ratio is the
+ * largest Lagrangian-to-Eulerian spacing kept, ratio > 0); level = 0..3
+ * forces that level on every triangle.  Outputs (device, capacity >= 4 ntri
+ * entries each; normal is [3][capacity]): markers in triangle order, then
+ * sub-triangle order as listed, x, y, z, area, normal, parent (base triangle
+ * index); tri_level (device uint8 [ntri]) the levels; *count (device int64)
+ * the number of markers written.  Geometry is evaluated in FP64 from the FP32
+ * vertices and rounded to FP32 once.  Device errors: a vertex index outside
+ * [0, nvert) raises MLS_E_ARG, a centroid with no Eulerian cell (adaptive
+ * level only) MLS_E_SUPPORT, with the lowest triangle index; such a triangle
+ * gets level 0 (NaN marker for a bad index).  May allocate a small scratch
+ * buffer on first use or growth (not while a graph is captured). */
+mls_status mls_refine(mls_ctx *ctx, int64_t ntri, const int32_t *tri, int64_t nvert, const float *xv,
+                      const float *yv, const float *zv, double ratio, int32_t level, int64_t capacity, float *x,
+                      float *y, float *z, float *area, float *normal, int32_t *parent, uint8_t *tri_level,
+                      int64_t *count, void *stream);
+
 /* Synchronise `stream`, then report and clear the device error word.
  * Returns MLS_OK or the device error; *first_bad (if non-NULL) receives the
  * lowest offending marker index (or -1). */
@@ -327,7 +359,7 @@ enum {
     MLS_K_BUILD_EXACT = 0, MLS_K_BUILD_FAST = 1, MLS_K_BUILD_LEARNED = 2, MLS_K_INTERP = 3,
     MLS_K_SPREAD_BIN = 4, MLS_K_SPREAD_TILES = 5, MLS_K_JITTER = 6, MLS_K_FORCE = 7,
     MLS_K_BUILD_INTERP = 8,  /* exact build fused with interpolation and forcing (mls_step, MLS_EXACT) */
-    MLS_K_COLLIDE = 9, MLS_K_COLLIDE_CLEAR = 10,
+    MLS_K_COLLIDE = 9, MLS_K_COLLIDE_CLEAR = 10, MLS_K_REFINE = 11,
     MLS_K_COUNT = 16
 };
 typedef struct {

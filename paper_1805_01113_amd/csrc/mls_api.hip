@@ -348,6 +348,7 @@ void mls_ctx_destroy(mls_ctx *ctx)
     hipFree(c.entries);
     hipFree(c.block_fmax);
     hipFree(c.tile_hmin_block);
+    hipFree(c.refine_scratch);
     hipFree(c.work);
     hipFree(c.step_ctr);
     mlp_free(c);
@@ -496,6 +497,30 @@ mls_status mls_collide_clear(mls_ctx *ctx, int64_t n, const float *x, const floa
         e = launch_collide_clear(ctx->c, n, x, y, z, coll, static_cast<hipStream_t>(stream));
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "collide clear launch");
+    return MLS_OK;
+}
+
+mls_status mls_refine(mls_ctx *ctx, int64_t ntri, const int32_t *tri, int64_t nvert, const float *xv,
+                      const float *yv, const float *zv, double ratio, int32_t level, int64_t capacity, float *x,
+                      float *y, float *z, float *area, float *normal, int32_t *parent, uint8_t *tri_level,
+                      int64_t *count, void *stream)
+{
+    if (!ctx) return MLS_E_ARG;
+    if (ntri < 0 || ntri > (int64_t)1 << 28) return fail(ctx, MLS_E_ARG, "bad triangle count");
+    if (nvert < 0 || nvert > (int64_t)0x7fffffff) return fail(ctx, MLS_E_ARG, "bad vertex count");
+    if (level < -1 || level > 3) return fail(ctx, MLS_E_ARG, "refinement level must be -1 (adaptive) or 0..3");
+    if (level < 0 && !(ratio > 0.0 && ratio < 1e30)) return fail(ctx, MLS_E_ARG, "bad refinement ratio");
+    if (capacity < 4 * ntri) return fail(ctx, MLS_E_ARG, "capacity below 4 markers per triangle");
+    if (!count) return fail(ctx, MLS_E_ARG, "null count");
+    if (ntri > 0 && (!tri || !xv || !yv || !zv || !x || !y || !z || !area || !normal || !parent || !tri_level))
+        return fail(ctx, MLS_E_ARG, "null array");
+    hipError_t e;
+    {
+        TimedLaunch t(ctx->c, MLS_K_REFINE, static_cast<hipStream_t>(stream));
+        e = launch_refine(ctx->c, ntri, tri, nvert, xv, yv, zv, ratio, level, capacity, x, y, z, area, normal,
+                          parent, tri_level, count, static_cast<hipStream_t>(stream));
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "refine launch");
     return MLS_OK;
 }
 

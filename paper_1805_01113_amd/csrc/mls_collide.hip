@@ -20,32 +20,6 @@ namespace {
 
 constexpr int kCollBlock = 256;
 
-// Cell along one axis that contains x: f[i] <= X < f[i+1], X wrapped into
-// [f0, f0 + L) on a periodic axis.  false for a non-finite coordinate or one
-// outside [f0, fn) on a wall axis.
-__device__ __forceinline__ bool cell_axis(const Axis &a, float xf, int &i)
-{
-    const double x = (double)xf;
-    if (!isfinite(x)) return false;
-    const int n = a.n;
-    const double X = a.periodic ? wrap_x(a, x) : x;
-    if (!(X >= fval(a, 0) && X < fval(a, n))) return false;
-    if (a.uniform) {
-        i = (int)floor((X - a.f0) * a.inv_h);
-        i = min(max(i, 0), n - 1);
-        while (i > 0 && X < fval(a, i)) --i;
-        while (i < n - 1 && X >= fval(a, i + 1)) ++i;
-    } else {
-        int lo = 0, hi = n;   // faces[lo] <= X < faces[hi]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (a.faces[mid] <= X) lo = mid; else hi = mid;
-        }
-        i = lo;
-    }
-    return true;
-}
-
 // Linear index [z][y][x] of the cell of marker l, or -1 (error raised).
 __device__ __forceinline__ int64_t marker_cell(const Grid &g, int64_t l, const float *x, const float *y,
                                                const float *z, ErrWord *err)

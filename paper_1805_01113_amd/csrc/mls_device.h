@@ -75,6 +75,31 @@ __device__ __forceinline__ double wrap_x(const Axis &a, double x)
     return X;
 }
 
+// Eulerian cell along one axis that contains x: f[i] <= X < f[i+1], X wrapped
+// into [f0, f0 + L) on a periodic axis.  false for a non-finite coordinate or
+// one outside [f0, fn) on a wall axis.
+__device__ __forceinline__ bool cell_axis(const Axis &a, double x, int &i)
+{
+    if (!isfinite(x)) return false;
+    const int n = a.n;
+    const double X = a.periodic ? wrap_x(a, x) : x;
+    if (!(X >= fval(a, 0) && X < fval(a, n))) return false;
+    if (a.uniform) {
+        i = (int)floor((X - a.f0) * a.inv_h);
+        i = min(max(i, 0), n - 1);
+        while (i > 0 && X < fval(a, i)) --i;
+        while (i < n - 1 && X >= fval(a, i + 1)) ++i;
+    } else {
+        int lo = 0, hi = n;   // faces[lo] <= X < faces[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (a.faces[mid] <= X) lo = mid; else hi = mid;
+        }
+        i = lo;
+    }
+    return true;
+}
+
 // Home node along one axis: the node whose control volume [lo, hi) contains
 // the marker.  Returns false if the support leaves a wall axis or x is not
 // finite.  On success ih_u is the unwrapped home index (a periodic face axis
@@ -347,6 +372,26 @@ __device__ __forceinline__ int64_t xcd_block()
 {
     const int nb = (int)gridDim.x, b = (int)blockIdx.x;
     return (int64_t)(b & 7) * (nb >> 3) + (b >> 3);
+}
+
+// Exclusive scan of v over a workgroup of 256 threads (4 wavefronts); sh holds
+// 4 words of LDS.  total receives the workgroup sum.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t &total)
+{
+    // inclusive scan within the wavefront, then across the 4 wavefronts
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) sh[wid] = x;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int q = 0; q < wid; ++q) base += sh[q];
+    total = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return base + x - v;
 }
 
 __host__ __device__ __forceinline__ int64_t round_up8(int64_t b) { return (b + 7) & ~(int64_t)7; }

@@ -161,6 +161,9 @@ struct Ctx {
     int cu_count = 256;
     // learned surrogate
     Mlp mlp;
+    // Lagrangian refinement: per-workgroup marker sums and offsets
+    uint32_t *refine_scratch = nullptr;
+    int64_t refine_cap = 0;
     // time step
     unsigned long long *step_ctr = nullptr;
     int64_t step_sorted_n = -1;   // markers of the last exact step (its rows are in tile order)
@@ -196,6 +199,10 @@ hipError_t launch_collide(const Ctx &c, int64_t n, const float *x, const float *
                           const int32_t *body, int32_t *coll, uint8_t *flags, hipStream_t s);
 hipError_t launch_collide_clear(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
                                 int32_t *coll, hipStream_t s);
+hipError_t launch_refine(Ctx &c, int64_t ntri, const int32_t *tri, int64_t nvert, const float *xv,
+                         const float *yv, const float *zv, double ratio, int level, int64_t cap, float *x,
+                         float *y, float *z, float *area, float *normal, int32_t *parent, uint8_t *tri_level,
+                         int64_t *count, hipStream_t s);
 hipError_t launch_interp(const Ctx &c, int64_t n, const uint32_t *home, const float *phi,
                          const float *u, const float *v, const float *w,
                          float *U, float *V, float *W, hipStream_t s);

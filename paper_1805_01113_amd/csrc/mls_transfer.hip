@@ -215,24 +215,6 @@ __global__ void k_zero_u32(uint32_t *__restrict__ p, int64_t n)
 // the partials, then each block scans its chunk.  off[ntiles] = total.
 constexpr int kScanChunk = 2048;   // elements per block (256 threads x 8)
 
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t &total)
-{
-    // inclusive scan within the wavefront, then across the 4 wavefronts
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    uint32_t x = v;
-    for (int off = 1; off < 64; off <<= 1) {
-        uint32_t y = __shfl_up(x, off);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) sh[wid] = x;
-    __syncthreads();
-    uint32_t base = 0;
-    for (int q = 0; q < wid; ++q) base += sh[q];
-    total = sh[0] + sh[1] + sh[2] + sh[3];
-    __syncthreads();
-    return base + x - v;
-}
-
 __global__ void __launch_bounds__(kBlock) k_scan_partials(const uint32_t *__restrict__ count, int64_t nt,
                                                           uint32_t *__restrict__ partial)
 {

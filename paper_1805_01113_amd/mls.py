@@ -76,7 +76,7 @@ class _TuneReport(ctypes.Structure):
 
 
 K_NAMES = ["build_exact", "build_fast", "build_learned", "interp", "spread_bin", "spread_tiles", "jitter", "force",
-           "build_interp", "collide", "collide_clear"]
+           "build_interp", "collide", "collide_clear", "refine"]
 
 
 class _Timing(ctypes.Structure):
@@ -106,6 +106,7 @@ def load(path: str = LIB_PATH, need_torch: bool = True):
     L.mls_spread.argtypes = [P, I64, P, P, P, P, P, P, P, P, P, P]
     L.mls_collide.argtypes = [P, I64, P, P, P, P, P, P, P]
     L.mls_collide_clear.argtypes = [P, I64, P, P, P, P, P]
+    L.mls_refine.argtypes = [P, I64, P, I64, P, P, P, ctypes.c_double, I32, I64, P, P, P, P, P, P, P, P, P]
     L.mls_sync.argtypes = [P, P, ctypes.POINTER(I64)]
     L.mls_last_error.argtypes = [P]
     L.mls_last_error.restype = ctypes.c_char_p
@@ -287,6 +288,36 @@ class Context:
                                    _stream(stream))
         self._raise(st, "mls_collide")
         return coll, flags
+
+    def refine(self, tri, xv, yv, zv, ratio=1.0, level=-1, stream=None, sync=True):
+        """Adaptive Lagrangian mesh refinement (Sec. 4): markers of the base
+        triangles tri [T, 3] (int32) over vertices xv, yv, zv.  Returns a dict
+        of device tensors x, y, z, area [M], normal [3, M], parent [M],
+        level [T] and the marker count M (syncs the stream to read it)."""
+        import torch
+        T = tri.shape[0] if tri.dim() == 2 else tri.numel() // 3
+        _check_dev(tri, torch.int32, 3 * T, "tri")
+        nv = xv.numel()
+        for a, nm in ((xv, "xv"), (yv, "yv"), (zv, "zv")):
+            _check_dev(a, torch.float32, nv, nm)
+        cap = max(4 * T, 1)
+        dev = xv.device
+        x, y, z, area = (torch.empty(cap, dtype=torch.float32, device=dev) for _ in range(4))
+        normal = torch.empty((3, cap), dtype=torch.float32, device=dev)
+        parent = torch.empty(cap, dtype=torch.int32, device=dev)
+        lev = torch.empty(max(T, 1), dtype=torch.uint8, device=dev)
+        count = torch.zeros(1, dtype=torch.int64, device=dev)
+        st = self._lib.mls_refine(self.h, T, _ptr(tri), nv, _ptr(xv), _ptr(yv), _ptr(zv), float(ratio), int(level),
+                                  cap, _ptr(x), _ptr(y), _ptr(z), _ptr(area), _ptr(normal), _ptr(parent), _ptr(lev),
+                                  _ptr(count), _stream(stream))
+        self._raise(st, "mls_refine")
+        out = dict(x=x, y=y, z=z, area=area, normal=normal, parent=parent, level=lev[:T], count_dev=count,
+                   capacity=cap)
+        if sync:
+            m = int(count.item())
+            out.update(count=m, x=x[:m], y=y[:m], z=z[:m], area=area[:m], normal=normal[:, :m],
+                       parent=parent[:m])
+        return out
 
     def collide_clear(self, x, y, z, coll, stream=None):
         """Returns the cells of the markers at x, y, z to zero."""

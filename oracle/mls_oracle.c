@@ -977,3 +977,132 @@ int orc_refine(const double *faces, const int32_t *n, const int32_t *periodic,
     *count = m;
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Derivative shape functions (eq. 6 differentiated in the marker position). */
+/* ------------------------------------------------------------------------ */
+/* The paper lists velocity gradients and pressure at the markers among the
+ * MLS operations a moving body needs, without formulas.  Reading used here:
+ * the gradient of the MLS approximation u(x) = sum_k phi_k(x) u_k with
+ * respect to the marker position x, i.e. the full derivative of eq. 6 in
+ * which the weights, and so A and B, move with the marker.  With the basis
+ * held fixed at the marker (p(y) = [1, (y - x_l)/H]), at y = x_l:
+ *   d Phi^T = dp^T A^-1 B - p^T A^-1 dA A^-1 B + p^T A^-1 dB,
+ *   p = e_0, dp = e_{1+d}, dA = sum_k dW_k p_k p_k^T, dB = [dW_k p_k],
+ * derivatives taken in the normalised coordinate xi_d = x_d / H_d; a node
+ * offset s = (node - x)/H moves by -d xi, so dW_k = -w'(s_{d,k}) times the
+ * other two factors.  Pressure lives at cell centres on every axis: its
+ * shape functions are those of "component" 3 (no face-staggered axis). */
+
+/* dw/ds of orc_weight_1d (0 where w is clipped to 0). */
+double orc_weight_1d_deriv(int kind, double eps, double R, double s)
+{
+    if (kind == ORC_W_CONST) return 0.0;
+    double g = exp(-(s / eps) * (s / eps));
+    double dg = -2.0 * s / (eps * eps) * g;
+    if (kind == ORC_W_GAUSS) return dg;
+    return g - exp(-(R / eps) * (R / eps)) > 0.0 ? dg : 0.0;
+}
+
+/* phi[k] as orc_mls_shape and dphi[d * ne + k] = d phi_k / d xi_d. */
+int orc_mls_shape_grad(int dim, const double *s, int kind, double eps, double R, double *phi, double *dphi)
+{
+    if (dim != 2 && dim != 3) return ORC_E_ARG;
+    const int m = dim + 1;
+    const int ne = dim == 2 ? 9 : 27;
+    double A[16] = {0}, dA[3][16], B[4 * 27], dB[3][4 * 27];
+    memset(dA, 0, sizeof(dA));
+    for (int k = 0; k < ne; ++k) {
+        double p[4], w[3], wd[3];
+        int kk = k;
+        p[0] = 1.0;
+        for (int d = 0; d < dim; ++d) {
+            int a = kk % 3; kk /= 3;
+            p[1 + d] = s[d * 3 + a];
+            w[d] = orc_weight_1d(kind, eps, R, s[d * 3 + a]);
+            wd[d] = orc_weight_1d_deriv(kind, eps, R, s[d * 3 + a]);
+        }
+        double W = 1.0;
+        for (int d = 0; d < dim; ++d) W *= w[d];
+        for (int i = 0; i < m; ++i) {
+            for (int j = 0; j < m; ++j) A[i * m + j] += W * p[i] * p[j];
+            B[i * ne + k] = W * p[i];
+        }
+        for (int d = 0; d < dim; ++d) {
+            double dW = -wd[d];
+            for (int e = 0; e < dim; ++e)
+                if (e != d) dW *= w[e];
+            for (int i = 0; i < m; ++i) {
+                for (int j = 0; j < m; ++j) dA[d][i * m + j] += dW * p[i] * p[j];
+                dB[d][i * ne + k] = dW * p[i];
+            }
+        }
+    }
+    /* T = A^-1 B, gamma = A^-1 e_0 (A symmetric, so p^T A^-1 = gamma^T) */
+    double Ac[16], T[4 * 27], gam[4] = {1.0, 0.0, 0.0, 0.0};
+    memcpy(Ac, A, sizeof(A));
+    memcpy(T, B, sizeof(double) * m * ne);
+    int rc = gepp_solve(m, Ac, ne, T);
+    if (rc != ORC_OK) return rc;
+    memcpy(Ac, A, sizeof(A));
+    rc = gepp_solve(m, Ac, 1, gam);
+    if (rc != ORC_OK) return rc;
+    for (int k = 0; k < ne; ++k) phi[k] = T[k];
+    for (int d = 0; d < dim; ++d) {
+        for (int k = 0; k < ne; ++k) {
+            double v = T[(1 + d) * ne + k];                 /* dp^T A^-1 B */
+            for (int i = 0; i < m; ++i) {
+                double dAT = 0.0;
+                for (int j = 0; j < m; ++j) dAT += dA[d][i * m + j] * T[j * ne + k];
+                v -= gam[i] * dAT;                           /* - p^T A^-1 dA A^-1 B */
+                v += gam[i] * dB[d][i * ne + k];             /* + p^T A^-1 dB */
+            }
+            dphi[d * ne + k] = v;
+        }
+    }
+    return ORC_OK;
+}
+
+/* Per marker, for staggering comp (0, 1, 2: the u, v, w grids; 3: cell
+ * centres): home[l*3 + d], phi[l*27 + k] and dphi[(l*3 + d)*27 + k] =
+ * d phi_k / d x_d in physical units.  Errors as orc_build_exact. */
+int orc_build_grad(const double *faces, const int32_t *n, const int32_t *periodic,
+                   int comp, int kind, double eps, double R,
+                   long nm, const float *x, const float *y, const float *z,
+                   int32_t *home, double *phi, double *dphi, long *bad)
+{
+    grid3 g;
+    grid_unpack(faces, n, periodic, &g);
+    int first_rc = ORC_OK;
+    long first_bad = -1;
+    if (comp < 0 || comp > 3) return ORC_E_ARG;
+    #pragma omp parallel for schedule(static)
+    for (long l = 0; l < nm; ++l) {
+        double xl[3] = {x[l], y[l], z[l]};
+        long h[3], ihu[3];
+        orc_axis_geo geo[3];
+        int rc = marker_geometry(&g, comp, xl, h, geo, ihu);
+        double s[9], dxi[3 * 27];
+        if (rc == ORC_OK) {
+            for (int d = 0; d < 3; ++d)
+                for (int a = 0; a < 3; ++a) s[d * 3 + a] = geo[d].s[a];
+            rc = orc_mls_shape_grad(3, s, kind, eps, R, phi + l * 27, dxi);
+        }
+        if (rc != ORC_OK) {
+            #pragma omp critical
+            {
+                if (first_bad < 0 || l < first_bad) { first_bad = l; first_rc = rc; }
+            }
+            for (int k = 0; k < 27; ++k) phi[l * 27 + k] = NAN;
+            for (int k = 0; k < 81; ++k) dphi[l * 81 + k] = NAN;
+            for (int d = 0; d < 3; ++d) home[l * 3 + d] = -1;
+            continue;
+        }
+        for (int d = 0; d < 3; ++d) {
+            home[l * 3 + d] = (int32_t)h[d];
+            for (int k = 0; k < 27; ++k) dphi[(l * 3 + d) * 27 + k] = dxi[d * 27 + k] / geo[d].H;
+        }
+    }
+    if (bad) *bad = first_bad;
+    return first_rc;
+}

@@ -72,6 +72,10 @@ def lib():
             L.orc_axis_nodes.argtypes = [P, P, P, i32, i32, P]
             L.orc_collide.argtypes = [P, P, P, i64, P, P, P, P, P, P, P, P]
             L.orc_refine.argtypes = [P, P, P, i64, P, i64, P, P, P, f64, i32, P, P, P, P, P, P, P, P, P]
+            L.orc_weight_1d_deriv.argtypes = [i32, f64, f64, f64]
+            L.orc_weight_1d_deriv.restype = f64
+            L.orc_mls_shape_grad.argtypes = [i32, P, i32, f64, f64, P, P]
+            L.orc_build_grad.argtypes = [P, P, P, i32, i32, f64, f64, i64, P, P, P, P, P, P]
             _lib = L
     return _lib
 
@@ -301,6 +305,50 @@ def refine(grid: Grid, tri, xv, yv, zv, ratio=1.0, level=-1, check=True):
     m = count.value
     return dict(x=x[:m], y=y[:m], z=z[:m], area=area[:m], normal=normal[:m], parent=parent[:m], level=lev,
                 count=m, rc=rc, bad=bad.value)
+
+
+COMP_CELL = 3   # staggering of cell-centred fields (pressure): no face axis
+
+
+def mls_shape_grad(s, kind=W_GAUSS_SHIFTED, eps=1.0, R=1.5):
+    """phi [3^dim] and d phi / d xi [dim, 3^dim] for node offsets s [dim, 3]
+    (normalised units; the marker's normalised coordinate xi moves the
+    offsets by -xi)."""
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    dim = s.shape[0]
+    phi = np.empty(3 ** dim)
+    dphi = np.empty((dim, 3 ** dim))
+    rc = lib().orc_mls_shape_grad(dim, _p(s), kind, eps, R, _p(phi), _p(dphi))
+    if rc != 0:
+        raise OracleError(rc, 0)
+    return phi, dphi
+
+
+def build_grad(grid: Grid, comp, x, y, z, kind=W_GAUSS_SHIFTED, eps=1.0, R=1.5, check=True):
+    """Exact shape functions and their derivatives in the marker position:
+    dict(home [N,3], phi [N,27], dphi [N,3,27] (d phi_k / d x_d)); comp 3 is
+    the cell-centred (pressure) staggering."""
+    x, y, z = _markers(x, y, z)
+    n = len(x)
+    home = np.empty((n, 3), dtype=np.int32)
+    phi = np.empty((n, 27))
+    dphi = np.empty((n, 3, 27))
+    bad = ctypes.c_long(-1)
+    rc = lib().orc_build_grad(*grid.args(), comp, kind, eps, R, n, _p(x), _p(y), _p(z), _p(home), _p(phi),
+                              _p(dphi), ctypes.byref(bad))
+    if rc != 0 and check:
+        raise OracleError(rc, bad.value)
+    return dict(home=home, phi=phi, dphi=dphi, rc=rc, bad=bad.value)
+
+
+def interp_grad(grid: Grid, comp, x, y, z, q):
+    """Value and gradient of the MLS approximation of field q (on the
+    staggering of comp) at the markers: (U [N], G [N, 3])."""
+    r = build_grad(grid, comp, x, y, z)
+    U = interp(grid, comp, r["home"], r["phi"], q)
+    G = np.stack([interp(grid, comp, r["home"], np.ascontiguousarray(r["dphi"][:, d, :]), q) for d in range(3)],
+                 axis=1)
+    return U, G
 
 
 # ---------------------------------------------------------------------------

@@ -308,6 +308,29 @@ def refinement_cost(torch, ctx, wl, steps):
             "triangles_per_s": round(T / (ms * 1e-3), 1), "alg_GBs": round(alg / (ms * 1e-3) / 1e9, 1)}
 
 
+def gradient_cost(torch, ctx, wl, x, y, z, fields, steps, t_per):
+    """Fused velocity values and gradients at the markers (derivative shape
+    functions, no Phi stored): time per call and throughput."""
+    from paper_1805_01113_amd import mls
+    n = wl.n
+    out = ctx.interp_grad(x, y, z, *fields)
+    ctx.sync()
+    del out
+    mls.timing_enable(ctx, True)
+    mls.timing_get(ctx, reset=True)
+    for _ in range(steps):
+        ctx.interp_grad(x, y, z, *fields)
+    torch.cuda.synchronize()
+    ctx.sync()
+    kt = mls.timing_get(ctx, reset=True)
+    mls.timing_enable(ctx, False)
+    ms = kt["interp_grad"][0] / kt["interp_grad"][1]
+    alg = 12 + 4.0 * t_per + 12 + 36     # positions, touched field values, U and G
+    return {"ms": round(ms, 4), "markers_per_s": round(n / (ms * 1e-3), 1),
+            "alg_bytes_per_marker": round(alg, 1), "alg_GBs": round(alg * n / (ms * 1e-3) / 1e9, 1),
+            "outputs": "U [3][n], G [9][n] (d u_c / d x_d)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -448,6 +471,8 @@ def main():
 
         extra["collision"] = collision_cost(torch, ctx, wl, x0, y0, z0, args.steps, ms_graph)
         log("collision detection: %s" % json.dumps(extra["collision"]))
+        extra["velocity_gradients"] = gradient_cost(torch, ctx, wl, x0, y0, z0, fields, args.steps, t_per)
+        log("velocity gradients: %s" % json.dumps(extra["velocity_gradients"]))
         if "centres" in wl.meta:
             extra["refinement"] = refinement_cost(torch, ctx, wl, args.steps)
             log("refinement: %s" % json.dumps(extra["refinement"]))

@@ -201,6 +201,34 @@ mls_status mls_spread(mls_ctx *ctx, int64_t n, const uint32_t *home, const float
                       const float *area, const float *Fx, const float *Fy, const float *Fz,
                       float *fx, float *fy, float *fz, void *stream);
 
+/* Derivative shape functions: the gradient with respect to the marker
+ * position x of the exact MLS shape functions of eq. 6, Phi(x) =
+ * W(x) p^T A(x)^-1 B(x), the weights (and so A and B) moving with the marker;
+ * the paper asks for velocity gradients and pressure at the markers of
+ * moving bodies without giving formulas, and this is the full derivative of
+ * its approximation.  stagger selects the node set: 0, 1, 2 the u, v, w grids
+ * as in mls_build, 3 the cell centres on every axis (pressure).  Writes, in
+ * the 64-marker blocked layout (npad = n rounded up to 64): home[l] packed as
+ * in mls_build (npad entries), phi[(b*27 + k)*64 + r] (27 npad) and
+ * dphi[((b*3 + d)*27 + k)*64 + r] = d phi_k / d x_d in physical units
+ * (81 npad), l = 64 b + r; padding lanes get home 0xffffffff and zeros.  The
+ * solve is FP32 with the condition bound of mls_build, redone in FP64 from
+ * the position above opts.kappa_tau (counted in mls_stats fp64_solves).
+ * Support errors as mls_build. */
+mls_status mls_build_grad(mls_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
+                          int32_t stagger, uint32_t *home, float *phi, float *dphi, void *stream);
+
+/* Fused value and gradient of the MLS approximation at the markers (no shape
+ * functions stored): for the staggered velocity fields u, v, w (device FP32,
+ * component grids as in mls_interp) U[c][l] (if U != NULL, [3][n]) and
+ * G[3c + d][l] = d u_c / d x_d ([9][n]); if p != NULL (device FP32 cell-centred
+ * field, [n_z][n_y][n_x] over the cells) also P[l] = p at the marker and
+ * GP[d][l] = d p / d x_d (either may be NULL).  Same arithmetic and errors as
+ * mls_build_grad. */
+mls_status mls_interp_grad(mls_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
+                           const float *u, const float *v, const float *w, float *U, float *G, const float *p,
+                           float *P, float *GP, void *stream);
+
 /* Coarse-grained collision detection (Sec. 5, the integer cell array of its
  * detection algorithm).  coll is a device int32 array with one entry per
  * Eulerian cell, C order [z][y][x] over the n_z x n_y x n_x cells of the
@@ -359,7 +387,7 @@ enum {
     MLS_K_BUILD_EXACT = 0, MLS_K_BUILD_FAST = 1, MLS_K_BUILD_LEARNED = 2, MLS_K_INTERP = 3,
     MLS_K_SPREAD_BIN = 4, MLS_K_SPREAD_TILES = 5, MLS_K_JITTER = 6, MLS_K_FORCE = 7,
     MLS_K_BUILD_INTERP = 8,  /* exact build fused with interpolation and forcing (mls_step, MLS_EXACT) */
-    MLS_K_COLLIDE = 9, MLS_K_COLLIDE_CLEAR = 10, MLS_K_REFINE = 11,
+    MLS_K_COLLIDE = 9, MLS_K_COLLIDE_CLEAR = 10, MLS_K_REFINE = 11, MLS_K_BUILD_GRAD = 12, MLS_K_INTERP_GRAD = 13,
     MLS_K_COUNT = 16
 };
 typedef struct {

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmls_hip.so")
 SOURCES = ["mls_api.hip", "mls_build.hip", "mls_transfer.hip", "mls_step.hip", "mls_mlp.hip", "mls_tune.hip",
-           "mls_collide.hip", "mls_refine.hip"]
+           "mls_collide.hip", "mls_refine.hip", "mls_grad.hip"]
 
 # -packed-fp32-ops: no packed FP32 instructions are generated (plain VALU FP32)
 COMPILE_FLAGS = [

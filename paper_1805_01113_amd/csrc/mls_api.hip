@@ -349,6 +349,7 @@ void mls_ctx_destroy(mls_ctx *ctx)
     hipFree(c.block_fmax);
     hipFree(c.tile_hmin_block);
     hipFree(c.refine_scratch);
+    hipFree(c.grad_queue);
     hipFree(c.work);
     hipFree(c.step_ctr);
     mlp_free(c);
@@ -521,6 +522,39 @@ mls_status mls_refine(mls_ctx *ctx, int64_t ntri, const int32_t *tri, int64_t nv
                           parent, tri_level, count, static_cast<hipStream_t>(stream));
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "refine launch");
+    return MLS_OK;
+}
+
+mls_status mls_build_grad(mls_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
+                          int32_t stagger, uint32_t *home, float *phi, float *dphi, void *stream)
+{
+    if (!ctx) return MLS_E_ARG;
+    if (n < 0 || n > (int64_t)0x1fffffff) return fail(ctx, MLS_E_ARG, "bad marker count");
+    if (stagger < 0 || stagger > 3) return fail(ctx, MLS_E_ARG, "staggering must be 0, 1, 2 (u, v, w) or 3 (cells)");
+    if (n > 0 && (!x || !y || !z || !home || !phi || !dphi)) return fail(ctx, MLS_E_ARG, "null array");
+    hipError_t e;
+    {
+        TimedLaunch t(ctx->c, MLS_K_BUILD_GRAD, static_cast<hipStream_t>(stream));
+        e = launch_build_grad(ctx->c, n, x, y, z, stagger, home, phi, dphi, static_cast<hipStream_t>(stream));
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "build_grad launch");
+    return MLS_OK;
+}
+
+mls_status mls_interp_grad(mls_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
+                           const float *u, const float *v, const float *w, float *U, float *G, const float *p,
+                           float *P, float *GP, void *stream)
+{
+    if (!ctx) return MLS_E_ARG;
+    if (n < 0 || n > (int64_t)0x1fffffff) return fail(ctx, MLS_E_ARG, "bad marker count");
+    if (n > 0 && (!x || !y || !z || !u || !v || !w || !G)) return fail(ctx, MLS_E_ARG, "null array");
+    if (n > 0 && p && !P && !GP) return fail(ctx, MLS_E_ARG, "pressure given without an output");
+    hipError_t e;
+    {
+        TimedLaunch t(ctx->c, MLS_K_INTERP_GRAD, static_cast<hipStream_t>(stream));
+        e = launch_interp_grad(ctx->c, n, x, y, z, u, v, w, p, U, G, P, GP, static_cast<hipStream_t>(stream));
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "interp_grad launch");
     return MLS_OK;
 }
 

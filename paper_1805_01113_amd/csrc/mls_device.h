@@ -160,7 +160,8 @@ __device__ __forceinline__ bool locate(const Axis &a, int is_face, double x, int
 
 // Support geometry along one axis (FP64 offsets, rounded to FP32 after the
 // subtraction so that stretched axes keep their digits).
-__device__ __forceinline__ bool axis_geo(const Axis &a, int is_face, double x, AxisGeo &g)
+// rH_out receives 1/H (physical units).
+__device__ __forceinline__ bool axis_geo(const Axis &a, int is_face, double x, AxisGeo &g, double &rH_out)
 {
     int ih;
     double X;
@@ -174,6 +175,7 @@ __device__ __forceinline__ bool axis_geo(const Axis &a, int is_face, double x, A
         g.s[2] = (float)(d0 + 1.0);
         g.xi = (float)(-d0);
         g.rho = 1.0f;
+        rH_out = a.inv_h;
     } else {
         const double xm = node_x(a, is_face, ih - 1);
         const double xp = node_x(a, is_face, ih + 1);
@@ -183,13 +185,20 @@ __device__ __forceinline__ bool axis_geo(const Axis &a, int is_face, double x, A
         g.s[2] = (float)((xp - X) * rH);
         g.xi = (float)((X - x0) * rH);
         g.rho = (float)((xp - x0) / (x0 - xm));
+        rH_out = rH;
     }
     g.ih = (a.periodic && ih >= a.n) ? ih - a.n : ih;
     return true;
 }
 
+__device__ __forceinline__ bool axis_geo(const Axis &a, int is_face, double x, AxisGeo &g)
+{
+    double rH;
+    return axis_geo(a, is_face, x, g, rH);
+}
+
 // FP64 offsets for the rare FP64 route (recomputed from the position).
-__device__ __forceinline__ void axis_offsets_d(const Axis &a, int is_face, double x, double s[3])
+__device__ __forceinline__ void axis_offsets_d(const Axis &a, int is_face, double x, double s[3], double &H)
 {
     int ih;
     double X;
@@ -197,10 +206,16 @@ __device__ __forceinline__ void axis_offsets_d(const Axis &a, int is_face, doubl
     double xm = node_x(a, is_face, ih - 1);
     double x0 = node_x(a, is_face, ih);
     double xp = node_x(a, is_face, ih + 1);
-    double H = 0.5 * (xp - xm);
+    H = 0.5 * (xp - xm);
     s[0] = (xm - X) / H;
     s[1] = (x0 - X) / H;
     s[2] = (xp - X) / H;
+}
+
+__device__ __forceinline__ void axis_offsets_d(const Axis &a, int is_face, double x, double s[3])
+{
+    double H;
+    axis_offsets_d(a, is_face, x, s, H);
 }
 #pragma clang fp contract(on)
 
@@ -222,6 +237,29 @@ __device__ __forceinline__ double weight1_d(const Weight &w, double s)
     double g = exp(-t * t);
     if (w.kind == MLS_W_GAUSS) return g;
     return fmax(g - w.cut_d, 0.0);
+}
+
+// Weight and its derivative dw/ds (0 where the shifted Gaussian is clipped).
+__device__ __forceinline__ void weight1_ds(const Weight &w, float s, float &v, float &dv)
+{
+    if (w.kind == MLS_W_CONST) { v = 1.0f; dv = 0.0f; return; }
+    const float t = s * w.inv_eps;
+    const float g = __expf(-t * t);
+    const float dg = -2.0f * t * w.inv_eps * g;
+    if (w.kind == MLS_W_GAUSS) { v = g; dv = dg; return; }
+    v = fmaxf(g - w.cut, 0.0f);
+    dv = g - w.cut > 0.0f ? dg : 0.0f;
+}
+
+__device__ __forceinline__ void weight1_ds(const Weight &w, double s, double &v, double &dv)
+{
+    if (w.kind == MLS_W_CONST) { v = 1.0; dv = 0.0; return; }
+    const double t = s * w.inv_eps_d;
+    const double g = exp(-t * t);
+    const double dg = -2.0 * t * w.inv_eps_d * g;
+    if (w.kind == MLS_W_GAUSS) { v = g; dv = dg; return; }
+    v = fmax(g - w.cut_d, 0.0);
+    dv = g - w.cut_d > 0.0 ? dg : 0.0;
 }
 
 // ---- moment matrix --------------------------------------------------------

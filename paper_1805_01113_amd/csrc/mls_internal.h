@@ -164,6 +164,9 @@ struct Ctx {
     // Lagrangian refinement: per-workgroup marker sums and offsets
     uint32_t *refine_scratch = nullptr;
     int64_t refine_cap = 0;
+    // derivative shape functions: queue of (marker, staggering) pairs for the FP64 route
+    uint32_t *grad_queue = nullptr;
+    int64_t grad_queue_cap = 0;
     // time step
     unsigned long long *step_ctr = nullptr;
     int64_t step_sorted_n = -1;   // markers of the last exact step (its rows are in tile order)
@@ -203,6 +206,11 @@ hipError_t launch_refine(Ctx &c, int64_t ntri, const int32_t *tri, int64_t nvert
                          const float *yv, const float *zv, double ratio, int level, int64_t cap, float *x,
                          float *y, float *z, float *area, float *normal, int32_t *parent, uint8_t *tri_level,
                          int64_t *count, hipStream_t s);
+hipError_t launch_build_grad(Ctx &c, int64_t n, const float *x, const float *y, const float *z, int stagger,
+                             uint32_t *home, float *phi, float *dphi, hipStream_t s);
+hipError_t launch_interp_grad(Ctx &c, int64_t n, const float *x, const float *y, const float *z,
+                              const float *u, const float *v, const float *w, const float *p, float *U, float *G,
+                              float *P, float *GP, hipStream_t s);
 hipError_t launch_interp(const Ctx &c, int64_t n, const uint32_t *home, const float *phi,
                          const float *u, const float *v, const float *w,
                          float *U, float *V, float *W, hipStream_t s);

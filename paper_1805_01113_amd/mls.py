@@ -76,7 +76,7 @@ class _TuneReport(ctypes.Structure):
 
 
 K_NAMES = ["build_exact", "build_fast", "build_learned", "interp", "spread_bin", "spread_tiles", "jitter", "force",
-           "build_interp", "collide", "collide_clear", "refine"]
+           "build_interp", "collide", "collide_clear", "refine", "build_grad", "interp_grad"]
 
 
 class _Timing(ctypes.Structure):
@@ -106,6 +106,8 @@ def load(path: str = LIB_PATH, need_torch: bool = True):
     L.mls_spread.argtypes = [P, I64, P, P, P, P, P, P, P, P, P, P]
     L.mls_collide.argtypes = [P, I64, P, P, P, P, P, P, P]
     L.mls_collide_clear.argtypes = [P, I64, P, P, P, P, P]
+    L.mls_build_grad.argtypes = [P, I64, P, P, P, I32, P, P, P, P]
+    L.mls_interp_grad.argtypes = [P, I64, P, P, P, P, P, P, P, P, P, P, P, P]
     L.mls_refine.argtypes = [P, I64, P, I64, P, P, P, ctypes.c_double, I32, I64, P, P, P, P, P, P, P, P, P]
     L.mls_sync.argtypes = [P, P, ctypes.POINTER(I64)]
     L.mls_last_error.argtypes = [P]
@@ -288,6 +290,54 @@ class Context:
                                    _stream(stream))
         self._raise(st, "mls_collide")
         return coll, flags
+
+    def build_grad(self, x, y, z, stagger, home=None, phi=None, dphi=None, stream=None):
+        """Exact shape functions and their derivatives in the marker position
+        for one staggering (0, 1, 2: u, v, w grids; 3: cell centres), in the
+        64-marker blocked layout: home [npad], phi [npad/64, 27, 64],
+        dphi [npad/64, 3, 27, 64]."""
+        import torch
+        n = x.numel()
+        for a, nm in ((x, "x"), (y, "y"), (z, "z")):
+            _check_dev(a, torch.float32, n, nm)
+        npd = npad(n)
+        dev = x.device
+        if home is None:
+            home = torch.empty(npd, dtype=torch.int32, device=dev)
+        if phi is None:
+            phi = torch.empty((npd // 64, 27, 64), dtype=torch.float32, device=dev)
+        if dphi is None:
+            dphi = torch.empty((npd // 64, 3, 27, 64), dtype=torch.float32, device=dev)
+        _check_dev(home, torch.int32, npd, "home")
+        _check_dev(phi, torch.float32, 27 * npd, "phi")
+        _check_dev(dphi, torch.float32, 81 * npd, "dphi")
+        st = self._lib.mls_build_grad(self.h, n, _ptr(x), _ptr(y), _ptr(z), int(stagger), _ptr(home), _ptr(phi),
+                                      _ptr(dphi), _stream(stream))
+        self._raise(st, "mls_build_grad")
+        return home, phi, dphi
+
+    def interp_grad(self, x, y, z, u, v, w, p=None, values=True, stream=None):
+        """Velocities U [3, n] (if values), their gradients G [9, n]
+        (G[3c + d] = d u_c / d x_d) and, for a cell-centred p, P [n] and
+        GP [3, n] at the markers."""
+        import torch
+        n = x.numel()
+        for a, nm in ((x, "x"), (y, "y"), (z, "z")):
+            _check_dev(a, torch.float32, n, nm)
+        for c, q in enumerate((u, v, w)):
+            _check_dev(q, torch.float32, int(np.prod(self.shape(c))), "field %d" % c)
+        dev = x.device
+        U = torch.empty((3, n), dtype=torch.float32, device=dev) if values else None
+        G = torch.empty((9, n), dtype=torch.float32, device=dev)
+        P = GP = None
+        if p is not None:
+            _check_dev(p, torch.float32, int(np.prod(self.cell_shape())), "p")
+            P = torch.empty(n, dtype=torch.float32, device=dev)
+            GP = torch.empty((3, n), dtype=torch.float32, device=dev)
+        st = self._lib.mls_interp_grad(self.h, n, _ptr(x), _ptr(y), _ptr(z), _ptr(u), _ptr(v), _ptr(w), _ptr(U),
+                                       _ptr(G), _ptr(p), _ptr(P), _ptr(GP), _stream(stream))
+        self._raise(st, "mls_interp_grad")
+        return dict(U=U, G=G, P=P, GP=GP)
 
     def refine(self, tri, xv, yv, zv, ratio=1.0, level=-1, stream=None, sync=True):
         """Adaptive Lagrangian mesh refinement (Sec. 4): markers of the base

@@ -443,6 +443,7 @@ def main():
         "build_learned": 12 + 12 + 324.0,
         "interp": 12 + 324 + 12 + 4.0 * t_per,
         "build_interp": 12 + 12 + 324 + 4.0 * t_per + 12 + 12,
+        "fast_interp": 12 + 12 + 324 + 4.0 * t_per + 12 + 12,
         "force": 24.0,
         "spread_tiles": 12 + 324 + 12 + 4 + 8.0 * t_per,
         "spread_bin": 0.0,

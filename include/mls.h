@@ -388,6 +388,7 @@ enum {
     MLS_K_SPREAD_BIN = 4, MLS_K_SPREAD_TILES = 5, MLS_K_JITTER = 6, MLS_K_FORCE = 7,
     MLS_K_BUILD_INTERP = 8,  /* exact build fused with interpolation and forcing (mls_step, MLS_EXACT) */
     MLS_K_COLLIDE = 9, MLS_K_COLLIDE_CLEAR = 10, MLS_K_REFINE = 11, MLS_K_BUILD_GRAD = 12, MLS_K_INTERP_GRAD = 13,
+    MLS_K_FAST_INTERP = 14,  /* fast-MLS fused with interpolation and forcing (mls_step, uniform grids) */
     MLS_K_COUNT = 16
 };
 typedef struct {

@@ -344,6 +344,207 @@ k_build_fast(const Grid *__restrict__ gp, const FastTables T, int64_t n,
     }
 }
 
+// fast-MLS fused with the interpolation and forcing of a time step, in
+// spreading-tile order like k_build_interp, for a grid whose axes are all
+// uniform (one table).  There the shape functions are mirror-symmetric in
+// each axis: phi at -xi_d is phi at xi_d with the support nodes a and 2 - a
+// of that axis exchanged, and with an odd sub-node count the sub-cells of the
+// table never straddle xi_d = 0.  So the kernel keeps only the octant
+// xi >= 0 of the table (nh^3 rows, nh = (n_sub + 1)/2: 14 KB for n_sub = 9)
+// in LDS.  The sub-cell and the weights (Shepard of eq. 10, or trilinear) are
+// those of the whole-table lookup; a corner in the negative half of an axis
+// reads the row of its mirror image, and the blended nodes of every such axis
+// are put back in place with a layer of conditional swaps.
+template <bool TRILINEAR>
+__global__ void __launch_bounds__(kBuildBlock)
+k_fast_interp(const Grid *__restrict__ gp, const float4 *__restrict__ tab, int nsub, int64_t n,
+              const uint32_t *__restrict__ order, const float *__restrict__ x, const float *__restrict__ y,
+              const float *__restrict__ z, uint32_t *__restrict__ home, float *__restrict__ phi,
+              uint8_t *__restrict__ route, const float *__restrict__ u, const float *__restrict__ v,
+              const float *__restrict__ w, const float *__restrict__ vb, const float *__restrict__ area, float inv_dt,
+              float *__restrict__ U, float *__restrict__ F, uint32_t *__restrict__ block_fmax, ErrWord *err)
+{
+    extern __shared__ float4 oct[];   // [nh^3][7]
+    const Grid &g = *gp;
+    const int nh = (nsub + 1) / 2, mid = (nsub - 1) / 2;
+    {
+        const int total = nh * nh * nh * 7;
+        for (int i = threadIdx.x; i < total; i += blockDim.x) {
+            const int r = i / 7, q4 = i % 7;
+            const int jx = r % nh, jy = (r / nh) % nh, jz = r / (nh * nh);
+            const int s = (mid + jx) + nsub * ((mid + jy) + nsub * (mid + jz));
+            oct[i] = tab[(int64_t)s * 7 + q4];
+        }
+    }
+    __syncthreads();
+    const int wave = wave_id(), lane = threadIdx.x & 63;
+    const int c = wave % 3;
+    const int grp = wave / 3;
+    const int64_t gstride = (int64_t)gridDim.x * kGroups * 64;
+    const float *q = c == 0 ? u : (c == 1 ? v : w);
+    const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
+    const float scale = (float)(nsub - 1);   // sub-cells per unit of xi (home CV [-1/2, 1/2))
+    const float step = 1.0f / scale;         // sub-cell width, (hi - lo) / (n_sub - 1)
+    float fmx = 0.f;
+    int64_t base = (xcd_block() * kGroups + grp) * 64;
+    uint32_t nm = 0;
+    float nx = 0.f, ny = 0.f, nz = 0.f;
+    if (base + lane < n) {
+        nm = order[base + lane];
+        nx = x[nm]; ny = y[nm]; nz = z[nm];
+    }
+    for (; base < n; base += gstride) {
+        const int64_t p = base + lane;
+        const int64_t m = nm;
+        const float cx = nx, cy = ny, cz = nz;
+        if (base + gstride + lane < n) {
+            nm = order[base + gstride + lane];
+            nx = x[nm]; ny = y[nm]; nz = z[nm];
+        }
+        if (p >= n) continue;
+        float *out = phi + ((((base >> 6) * 3 + c) * kNe) << 6) + lane;
+        uint32_t *hout = home + (((base >> 6) * 3 + c) << 6) + lane;
+        uint8_t *rout = route ? route + (((base >> 6) * 3 + c) << 6) + lane : nullptr;
+        const double px = (double)cx, py = (double)cy, pz = (double)cz;
+        AxisGeo G[3];
+        bool ok = axis_geo(g.ax[0], c == 0, px, G[0]);
+        ok = ok && axis_geo(g.ax[1], c == 1, py, G[1]);
+        ok = ok && axis_geo(g.ax[2], c == 2, pz, G[2]);
+        if (!ok) {
+            mark_failed(err, m, px, py, pz, hout, out, rout);
+            U[c * n + m] = __builtin_nanf("");
+            F[c * n + m] = __builtin_nanf("");
+            continue;
+        }
+        *hout = pack_home(G[0].ih, G[1].ih, G[2].ih);
+        int64_t ox[3], oy[3], oz[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            ox[a] = nb_index(G[0].ih, a - 1, nxc, g.ax[0].periodic);
+            oy[a] = (int64_t)nb_index(G[1].ih, a - 1, nyc, g.ax[1].periodic) * nxc;
+            oz[a] = (int64_t)nb_index(G[2].ih, a - 1, nzc, g.ax[2].periodic) * nxc * nyc;
+        }
+        float qv[kNe];
+#pragma unroll
+        for (int k = 0; k < kNe; ++k) qv[k] = q[oz[k / 9] + oy[(k / 3) % 3] + ox[k % 3]];
+        // the sub-cell and the blend weights in the true frame, as the
+        // whole-table lookup computes them (so a marker on a sub-cell face
+        // gets the same sub-cell); only the rows come from the mirror image
+        bool flip[3];
+        int jj[3];
+        float tf[3], t0[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const float xi = G[d].xi;
+            int j = (int)floorf((xi + 0.5f) * scale);
+            j = min(max(j, 0), nsub - 2);
+            jj[d] = j;
+            flip[d] = j < mid;
+            t0[d] = -0.5f + (float)j * step;
+            tf[d] = (xi - t0[d]) / step;
+        }
+        float alpha[8];
+        if (TRILINEAR) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                alpha[i] = ((i & 1) ? tf[0] : 1.f - tf[0]) * (((i >> 1) & 1) ? tf[1] : 1.f - tf[1]) *
+                           (((i >> 2) & 1) ? tf[2] : 1.f - tf[2]);
+        } else {
+            float d2[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                float acc = 0.f;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const float e = G[d].xi - (t0[d] + (float)((i >> d) & 1) * step);
+                    acc += e * e;
+                }
+                d2[i] = acc;
+            }
+            float pre[8], suf[8];
+            pre[0] = 1.f;
+#pragma unroll
+            for (int i = 1; i < 8; ++i) pre[i] = pre[i - 1] * d2[i - 1];
+            suf[7] = 1.f;
+#pragma unroll
+            for (int i = 6; i >= 0; --i) suf[i] = suf[i + 1] * d2[i + 1];
+            float den = 0.f;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) { alpha[i] = pre[i] * suf[i]; den += alpha[i]; }
+            const float rden = 1.f / den;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) alpha[i] *= rden;
+        }
+        float ph[28];
+#pragma unroll
+        for (int k = 0; k < 28; ++k) ph[k] = 0.f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            // octant row of corner i: sub-node j + bit, mirrored on flipped axes
+            int oj[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int jn = jj[d] + ((i >> d) & 1);
+                oj[d] = flip[d] ? mid - jn : jn - mid;
+            }
+            const int r = oj[0] + nh * (oj[1] + nh * oj[2]);
+            const float4 *row = oct + r * 7;
+#pragma unroll
+            for (int q4 = 0; q4 < 7; ++q4) {
+                const float4 t = row[q4];
+                ph[4 * q4] += alpha[i] * t.x;
+                ph[4 * q4 + 1] += alpha[i] * t.y;
+                ph[4 * q4 + 2] += alpha[i] * t.z;
+                ph[4 * q4 + 3] += alpha[i] * t.w;
+            }
+        }
+        // back from the octant: exchange nodes a and 2 - a of every mirrored axis
+#pragma unroll
+        for (int o = 0; o < 9; ++o) {
+            const int k0 = 3 * o;                      // x: (0, b, c) <-> (2, b, c)
+            const float t0 = ph[k0], t2 = ph[k0 + 2];
+            ph[k0] = flip[0] ? t2 : t0;
+            ph[k0 + 2] = flip[0] ? t0 : t2;
+        }
+#pragma unroll
+        for (int o = 0; o < 9; ++o) {
+            const int k0 = (o % 3) + 9 * (o / 3);      // y: (a, 0, c) <-> (a, 2, c)
+            const float t0 = ph[k0], t2 = ph[k0 + 6];
+            ph[k0] = flip[1] ? t2 : t0;
+            ph[k0 + 6] = flip[1] ? t0 : t2;
+        }
+#pragma unroll
+        for (int o = 0; o < 9; ++o) {
+            const int k0 = o;                          // z: (a, b, 0) <-> (a, b, 2)
+            const float t0 = ph[k0], t2 = ph[k0 + 18];
+            ph[k0] = flip[2] ? t2 : t0;
+            ph[k0 + 18] = flip[2] ? t0 : t2;
+        }
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < kNe; ++k) {
+            out[k * kLanes] = ph[k];
+            acc += ph[k] * qv[k];
+        }
+        if (rout) *rout = 0;
+        const float f = ((vb ? vb[c * n + m] : 0.0f) - acc) * inv_dt;
+        U[c * n + m] = acc;
+        F[c * n + m] = f;
+        const float af = fabsf(area[m]) * fabsf(f);
+        if (!(af <= 3.0e38f)) raise_error(err, m, MLS_E_RANGE);
+        else fmx = fmaxf(fmx, af);
+    }
+    for (int off = 32; off > 0; off >>= 1) fmx = fmaxf(fmx, __shfl_xor(fmx, off));
+    __shared__ float bm[kBuildBlock / 64];
+    if (lane == 0) bm[wave] = fmx;
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        float vv = 0.f;
+        for (int q2 = threadIdx.x; q2 < kBuildBlock / 64; q2 += 3) vv = fmaxf(vv, bm[q2]);
+        block_fmax[3 * blockIdx.x + threadIdx.x] = __float_as_uint(vv);
+    }
+}
+
 // Table build: one lane per (table, sub-node); exact MLS in FP64 at the
 // sub-node from the table's normalised support geometry.
 //   geo_in[t][d][0..2]: support node positions relative to the home node (units of H)
@@ -440,6 +641,34 @@ hipError_t launch_build_interp(const Ctx &c, int64_t n, const float *x, const fl
     hipLaunchKernelGGL(k_build_interp, dim3(build_grid(n, c.cu_count, c.build_blocks_per_cu)), dim3(kBuildBlock), 0,
                        s, c.d_grid, c.w, tau, n, c.entries, x, y, z, home, phi, route, u, v, w, vb, area, 1.0f / dt,
                        U, F, c.block_fmax, c.err, c.stats);
+    return hipGetLastError();
+}
+
+bool fast_fused_ok(const Ctx &c)
+{
+    const int nsub = c.opts.n_sub;
+    const int nh = (nsub + 1) / 2;
+    return c.tables && c.n_tables == 1 && c.stretched_axis < 0 && (nsub & 1) &&
+           (int64_t)nh * nh * nh * kTableStride * 4 <= 64 * 1024;
+}
+
+hipError_t launch_fast_interp(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
+                              uint32_t *home, float *phi, uint8_t *route, const float *u, const float *v,
+                              const float *w, const float *vb, const float *area, float dt, float *U, float *F,
+                              hipStream_t s, bool trilinear_blend)
+{
+    if (n == 0) return hipSuccess;
+    if (!fast_fused_ok(c)) return hipErrorInvalidValue;
+    const int nsub = c.opts.n_sub, nh = (nsub + 1) / 2;
+    const size_t lds = (size_t)nh * nh * nh * kTableStride * sizeof(float);
+    const dim3 grid(build_grid(n, c.cu_count, c.build_blocks_per_cu));
+    const float4 *tab = reinterpret_cast<const float4 *>(c.tables);
+    if (trilinear_blend)
+        hipLaunchKernelGGL(k_fast_interp<true>, grid, dim3(kBuildBlock), lds, s, c.d_grid, tab, nsub, n, c.entries, x,
+                           y, z, home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.block_fmax, c.err);
+    else
+        hipLaunchKernelGGL(k_fast_interp<false>, grid, dim3(kBuildBlock), lds, s, c.d_grid, tab, nsub, n, c.entries, x,
+                           y, z, home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.block_fmax, c.err);
     return hipGetLastError();
 }
 

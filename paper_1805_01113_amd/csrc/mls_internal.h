@@ -195,6 +195,14 @@ hipError_t launch_build_exact(const Ctx &c, int64_t n, const float *x, const flo
                               uint32_t *home, float *phi, uint8_t *route, hipStream_t s);
 hipError_t launch_build_fast(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
                              uint32_t *home, float *phi, uint8_t *route, hipStream_t s, bool trilinear_blend);
+// fast-MLS fused with interpolation and forcing in spreading-tile order (uniform
+// grids: one symmetric table, odd sub-node count); fast_fused_ok tells whether
+// the context qualifies (tables built).
+bool fast_fused_ok(const Ctx &c);
+hipError_t launch_fast_interp(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
+                              uint32_t *home, float *phi, uint8_t *route, const float *u, const float *v,
+                              const float *w, const float *vb, const float *area, float dt, float *U, float *F,
+                              hipStream_t s, bool trilinear_blend);
 hipError_t launch_build_learned(Ctx &c, int64_t n, const float *x, const float *y, const float *z,
                                 uint32_t *home, float *phi, uint8_t *route, hipStream_t s);
 hipError_t launch_table_build(const Ctx &c, hipStream_t s);

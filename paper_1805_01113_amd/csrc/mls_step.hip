@@ -147,15 +147,26 @@ mls_status mls_step(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buff
     }
     mls_status st = MLS_OK;
     hipError_t e;
-    if (desc->method == MLS_EXACT) {
-        // exact MLS in spreading-tile order: bin the markers from their
-        // positions, build with interpolation and forcing fused (phi is not
-        // read back), spread reading each tile's rows contiguously
+    const bool fast = desc->method == MLS_FAST || desc->method == MLS_FAST_LINEAR;
+    if (fast) {
+        // tables are built once per context (before any graph capture)
+        st = mls_fast_tables(ctx, nullptr, nullptr, nullptr, nullptr, nullptr, stream);
+        if (st != MLS_OK) return st;
+    }
+    if (desc->method == MLS_EXACT || (fast && fast_fused_ok(c))) {
+        // exact MLS, or fast-MLS on a uniform grid, in spreading-tile order:
+        // bin the markers from their positions, build with interpolation and
+        // forcing fused (phi is not read back), spread reading each tile's
+        // rows contiguously
         st = mls_reserve(ctx, n);
         if (st != MLS_OK) return st;
         e = launch_sort_positions(c, n, bx, by, bz, s);
         if (e != hipSuccess) return MLS_E_HIP;
-        {
+        if (fast) {
+            TimedLaunch t(c, MLS_K_FAST_INTERP, s);
+            e = launch_fast_interp(c, n, bx, by, bz, b->home, b->phi, b->route, b->u, b->v, b->w, b->vb, b->area,
+                                   desc->dt, b->U, b->F, s, desc->method == MLS_FAST_LINEAR);
+        } else {
             TimedLaunch t(c, MLS_K_BUILD_INTERP, s);
             e = launch_build_interp(c, n, bx, by, bz, b->home, b->phi, b->route, b->u, b->v, b->w, b->vb, b->area,
                                     desc->dt, b->U, b->F, s);

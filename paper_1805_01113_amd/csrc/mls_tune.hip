@@ -184,13 +184,24 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, const mls_step_buffers *b,
     const float *F = b->F;
     // the exact step bins the markers and runs the build fused with
     // interpolation and forcing, then spreads in tile order
-    const bool exact = method == MLS_EXACT;
+    const bool fast = method == MLS_FAST || method == MLS_FAST_LINEAR;
+    if (fast) {
+        st = mls_fast_tables(ctx, nullptr, nullptr, nullptr, nullptr, nullptr, stream);
+        if (st != MLS_OK) { c.timing = timing; return st; }
+    }
+    // exact and (on uniform grids) fast-MLS run fused and in tile order
+    const bool exact = method == MLS_EXACT || (fast && fast_fused_ok(c));
     auto build = [&]() {
         if (!exact) return mls_build(ctx, n, b->x0, b->y0, b->z0, method, b->home, b->phi, nullptr, stream);
         hipError_t e = launch_sort_positions(c, n, b->x0, b->y0, b->z0, s);
-        if (e == hipSuccess)
-            e = launch_build_interp(c, n, b->x0, b->y0, b->z0, b->home, b->phi, nullptr, b->u, b->v, b->w, b->vb,
-                                    b->area, 1.0f, b->U, b->F, s);
+        if (e == hipSuccess) {
+            if (fast)
+                e = launch_fast_interp(c, n, b->x0, b->y0, b->z0, b->home, b->phi, nullptr, b->u, b->v, b->w, b->vb,
+                                       b->area, 1.0f, b->U, b->F, s, method == MLS_FAST_LINEAR);
+            else
+                e = launch_build_interp(c, n, b->x0, b->y0, b->z0, b->home, b->phi, nullptr, b->u, b->v, b->w, b->vb,
+                                        b->area, 1.0f, b->U, b->F, s);
+        }
         return e == hipSuccess ? MLS_OK : MLS_E_HIP;
     };
     auto interp = [&]() { return mls_interp(ctx, n, b->home, b->phi, b->u, b->v, b->w, U, V, Wv, stream); };

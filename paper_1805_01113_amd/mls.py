@@ -76,7 +76,8 @@ class _TuneReport(ctypes.Structure):
 
 
 K_NAMES = ["build_exact", "build_fast", "build_learned", "interp", "spread_bin", "spread_tiles", "jitter", "force",
-           "build_interp", "collide", "collide_clear", "refine", "build_grad", "interp_grad"]
+           "build_interp", "collide", "collide_clear", "refine", "build_grad", "interp_grad",
+           "fast_interp"]
 
 
 class _Timing(ctypes.Structure):

@@ -120,3 +120,100 @@ def test_exact_step_rows_follow_the_reported_order(orc):
     assert max(errs) <= PHI_TOL
     with pytest.raises(mls.MLSError):
         mls.step_order(ctx, n - 1)
+
+
+@pytest.mark.parametrize("method,blend", [(1, 0), (3, 1)])
+def test_fast_step_fused_matches_oracle(orc, method, blend):
+    """fast-MLS on a uniform grid runs fused with interpolation and forcing in
+    tile order (octant table in LDS, mirrored lookup): the rows, U and the
+    forcing against the oracle's table blend on the jittered positions."""
+    import torch
+    from paper_1805_01113_amd import mls
+    wl = W.ellipsoids(n_bodies=40, n=128, cfg_id=303)
+    ctx, bufs = _setup(torch, wl)
+    n = wl.n
+    mls.timing_enable(ctx, True)
+    mls.timing_get(ctx, reset=True)
+    mls.step_counter_set(ctx, 4)
+    mls.step(ctx, bufs, method=method, dt=1.0, jitter=0.1 / 128, seed=2)
+    ctx.sync()
+    kt = mls.timing_get(ctx, reset=True)
+    assert "fast_interp" in kt and "build_fast" not in kt, kt
+    order = mls.step_order(ctx, n).cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(order), np.arange(n))
+    xj = [t.cpu().numpy() for t in (bufs.x, bufs.y, bufs.z)]
+    h = mls.unpack_home(bufs.home.cpu().numpy().view(np.uint32), n)
+    p = mls.unpack_phi(bufs.phi.cpu().numpy(), n)
+    g = orc.Grid(wl.grid.faces, wl.grid.periodic)
+    fields = [f.cpu().numpy() for f in bufs.fields]
+    Ug = bufs.U.cpu().numpy()
+    ep, eu, ef = [], [], []
+    for c in range(3):
+        ref = orc.build_fast(g, c, *xj, blend=blend)
+        assert np.array_equal(h[c], ref["home"][order])
+        ep.append(normwise(p[c], ref["phi"][order]))
+        Uo = orc.interp(g, c, ref["home"], ref["phi"], fields[c])
+        eu.append(normwise(Ug[c], Uo))
+        fo, _ = orc.spread(g, c, ref["home"], ref["phi"], wl.area, (-Uo).astype(np.float32))
+        ef.append(normwise(bufs.forcing[c].cpu().numpy(), fo))
+    say("fused fast step (blend %d): phi %s, U %s, forcing %s" %
+        (blend, ["%.1e" % e for e in ep], ["%.1e" % e for e in eu], ["%.1e" % e for e in ef]))
+    assert max(ep) <= PHI_TOL and max(eu) <= U_TOL and max(ef) <= F_TOL
+    # the standalone build (whole table in global memory) gives the same rows
+    home2, phi2, _ = ctx.build(bufs.x, bufs.y, bufs.z, method=method)
+    ctx.sync()
+    p2 = mls.unpack_phi(phi2.cpu().numpy(), n)
+    for c in range(3):
+        assert np.abs(p[c] - p2[c][order]).max() <= 1e-6 * np.abs(p2[c]).max()
+
+
+def test_fast_step_graph_replays_match_eager():
+    import torch
+    from paper_1805_01113_amd import mls
+    wl = W.uneven_bodies(n_bodies=200, n=256, cfg_id=304)
+    ctx, bufs = _setup(torch, wl)
+    amp = 0.1 / 256
+    graph = mls.StepGraph(ctx, bufs, method=mls.MLS_FAST_LINEAR, dt=1.0, jitter=amp, seed=6)
+    ref = []
+    mls.step_counter_set(ctx, 0)
+    for s in range(2):
+        for f in bufs.forcing:
+            f.zero_()
+        mls.step(ctx, bufs, method=mls.MLS_FAST_LINEAR, dt=1.0, jitter=amp, seed=6)
+        ctx.sync()
+        ref.append((bufs.U.cpu().numpy().copy(), [f.cpu().numpy().copy() for f in bufs.forcing]))
+    mls.step_counter_set(ctx, 0)
+    for s in range(2):
+        for f in bufs.forcing:
+            f.zero_()
+        torch.cuda.synchronize()
+        graph.launch(1)
+        ctx.sync()
+        assert np.array_equal(bufs.U.cpu().numpy(), ref[s][0])
+        for c in range(3):
+            assert np.array_equal(bufs.forcing[c].cpu().numpy(), ref[s][1][c])
+    graph.close()
+
+
+def test_fast_step_stretched_takes_the_generic_path(orc):
+    """On a stretched grid (one table per plane) fast-MLS keeps the unfused
+    path and still matches the oracle."""
+    import torch
+    from paper_1805_01113_amd import mls
+    wl = W.stretched_channel(n_bodies=30, nxy=64, nz=96, cfg_id=305)
+    ctx, bufs = _setup(torch, wl)
+    mls.timing_enable(ctx, True)
+    mls.timing_get(ctx, reset=True)
+    mls.step(ctx, bufs, method=mls.MLS_FAST_LINEAR, dt=1.0, jitter=0.0, seed=0)
+    ctx.sync()
+    kt = mls.timing_get(ctx, reset=True)
+    assert "build_fast" in kt and "fast_interp" not in kt, kt
+    g = orc.Grid(wl.grid.faces, wl.grid.periodic)
+    fields = [f.cpu().numpy() for f in bufs.fields]
+    errs = []
+    for c in range(3):
+        ref = orc.build_fast(g, c, wl.x, wl.y, wl.z, blend=1)
+        Uo = orc.interp(g, c, ref["home"], ref["phi"], fields[c])
+        errs.append(normwise(bufs.U[c].cpu().numpy(), Uo))
+    say("stretched fast_linear step U err %s" % ["%.1e" % e for e in errs])
+    assert max(errs) <= U_TOL

@@ -103,23 +103,27 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
     const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
     unsigned long long routed = 0;
     float kmax = 0.f, fmx = 0.f;
-    // the next item's marker and coordinates are loaded one iteration ahead
     int64_t base = (xcd_block() * kGroups + grp) * 64;
-    uint32_t nm = 0;
-    float nx = 0.f, ny = 0.f, nz = 0.f;
-    if (base + lane < n) {
-        nm = order[base + lane];
-        nx = x[nm]; ny = y[nm]; nz = z[nm];
-    }
+    // Pipelined operand loads: the marker of the item after next, and the
+    // position and area of the next item, are requested an iteration ahead.
+    // Loads and stores share one completion counter that drains in order, so
+    // every path through the loop issues the same memory operations: a lane
+    // past the end repeats the last marker (writing identical values, its
+    // shape function into a padding row) and a marker without a support is
+    // computed on a neutral stencil at node 0 and stored as NaN.  A branch
+    // around stores would make the compiler wait for all of them before the
+    // next item's operands.
+    const int64_t last = n - 1;
+    uint32_t nm = order[min(base + lane, last)];
+    float nx = x[nm], ny = y[nm], nz = z[nm], na = area[nm];
+    uint32_t nm2 = order[min(base + gstride + lane, last)];
     for (; base < n; base += gstride) {
-        const int64_t p = base + lane;
+        const bool valid = base + lane < n;
         const int64_t m = nm;
-        const float cx = nx, cy = ny, cz = nz;
-        if (base + gstride + lane < n) {
-            nm = order[base + gstride + lane];
-            nx = x[nm]; ny = y[nm]; nz = z[nm];
-        }
-        if (p >= n) continue;
+        const float cx = nx, cy = ny, cz = nz, ca = na;
+        nm = nm2;
+        nx = x[nm]; ny = y[nm]; nz = z[nm]; na = area[nm];
+        nm2 = order[min(base + 2 * gstride + lane, last)];
         float *out = phi + ((((base >> 6) * 3 + c) * kNe) << 6) + lane;
         uint32_t *hout = home + (((base >> 6) * 3 + c) << 6) + lane;
         uint8_t *rout = route ? route + (((base >> 6) * 3 + c) << 6) + lane : nullptr;
@@ -128,39 +132,46 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
         bool ok = axis_geo(g.ax[0], c == 0, px, G[0]);
         ok = ok && axis_geo(g.ax[1], c == 1, py, G[1]);
         ok = ok && axis_geo(g.ax[2], c == 2, pz, G[2]);
-        if (!ok) {
-            mark_failed(err, m, px, py, pz, hout, out, rout);
-            U[c * n + m] = __builtin_nanf("");
-            F[c * n + m] = __builtin_nanf("");
-            continue;
-        }
-        *hout = pack_home(G[0].ih, G[1].ih, G[2].ih);
+        if (!ok) neutral_geo(G);
+        *hout = ok ? pack_home(G[0].ih, G[1].ih, G[2].ih) : 0xffffffffu;
         // the 27 field values are requested before the solve, which hides
         // their latency
         int64_t ox[3], oy[3], oz[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            ox[a] = nb_index(G[0].ih, a - 1, nxc, g.ax[0].periodic);
-            oy[a] = (int64_t)nb_index(G[1].ih, a - 1, nyc, g.ax[1].periodic) * nxc;
-            oz[a] = (int64_t)nb_index(G[2].ih, a - 1, nzc, g.ax[2].periodic) * nxc * nyc;
+            ox[a] = ok ? nb_index(G[0].ih, a - 1, nxc, g.ax[0].periodic) : 0;
+            oy[a] = ok ? (int64_t)nb_index(G[1].ih, a - 1, nyc, g.ax[1].periodic) * nxc : 0;
+            oz[a] = ok ? (int64_t)nb_index(G[2].ih, a - 1, nzc, g.ax[2].periodic) * nxc * nyc : 0;
         }
         float qv[kNe];
 #pragma unroll
         for (int k = 0; k < kNe; ++k) qv[k] = q[oz[k / 9] + oy[(k / 3) % 3] + ox[k % 3]];
+        const float vbv = vb ? vb[c * n + m] : 0.0f;
         float ph[kNe];
-        if (!exact_from_geo(g, W, tau, c, m, px, py, pz, G, out, rout, 0, err, routed, kmax, ph)) {
-#pragma unroll
-            for (int k = 0; k < kNe; ++k) ph[k] = out[k * kLanes];
+        bool fp64 = false;
+        if (!exact_fp32(W, tau, G, ph, kmax)) {
+            // rare: FP64 re-solve from the position
+            fp64 = true;
+            if (valid) ++routed;
+            if (!solve_fp64_regs(g, W, c, px, py, pz, ph)) raise_error(err, m, MLS_E_SINGULAR);
         }
+        if (rout) *rout = fp64 ? 1 : 0;
+        const float nan = __builtin_nanf("");
+#pragma unroll
+        for (int k = 0; k < kNe; ++k) out[k * kLanes] = ok ? ph[k] : nan;
         float acc = 0.f;
 #pragma unroll
         for (int k = 0; k < kNe; ++k) acc += ph[k] * qv[k];
-        const float f = ((vb ? vb[c * n + m] : 0.0f) - acc) * inv_dt;
-        U[c * n + m] = acc;
-        F[c * n + m] = f;
-        const float af = fabsf(area[m]) * fabsf(f);
-        if (!(af <= 3.0e38f)) raise_error(err, m, MLS_E_RANGE);   // non-finite force (NaN fails too)
-        else fmx = fmaxf(fmx, af);
+        const float f = (vbv - acc) * inv_dt;
+        U[c * n + m] = ok ? acc : nan;
+        F[c * n + m] = ok ? f : nan;
+        if (!ok) {
+            raise_error(err, m, isfinite(px) && isfinite(py) && isfinite(pz) ? MLS_E_SUPPORT : MLS_E_NONFINITE);
+        } else {
+            const float af = fabsf(ca) * fabsf(f);
+            if (!(af <= 3.0e38f)) raise_error(err, m, MLS_E_RANGE);   // non-finite force (NaN fails too)
+            else fmx = fmaxf(fmx, af);
+        }
     }
     unsigned long long tot = routed;
     for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
@@ -356,7 +367,7 @@ k_build_fast(const Grid *__restrict__ gp, const FastTables T, int64_t n,
 // reads the row of its mirror image, and the blended nodes of every such axis
 // are put back in place with a layer of conditional swaps.
 template <bool TRILINEAR>
-__global__ void __launch_bounds__(kBuildBlock)
+__global__ void __launch_bounds__(kBuildBlock) __attribute__((amdgpu_waves_per_eu(4)))
 k_fast_interp(const Grid *__restrict__ gp, const float4 *__restrict__ tab, int nsub, int64_t n,
               const uint32_t *__restrict__ order, const float *__restrict__ x, const float *__restrict__ y,
               const float *__restrict__ z, uint32_t *__restrict__ home, float *__restrict__ phi,
@@ -387,21 +398,18 @@ k_fast_interp(const Grid *__restrict__ gp, const float4 *__restrict__ tab, int n
     const float step = 1.0f / scale;         // sub-cell width, (hi - lo) / (n_sub - 1)
     float fmx = 0.f;
     int64_t base = (xcd_block() * kGroups + grp) * 64;
-    uint32_t nm = 0;
-    float nx = 0.f, ny = 0.f, nz = 0.f;
-    if (base + lane < n) {
-        nm = order[base + lane];
-        nx = x[nm]; ny = y[nm]; nz = z[nm];
-    }
+    // Operand loads pipelined an iteration ahead and one sequence of memory
+    // operations on every path, as in k_build_interp.
+    const int64_t last = n - 1;
+    uint32_t nm = order[min(base + lane, last)];
+    float nx = x[nm], ny = y[nm], nz = z[nm], na = area[nm];
+    uint32_t nm2 = order[min(base + gstride + lane, last)];
     for (; base < n; base += gstride) {
-        const int64_t p = base + lane;
         const int64_t m = nm;
-        const float cx = nx, cy = ny, cz = nz;
-        if (base + gstride + lane < n) {
-            nm = order[base + gstride + lane];
-            nx = x[nm]; ny = y[nm]; nz = z[nm];
-        }
-        if (p >= n) continue;
+        const float cx = nx, cy = ny, cz = nz, ca = na;
+        nm = nm2;
+        nx = x[nm]; ny = y[nm]; nz = z[nm]; na = area[nm];
+        nm2 = order[min(base + 2 * gstride + lane, last)];
         float *out = phi + ((((base >> 6) * 3 + c) * kNe) << 6) + lane;
         uint32_t *hout = home + (((base >> 6) * 3 + c) << 6) + lane;
         uint8_t *rout = route ? route + (((base >> 6) * 3 + c) << 6) + lane : nullptr;
@@ -410,23 +418,19 @@ k_fast_interp(const Grid *__restrict__ gp, const float4 *__restrict__ tab, int n
         bool ok = axis_geo(g.ax[0], c == 0, px, G[0]);
         ok = ok && axis_geo(g.ax[1], c == 1, py, G[1]);
         ok = ok && axis_geo(g.ax[2], c == 2, pz, G[2]);
-        if (!ok) {
-            mark_failed(err, m, px, py, pz, hout, out, rout);
-            U[c * n + m] = __builtin_nanf("");
-            F[c * n + m] = __builtin_nanf("");
-            continue;
-        }
-        *hout = pack_home(G[0].ih, G[1].ih, G[2].ih);
+        if (!ok) neutral_geo(G);
+        *hout = ok ? pack_home(G[0].ih, G[1].ih, G[2].ih) : 0xffffffffu;
         int64_t ox[3], oy[3], oz[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            ox[a] = nb_index(G[0].ih, a - 1, nxc, g.ax[0].periodic);
-            oy[a] = (int64_t)nb_index(G[1].ih, a - 1, nyc, g.ax[1].periodic) * nxc;
-            oz[a] = (int64_t)nb_index(G[2].ih, a - 1, nzc, g.ax[2].periodic) * nxc * nyc;
+            ox[a] = ok ? nb_index(G[0].ih, a - 1, nxc, g.ax[0].periodic) : 0;
+            oy[a] = ok ? (int64_t)nb_index(G[1].ih, a - 1, nyc, g.ax[1].periodic) * nxc : 0;
+            oz[a] = ok ? (int64_t)nb_index(G[2].ih, a - 1, nzc, g.ax[2].periodic) * nxc * nyc : 0;
         }
         float qv[kNe];
 #pragma unroll
         for (int k = 0; k < kNe; ++k) qv[k] = q[oz[k / 9] + oy[(k / 3) % 3] + ox[k % 3]];
+        const float vbv = vb ? vb[c * n + m] : 0.0f;
         // the sub-cell and the blend weights in the true frame, as the
         // whole-table lookup computes them (so a marker on a sub-cell face
         // gets the same sub-cell); only the rows come from the mirror image
@@ -520,19 +524,24 @@ k_fast_interp(const Grid *__restrict__ gp, const float4 *__restrict__ tab, int n
             ph[k0] = flip[2] ? t2 : t0;
             ph[k0 + 18] = flip[2] ? t0 : t2;
         }
+        const float nan = __builtin_nanf("");
         float acc = 0.f;
 #pragma unroll
         for (int k = 0; k < kNe; ++k) {
-            out[k * kLanes] = ph[k];
+            out[k * kLanes] = ok ? ph[k] : nan;
             acc += ph[k] * qv[k];
         }
         if (rout) *rout = 0;
-        const float f = ((vb ? vb[c * n + m] : 0.0f) - acc) * inv_dt;
-        U[c * n + m] = acc;
-        F[c * n + m] = f;
-        const float af = fabsf(area[m]) * fabsf(f);
-        if (!(af <= 3.0e38f)) raise_error(err, m, MLS_E_RANGE);
-        else fmx = fmaxf(fmx, af);
+        const float f = (vbv - acc) * inv_dt;
+        U[c * n + m] = ok ? acc : nan;
+        F[c * n + m] = ok ? f : nan;
+        if (!ok) {
+            raise_error(err, m, isfinite(px) && isfinite(py) && isfinite(pz) ? MLS_E_SUPPORT : MLS_E_NONFINITE);
+        } else {
+            const float af = fabsf(ca) * fabsf(f);
+            if (!(af <= 3.0e38f)) raise_error(err, m, MLS_E_RANGE);
+            else fmx = fmaxf(fmx, af);
+        }
     }
     for (int off = 32; off > 0; off >>= 1) fmx = fmaxf(fmx, __shfl_xor(fmx, off));
     __shared__ float bm[kBuildBlock / 64];

@@ -46,6 +46,54 @@ __device__ __forceinline__ bool solve_fp64(const Grid &g, const Weight &W, int c
     return ok;
 }
 
+// Stencil for a marker without a support: the uniform node offsets -1, 0, 1
+// at node 0.  The fused kernels compute such a marker like any other (so all
+// lanes issue the same memory operations) and store NaN in its place.
+__device__ __forceinline__ void neutral_geo(AxisGeo G[3])
+{
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        G[d].ih = 0;
+        G[d].s[0] = -1.f; G[d].s[1] = 0.f; G[d].s[2] = 1.f;
+        G[d].xi = 0.f;
+        G[d].rho = 1.f;
+    }
+}
+
+// The same FP64 re-solve with the 27 values returned in registers.
+__device__ __forceinline__ bool solve_fp64_regs(const Grid &g, const Weight &W, int c, double px, double py,
+                                                double pz, float ph[kNe])
+{
+    double s[3][3], w[3][3];
+    Moments<double> m[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        axis_offsets_d(g.ax[d], d == c, d == 0 ? px : (d == 1 ? py : pz), s[d]);
+        double m0 = 0, m1 = 0, m2 = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            w[d][a] = weight1_d(W, s[d][a]);
+            m0 += w[d][a]; m1 += w[d][a] * s[d][a]; m2 += w[d][a] * s[d][a] * s[d][a];
+        }
+        m[d] = {m0, m1, m2};
+    }
+    double A[10], L[10], gam[4] = {0.0, 0.0, 0.0, 0.0};
+    assemble(m[0], m[1], m[2], A);
+    const bool ok = cholesky4(A, L);
+    if (ok) {
+        const double e0[4] = {1.0, 0.0, 0.0, 0.0};
+        chol_solve(L, e0, gam);
+    }
+#pragma unroll
+    for (int k = 0; k < kNe; ++k) {
+        const int a = k % 3, b = (k / 3) % 3, cc = k / 9;
+        const double W3 = w[0][a] * w[1][b] * w[2][cc];
+        ph[k] = ok ? (float)(W3 * (gam[0] + gam[1] * s[0][a] + gam[2] * s[1][b] + gam[3] * s[2][cc]))
+                   : __builtin_nanf("");
+    }
+    return ok;
+}
+
 __device__ __forceinline__ void mark_failed(ErrWord *err, int64_t l, double px, double py, double pz,
                                             uint32_t *hout, float *out, uint8_t *rout)
 {

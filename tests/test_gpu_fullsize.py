@@ -83,7 +83,11 @@ def _near(cells, probes, dims, periodic, reach=2):
 
 
 def _check(orc, torch, wl, bufs, fields, forcing, amp, counter, u_tol, label, forcing_check=True, n_sample=1500,
-           n_probe=40):
+           n_probe=40, build=None):
+    """build(g, c, x, y, z) -> dict(home, phi): the oracle's shape functions
+    for the method under test (exact MLS by default)."""
+    if build is None:
+        build = orc.build_exact
     g = orc.Grid(wl.grid.faces, wl.grid.periodic)
     xj = orc.jitter(wl.x, wl.y, wl.z, counter, np.float32(amp), 20180503)
     r = np.random.default_rng(7)
@@ -95,7 +99,7 @@ def _check(orc, torch, wl, bufs, fields, forcing, amp, counter, u_tol, label, fo
     cells = [_cells(wl.grid.faces[d], wl.grid.periodic[d], xj[d]) for d in range(3)]
     for c in range(3):
         q = fields[c].cpu().numpy()
-        ref = orc.build_exact(g, c, *[a[sample] for a in xj])
+        ref = build(g, c, *[a[sample] for a in xj])
         Uo = orc.interp(g, c, ref["home"], ref["phi"], q)
         del q
         eu = normwise(Ug[c][sample], Uo)
@@ -105,7 +109,7 @@ def _check(orc, torch, wl, bufs, fields, forcing, amp, counter, u_tol, label, fo
             # forcing at probe nodes: home nodes of some sampled markers
             probes = ref["home"][r.choice(n_sample, n_probe, replace=False)]
             idx = np.nonzero(_near(cells, probes, ncell, wl.grid.periodic))[0]
-            refn = orc.build_exact(g, c, *[a[idx] for a in xj])
+            refn = build(g, c, *[a[idx] for a in xj])
             fo, _ = orc.spread(g, c, refn["home"], refn["phi"], wl.area[idx], Fg[c][idx])
             pv_o = np.array([fo[k, j, i] for i, j, k in probes])
             del fo
@@ -158,3 +162,20 @@ def test_stretched_channel_full_size_exact_and_learned(orc, tmp_path):
         ctx.close()
         del bufs, fields, forcing
         torch.cuda.empty_cache()
+
+
+def test_uneven_bodies_full_size_fast_trilinear(orc, tmp_path):
+    """The fused fast-MLS step (trilinear blend, octant table in LDS) at full
+    size: U of sampled markers, forcing at probe nodes and conservation
+    against the oracle's table blend."""
+    import torch
+    from paper_1805_01113_amd import mls
+    from paper_1805_01113_amd import workloads as W
+    wl = W.uneven_bodies()
+    ctx, bufs, fields, forcing, amp, counter = _run_step(torch, wl, mls.MLS_FAST_LINEAR, str(tmp_path / "t.jsonl"))
+
+    def build(g, c, x, y, z):
+        return orc.build_fast(g, c, x, y, z, blend=orc.BLEND_TRILINEAR)
+
+    _check(orc, torch, wl, bufs, fields, forcing, amp, counter, U_TOL, "uneven fast trilinear", build=build)
+    ctx.close()

@@ -209,9 +209,15 @@ def compare_methods(torch, ctx, wl, bufs, fields, forcing, x0, y0, z0, area, jit
             tot = st["learned"] + st["fallbacks"]
             row["fallback_rate"] = st["fallbacks"] / max(1, tot)
             row["network_kept"] = st["learned"]
+        saved = None
         if m == main_method:
             ms = ms_main
         else:
+            if not args.no_tune:
+                # each method with the launch shapes tuned for it
+                saved = ctx.tune_get()
+                ctx.autotune(bufs, method=m, cache_path=args.tune_cache)
+                row["autotune"] = {k: v for k, v in ctx.tune_get().items()}
             g2 = mls.StepGraph(ctx, bufs, method=m, dt=1.0, jitter=jitter, seed=seed)
             g2.launch(args.warmup)
             torch.cuda.synchronize()
@@ -227,6 +233,9 @@ def compare_methods(torch, ctx, wl, bufs, fields, forcing, x0, y0, z0, area, jit
         row["batched"] = {"ms_per_step": round(ms, 4), "markers_per_s": round(n / (ms * 1e-3), 1)}
         rate = per_body_rate(torch, ctx, wl, bufs, fields, forcing, x0, y0, z0, area, m, jitter, seed, stream, sub)
         row["per_body"] = {"markers_per_s": round(rate, 1), "bodies_timed": sub}
+        if saved is not None:
+            ctx.tune_set(**{k: saved[k] for k in ("spread_tile", "spread_blocks_per_cu", "build_blocks_per_cu",
+                                                 "interp_blocks_per_cu")})
         log("%s: batched %.3f ms/step (%.3e markers/s), per-body %.3e markers/s, interp err vs exact %.2e%s"
             % (name, ms, n / (ms * 1e-3), rate, err,
                (", fallback rate %.4f" % row["fallback_rate"]) if "fallback_rate" in row else ""))

@@ -451,10 +451,13 @@ def main():
         "build_fast": 12 + 12 + 324.0,
         "build_learned": 12 + 12 + 324.0,
         "interp": 12 + 324 + 12 + 4.0 * t_per,
-        "build_interp": 12 + 12 + 324 + 4.0 * t_per + 12 + 12,
-        "fast_interp": 12 + 12 + 324 + 4.0 * t_per + 12 + 12,
+        # positions, homes, phi, touched field values, U and F by marker, A F by row
+        "build_interp": 12 + 12 + 324 + 4.0 * t_per + 12 + 12 + 12,
+        "fast_interp": 12 + 12 + 324 + 4.0 * t_per + 12 + 12 + 12,
         "force": 24.0,
-        "spread_tiles": 12 + 324 + 12 + 4 + 8.0 * t_per,
+        # homes, phi, A F by row (tile order; by marker for the standalone spreading:
+        # A and F, 16 bytes), read-modify-write of the touched field values
+        "spread_tiles": 12 + 324 + 12 + 8.0 * t_per,
         "spread_bin": 0.0,
     }
     kernels = {}

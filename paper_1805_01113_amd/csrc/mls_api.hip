@@ -346,6 +346,7 @@ void mls_ctx_destroy(mls_ctx *ctx)
     hipFree(c.tile_active);
     hipFree(c.block_sums);
     hipFree(c.entries);
+    hipFree(c.af_rows);
     hipFree(c.block_fmax);
     hipFree(c.tile_hmin_block);
     hipFree(c.refine_scratch);
@@ -365,11 +366,21 @@ mls_status mls_reserve(mls_ctx *ctx, int64_t n)
     if (n <= c.cap_markers) return MLS_OK;
     hipDeviceSynchronize();
     hipFree(c.entries);
+    hipFree(c.af_rows);
     c.entries = nullptr;
+    c.af_rows = nullptr;
     c.cap_markers = 0;
+    c.af_stride = 0;
+    const int64_t stride = (n + 63) / 64 * 64;
     hipError_t e = hipMalloc((void **)&c.entries, (size_t)n * sizeof(uint32_t));
-    if (e != hipSuccess) return hip_fail(ctx, e, "spread scratch");
+    if (e == hipSuccess) e = hipMalloc((void **)&c.af_rows, (size_t)3 * stride * sizeof(float));
+    if (e != hipSuccess) {
+        hipFree(c.entries);
+        c.entries = nullptr;
+        return hip_fail(ctx, e, "spread scratch");
+    }
     c.cap_markers = n;
+    c.af_stride = stride;
     return MLS_OK;
 }
 

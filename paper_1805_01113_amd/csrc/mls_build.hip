@@ -92,7 +92,8 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
                uint32_t *__restrict__ home, float *__restrict__ phi, uint8_t *__restrict__ route,
                const float *__restrict__ u, const float *__restrict__ v, const float *__restrict__ w,
                const float *__restrict__ vb, const float *__restrict__ area, float inv_dt, float *__restrict__ U,
-               float *__restrict__ F, uint32_t *__restrict__ block_fmax, ErrWord *err, DevStats *st)
+               float *__restrict__ F, float *__restrict__ af_rows, int64_t af_stride, uint32_t *__restrict__ block_fmax,
+               ErrWord *err, DevStats *st)
 {
     const Grid &g = *gp;
     const int wave = wave_id(), lane = threadIdx.x & 63;
@@ -165,6 +166,8 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
         const float f = (vbv - acc) * inv_dt;
         U[c * n + m] = ok ? acc : nan;
         F[c * n + m] = ok ? f : nan;
+        // A_l F_l by row for the spreading (row p < af_stride: padding rows too)
+        af_rows[c * af_stride + base + lane] = ok ? ca * f : 0.0f;
         if (!ok) {
             raise_error(err, m, isfinite(px) && isfinite(py) && isfinite(pz) ? MLS_E_SUPPORT : MLS_E_NONFINITE);
         } else {
@@ -373,7 +376,8 @@ k_fast_interp(const Grid *__restrict__ gp, const float4 *__restrict__ tab, int n
               const float *__restrict__ z, uint32_t *__restrict__ home, float *__restrict__ phi,
               uint8_t *__restrict__ route, const float *__restrict__ u, const float *__restrict__ v,
               const float *__restrict__ w, const float *__restrict__ vb, const float *__restrict__ area, float inv_dt,
-              float *__restrict__ U, float *__restrict__ F, uint32_t *__restrict__ block_fmax, ErrWord *err)
+              float *__restrict__ U, float *__restrict__ F, float *__restrict__ af_rows, int64_t af_stride,
+              uint32_t *__restrict__ block_fmax, ErrWord *err)
 {
     extern __shared__ float4 oct[];   // [nh^3][7]
     const Grid &g = *gp;
@@ -535,6 +539,8 @@ k_fast_interp(const Grid *__restrict__ gp, const float4 *__restrict__ tab, int n
         const float f = (vbv - acc) * inv_dt;
         U[c * n + m] = ok ? acc : nan;
         F[c * n + m] = ok ? f : nan;
+        // A_l F_l by row for the spreading (row p < af_stride: padding rows too)
+        af_rows[c * af_stride + base + lane] = ok ? ca * f : 0.0f;
         if (!ok) {
             raise_error(err, m, isfinite(px) && isfinite(py) && isfinite(pz) ? MLS_E_SUPPORT : MLS_E_NONFINITE);
         } else {
@@ -649,7 +655,7 @@ hipError_t launch_build_interp(const Ctx &c, int64_t n, const float *x, const fl
     const float tau = (float)(c.opts.kappa_tau > 3.0e38 ? 3.0e38 : c.opts.kappa_tau);
     hipLaunchKernelGGL(k_build_interp, dim3(build_grid(n, c.cu_count, c.build_blocks_per_cu)), dim3(kBuildBlock), 0,
                        s, c.d_grid, c.w, tau, n, c.entries, x, y, z, home, phi, route, u, v, w, vb, area, 1.0f / dt,
-                       U, F, c.block_fmax, c.err, c.stats);
+                       U, F, c.af_rows, c.af_stride, c.block_fmax, c.err, c.stats);
     return hipGetLastError();
 }
 
@@ -674,10 +680,12 @@ hipError_t launch_fast_interp(const Ctx &c, int64_t n, const float *x, const flo
     const float4 *tab = reinterpret_cast<const float4 *>(c.tables);
     if (trilinear_blend)
         hipLaunchKernelGGL(k_fast_interp<true>, grid, dim3(kBuildBlock), lds, s, c.d_grid, tab, nsub, n, c.entries, x,
-                           y, z, home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.block_fmax, c.err);
+                           y, z, home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.af_rows, c.af_stride,
+                           c.block_fmax, c.err);
     else
         hipLaunchKernelGGL(k_fast_interp<false>, grid, dim3(kBuildBlock), lds, s, c.d_grid, tab, nsub, n, c.entries, x,
-                           y, z, home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.block_fmax, c.err);
+                           y, z, home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.af_rows, c.af_stride,
+                           c.block_fmax, c.err);
     return hipGetLastError();
 }
 

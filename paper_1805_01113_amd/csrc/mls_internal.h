@@ -148,6 +148,8 @@ struct Ctx {
     uint32_t *tile_active = nullptr;   // ntiles: non-empty tiles, grouped by colour
     uint32_t *block_sums = nullptr;    // scan partials
     uint32_t *entries = nullptr;       // cap_markers: markers sorted by tile
+    float *af_rows = nullptr;          // [3][af_stride]: A_l F_l of the exact step's rows (tile order)
+    int64_t af_stride = 0;             // cap_markers rounded up to 64
     uint32_t *block_fmax = nullptr;    // per-block force maxima of the counting pass (3 per block)
     uint32_t *work = nullptr;          // [0..26] active-list sizes per colour, [32..58] cursors,
                                        // [64..66] max |A F| per component (FP32 bits)

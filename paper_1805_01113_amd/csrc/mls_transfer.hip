@@ -371,7 +371,8 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                 const float *__restrict__ Fy, const float *__restrict__ Fz, float *__restrict__ fx,
                 float *__restrict__ fy, float *__restrict__ fz, const uint32_t *__restrict__ off,
                 const uint32_t *__restrict__ entries, const uint32_t *__restrict__ active, uint32_t *work,
-                const uint32_t *__restrict__ fmax_bits, ErrWord *err)
+                const uint32_t *__restrict__ fmax_bits, const float *__restrict__ af_rows, int64_t af_stride,
+                ErrWord *err)
 {
     const Grid &g = *gp;
     extern __shared__ unsigned long long acc[];     // the box of one component
@@ -420,7 +421,9 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
             const float *Fc = c == 0 ? Fx : (c == 1 ? Fy : Fz);
             __syncthreads();
             for (uint32_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
-                const uint32_t m = entries[e];
+                // tile order: the row is the entry and A_l F_l comes by row, so
+                // no load waits for the marker index (read on the error path only)
+                const uint32_t m = SORTED ? 0u : entries[e];
                 const int64_t row = SORTED ? (int64_t)e : (int64_t)m;
                 int hi, hj, hk;
                 unpack_home(home[home_at(row, c)], hi, hj, hk);
@@ -446,7 +449,7 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                             (unsigned)iz[a] < (unsigned)bz;
                 }
                 if (!inbox) {           // cannot happen for a home written by the build
-                    raise_error(err, m, MLS_E_RANGE);
+                    raise_error(err, SORTED ? entries[e] : m, MLS_E_RANGE);
                     continue;
                 }
                 float hl = 0.f, den = 0.f;
@@ -457,7 +460,8 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                     den += ph[k] * (wx[a] * wy[b] * wz[cz]);
                 }
                 // c_l F_l = A_l h_l F_l / sum_k phi_k dV_k   (eq. 8), pre-scaled
-                const float vsc = area[m] * (hl * (1.0f / 3.0f)) * Fc[m] / den * scale_f;
+                const float af = SORTED ? af_rows[c * af_stride + e] : area[m] * Fc[m];
+                const float vsc = af * (hl * (1.0f / 3.0f)) / den * scale_f;
                 bool range_ok = true;
 #pragma unroll
                 for (int k = 0; k < kNe; ++k) {
@@ -468,7 +472,7 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                     const long long qv = (long long)(int)rintf(vs);
                     if (qv != 0) atomicAdd(&acc[(iz[cz] * by + iy[b]) * bx + ix[a]], (unsigned long long)qv);
                 }
-                if (!range_ok) raise_error(err, m, MLS_E_RANGE);
+                if (!range_ok) raise_error(err, SORTED ? entries[e] : m, MLS_E_RANGE);
             }
             __syncthreads();
             // flush: the box nodes of a thread are read in batches of kFlush
@@ -537,7 +541,7 @@ static hipError_t launch_tiles(Ctx &c, int64_t n, const uint32_t *home, const fl
         if (c.colour_tiles[col] == 0) continue;
         hipLaunchKernelGGL(k_spread_colour<SORTED>, dim3(persist), dim3(kBlock), lds, s, c.d_grid, col, n, home, phi,
                            area, Fx, Fy, Fz, fx, fy, fz, c.tile_off, c.entries, c.tile_active, c.work, c.work + 64,
-                           c.err);
+                           SORTED ? c.af_rows : nullptr, c.af_stride, c.err);
     }
     return hipGetLastError();
 }

@@ -361,6 +361,19 @@ __device__ __forceinline__ int box_local(const Axis &a, int ntile, int nodes, in
     return l;
 }
 
+// Workgroup barrier for LDS only.  The phases of a tile share data through
+// LDS alone: each field node is flushed by one thread and same-colour tiles
+// never overlap, so no thread needs another's global stores.  A full
+// __syncthreads would also wait for every outstanding global store (the
+// flush of the previous component) before the next phase could start.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): this thread's LDS operations are done
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // SORTED: row e of home / phi belongs to marker entries[e] (the exact time
 // step writes them in tile order), so a tile reads its rows contiguously;
 // otherwise home / phi are indexed by marker.
@@ -388,7 +401,7 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
             const int64_t t = i < nact ? (int64_t)active[abase + i] : -1;
             tile_sh = t < g.ntiles ? t : -1;
         }
-        __syncthreads();
+        lds_barrier();
         const int64_t t = tile_sh;
         if (t < 0) break;
         const uint32_t beg = off[t], end = off[t + 1];
@@ -419,7 +432,7 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
             const float lim = 1073741824.0f;            // 2^30
             const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
             const float *Fc = c == 0 ? Fx : (c == 1 ? Fy : Fz);
-            __syncthreads();
+            lds_barrier();
             for (uint32_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
                 // tile order: the row is the entry and A_l F_l comes by row, so
                 // no load waits for the marker index (read on the error path only)
@@ -474,7 +487,7 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                 }
                 if (!range_ok) raise_error(err, SORTED ? entries[e] : m, MLS_E_RANGE);
             }
-            __syncthreads();
+            lds_barrier();
             // flush: the box nodes of a thread are read in batches of kFlush
             // before any is written back, so their loads overlap
             constexpr int kFlush = 8;
@@ -509,7 +522,7 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                 for (int u = 0; u < kFlush; ++u)
                     if (dst[u]) *dst[u] = old[u] + add[u];
             }
-            __syncthreads();
+            lds_barrier();
         }
     }
 }

@@ -400,9 +400,10 @@ mls_status mls_timing_get(mls_ctx *ctx, mls_timing *out, int32_t reset);
 
 /* ---- launch shapes and the autotuner (an addition to the paper's method) ---
  * spread_tile: edge of the spreading tiles (4..16, as mls_opts.spread_tile);
- * *_blocks_per_cu (1..64): resident workgroups per compute unit of the
+ * *_blocks_per_cu (1..64): workgroups per compute unit in the grid of the
  * spreading tile launches (bounded further by the LDS of a tile's boxes), of
- * the exact / fast build and of the interpolation. */
+ * the exact / fast build and of the interpolation; a grid-stride loop covers
+ * the work beyond the grid. */
 typedef struct {
     int32_t spread_tile;
     int32_t spread_blocks_per_cu;

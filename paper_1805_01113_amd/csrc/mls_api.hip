@@ -318,7 +318,7 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
     hipMemset(c.stats, 0, sizeof(DevStats));
     hipMemset(c.work, 0, 128 * sizeof(uint32_t));
     hipMemset(c.step_ctr, 0, sizeof(unsigned long long));
-    if (hipMalloc((void **)&c.block_fmax, (size_t)3 * (c.cu_count * kMaxBlocksPerCu + 8) * sizeof(uint32_t)) != hipSuccess) {
+    if (hipMalloc((void **)&c.block_fmax, (size_t)3 * (c.cu_count * kMaxBlocksPerCu + kBuildGridMultiple) * sizeof(uint32_t)) != hipSuccess) {
         mls_ctx_destroy(ctx);
         return MLS_E_NOMEM;
     }

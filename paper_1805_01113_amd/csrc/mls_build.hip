@@ -15,30 +15,53 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// Work split of the build kernels: a block holds kGroups groups of 64
-// consecutive markers; each group is handled by three wavefronts, one per
-// velocity component, so a wavefront stores 64 consecutive floats per
-// support node and the component is uniform across it.
-constexpr int kGroups = 2;
-constexpr int kBuildBlock = 3 * 64 * kGroups;
+// Work split of the build kernels.  64 consecutive markers (rows) form an
+// item, and each item is handled by three wavefronts, one per velocity
+// component, so a wavefront stores 64 consecutive floats per support node and
+// its component is uniform.  The wavefronts of the grid are numbered
+// XCD-contiguously (workgroup xcd_block(), then wavefront within it);
+// wavefront gw takes component gw % 3 of the items gw / 3, gw / 3 + S, ...,
+// where S is a third of the grid's wavefronts.  A workgroup is kBuildWaves
+// wavefronts whatever the register budget, so the compute unit's wavefront
+// slots fill completely (a workgroup of two whole items, six wavefronts, left
+// two of eight slots idle at two wavefronts per SIMD).  The grid is a multiple
+// of 24 workgroups: the three wavefronts of an item then run on one XCD.
+constexpr int kBuildWaves = 4;
+constexpr int kBuildBlock = 64 * kBuildWaves;
 
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
-__global__ void __launch_bounds__(kBuildBlock)
+// component of wavefront w of this workgroup
+__device__ __forceinline__ int wave_component(int w) { return (int)((xcd_block() * kBuildWaves + w) % 3); }
+
+struct WaveWork {
+    int c;            // velocity component
+    int64_t base;     // first row of the first item
+    int64_t stride;   // rows between successive items of the wavefront
+};
+
+__device__ __forceinline__ WaveWork wave_work()
+{
+    const int gw = (int)xcd_block() * kBuildWaves + wave_id();
+    const int tw = (int)gridDim.x * kBuildWaves;
+    return {gw % 3, (int64_t)(gw / 3) * 64, (int64_t)(tw / 3) * 64};
+}
+
+__global__ void __launch_bounds__(kBuildBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_build_exact(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n,
               const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
               uint32_t *__restrict__ home, float *__restrict__ phi, uint8_t *__restrict__ route,
               ErrWord *err, DevStats *st)
 {
     const Grid &g = *gp;
-    const int wave = wave_id(), lane = threadIdx.x & 63;
-    const int c = wave % 3;
-    const int grp = wave / 3;
-    const int64_t gstride = (int64_t)gridDim.x * kGroups * 64;
+    const int lane = threadIdx.x & 63;
+    const WaveWork ww = wave_work();
+    const int c = ww.c;
+    const int64_t gstride = ww.stride;
     unsigned long long routed = 0;
     float kmax = 0.f;
     // the next item's coordinates are loaded one iteration ahead
-    int64_t base = (xcd_block() * kGroups + grp) * 64;
+    int64_t base = ww.base;
     float nx = 0.f, ny = 0.f, nz = 0.f;
     if (base + lane < n) { nx = x[base + lane]; ny = y[base + lane]; nz = z[base + lane]; }
     for (; base < n; base += gstride) {
@@ -86,7 +109,7 @@ k_build_exact(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n,
 // F[c][m] = (V_b - U) / dt, so phi is not read back (the FP64 route reads its
 // own stored values).  Each workgroup also records max |A_m F_m| per component
 // in block_fmax[3 blockIdx + c], the scale of the spreading sums.
-__global__ void __launch_bounds__(kBuildBlock)
+__global__ void __launch_bounds__(kBuildBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n, const uint32_t *__restrict__ order,
                const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
                uint32_t *__restrict__ home, float *__restrict__ phi, uint8_t *__restrict__ route,
@@ -97,14 +120,14 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
 {
     const Grid &g = *gp;
     const int wave = wave_id(), lane = threadIdx.x & 63;
-    const int c = wave % 3;
-    const int grp = wave / 3;
-    const int64_t gstride = (int64_t)gridDim.x * kGroups * 64;
+    const WaveWork ww = wave_work();
+    const int c = ww.c;
+    const int64_t gstride = ww.stride;
     const float *q = c == 0 ? u : (c == 1 ? v : w);
     const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
     unsigned long long routed = 0;
     float kmax = 0.f, fmx = 0.f;
-    int64_t base = (xcd_block() * kGroups + grp) * 64;
+    int64_t base = ww.base;
     // Pipelined operand loads: the marker of the item after next, and the
     // position and area of the next item, are requested an iteration ahead.
     // Loads and stores share one completion counter that drains in order, so
@@ -134,7 +157,7 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
         ok = ok && axis_geo(g.ax[1], c == 1, py, G[1]);
         ok = ok && axis_geo(g.ax[2], c == 2, pz, G[2]);
         if (!ok) neutral_geo(G);
-        *hout = ok ? pack_home(G[0].ih, G[1].ih, G[2].ih) : 0xffffffffu;
+        st_stream(hout, ok ? pack_home(G[0].ih, G[1].ih, G[2].ih) : 0xffffffffu);
         // the 27 field values are requested before the solve, which hides
         // their latency
         int64_t ox[3], oy[3], oz[3];
@@ -159,15 +182,15 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
         if (rout) *rout = fp64 ? 1 : 0;
         const float nan = __builtin_nanf("");
 #pragma unroll
-        for (int k = 0; k < kNe; ++k) out[k * kLanes] = ok ? ph[k] : nan;
+        for (int k = 0; k < kNe; ++k) st_stream(&out[k * kLanes], ok ? ph[k] : nan);
         float acc = 0.f;
 #pragma unroll
         for (int k = 0; k < kNe; ++k) acc += ph[k] * qv[k];
         const float f = (vbv - acc) * inv_dt;
-        U[c * n + m] = ok ? acc : nan;
-        F[c * n + m] = ok ? f : nan;
+        st_stream(&U[c * n + m], ok ? acc : nan);
+        st_stream(&F[c * n + m], ok ? f : nan);
         // A_l F_l by row for the spreading (row p < af_stride: padding rows too)
-        af_rows[c * af_stride + base + lane] = ok ? ca * f : 0.0f;
+        st_stream(&af_rows[c * af_stride + base + lane], ok ? ca * f : 0.0f);
         if (!ok) {
             raise_error(err, m, isfinite(px) && isfinite(py) && isfinite(pz) ? MLS_E_SUPPORT : MLS_E_NONFINITE);
         } else {
@@ -181,7 +204,7 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
     float km = kmax;
     for (int off = 32; off > 0; off >>= 1) km = fmaxf(km, __shfl_xor(km, off));
     for (int off = 32; off > 0; off >>= 1) fmx = fmaxf(fmx, __shfl_xor(fmx, off));
-    __shared__ float bm[kBuildBlock / 64];
+    __shared__ float bm[kBuildWaves];
     if (lane == 0) {
         if (tot) atomicAdd(&st->fp64_solves, tot);
         if (km > 0.f) atomicMax(&st->kappa_max_bits, __float_as_uint(km));
@@ -190,7 +213,8 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
     __syncthreads();
     if (threadIdx.x < 3) {
         float v = 0.f;
-        for (int q2 = threadIdx.x; q2 < kBuildBlock / 64; q2 += 3) v = fmaxf(v, bm[q2]);
+        for (int q2 = 0; q2 < kBuildWaves; ++q2)
+            if (wave_component(q2) == (int)threadIdx.x) v = fmaxf(v, bm[q2]);
         block_fmax[3 * blockIdx.x + threadIdx.x] = __float_as_uint(v);
     }
 }
@@ -259,7 +283,7 @@ __device__ __forceinline__ void shepard(const float *__restrict__ tab, const flo
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int k = 4 * q + e;
-            if (k < kNe) out[k * kLanes] = vals[e];
+            if (k < kNe) st_stream(&out[k * kLanes], vals[e]);
         }
     }
 }
@@ -303,25 +327,25 @@ __device__ __forceinline__ void trilinear(const float *__restrict__ tab, const f
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int k = 4 * q + e;
-            if (k < kNe) out[k * kLanes] = vals[e];
+            if (k < kNe) st_stream(&out[k * kLanes], vals[e]);
         }
     }
 }
 
 template <bool TRILINEAR>
-__global__ void __launch_bounds__(kBuildBlock)
+__global__ void __launch_bounds__(kBuildBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_build_fast(const Grid *__restrict__ gp, const FastTables T, int64_t n,
              const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
              uint32_t *__restrict__ home, float *__restrict__ phi, uint8_t *__restrict__ route, ErrWord *err)
 {
     const Grid &g = *gp;
-    const int wave = wave_id(), lane = threadIdx.x & 63;
-    const int c = wave % 3;
-    const int grp = wave / 3;
-    const int64_t gstride = (int64_t)gridDim.x * kGroups * 64;
+    const int lane = threadIdx.x & 63;
+    const WaveWork ww = wave_work();
+    const int c = ww.c;
+    const int64_t gstride = ww.stride;
     const int64_t rows = (int64_t)T.n_sub * T.n_sub * T.n_sub;
     // the next item's coordinates are loaded one iteration ahead
-    int64_t base = (xcd_block() * kGroups + grp) * 64;
+    int64_t base = ww.base;
     float nx = 0.f, ny = 0.f, nz = 0.f;
     if (base + lane < n) { nx = x[base + lane]; ny = y[base + lane]; nz = z[base + lane]; }
     for (; base < n; base += gstride) {
@@ -393,15 +417,15 @@ k_fast_interp(const Grid *__restrict__ gp, const float4 *__restrict__ tab, int n
     }
     __syncthreads();
     const int wave = wave_id(), lane = threadIdx.x & 63;
-    const int c = wave % 3;
-    const int grp = wave / 3;
-    const int64_t gstride = (int64_t)gridDim.x * kGroups * 64;
+    const WaveWork ww = wave_work();
+    const int c = ww.c;
+    const int64_t gstride = ww.stride;
     const float *q = c == 0 ? u : (c == 1 ? v : w);
     const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
     const float scale = (float)(nsub - 1);   // sub-cells per unit of xi (home CV [-1/2, 1/2))
     const float step = 1.0f / scale;         // sub-cell width, (hi - lo) / (n_sub - 1)
     float fmx = 0.f;
-    int64_t base = (xcd_block() * kGroups + grp) * 64;
+    int64_t base = ww.base;
     // Operand loads pipelined an iteration ahead and one sequence of memory
     // operations on every path, as in k_build_interp.
     const int64_t last = n - 1;
@@ -423,7 +447,7 @@ k_fast_interp(const Grid *__restrict__ gp, const float4 *__restrict__ tab, int n
         ok = ok && axis_geo(g.ax[1], c == 1, py, G[1]);
         ok = ok && axis_geo(g.ax[2], c == 2, pz, G[2]);
         if (!ok) neutral_geo(G);
-        *hout = ok ? pack_home(G[0].ih, G[1].ih, G[2].ih) : 0xffffffffu;
+        st_stream(hout, ok ? pack_home(G[0].ih, G[1].ih, G[2].ih) : 0xffffffffu);
         int64_t ox[3], oy[3], oz[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -532,15 +556,15 @@ k_fast_interp(const Grid *__restrict__ gp, const float4 *__restrict__ tab, int n
         float acc = 0.f;
 #pragma unroll
         for (int k = 0; k < kNe; ++k) {
-            out[k * kLanes] = ok ? ph[k] : nan;
+            st_stream(&out[k * kLanes], ok ? ph[k] : nan);
             acc += ph[k] * qv[k];
         }
         if (rout) *rout = 0;
         const float f = (vbv - acc) * inv_dt;
-        U[c * n + m] = ok ? acc : nan;
-        F[c * n + m] = ok ? f : nan;
+        st_stream(&U[c * n + m], ok ? acc : nan);
+        st_stream(&F[c * n + m], ok ? f : nan);
         // A_l F_l by row for the spreading (row p < af_stride: padding rows too)
-        af_rows[c * af_stride + base + lane] = ok ? ca * f : 0.0f;
+        st_stream(&af_rows[c * af_stride + base + lane], ok ? ca * f : 0.0f);
         if (!ok) {
             raise_error(err, m, isfinite(px) && isfinite(py) && isfinite(pz) ? MLS_E_SUPPORT : MLS_E_NONFINITE);
         } else {
@@ -550,12 +574,13 @@ k_fast_interp(const Grid *__restrict__ gp, const float4 *__restrict__ tab, int n
         }
     }
     for (int off = 32; off > 0; off >>= 1) fmx = fmaxf(fmx, __shfl_xor(fmx, off));
-    __shared__ float bm[kBuildBlock / 64];
+    __shared__ float bm[kBuildWaves];
     if (lane == 0) bm[wave] = fmx;
     __syncthreads();
     if (threadIdx.x < 3) {
         float vv = 0.f;
-        for (int q2 = threadIdx.x; q2 < kBuildBlock / 64; q2 += 3) vv = fmaxf(vv, bm[q2]);
+        for (int q2 = 0; q2 < kBuildWaves; ++q2)
+            if (wave_component(q2) == (int)threadIdx.x) vv = fmaxf(vv, bm[q2]);
         block_fmax[3 * blockIdx.x + threadIdx.x] = __float_as_uint(vv);
     }
 }
@@ -610,14 +635,17 @@ k_table_build(const Weight W, int64_t count, int nsub, const double *__restrict_
     }
 }
 
-// Workgroups of a build launch: one per kGroups x 64 markers, at most
-// blocks_per_cu per compute unit (the rest is covered by the grid stride).
+// Workgroups of a build launch: enough for three wavefronts per item of 64
+// markers, at most blocks_per_cu per compute unit (the rest is covered by the
+// grid stride), rounded up to a multiple of 24 (8 XCDs x 3 components).
 int build_grid(int64_t n, int cu, int blocks_per_cu)
 {
-    int64_t b = (n + kGroups * 64 - 1) / (kGroups * 64);
+    const int64_t items = (n + 63) / 64;
+    int64_t b = (3 * items + kBuildWaves - 1) / kBuildWaves;
     const int64_t cap = (int64_t)cu * blocks_per_cu;
     if (b > cap) b = cap;
-    return (int)round_up8(b < 1 ? 1 : b);   // a multiple of 8 for the XCD mapping
+    if (b < 1) b = 1;
+    return (int)((b + kBuildGridMultiple - 1) / kBuildGridMultiple * kBuildGridMultiple);
 }
 
 }  // namespace

@@ -374,6 +374,16 @@ __device__ __forceinline__ int64_t home_at(int64_t l, int c)
     return (((l >> 6) * 3 + c) << 6) + (l & 63);
 }
 
+// Store of an output that the kernel writes once and never reads back (shape
+// functions, homes, interpolated values, forces), with the non-temporal
+// (streaming) cache policy, so it does not take cache lines from the field
+// values that neighbouring markers gather again.
+template <typename T>
+__device__ __forceinline__ void st_stream(T *p, T v)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
 __device__ __forceinline__ uint32_t pack_home(int i, int j, int k)
 {
     return (uint32_t)i | ((uint32_t)j << kPackI) | ((uint32_t)k << (kPackI + kPackJ));

@@ -161,7 +161,7 @@ __device__ __forceinline__ bool exact_from_geo(const Grid &g, const Weight &W, f
 {
     if (exact_fp32(W, tau, G, ph, kmax)) {
 #pragma unroll
-        for (int k = 0; k < kNe; ++k) out[k * kLanes] = ph[k];
+        for (int k = 0; k < kNe; ++k) st_stream(&out[k * kLanes], ph[k]);
         if (rout) *rout = route_bits;
         return true;
     }

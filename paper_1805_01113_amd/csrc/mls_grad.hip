@@ -246,14 +246,14 @@ k_build_grad(const Grid *__restrict__ gp, Weight Wt, float tau, int c, int64_t n
             for (int k = 0; k < 3 * kNe; ++k) dp[k * kLanes] = __builtin_nanf("");
             continue;
         }
-        home[l] = (uint32_t)ih[0] | ((uint32_t)ih[1] << 11) | ((uint32_t)ih[2] << 22);
+        st_stream(&home[l], (uint32_t)ih[0] | ((uint32_t)ih[1] << 11) | ((uint32_t)ih[2] << 22));
         if (grad_coef(Wt, tau, q, kmax)) {
             for_each_node<false>(q, Wt, [&](int a, int b, int cz, float v, const float dv[3]) {
                 const int k = a + 3 * b + 9 * cz;
-                ph[k * kLanes] = v;
-                dp[k * kLanes] = dv[0];
-                dp[(kNe + k) * kLanes] = dv[1];
-                dp[(2 * kNe + k) * kLanes] = dv[2];
+                st_stream(&ph[k * kLanes], v);
+                st_stream(&dp[k * kLanes], dv[0]);
+                st_stream(&dp[(kNe + k) * kLanes], dv[1]);
+                st_stream(&dp[(2 * kNe + k) * kLanes], dv[2]);
             });
         } else {
             ++routed;

@@ -20,6 +20,7 @@ constexpr int kTableStride = 28;  // table row: 27 values + 1 pad (16-byte rows)
 constexpr int kMaxTile = 16;      // a periodic axis of up to this many cells is one spreading tile
 constexpr int kMaxBoxTile = 16;   // largest tile edge cut from a longer axis (an int64 box of edge + 3 in LDS)
 constexpr int kMaxBlocksPerCu = 64;   // largest tunable workgroups per compute unit of a launch
+constexpr int kBuildGridMultiple = 24;   // build grids are a multiple of this many workgroups
 constexpr int kPackI = 11, kPackJ = 11;  // home packing i | j << 11 | k << 22
 constexpr uint32_t kMaskI = (1u << kPackI) - 1, kMaskJ = (1u << kPackJ) - 1;
 
@@ -158,7 +159,7 @@ struct Ctx {
     // launch shapes (autotuned): resident workgroups per compute unit
     int spread_blocks_per_cu = 8;      // effective (bounded by the LDS of the tile boxes)
     int spread_blocks_per_cu_req = 8;  // requested
-    int build_blocks_per_cu = 16;
+    int build_blocks_per_cu = 32;
     int interp_blocks_per_cu = 32;
     int cu_count = 256;
     // learned surrogate

@@ -118,7 +118,7 @@ void cache_append(const char *path, const std::string &key, const mls_tune_repor
     fclose(f);
 }
 
-bool bpc_ok(int v) { return v >= 1 && v <= 64; }
+bool bpc_ok(int v) { return v >= 1 && v <= kMaxBlocksPerCu; }
 
 }  // namespace
 
@@ -216,7 +216,7 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, const mls_step_buffers *b,
     mls_tune best = cur;
     // build shapes (the learned build has one workgroup per compute unit)
     double t_build = 1e30;
-    const int bpcs[] = {4, 8, 16, 32};
+    const int bpcs[] = {8, 16, 32, 64};
     if (method != MLS_LEARNED) {
         for (int v : bpcs) {
             c.build_blocks_per_cu = v;

@@ -61,6 +61,8 @@ struct Grid {
     int32_t ncol_tiles[3][3]; // [axis colour][axis]: tiles of that colour along the axis
     int64_t colour_base[27];  // first slot of each colour in the active-tile list
     double h_min;         // smallest node spacing over all axes and components
+    float const_width;    // the control-volume width when every width of every axis and node kind is
+                          // bitwise equal (uniform periodic grids), else 0
 };
 
 // Device error word: lowest offending marker index in the upper 56 bits, the

@@ -395,6 +395,14 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
     const int64_t abase = g.colour_base[colour];
     const uint32_t nact = (uint32_t)min((int64_t)work[colour], colour_end(g, colour) - abase);
     __shared__ int64_t tile_sh;
+    // The box is cleared once here; afterwards every flush returns the nodes
+    // it reads to zero, so each component and tile starts from a clear box.
+    for (int q = threadIdx.x; q < bnodes; q += blockDim.x) acc[q] = 0ull;
+    // box-local coordinates of a node index without integer division: with
+    // fewer than 2^22 nodes, (q + 1/2) times the FP32 reciprocal of the divisor
+    // stays within 1/2 of a quotient's interval from its floor
+    const float inv_bx = 1.0f / (float)bx, inv_bxy = 1.0f / (float)(bx * by);
+    const float cw = g.const_width;
     for (;;) {
         if (threadIdx.x == 0) {
             const uint32_t i = atomicAdd(&work[32 + colour], 1u);
@@ -418,7 +426,6 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
         // workgroups fit a compute unit and tiles can be larger
 #pragma unroll 1
         for (int c = 0; c < 3; ++c) {
-            for (int q = threadIdx.x; q < bnodes; q += blockDim.x) acc[q] = 0ull;
             // c_l <= A_l / h^2 for a shape function with sum phi dV close to dV, h
             // the smallest control-volume width near the tile; with |phi| <= 2
             // every contribution |c_l phi_k F_l| stays below bound = 8 max|A F| / h^2.
@@ -444,20 +451,17 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                 float ph[kNe];
 #pragma unroll
                 for (int k = 0; k < kNe; ++k) ph[k] = p[k * kLanes];
-                int ix[3], iy[3], iz[3];
-                float wx[3], wy[3], wz[3];
+                const float af = SORTED ? af_rows[c * af_stride + e] : area[m] * Fc[m];
+                int gx[3], gy[3], gz[3], ix[3], iy[3], iz[3];
                 bool inbox = true;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const int gx = nb_index(hi, a - 1, nxc, AX.periodic);
-                    const int gy = nb_index(hj, a - 1, nyc, AY.periodic);
-                    const int gz = nb_index(hk, a - 1, nzc, AZ.periodic);
-                    wx[a] = width_of(AX, c == 0, gx);
-                    wy[a] = width_of(AY, c == 1, gy);
-                    wz[a] = width_of(AZ, c == 2, gz);
-                    ix[a] = box_local(AX, g.ntile[0], nxc, b0x, gx);
-                    iy[a] = box_local(AY, g.ntile[1], nyc, b0y, gy);
-                    iz[a] = box_local(AZ, g.ntile[2], nzc, b0z, gz);
+                    gx[a] = nb_index(hi, a - 1, nxc, AX.periodic);
+                    gy[a] = nb_index(hj, a - 1, nyc, AY.periodic);
+                    gz[a] = nb_index(hk, a - 1, nzc, AZ.periodic);
+                    ix[a] = box_local(AX, g.ntile[0], nxc, b0x, gx[a]);
+                    iy[a] = box_local(AY, g.ntile[1], nyc, b0y, gy[a]);
+                    iz[a] = box_local(AZ, g.ntile[2], nzc, b0z, gz[a]);
                     inbox = inbox && (unsigned)ix[a] < (unsigned)bx && (unsigned)iy[a] < (unsigned)by &&
                             (unsigned)iz[a] < (unsigned)bz;
                 }
@@ -466,26 +470,56 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                     continue;
                 }
                 float hl = 0.f, den = 0.f;
+                if (cw > 0.f) {
+                    // every width equals cw: the same sums as below without the
+                    // width tables
+                    const float s3 = cw + cw + cw, p3 = cw * cw * cw;
 #pragma unroll
-                for (int k = 0; k < kNe; ++k) {
-                    const int a = k % 3, b = (k / 3) % 3, cz = k / 9;
-                    hl += ph[k] * (wx[a] + wy[b] + wz[cz]);
-                    den += ph[k] * (wx[a] * wy[b] * wz[cz]);
+                    for (int k = 0; k < kNe; ++k) {
+                        hl += ph[k] * s3;
+                        den += ph[k] * p3;
+                    }
+                } else {
+                    float wx[3], wy[3], wz[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        wx[a] = width_of(AX, c == 0, gx[a]);
+                        wy[a] = width_of(AY, c == 1, gy[a]);
+                        wz[a] = width_of(AZ, c == 2, gz[a]);
+                    }
+#pragma unroll
+                    for (int k = 0; k < kNe; ++k) {
+                        const int a = k % 3, b = (k / 3) % 3, cz = k / 9;
+                        hl += ph[k] * (wx[a] + wy[b] + wz[cz]);
+                        den += ph[k] * (wx[a] * wy[b] * wz[cz]);
+                    }
                 }
                 // c_l F_l = A_l h_l F_l / sum_k phi_k dV_k   (eq. 8), pre-scaled
-                const float af = SORTED ? af_rows[c * af_stride + e] : area[m] * Fc[m];
                 const float vsc = af * (hl * (1.0f / 3.0f)) / den * scale_f;
-                bool range_ok = true;
+                // Rounding is monotonic, so |phi_k vsc| <= max_k |phi_k| |vsc| for
+                // every k, with equality at the largest: one comparison bounds all
+                // 27 scaled contributions.  A NaN or infinity in phi or the force
+                // reaches vsc through hl, den or af and fails it too.
+                float pm = 0.f;
+#pragma unroll
+                for (int k = 0; k < kNe; ++k) pm = fmaxf(pm, fabsf(ph[k]));
+                if (!(fabsf(vsc) * pm < lim)) {
+                    raise_error(err, SORTED ? entries[e] : m, MLS_E_RANGE);
+                    continue;
+                }
+                // byte offsets of the box rows (b, cz) and columns a
+                uint32_t rowo[9], colo[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) colo[a] = (uint32_t)ix[a] * 8u;
+#pragma unroll
+                for (int r = 0; r < 9; ++r) rowo[r] = (uint32_t)((iz[r / 3] * by + iy[r % 3]) * bx) * 8u;
 #pragma unroll
                 for (int k = 0; k < kNe; ++k) {
-                    const int a = k % 3, b = (k / 3) % 3, cz = k / 9;
-                    float vs = ph[k] * vsc;
-                    range_ok = range_ok && (fabsf(vs) < lim);
-                    vs = fminf(fmaxf(vs, -lim), lim);
-                    const long long qv = (long long)(int)rintf(vs);
-                    if (qv != 0) atomicAdd(&acc[(iz[cz] * by + iy[b]) * bx + ix[a]], (unsigned long long)qv);
+                    const long long qv = (long long)(int)rintf(ph[k] * vsc);
+                    atomicAdd(reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(acc) + rowo[k / 3] +
+                                                                     colo[k % 3]),
+                              (unsigned long long)qv);
                 }
-                if (!range_ok) raise_error(err, SORTED ? entries[e] : m, MLS_E_RANGE);
             }
             lds_barrier();
             // flush: the box nodes of a thread are read in batches of kFlush
@@ -505,7 +539,11 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                     if (q >= bnodes) continue;
                     const long long sv = (long long)acc[q];
                     if (sv == 0) continue;
-                    const int lx = q % bx, ly = (q / bx) % by, lz = q / (bx * by);
+                    acc[q] = 0ull;
+                    const int lz = (int)(((float)q + 0.5f) * inv_bxy);
+                    const int rq = q - lz * (bx * by);
+                    const int ly = (int)(((float)rq + 0.5f) * inv_bx);
+                    const int lx = rq - ly * bx;
                     int gx = b0x + lx, gy = b0y + ly, gz = b0z + lz;
                     if (AX.periodic) gx = gx < 0 ? gx + nxc : (gx >= nxc ? gx - nxc : gx);
                     if (AY.periodic) gy = gy < 0 ? gy + nyc : (gy >= nyc ? gy - nyc : gy);

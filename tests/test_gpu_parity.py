@@ -265,3 +265,38 @@ def test_spread_conserves_force_full_ellipsoids(orc, torch_cuda):
         scale = float(np.sum(np.abs(wl.force[c]) * wl.area * h))
         say("conservation comp %d: |lhs-rhs|/sum|F dV| = %.2e" % (c, abs(lhs - rhs) / scale))
         assert abs(lhs - rhs) <= 1e-5 * scale
+
+
+def test_spread_range_errors_report_the_marker(orc, torch_cuda):
+    """A non-finite force, or a non-finite shape-function value of a marker with
+    a valid support, is reported as MLS_E_RANGE with the lowest offending
+    marker; a clean rerun reports nothing and matches the oracle."""
+    import torch
+    from paper_1805_01113_amd import mls
+    wl = W.ellipsoids(n_bodies=20, n=64, cfg_id=202)
+    gs = wl.grid
+    ctx = _ctx(gs)
+    home, phi, _ = ctx.build(to_dev(wl.x), to_dev(wl.y), to_dev(wl.z))
+    ctx.sync()
+    fields = lambda: [torch.zeros(gs.shape(c), device="cuda") for c in range(3)]
+    F = wl.force.copy()
+    F[1, 37] = np.nan
+    F[2, 90] = np.inf
+    ctx.spread(home, phi, to_dev(wl.area), to_dev(F), fields())
+    assert ctx.sync(raise_on_error=False) == (mls.MLS_E_RANGE, 37)
+    # phi of marker 50, component 0, node 13 -> NaN (blocked layout [block][comp][node][lane])
+    bad_phi = phi.clone()
+    b, r = divmod(50, 64)
+    bad_phi[((b * 3 + 0) * 27 + 13) * 64 + r] = float("nan")
+    ctx.spread(home, bad_phi, to_dev(wl.area), to_dev(wl.force), fields())
+    assert ctx.sync(raise_on_error=False) == (mls.MLS_E_RANGE, 50)
+    fo = fields()
+    ctx.spread(home, phi, to_dev(wl.area), to_dev(wl.force), fo)
+    assert ctx.sync(raise_on_error=False) == (0, -1)
+    g = _ogrid(orc, gs)
+    errs = []
+    for c in range(3):
+        ref = orc.build_exact(g, c, wl.x, wl.y, wl.z)
+        fref, _ = orc.spread(g, c, ref["home"], ref["phi"], wl.area, wl.force[c])
+        errs.append(normwise(fo[c].cpu().numpy(), fref))
+    assert max(errs) <= F_TOL

@@ -352,6 +352,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (JSON lines)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--full-phi", action="store_true",
+                    help="exact steps store all 27 shape-function values per row instead of the compact form")
     ap.add_argument("--no-extra", action="store_true", help="skip the eager / per-body / fast comparisons")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB (counter calibration)")
@@ -411,7 +413,11 @@ def main():
         log("autotune (%.1fs): %s" % (time.time() - t_a, json.dumps(tune)))
     jitter = 0.1 * h_min
     seed = 20180503
-    graph = mls.StepGraph(ctx, bufs, method=method, dt=1.0, jitter=jitter, seed=seed)
+    # exact steps keep the transfer functions compact (gamma and the support
+    # offsets) unless --full-phi: the same U, F and forcing, fewer bytes
+    compact = method == mls.MLS_EXACT and not args.full_phi
+    nf = 7 if all(wl.grid.uniform_axis(d) for d in range(3)) else 13
+    graph = mls.StepGraph(ctx, bufs, method=method, dt=1.0, jitter=jitter, seed=seed, compact=compact)
     stream = torch.cuda.current_stream()
 
     # ---- timed region: graph replays ------------------------------------------
@@ -435,7 +441,7 @@ def main():
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(args.steps):
-        mls.step(ctx, bufs, method=method, dt=1.0, jitter=jitter, seed=seed)
+        mls.step(ctx, bufs, method=method, dt=1.0, jitter=jitter, seed=seed, compact=compact)
     e1.record(stream)
     torch.cuda.synchronize()
     ms_eager = e0.elapsed_time(e1) / max(args.steps, 1)
@@ -444,7 +450,9 @@ def main():
     ctx.sync()
     T = touched_nodes(torch, ctx, bufs.home, n)
     t_per = T / n
-    # algorithmic bytes per marker: what each kernel must move at least once
+    # algorithmic bytes per marker: what each kernel must move at least once;
+    # the transfer function of a row is 27 floats, or nf in the compact form
+    tf = 4.0 * 3 * (nf if compact else 27)
     alg = {
         "jitter": 24.0,
         "build_exact": 12 + 12 + 324.0,
@@ -452,12 +460,12 @@ def main():
         "build_learned": 12 + 12 + 324.0,
         "interp": 12 + 324 + 12 + 4.0 * t_per,
         # positions, homes, phi, touched field values, U and F by marker, A F by row
-        "build_interp": 12 + 12 + 324 + 4.0 * t_per + 12 + 12 + 12,
+        "build_interp": 12 + 12 + tf + 4.0 * t_per + 12 + 12 + 12,
         "fast_interp": 12 + 12 + 324 + 4.0 * t_per + 12 + 12 + 12,
         "force": 24.0,
         # homes, phi, A F by row (tile order; by marker for the standalone spreading:
         # A and F, 16 bytes), read-modify-write of the touched field values
-        "spread_tiles": 12 + 324 + 12 + 8.0 * t_per,
+        "spread_tiles": 12 + (tf if method == mls.MLS_EXACT else 324) + 12 + 8.0 * t_per,
         "spread_bin": 0.0,
     }
     kernels = {}
@@ -511,7 +519,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "markers": n, "bodies": int(len(wl.body_offsets) - 1),
                    "grid": list(wl.grid.n), "method": args.method, "execution": "hipgraph_batched",
-                   "step": "jitter+build+interp+force+spread"},
+                   "step": "jitter+build+interp+force+spread",
+                   "transfer_function": ("compact, %d floats per row" % nf) if compact else "27 floats per row"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "extra": extra,

@@ -335,12 +335,25 @@ mls_status mls_fast_tables(mls_ctx *ctx, float *dst, int64_t *count, int32_t *ro
  * the forcing do not.  With the other methods rows are in marker order.  All buffers are caller-owned device arrays:
  * x0,y0,z0 [n] (read), x,y,z [n] (written by jitter), area [n], vb [3][n] or
  * NULL, home, phi and route (or NULL) in the blocked layout above, U [3][n], F [3][n],
- * the velocity fields u,v,w and the forcing fields fx,fy,fz. */
+ * the velocity fields u,v,w and the forcing fields fx,fy,fz.
+ *
+ * flags MLS_STEP_COMPACT (MLS_EXACT only; ignored by the other methods): the
+ * step keeps each (marker, component) transfer function in its defining
+ * quantities instead of its 27 values -- gamma = A^{-1} e_0 of eq. 5 and the
+ * support offsets (one per axis when all axes are uniform, else three) -- in
+ * context scratch, and the spreading evaluates phi_k = W_k (gamma . p_k)
+ * from them with the build's arithmetic, so it spreads with the values the
+ * interpolation used.  phi then receives only the rows of the pairs solved
+ * in FP64; its other rows are left as they were.  Results (U, F, forcing)
+ * are those of the default step. */
+enum { MLS_STEP_COMPACT = 1 };
+
 typedef struct {
     int32_t method;
     float dt;
     float jitter;
     uint64_t seed;
+    int32_t flags;     /* 0 or MLS_STEP_COMPACT */
 } mls_step_desc;
 
 typedef struct {

@@ -42,7 +42,7 @@ def build(verbose: bool = True, jobs: int = 4) -> str:
         if verbose and out.strip():
             sys.stderr.write(out.decode(errors="replace"))
     tmp = LIB + ".tmp%d" % os.getpid()
-    subprocess.check_call(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
+    subprocess.check_call(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,-z,defs", *objs, "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

@@ -157,6 +157,42 @@ mls_status mls::setup_tiles(Ctx &c, int want)
     return MLS_OK;
 }
 
+namespace mls {
+
+// Row width of the compact transfer function on this grid: gamma and one
+// offset per axis when every axis is uniform, else gamma and three offsets
+// per axis.
+int compact_nf(const Ctx &c)
+{
+    return (c.g.ax[0].uniform && c.g.ax[1].uniform && c.g.ax[2].uniform) ? 7 : 13;
+}
+
+// Scratch of a compact exact step for n markers: the coefficient rows and the
+// queue of rows solved in FP64.
+mls_status reserve_compact(mls_ctx *ctx, int64_t n)
+{
+    Ctx &c = ctx->c;
+    if (n <= c.coef_cap) return MLS_OK;
+    hipDeviceSynchronize();
+    hipFree(c.coef_rows);
+    hipFree(c.route_queue);
+    c.coef_rows = nullptr;
+    c.route_queue = nullptr;
+    c.coef_cap = 0;
+    const int64_t npad = (n + 63) / 64 * 64;
+    hipError_t e = hipMalloc((void **)&c.coef_rows, (size_t)3 * 13 * npad * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&c.route_queue, (size_t)(1 + 3 * n) * sizeof(uint32_t));
+    if (e != hipSuccess) {
+        hipFree(c.coef_rows);
+        c.coef_rows = nullptr;
+        return hip_fail(ctx, e, "compact step scratch");
+    }
+    c.coef_cap = n;
+    return MLS_OK;
+}
+
+}  // namespace mls
+
 extern "C" {
 
 const char *mls_version(void) { return "mls_hip 0.1.0 (gfx950)"; }
@@ -352,6 +388,8 @@ void mls_ctx_destroy(mls_ctx *ctx)
     hipFree(c.block_sums);
     hipFree(c.entries);
     hipFree(c.af_rows);
+    hipFree(c.coef_rows);
+    hipFree(c.route_queue);
     hipFree(c.block_fmax);
     hipFree(c.tile_hmin_block);
     hipFree(c.refine_scratch);

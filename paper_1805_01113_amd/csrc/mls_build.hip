@@ -109,6 +109,15 @@ k_build_exact(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n,
 // F[c][m] = (V_b - U) / dt, so phi is not read back (the FP64 route reads its
 // own stored values).  Each workgroup also records max |A_m F_m| per component
 // in block_fmax[3 blockIdx + c], the scale of the spreading sums.
+//
+// NF = 0 stores the 27 values of phi per row.  NF = 7 or 13 stores the
+// compact transfer function instead (rows of NF floats, blocked like phi):
+// gamma = A^{-1} e_0, then per axis the centre offset s_1 (NF = 7, every axis
+// uniform: the outer offsets are s_1 -+ 1 in FP32) or the three offsets s_a
+// (NF = 13).  phi_k = W_k (gamma . p_k) follows from them with the weights;
+// a row solved in FP64 is marked by a NaN gamma_0 and its position in tile
+// order is queued in rq (count first), so that k_route_phi stores its phi.
+template <int NF>
 __global__ void __launch_bounds__(kBuildBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n, const uint32_t *__restrict__ order,
                const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
@@ -116,7 +125,7 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
                const float *__restrict__ u, const float *__restrict__ v, const float *__restrict__ w,
                const float *__restrict__ vb, const float *__restrict__ area, float inv_dt, float *__restrict__ U,
                float *__restrict__ F, float *__restrict__ af_rows, int64_t af_stride, uint32_t *__restrict__ block_fmax,
-               ErrWord *err, DevStats *st)
+               float *__restrict__ coef, uint32_t *__restrict__ rq, ErrWord *err, DevStats *st)
 {
     const Grid &g = *gp;
     const int wave = wave_id(), lane = threadIdx.x & 63;
@@ -172,8 +181,9 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
         for (int k = 0; k < kNe; ++k) qv[k] = q[oz[k / 9] + oy[(k / 3) % 3] + ox[k % 3]];
         const float vbv = vb ? vb[c * n + m] : 0.0f;
         float ph[kNe];
+        float gam[4] = {0.f, 0.f, 0.f, 0.f};
         bool fp64 = false;
-        if (!exact_fp32(W, tau, G, ph, kmax)) {
+        if (!exact_fp32(W, tau, G, ph, kmax, gam)) {
             // rare: FP64 re-solve from the position
             fp64 = true;
             if (valid) ++routed;
@@ -181,8 +191,33 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
         }
         if (rout) *rout = fp64 ? 1 : 0;
         const float nan = __builtin_nanf("");
+        if constexpr (NF == 0) {
 #pragma unroll
-        for (int k = 0; k < kNe; ++k) st_stream(&out[k * kLanes], ok ? ph[k] : nan);
+            for (int k = 0; k < kNe; ++k) st_stream(&out[k * kLanes], ok ? ph[k] : nan);
+        } else {
+            float *cr = coef + ((((base >> 6) * 3 + c) * NF) << 6) + lane;
+            st_stream(&cr[0], ok && !fp64 ? gam[0] : nan);
+#pragma unroll
+            for (int j = 1; j < 4; ++j) st_stream(&cr[j * kLanes], gam[j]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if constexpr (NF == 7) {
+                    st_stream(&cr[(4 + d) * kLanes], G[d].s[1]);
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) st_stream(&cr[(4 + 3 * d + a) * kLanes], G[d].s[a]);
+                }
+            }
+            // queue the rows solved in FP64 (rare; one reservation per wavefront)
+            const unsigned long long rmask = __ballot(fp64 && ok && valid);
+            if (rmask) {
+                uint32_t slot = 0;
+                if (lane == 0) slot = atomicAdd(rq, (uint32_t)__popcll(rmask));
+                slot = __shfl(slot, 0);
+                if (fp64 && ok && valid)
+                    rq[1 + slot + __popcll(rmask & ((1ull << lane) - 1ull))] = (uint32_t)((base + lane) << 2) | c;
+            }
+        }
         float acc = 0.f;
 #pragma unroll
         for (int k = 0; k < kNe; ++k) acc += ph[k] * qv[k];
@@ -216,6 +251,32 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
         for (int q2 = 0; q2 < kBuildWaves; ++q2)
             if (wave_component(q2) == (int)threadIdx.x) v = fmaxf(v, bm[q2]);
         block_fmax[3 * blockIdx.x + threadIdx.x] = __float_as_uint(v);
+    }
+}
+
+// Zeroes n words (a kernel rather than a memset node, for graph capture).
+__global__ void k_clear_words(uint32_t *p, int64_t n)
+{
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+// Phi of the rows that the compact step build solved in FP64: entry i of rq
+// (after the count) is row << 2 | component, row in tile order; the FP64
+// re-solve stores the row's 27 values into phi in the blocked layout.
+__global__ void __launch_bounds__(kBlock)
+k_route_phi(const Grid *__restrict__ gp, const Weight W, const uint32_t *__restrict__ order,
+            const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
+            const uint32_t *__restrict__ rq, float *__restrict__ phi, ErrWord *err)
+{
+    const Grid &g = *gp;
+    const uint32_t cnt = rq[0];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
+        const uint32_t e = rq[1 + i];
+        const int64_t row = e >> 2;
+        const int c = (int)(e & 3u);
+        const uint32_t m = order[row];
+        if (!solve_fp64(g, W, c, (double)x[m], (double)y[m], (double)z[m], phi + phi_at(row, c)))
+            raise_error(err, m, MLS_E_SINGULAR);
     }
 }
 
@@ -681,9 +742,25 @@ hipError_t launch_build_interp(const Ctx &c, int64_t n, const float *x, const fl
 {
     if (n == 0) return hipSuccess;
     const float tau = (float)(c.opts.kappa_tau > 3.0e38 ? 3.0e38 : c.opts.kappa_tau);
-    hipLaunchKernelGGL(k_build_interp, dim3(build_grid(n, c.cu_count, c.build_blocks_per_cu)), dim3(kBuildBlock), 0,
-                       s, c.d_grid, c.w, tau, n, c.entries, x, y, z, home, phi, route, u, v, w, vb, area, 1.0f / dt,
-                       U, F, c.af_rows, c.af_stride, c.block_fmax, c.err, c.stats);
+    const dim3 grid(build_grid(n, c.cu_count, c.build_blocks_per_cu));
+    if (c.step_nf == 0) {
+        hipLaunchKernelGGL(k_build_interp<0>, grid, dim3(kBuildBlock), 0, s, c.d_grid, c.w, tau, n, c.entries, x, y, z,
+                           home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.af_rows, c.af_stride, c.block_fmax,
+                           nullptr, nullptr, c.err, c.stats);
+        return hipGetLastError();
+    }
+    // compact rows: clear the FP64 queue count, build, then store phi of the queued rows
+    hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, s, c.route_queue, (int64_t)1);
+    if (c.step_nf == 7)
+        hipLaunchKernelGGL(k_build_interp<7>, grid, dim3(kBuildBlock), 0, s, c.d_grid, c.w, tau, n, c.entries, x, y,
+                           z, home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.af_rows, c.af_stride,
+                           c.block_fmax, c.coef_rows, c.route_queue, c.err, c.stats);
+    else
+        hipLaunchKernelGGL(k_build_interp<13>, grid, dim3(kBuildBlock), 0, s, c.d_grid, c.w, tau, n, c.entries, x, y,
+                           z, home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.af_rows, c.af_stride,
+                           c.block_fmax, c.coef_rows, c.route_queue, c.err, c.stats);
+    hipLaunchKernelGGL(k_route_phi, dim3(c.cu_count), dim3(kBlock), 0, s, c.d_grid, c.w, c.entries, x, y, z,
+                       c.route_queue, phi, c.err);
     return hipGetLastError();
 }
 

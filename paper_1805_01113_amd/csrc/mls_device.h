@@ -169,10 +169,13 @@ __device__ __forceinline__ bool axis_geo(const Axis &a, int is_face, double x, A
     const double x0 = node_x(a, is_face, ih);
     if (a.uniform) {
         // neighbours one spacing away; H = h
+        // the outer offsets are formed in FP32 from the rounded centre offset,
+        // so that the centre offset alone reproduces all three bit for bit
+        // (the compact transfer function of a time step stores only it)
         const double d0 = (x0 - X) * a.inv_h;
-        g.s[0] = (float)(d0 - 1.0);
         g.s[1] = (float)d0;
-        g.s[2] = (float)(d0 + 1.0);
+        g.s[0] = g.s[1] - 1.0f;
+        g.s[2] = g.s[1] + 1.0f;
         g.xi = (float)(-d0);
         g.rho = 1.0f;
         rH_out = a.inv_h;
@@ -221,13 +224,14 @@ __device__ __forceinline__ void axis_offsets_d(const Axis &a, int is_face, doubl
 
 // ---- weight function ------------------------------------------------------
 
+// Selects rather than branches on the (uniform) kind, so that consecutive
+// evaluations stay in one basic block and interleave.
 __device__ __forceinline__ float weight1(const Weight &w, float s)
 {
-    if (w.kind == MLS_W_CONST) return 1.0f;
-    float t = s * w.inv_eps;
-    float g = __expf(-t * t);
-    if (w.kind == MLS_W_GAUSS) return g;
-    return fmaxf(g - w.cut, 0.0f);
+    const float t = s * w.inv_eps;
+    const float g = __expf(-t * t);
+    const float r = w.kind == MLS_W_GAUSS ? g : fmaxf(g - w.cut, 0.0f);
+    return w.kind == MLS_W_CONST ? 1.0f : r;
 }
 
 __device__ __forceinline__ double weight1_d(const Weight &w, double s)

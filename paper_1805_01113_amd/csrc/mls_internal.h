@@ -152,6 +152,10 @@ struct Ctx {
     uint32_t *block_sums = nullptr;    // scan partials
     uint32_t *entries = nullptr;       // cap_markers: markers sorted by tile
     float *af_rows = nullptr;          // [3][af_stride]: A_l F_l of the exact step's rows (tile order)
+    float *coef_rows = nullptr;        // compact transfer functions of a compact exact step, rows of step_nf floats
+    uint32_t *route_queue = nullptr;   // [1 + 3 cap]: count, then row << 2 | component of its FP64-solved rows
+    int64_t coef_cap = 0;              // markers the two buffers above hold
+    int step_nf = 0;                   // row width of the step being enqueued: 0 (full phi), 7 or 13
     int64_t af_stride = 0;             // cap_markers rounded up to 64
     uint32_t *block_fmax = nullptr;    // per-block force maxima of the counting pass (3 per block)
     uint32_t *work = nullptr;          // [0..26] active-list sizes per colour, [32..58] cursors,
@@ -238,6 +242,8 @@ hipError_t launch_spread(Ctx &c, int64_t n, const uint32_t *home, const float *p
 // force maxima, and the tile kernels read the rows of a tile contiguously.
 int build_blocks(const Ctx &c, int64_t n);   // workgroups of a build launch over n markers
 hipError_t launch_sort_positions(Ctx &c, int64_t n, const float *x, const float *y, const float *z, hipStream_t s);
+int compact_nf(const Ctx &c);
+mls_status reserve_compact(mls_ctx *ctx, int64_t n);
 hipError_t launch_build_interp(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
                                uint32_t *home, float *phi, uint8_t *route, const float *u, const float *v,
                                const float *w, const float *vb, const float *area, float dt, float *U, float *F,

@@ -153,6 +153,7 @@ mls_status mls_step(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buff
         st = mls_fast_tables(ctx, nullptr, nullptr, nullptr, nullptr, nullptr, stream);
         if (st != MLS_OK) return st;
     }
+    if ((desc->flags & ~MLS_STEP_COMPACT) != 0) return MLS_E_ARG;
     if (desc->method == MLS_EXACT || (fast && fast_fused_ok(c))) {
         // exact MLS, or fast-MLS on a uniform grid, in spreading-tile order:
         // bin the markers from their positions, build with interpolation and
@@ -160,6 +161,17 @@ mls_status mls_step(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buff
         // rows contiguously
         st = mls_reserve(ctx, n);
         if (st != MLS_OK) return st;
+        const bool compact = desc->method == MLS_EXACT && (desc->flags & MLS_STEP_COMPACT);
+        if (compact) {
+            st = reserve_compact(ctx, n);
+            if (st != MLS_OK) return st;
+        }
+        // the row width applies to this step's launches only
+        struct NfReset {
+            Ctx &c;
+            ~NfReset() { c.step_nf = 0; }
+        } nf_reset{c};
+        c.step_nf = compact ? compact_nf(c) : 0;
         e = launch_sort_positions(c, n, bx, by, bz, s);
         if (e != hipSuccess) return MLS_E_HIP;
         if (fast) {
@@ -218,6 +230,10 @@ mls_status mls_graph_create(mls_ctx *ctx, const mls_step_desc *desc, const mls_s
     // everything that allocates or synchronises happens before the capture
     mls_status st = mls_reserve(ctx, b->n);
     if (st != MLS_OK) return st;
+    if (desc->method == MLS_EXACT && (desc->flags & MLS_STEP_COMPACT)) {
+        st = reserve_compact(ctx, b->n);
+        if (st != MLS_OK) return st;
+    }
     hipStream_t cs;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return MLS_E_HIP;
     if (desc->method == MLS_FAST || desc->method == MLS_FAST_LINEAR) {

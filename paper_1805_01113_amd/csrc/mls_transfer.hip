@@ -14,7 +14,7 @@
 //      global update is a plain read-modify-write.
 // The fixed-point scale of a tile is a power of two chosen from the largest
 // |A_l F_l| among the tile's markers, so that no sum can overflow.
-#include "mls_device.h"
+#include "mls_exact.h"
 
 namespace mls {
 
@@ -75,6 +75,14 @@ k_interp(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ ho
 // contributions are summed in 64-bit fixed point, whose sum does not depend on
 // the order of the markers: the result is bitwise reproducible.
 
+// Tile index of cell i on an axis with tile edge 1/inv_tile: the exact quotient
+// i / tile, since i + 1/2 stays at least 1/(2 tile) from a multiple of tile and
+// the FP32 product errs by far less for cells and tiles below 2^11.
+__device__ __forceinline__ int tile_of(int i, float inv_tile)
+{
+    return (int)(((float)i + 0.5f) * inv_tile);
+}
+
 __device__ __forceinline__ int64_t marker_tile(const Grid &g, const uint32_t *__restrict__ home, int64_t l,
                                                bool &valid)
 {
@@ -86,9 +94,9 @@ __device__ __forceinline__ int64_t marker_tile(const Grid &g, const uint32_t *__
         valid = valid && home_ok(g, c, hc[c][0], hc[c][1], hc[c][2]);
     }
     // the cell on axis d is the home of component (d + 1) % 3 (centre-staggered on d)
-    const int tx = hc[1][0] / g.ax[0].tile;
-    const int ty = hc[2][1] / g.ax[1].tile;
-    const int tz = hc[0][2] / g.ax[2].tile;
+    const int tx = tile_of(hc[1][0], 1.0f / (float)g.ax[0].tile);
+    const int ty = tile_of(hc[2][1], 1.0f / (float)g.ax[1].tile);
+    const int tz = tile_of(hc[0][2], 1.0f / (float)g.ax[2].tile);
     return ((int64_t)tz * g.ntile[1] + ty) * g.ntile[0] + tx;
 }
 
@@ -173,6 +181,7 @@ k_bin_pos(const Grid *__restrict__ gp, int64_t n, const float *__restrict__ x, c
     const int lane = threadIdx.x & 63;
     const unsigned long long lower = (1ull << lane) - 1ull;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const float itx = 1.0f / (float)g.ax[0].tile, ity = 1.0f / (float)g.ax[1].tile, itz = 1.0f / (float)g.ax[2].tile;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
         const int64_t l = base + lane;
         int64_t t = -1;
@@ -187,8 +196,8 @@ k_bin_pos(const Grid *__restrict__ gp, int64_t n, const float *__restrict__ x, c
                 ok = ok && locate(g.ax[d], 0, p[d], ih, X);
                 cell[d] = ih;
             }
-            t = ok ? ((int64_t)(cell[2] / g.ax[2].tile) * g.ntile[1] + cell[1] / g.ax[1].tile) * g.ntile[0] +
-                         cell[0] / g.ax[0].tile
+            t = ok ? ((int64_t)tile_of(cell[2], itz) * g.ntile[1] + tile_of(cell[1], ity)) * g.ntile[0] +
+                         tile_of(cell[0], itx)
                    : g.ntiles;
         }
         unsigned long long pending = __ballot(t >= 0);
@@ -377,7 +386,11 @@ __device__ __forceinline__ void lds_barrier()
 // SORTED: row e of home / phi belongs to marker entries[e] (the exact time
 // step writes them in tile order), so a tile reads its rows contiguously;
 // otherwise home / phi are indexed by marker.
-template <bool SORTED>
+// NF > 0 (sorted rows of a compact exact step): phi is evaluated from the
+// row's compact transfer function (gamma and the support offsets, NF = 7 or
+// 13 floats, see k_build_interp) with the build's own arithmetic, or read
+// from phi for a row the build solved in FP64 (NaN gamma_0).
+template <bool SORTED, int NF>
 __global__ void __launch_bounds__(kBlock)
 k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32_t *__restrict__ home,
                 const float *__restrict__ phi, const float *__restrict__ area, const float *__restrict__ Fx,
@@ -385,7 +398,7 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                 float *__restrict__ fy, float *__restrict__ fz, const uint32_t *__restrict__ off,
                 const uint32_t *__restrict__ entries, const uint32_t *__restrict__ active, uint32_t *work,
                 const uint32_t *__restrict__ fmax_bits, const float *__restrict__ af_rows, int64_t af_stride,
-                ErrWord *err)
+                const float *__restrict__ coef, const Weight W, ErrWord *err)
 {
     const Grid &g = *gp;
     extern __shared__ unsigned long long acc[];     // the box of one component
@@ -447,11 +460,44 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                 const int64_t row = SORTED ? (int64_t)e : (int64_t)m;
                 int hi, hj, hk;
                 unpack_home(home[home_at(row, c)], hi, hj, hk);
-                const float *p = phi + phi_at(row, c);
-                float ph[kNe];
-#pragma unroll
-                for (int k = 0; k < kNe; ++k) ph[k] = p[k * kLanes];
                 const float af = SORTED ? af_rows[c * af_stride + e] : area[m] * Fc[m];
+                float ph[kNe];
+                if constexpr (NF == 0) {
+                    const float *p = phi + phi_at(row, c);
+#pragma unroll
+                    for (int k = 0; k < kNe; ++k) ph[k] = p[k * kLanes];
+                } else {
+                    const float *cr = coef + ((((row >> 6) * 3 + c) * NF) << 6) + (row & 63);
+                    float cf[NF];
+#pragma unroll
+                    for (int j = 0; j < NF; ++j) cf[j] = cr[j * kLanes];
+                    // evaluated for every row (all loads issue at once); a row the
+                    // build solved in FP64 has a NaN gamma_0 and its stored phi is
+                    // read instead, under a wavefront-wide test
+                    float sv[3][3], wv[3][3];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        if constexpr (NF == 7) {
+                            sv[d][1] = cf[4 + d];
+                            sv[d][0] = sv[d][1] - 1.0f;
+                            sv[d][2] = sv[d][1] + 1.0f;
+                        } else {
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) sv[d][a] = cf[4 + 3 * d + a];
+                        }
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) wv[d][a] = weight1(W, sv[d][a]);
+                    }
+                    phi_from_gamma(wv, sv, cf, ph);
+                    const bool stored = cf[0] != cf[0];
+                    if (__any(stored)) {
+                        if (stored) {
+                            const float *p = phi + phi_at(row, c);
+#pragma unroll
+                            for (int k = 0; k < kNe; ++k) ph[k] = p[k * kLanes];
+                        }
+                    }
+                }
                 int gx[3], gy[3], gz[3], ix[3], iy[3], iz[3];
                 bool inbox = true;
 #pragma unroll
@@ -575,7 +621,7 @@ int grid_for(int64_t work, int cu)
 
 }  // namespace
 
-template <bool SORTED>
+template <bool SORTED, int NF>
 static hipError_t launch_tiles(Ctx &c, int64_t n, const uint32_t *home, const float *phi, const float *area,
                                const float *Fx, const float *Fy, const float *Fz, float *fx, float *fy, float *fz,
                                hipStream_t s)
@@ -583,16 +629,16 @@ static hipError_t launch_tiles(Ctx &c, int64_t n, const uint32_t *home, const fl
     const size_t lds = (size_t)c.g.box[0] * c.g.box[1] * c.g.box[2] * sizeof(unsigned long long);
     const int persist = c.cu_count * c.spread_blocks_per_cu;
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_spread_colour<SORTED>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_spread_colour<SORTED, NF>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     TimedLaunch tt(c, MLS_K_SPREAD_TILES, s);
     for (int col = 0; col < 27; ++col) {
         if (c.colour_tiles[col] == 0) continue;
-        hipLaunchKernelGGL(k_spread_colour<SORTED>, dim3(persist), dim3(kBlock), lds, s, c.d_grid, col, n, home, phi,
-                           area, Fx, Fy, Fz, fx, fy, fz, c.tile_off, c.entries, c.tile_active, c.work, c.work + 64,
-                           SORTED ? c.af_rows : nullptr, c.af_stride, c.err);
+        hipLaunchKernelGGL((k_spread_colour<SORTED, NF>), dim3(persist), dim3(kBlock), lds, s, c.d_grid, col, n, home,
+                           phi, area, Fx, Fy, Fz, fx, fy, fz, c.tile_off, c.entries, c.tile_active, c.work, c.work + 64,
+                           SORTED ? c.af_rows : nullptr, c.af_stride, NF ? c.coef_rows : nullptr, c.w, c.err);
     }
     return hipGetLastError();
 }
@@ -632,7 +678,7 @@ hipError_t launch_spread(Ctx &c, int64_t n, const uint32_t *home, const float *p
         hipLaunchKernelGGL(k_active_tiles, dim3((unsigned)((nt + kActiveChunk - 1) / kActiveChunk)), dim3(kBlock), 0,
                            s, c.d_grid, c.tile_off, c.tile_active, c.work);
     }
-    return launch_tiles<false>(c, n, home, phi, area, Fx, Fy, Fz, fx, fy, fz, s);
+    return launch_tiles<false, 0>(c, n, home, phi, area, Fx, Fy, Fz, fx, fy, fz, s);
 }
 
 hipError_t launch_sort_positions(Ctx &c, int64_t n, const float *x, const float *y, const float *z, hipStream_t s)
@@ -670,7 +716,9 @@ hipError_t launch_spread_sorted(Ctx &c, int64_t n, const uint32_t *home, const f
         hipLaunchKernelGGL(k_active_tiles, dim3((unsigned)((nt + kActiveChunk - 1) / kActiveChunk)), dim3(kBlock), 0,
                            s, c.d_grid, c.tile_off, c.tile_active, c.work);
     }
-    return launch_tiles<true>(c, n, home, phi, area, Fx, Fy, Fz, fx, fy, fz, s);
+    if (c.step_nf == 7) return launch_tiles<true, 7>(c, n, home, phi, area, Fx, Fy, Fz, fx, fy, fz, s);
+    if (c.step_nf == 13) return launch_tiles<true, 13>(c, n, home, phi, area, Fx, Fy, Fz, fx, fy, fz, s);
+    return launch_tiles<true, 0>(c, n, home, phi, area, Fx, Fy, Fz, fx, fy, fz, s);
 }
 
 }  // namespace mls

@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmls_hip.so")
 
 MLS_EXACT, MLS_FAST, MLS_LEARNED, MLS_FAST_LINEAR = 0, 1, 2, 3
+MLS_STEP_COMPACT = 1
 MLS_OK, MLS_E_ARG, MLS_E_SUPPORT, MLS_E_SINGULAR, MLS_E_NONFINITE, MLS_E_HIP, MLS_E_NOMEM, MLS_E_RANGE = \
     0, -1, -2, -3, -4, -5, -6, -7
 W_GAUSS_SHIFTED, W_GAUSS, W_CONST = 0, 1, 2
@@ -54,7 +55,7 @@ class _Stats(ctypes.Structure):
 
 class _StepDesc(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("dt", ctypes.c_float), ("jitter", ctypes.c_float),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("flags", ctypes.c_int32)]
 
 
 class _StepBuf(ctypes.Structure):
@@ -550,12 +551,16 @@ class StepBuffers:
         return b
 
 
-def _desc(method, dt, jitter, seed):
-    return _StepDesc(int(method), float(dt), float(jitter), int(seed))
+def _desc(method, dt, jitter, seed, compact=False):
+    return _StepDesc(int(method), float(dt), float(jitter), int(seed), MLS_STEP_COMPACT if compact else 0)
 
 
-def step(ctx: "Context", bufs: StepBuffers, method=MLS_EXACT, dt=1.0, jitter=0.0, seed=0, stream=None):
-    d = _desc(method, dt, jitter, seed)
+def step(ctx: "Context", bufs: StepBuffers, method=MLS_EXACT, dt=1.0, jitter=0.0, seed=0, stream=None,
+         compact=False):
+    """One time step (mls_step).  compact=True (exact MLS): the transfer
+    functions stay in their compact form (MLS_STEP_COMPACT); bufs.phi then
+    receives only the rows solved in FP64."""
+    d = _desc(method, dt, jitter, seed, compact)
     b = bufs.struct()
     ctx._raise(ctx._lib.mls_step(ctx.h, ctypes.byref(d), ctypes.byref(b), _stream(stream)), "mls_step")
 
@@ -575,10 +580,11 @@ def step_counter_set(ctx: "Context", value: int, stream=None):
 class StepGraph:
     """One step captured as a HIP graph (mls_graph_create) and replayed."""
 
-    def __init__(self, ctx: "Context", bufs: StepBuffers, method=MLS_EXACT, dt=1.0, jitter=0.0, seed=0):
+    def __init__(self, ctx: "Context", bufs: StepBuffers, method=MLS_EXACT, dt=1.0, jitter=0.0, seed=0,
+                 compact=False):
         self.ctx = ctx
         self.bufs = bufs      # keeps the baked-in buffers alive
-        d = _desc(method, dt, jitter, seed)
+        d = _desc(method, dt, jitter, seed, compact)
         b = bufs.struct()
         h = ctypes.c_void_p()
         ctx._raise(ctx._lib.mls_graph_create(ctx.h, ctypes.byref(d), ctypes.byref(b), ctypes.byref(h)),

@@ -79,6 +79,11 @@ class GridSpec:
     def h_min(self) -> float:
         return min(float(np.min(np.diff(f))) for f in self.faces)
 
+    def uniform_axis(self, axis: int) -> bool:
+        """All cell widths along the axis equal (to 1e-9 relative)."""
+        w = np.diff(np.asarray(self.faces[axis], dtype=np.float64))
+        return bool(w.max() <= w.min() * (1.0 + 1e-9))
+
 
 # ---------------------------------------------------------------------------
 # Surfaces

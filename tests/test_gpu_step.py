@@ -217,3 +217,106 @@ def test_fast_step_stretched_takes_the_generic_path(orc):
         errs.append(normwise(bufs.U[c].cpu().numpy(), Uo))
     say("stretched fast_linear step U err %s" % ["%.1e" % e for e in errs])
     assert max(errs) <= U_TOL
+
+
+def _run_step(torch, mls, ctx, bufs, counter, compact, method=0, jitter=0.0, seed=0, dt=0.5):
+    for f in bufs.forcing:
+        f.zero_()
+    mls.step_counter_set(ctx, counter)
+    mls.step(ctx, bufs, method=method, dt=dt, jitter=jitter, seed=seed, compact=compact)
+    ctx.sync()
+    return (bufs.U.cpu().numpy().copy(), bufs.F.cpu().numpy().copy(),
+            [f.cpu().numpy().copy() for f in bufs.forcing])
+
+
+def _rows_by_marker(mls, ctx, bufs, n):
+    order = mls.step_order(ctx, n).cpu().numpy().astype(np.int64)
+    rows = mls.unpack_phi(bufs.phi.cpu().numpy(), n)
+    out = np.empty_like(rows)
+    out[:, order] = rows
+    return out
+
+
+def _compact_vs_full(torch, mls, wl, amp, label, **ctx_kw):
+    ctx = mls.Context(wl.grid.faces, wl.grid.periodic, **ctx_kw)
+    x0, y0, z0, area = [to_dev(a) for a in (wl.x, wl.y, wl.z, wl.area)]
+    fields = wl.fields("cuda")
+    forcing = [torch.zeros(wl.grid.shape(c), device="cuda") for c in range(3)]
+    bufs = mls.StepBuffers(ctx, x0, y0, z0, area, fields, forcing)
+    n = wl.n
+    full = _run_step(torch, mls, ctx, bufs, 5, False, jitter=amp, seed=3)
+    # phi rows by marker (the order of the rows inside a tile may change between runs)
+    phi_full = _rows_by_marker(mls, ctx, bufs, n)
+    bufs.phi.fill_(-7.0)
+    comp = _run_step(torch, mls, ctx, bufs, 5, True, jitter=amp, seed=3)
+    ctx.last_phi_by_marker = _rows_by_marker(mls, ctx, bufs, n)
+    assert np.array_equal(full[0], comp[0]) and np.array_equal(full[1], comp[1]), "U / F differ"
+    same = all(np.array_equal(full[2][c], comp[2][c]) for c in range(3))
+    errs = [normwise(comp[2][c], full[2][c]) for c in range(3)]
+    say("%s: compact vs full forcing bitwise %s (normwise %s)" % (label, same, ["%.1e" % e for e in errs]))
+    assert same, "the compact spreading must evaluate the build's phi bit for bit"
+    return ctx, bufs, phi_full
+
+
+def test_compact_step_equals_full_step_uniform(orc):
+    """Uniform grid (rows of 7 floats): U, F and the forcing of a compact exact
+    step equal the default step's bit for bit, and match the oracle."""
+    import torch
+    from paper_1805_01113_amd import mls
+    wl = W.uneven_bodies(n_bodies=300, n=256, cfg_id=306)
+    ctx, bufs, _ = _compact_vs_full(torch, mls, wl, 0.1 / 256, "uniform 256^3")
+    g = orc.Grid(wl.grid.faces, wl.grid.periodic)
+    xj = [t.cpu().numpy() for t in (bufs.x, bufs.y, bufs.z)]
+    fields = [f.cpu().numpy() for f in bufs.fields]
+    errs = []
+    s = np.arange(0, wl.n, 7)
+    for c in range(3):
+        ref = orc.build_exact(g, c, *xj)
+        Uo = orc.interp(g, c, ref["home"], ref["phi"], fields[c])
+        errs.append(normwise(bufs.U[c].cpu().numpy(), Uo))
+        fo, _ = orc.spread(g, c, ref["home"], ref["phi"], wl.area, ((0.0 - Uo) / 0.5).astype(np.float32))
+        errs.append(normwise(bufs.forcing[c].cpu().numpy(), fo))
+    say("compact step vs oracle (U, forcing per component): %s" % ["%.1e" % e for e in errs])
+    assert max(errs) <= max(U_TOL, F_TOL)
+
+
+def test_compact_step_equals_full_step_stretched():
+    """Stretched wall-bounded axis (rows of 13 floats)."""
+    import torch
+    from paper_1805_01113_amd import mls
+    wl = W.stretched_channel(n_bodies=30, nxy=64, nz=96, cfg_id=307)
+    _compact_vs_full(torch, mls, wl, 0.0, "stretched 64x64x96")
+
+
+def test_compact_step_forced_fp64_route():
+    """Every (marker, component) above the routing threshold: the rows are
+    queued, their phi is stored by the FP64 pass, and the spreading reads it;
+    the forcing still equals the default step's, and phi equals the default
+    step's rows."""
+    import torch
+    from paper_1805_01113_amd import mls
+    wl = W.stretched_channel(n_bodies=12, nxy=48, nz=64, cfg_id=308)
+    ctx, bufs, phi_full = _compact_vs_full(torch, mls, wl, 0.0, "forced FP64", kappa_tau=0.5)
+    assert np.array_equal(phi_full, ctx.last_phi_by_marker)
+
+
+def test_compact_step_graph_replays_match_eager():
+    import torch
+    from paper_1805_01113_amd import mls
+    wl = W.uneven_bodies(n_bodies=200, n=256, cfg_id=309)
+    ctx, bufs = _setup(torch, wl)
+    amp = 0.1 / 256
+    ref = [_run_step(torch, mls, ctx, bufs, s, True, jitter=amp, seed=8, dt=1.0) for s in range(2)]
+    graph = mls.StepGraph(ctx, bufs, method=mls.MLS_EXACT, dt=1.0, jitter=amp, seed=8, compact=True)
+    mls.step_counter_set(ctx, 0)
+    for s in range(2):
+        for f in bufs.forcing:
+            f.zero_()
+        torch.cuda.synchronize()
+        graph.launch(1)
+        ctx.sync()
+        assert np.array_equal(bufs.U.cpu().numpy(), ref[s][0])
+        for c in range(3):
+            assert np.array_equal(bufs.forcing[c].cpu().numpy(), ref[s][2][c]), "replay %d forcing %d" % (s, c)
+        _ = (bufs.U * 2).sum().item()
+    graph.close()

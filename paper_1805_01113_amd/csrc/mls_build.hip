@@ -118,7 +118,7 @@ k_build_exact(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n,
 // a row solved in FP64 is marked by a NaN gamma_0 and its position in tile
 // order is queued in rq (count first), so that k_route_phi stores its phi.
 template <int NF>
-__global__ void __launch_bounds__(kBuildBlock) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(kBuildBlock) __attribute__((amdgpu_waves_per_eu(NF == 0 ? 2 : 3)))
 k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n, const uint32_t *__restrict__ order,
                const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
                uint32_t *__restrict__ home, float *__restrict__ phi, uint8_t *__restrict__ route,
@@ -187,7 +187,9 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
             // rare: FP64 re-solve from the position
             fp64 = true;
             if (valid) ++routed;
-            if (!solve_fp64_regs(g, W, c, px, py, pz, ph)) raise_error(err, m, MLS_E_SINGULAR);
+            // full rows solve in FP64 here; compact rows leave it to k_route_rows
+            if constexpr (NF == 0)
+                if (!solve_fp64_regs(g, W, c, px, py, pz, ph)) raise_error(err, m, MLS_E_SINGULAR);
         }
         if (rout) *rout = fp64 ? 1 : 0;
         const float nan = __builtin_nanf("");
@@ -228,7 +230,7 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
         st_stream(&af_rows[c * af_stride + base + lane], ok ? ca * f : 0.0f);
         if (!ok) {
             raise_error(err, m, isfinite(px) && isfinite(py) && isfinite(pz) ? MLS_E_SUPPORT : MLS_E_NONFINITE);
-        } else {
+        } else if (NF == 0 || !fp64) {   // a queued compact row gets its U, F and A F from k_route_rows
             const float af = fabsf(ca) * fabsf(f);
             if (!(af <= 3.0e38f)) raise_error(err, m, MLS_E_RANGE);   // non-finite force (NaN fails too)
             else fmx = fmaxf(fmx, af);
@@ -260,13 +262,20 @@ __global__ void k_clear_words(uint32_t *p, int64_t n)
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
-// Phi of the rows that the compact step build solved in FP64: entry i of rq
-// (after the count) is row << 2 | component, row in tile order; the FP64
-// re-solve stores the row's 27 values into phi in the blocked layout.
+// The rows that the compact step build left to FP64: entry i of rq (after the
+// count) is row << 2 | component, row in tile order.  For each, the FP64
+// re-solve of the pair, its phi stored into the blocked rows, and the
+// interpolation and direct forcing that the build skipped: U and F by marker,
+// A F by row, and max |A F| into fmax_slot[c] (reduced with the per-workgroup
+// maxima of the build).
 __global__ void __launch_bounds__(kBlock)
-k_route_phi(const Grid *__restrict__ gp, const Weight W, const uint32_t *__restrict__ order,
-            const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
-            const uint32_t *__restrict__ rq, float *__restrict__ phi, ErrWord *err)
+k_route_rows(const Grid *__restrict__ gp, const Weight W, int64_t n, const uint32_t *__restrict__ order,
+             const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
+             const uint32_t *__restrict__ home, const uint32_t *__restrict__ rq, float *__restrict__ phi,
+             const float *__restrict__ u, const float *__restrict__ v, const float *__restrict__ w,
+             const float *__restrict__ vb, const float *__restrict__ area, float inv_dt, float *__restrict__ U,
+             float *__restrict__ F, float *__restrict__ af_rows, int64_t af_stride, uint32_t *__restrict__ fmax_slot,
+             ErrWord *err)
 {
     const Grid &g = *gp;
     const uint32_t cnt = rq[0];
@@ -275,8 +284,32 @@ k_route_phi(const Grid *__restrict__ gp, const Weight W, const uint32_t *__restr
         const int64_t row = e >> 2;
         const int c = (int)(e & 3u);
         const uint32_t m = order[row];
-        if (!solve_fp64(g, W, c, (double)x[m], (double)y[m], (double)z[m], phi + phi_at(row, c)))
-            raise_error(err, m, MLS_E_SINGULAR);
+        float ph[kNe];
+        if (!solve_fp64_regs(g, W, c, (double)x[m], (double)y[m], (double)z[m], ph)) raise_error(err, m, MLS_E_SINGULAR);
+        float *out = phi + phi_at(row, c);
+#pragma unroll
+        for (int k = 0; k < kNe; ++k) out[k * kLanes] = ph[k];
+        int hi, hj, hk;
+        unpack_home(home[home_at(row, c)], hi, hj, hk);
+        const float *q = c == 0 ? u : (c == 1 ? v : w);
+        const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < kNe; ++k) {
+            const int64_t gx = nb_index(hi, k % 3 - 1, nxc, g.ax[0].periodic);
+            const int64_t gy = nb_index(hj, (k / 3) % 3 - 1, nyc, g.ax[1].periodic);
+            const int64_t gz = nb_index(hk, k / 9 - 1, nzc, g.ax[2].periodic);
+            acc += ph[k] * q[(gz * nyc + gy) * nxc + gx];
+        }
+        const float vbv = vb ? vb[c * n + m] : 0.0f;
+        const float f = (vbv - acc) * inv_dt;
+        const float ca = area[m];
+        U[c * n + m] = acc;
+        F[c * n + m] = f;
+        af_rows[c * af_stride + row] = ca * f;
+        const float af = fabsf(ca) * fabsf(f);
+        if (!(af <= 3.0e38f)) raise_error(err, m, MLS_E_RANGE);
+        else atomicMax(&fmax_slot[c], __float_as_uint(af));
     }
 }
 
@@ -749,8 +782,11 @@ hipError_t launch_build_interp(const Ctx &c, int64_t n, const float *x, const fl
                            nullptr, nullptr, c.err, c.stats);
         return hipGetLastError();
     }
-    // compact rows: clear the FP64 queue count, build, then store phi of the queued rows
+    // compact rows: clear the FP64 queue count and the extra force-maximum slot
+    // after the workgroups' own, build, then finish the queued rows
+    uint32_t *fmax_slot = c.block_fmax + 3 * (int64_t)grid.x;
     hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, s, c.route_queue, (int64_t)1);
+    hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, s, fmax_slot, (int64_t)3);
     if (c.step_nf == 7)
         hipLaunchKernelGGL(k_build_interp<7>, grid, dim3(kBuildBlock), 0, s, c.d_grid, c.w, tau, n, c.entries, x, y,
                            z, home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.af_rows, c.af_stride,
@@ -759,8 +795,9 @@ hipError_t launch_build_interp(const Ctx &c, int64_t n, const float *x, const fl
         hipLaunchKernelGGL(k_build_interp<13>, grid, dim3(kBuildBlock), 0, s, c.d_grid, c.w, tau, n, c.entries, x, y,
                            z, home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.af_rows, c.af_stride,
                            c.block_fmax, c.coef_rows, c.route_queue, c.err, c.stats);
-    hipLaunchKernelGGL(k_route_phi, dim3(c.cu_count), dim3(kBlock), 0, s, c.d_grid, c.w, c.entries, x, y, z,
-                       c.route_queue, phi, c.err);
+    hipLaunchKernelGGL(k_route_rows, dim3(c.cu_count), dim3(kBlock), 0, s, c.d_grid, c.w, n, c.entries, x, y, z,
+                       home, c.route_queue, phi, u, v, w, vb, area, 1.0f / dt, U, F, c.af_rows, c.af_stride, fmax_slot,
+                       c.err);
     return hipGetLastError();
 }
 

@@ -711,8 +711,9 @@ hipError_t launch_spread_sorted(Ctx &c, int64_t n, const uint32_t *home, const f
         // call may follow another spreading of the same sort)
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBlock), 0, s, c.work, (int64_t)64);
         // force bound from the build's per-block maxima (no scan: nb = 0)
+        // (a compact step's FP64 rows keep their maximum in one more slot)
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, c.block_sums, (int64_t)0, c.block_fmax,
-                           build_blocks(c, n), c.work + 64);
+                           build_blocks(c, n) + (c.step_nf ? 1 : 0), c.work + 64);
         hipLaunchKernelGGL(k_active_tiles, dim3((unsigned)((nt + kActiveChunk - 1) / kActiveChunk)), dim3(kBlock), 0,
                            s, c.d_grid, c.tile_off, c.tile_active, c.work);
     }

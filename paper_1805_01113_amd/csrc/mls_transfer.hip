@@ -386,6 +386,60 @@ __device__ __forceinline__ void lds_barrier()
 // SORTED: row e of home / phi belongs to marker entries[e] (the exact time
 // step writes them in tile order), so a tile reads its rows contiguously;
 // otherwise home / phi are indexed by marker.
+// Adds a tile's box (64-bit fixed point, scale qscale) into the FP32 field f
+// and returns its nodes to zero.  A thread's box nodes are read in batches of
+// kFlush before any is written back, so their loads overlap.  Box coordinates
+// come from FP32 reciprocals of the box edges (exact below 2^22 nodes).
+// INSIDE: the box lies inside the grid, so a node's index is the origin's
+// plus an affine offset; otherwise periodic axes wrap and nodes past a wall
+// are skipped.
+template <bool INSIDE>
+__device__ __forceinline__ void flush_box(const Grid &g, int c, unsigned long long *acc, int bnodes, int bx, int by,
+                                          int b0x, int b0y, int b0z, int nxc, int nyc, int nzc, float inv_bx,
+                                          float inv_bxy, double qscale, float *__restrict__ f)
+{
+    constexpr int kFlush = 8;
+    const Axis &AX = g.ax[0], &AY = g.ax[1], &AZ = g.ax[2];
+    float *const fo = INSIDE ? f + field_index(g, c, b0x, b0y, b0z) : f;
+    const int sz = nxc * nyc;
+    for (int q0 = threadIdx.x; q0 < bnodes; q0 += kFlush * blockDim.x) {
+        float *dst[kFlush];
+        float add[kFlush];
+        float old[kFlush];
+#pragma unroll
+        for (int u = 0; u < kFlush; ++u) {
+            dst[u] = nullptr;
+            add[u] = 0.f;
+            const int q = q0 + u * blockDim.x;
+            if (q >= bnodes) continue;
+            const long long sv = (long long)acc[q];
+            if (sv == 0) continue;
+            acc[q] = 0ull;
+            const int lz = (int)(((float)q + 0.5f) * inv_bxy);
+            const int rq = q - lz * (bx * by);
+            const int ly = (int)(((float)rq + 0.5f) * inv_bx);
+            const int lx = rq - ly * bx;
+            if constexpr (INSIDE) {
+                dst[u] = fo + (lz * sz + ly * nxc + lx);
+            } else {
+                int gx = b0x + lx, gy = b0y + ly, gz = b0z + lz;
+                if (AX.periodic) gx = gx < 0 ? gx + nxc : (gx >= nxc ? gx - nxc : gx);
+                if (AY.periodic) gy = gy < 0 ? gy + nyc : (gy >= nyc ? gy - nyc : gy);
+                if (AZ.periodic) gz = gz < 0 ? gz + nzc : (gz >= nzc ? gz - nzc : gz);
+                if ((unsigned)gx >= (unsigned)nxc || (unsigned)gy >= (unsigned)nyc || (unsigned)gz >= (unsigned)nzc)
+                    continue;
+                dst[u] = f + field_index(g, c, gx, gy, gz);
+            }
+            add[u] = (float)((double)sv * qscale);
+        }
+#pragma unroll
+        for (int u = 0; u < kFlush; ++u) old[u] = dst[u] ? *dst[u] : 0.f;
+#pragma unroll
+        for (int u = 0; u < kFlush; ++u)
+            if (dst[u]) *dst[u] = old[u] + add[u];
+    }
+}
+
 // NF > 0 (sorted rows of a compact exact step): phi is evaluated from the
 // row's compact transfer function (gamma and the support offsets, NF = 7 or
 // 13 floats, see k_build_interp) with the build's own arithmetic, or read
@@ -570,42 +624,16 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
             lds_barrier();
             // flush: the box nodes of a thread are read in batches of kFlush
             // before any is written back, so their loads overlap
-            constexpr int kFlush = 8;
             float *f = c == 0 ? fx : (c == 1 ? fy : fz);
             const double qscale = ldexp(1.0, -S);
-            for (int q0 = threadIdx.x; q0 < bnodes; q0 += kFlush * blockDim.x) {
-                float *dst[kFlush];
-                float add[kFlush];
-                float old[kFlush];
-#pragma unroll
-                for (int u = 0; u < kFlush; ++u) {
-                    dst[u] = nullptr;
-                    add[u] = 0.f;
-                    const int q = q0 + u * blockDim.x;
-                    if (q >= bnodes) continue;
-                    const long long sv = (long long)acc[q];
-                    if (sv == 0) continue;
-                    acc[q] = 0ull;
-                    const int lz = (int)(((float)q + 0.5f) * inv_bxy);
-                    const int rq = q - lz * (bx * by);
-                    const int ly = (int)(((float)rq + 0.5f) * inv_bx);
-                    const int lx = rq - ly * bx;
-                    int gx = b0x + lx, gy = b0y + ly, gz = b0z + lz;
-                    if (AX.periodic) gx = gx < 0 ? gx + nxc : (gx >= nxc ? gx - nxc : gx);
-                    if (AY.periodic) gy = gy < 0 ? gy + nyc : (gy >= nyc ? gy - nyc : gy);
-                    if (AZ.periodic) gz = gz < 0 ? gz + nzc : (gz >= nzc ? gz - nzc : gz);
-                    if ((unsigned)gx >= (unsigned)nxc || (unsigned)gy >= (unsigned)nyc ||
-                        (unsigned)gz >= (unsigned)nzc)
-                        continue;
-                    dst[u] = f + field_index(g, c, gx, gy, gz);
-                    add[u] = (float)((double)sv * qscale);
-                }
-#pragma unroll
-                for (int u = 0; u < kFlush; ++u) old[u] = dst[u] ? *dst[u] : 0.f;
-#pragma unroll
-                for (int u = 0; u < kFlush; ++u)
-                    if (dst[u]) *dst[u] = old[u] + add[u];
-            }
+            // a box inside the component's grid on every axis (no wrap, no node
+            // past a wall) addresses its nodes as offsets from its origin
+            const bool inside = b0x >= 0 && b0y >= 0 && b0z >= 0 && b0x + bx <= nxc && b0y + by <= nyc &&
+                                b0z + bz <= nzc;
+            if (inside)
+                flush_box<true>(g, c, acc, bnodes, bx, by, b0x, b0y, b0z, nxc, nyc, nzc, inv_bx, inv_bxy, qscale, f);
+            else
+                flush_box<false>(g, c, acc, bnodes, bx, by, b0x, b0y, b0z, nxc, nyc, nzc, inv_bx, inv_bxy, qscale, f);
             lds_barrier();
         }
     }

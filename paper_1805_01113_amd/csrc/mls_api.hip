@@ -388,6 +388,7 @@ void mls_ctx_destroy(mls_ctx *ctx)
     hipFree(c.block_sums);
     hipFree(c.entries);
     hipFree(c.af_rows);
+    hipFree(c.marker_tile);
     hipFree(c.coef_rows);
     hipFree(c.route_queue);
     hipFree(c.block_fmax);
@@ -410,16 +411,21 @@ mls_status mls_reserve(mls_ctx *ctx, int64_t n)
     hipDeviceSynchronize();
     hipFree(c.entries);
     hipFree(c.af_rows);
+    hipFree(c.marker_tile);
     c.entries = nullptr;
     c.af_rows = nullptr;
+    c.marker_tile = nullptr;
     c.cap_markers = 0;
     c.af_stride = 0;
     const int64_t stride = (n + 63) / 64 * 64;
     hipError_t e = hipMalloc((void **)&c.entries, (size_t)n * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc((void **)&c.af_rows, (size_t)3 * stride * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&c.marker_tile, (size_t)n * sizeof(uint32_t));
     if (e != hipSuccess) {
         hipFree(c.entries);
+        hipFree(c.af_rows);
         c.entries = nullptr;
+        c.af_rows = nullptr;
         return hip_fail(ctx, e, "spread scratch");
     }
     c.cap_markers = n;

@@ -152,6 +152,7 @@ struct Ctx {
     uint32_t *block_sums = nullptr;    // scan partials
     uint32_t *entries = nullptr;       // cap_markers: markers sorted by tile
     float *af_rows = nullptr;          // [3][af_stride]: A_l F_l of the exact step's rows (tile order)
+    uint32_t *marker_tile = nullptr;   // [cap_markers]: spreading tile of each marker (binning from positions)
     float *coef_rows = nullptr;        // compact transfer functions of a compact exact step, rows of step_nf floats
     uint32_t *route_queue = nullptr;   // [1 + 3 cap]: count, then row << 2 | component of its FP64-solved rows
     int64_t coef_cap = 0;              // markers the two buffers above hold

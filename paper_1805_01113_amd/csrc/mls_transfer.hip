@@ -170,12 +170,14 @@ k_bin(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home,
 // Binning straight from the marker positions (the exact time step): the
 // tile of the cell that holds the marker (centre-staggered home on each
 // axis); a marker whose cell support leaves a wall axis, or whose position is
-// not finite, goes to the extra bucket ntiles, after all tiles.
+// not finite, goes to the extra bucket ntiles, after all tiles.  The counting
+// pass locates the markers and records each one's tile in tiles[]; the
+// filling pass reads it back.
 template <bool FILL>
 __global__ void __launch_bounds__(kBlock)
 k_bin_pos(const Grid *__restrict__ gp, int64_t n, const float *__restrict__ x, const float *__restrict__ y,
           const float *__restrict__ z, uint32_t *__restrict__ count, uint32_t *__restrict__ cursor,
-          uint32_t *__restrict__ entries)
+          uint32_t *__restrict__ entries, uint32_t *__restrict__ tiles)
 {
     const Grid &g = *gp;
     const int lane = threadIdx.x & 63;
@@ -186,19 +188,24 @@ k_bin_pos(const Grid *__restrict__ gp, int64_t n, const float *__restrict__ x, c
         const int64_t l = base + lane;
         int64_t t = -1;
         if (l < n) {
-            const double p[3] = {(double)x[l], (double)y[l], (double)z[l]};
-            int cell[3];
-            bool ok = true;
+            if (FILL) {
+                t = tiles[l];
+            } else {
+                const double p[3] = {(double)x[l], (double)y[l], (double)z[l]};
+                int cell[3];
+                bool ok = true;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                int ih = 0;
-                double X;
-                ok = ok && locate(g.ax[d], 0, p[d], ih, X);
-                cell[d] = ih;
+                for (int d = 0; d < 3; ++d) {
+                    int ih = 0;
+                    double X;
+                    ok = ok && locate(g.ax[d], 0, p[d], ih, X);
+                    cell[d] = ih;
+                }
+                t = ok ? ((int64_t)tile_of(cell[2], itz) * g.ntile[1] + tile_of(cell[1], ity)) * g.ntile[0] +
+                             tile_of(cell[0], itx)
+                       : g.ntiles;
+                tiles[l] = (uint32_t)t;
             }
-            t = ok ? ((int64_t)tile_of(cell[2], itz) * g.ntile[1] + tile_of(cell[1], ity)) * g.ntile[0] +
-                         tile_of(cell[0], itx)
-                   : g.ntiles;
         }
         unsigned long long pending = __ballot(t >= 0);
         while (pending) {
@@ -717,13 +724,13 @@ hipError_t launch_sort_positions(Ctx &c, int64_t n, const float *x, const float 
     TimedLaunch tb(c, MLS_K_SPREAD_BIN, s);
     hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(nt, c.cu_count)), dim3(kBlock), 0, s, c.tile_count, nt);
     hipLaunchKernelGGL(k_bin_pos<false>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, x, y, z,
-                       c.tile_count, c.tile_cursor, c.entries);
+                       c.tile_count, c.tile_cursor, c.entries, c.marker_tile);
     hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)nb), dim3(kBlock), 0, s, c.tile_count, nt, c.block_sums);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, c.block_sums, nb, c.block_fmax, 0, c.work + 64);
     hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kBlock), 0, s, c.tile_count, nt, c.block_sums,
                        c.tile_off, c.tile_cursor, c.work);
     hipLaunchKernelGGL(k_bin_pos<true>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, x, y, z,
-                       c.tile_count, c.tile_cursor, c.entries);
+                       c.tile_count, c.tile_cursor, c.entries, c.marker_tile);
     return hipGetLastError();
 }
 

@@ -451,8 +451,12 @@ __device__ __forceinline__ void flush_box(const Grid &g, int c, unsigned long lo
 // row's compact transfer function (gamma and the support offsets, NF = 7 or
 // 13 floats, see k_build_interp) with the build's own arithmetic, or read
 // from phi for a row the build solved in FP64 (NaN gamma_0).
+// Sorted rows: at most 80 registers (6 wavefronts per SIMD).  The tile phases
+// are bound by memory latency and barriers, and a sixth wavefront per SIMD
+// hides more of it than the registers cost (measured; an eighth spills).  The
+// standalone spreading, which gathers by marker, would spill at 80.
 template <bool SORTED, int NF>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SORTED ? 6 : 5)))
 k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32_t *__restrict__ home,
                 const float *__restrict__ phi, const float *__restrict__ area, const float *__restrict__ Fx,
                 const float *__restrict__ Fy, const float *__restrict__ Fz, float *__restrict__ fx,

@@ -128,7 +128,8 @@ mls_status mls_step(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buff
     if (!ctx || !desc || !b) return MLS_E_ARG;
     Ctx &c = ctx->c;
     const int64_t n = b->n;
-    if (n < 0 || !(desc->dt > 0.0f) || !(desc->jitter >= 0.0f)) return MLS_E_ARG;
+    if (n < 0 || !(desc->dt > 0.0f) || !(desc->jitter >= 0.0f) || (desc->flags & ~MLS_STEP_COMPACT) != 0)
+        return MLS_E_ARG;
     if (n == 0) return MLS_OK;
     if (!b->x0 || !b->y0 || !b->z0 || !b->area || !b->home || !b->phi || !b->u || !b->v || !b->w || !b->U ||
         !b->F || !b->fx || !b->fy || !b->fz)
@@ -153,7 +154,6 @@ mls_status mls_step(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buff
         st = mls_fast_tables(ctx, nullptr, nullptr, nullptr, nullptr, nullptr, stream);
         if (st != MLS_OK) return st;
     }
-    if ((desc->flags & ~MLS_STEP_COMPACT) != 0) return MLS_E_ARG;
     if (desc->method == MLS_EXACT || (fast && fast_fused_ok(c))) {
         // exact MLS, or fast-MLS on a uniform grid, in spreading-tile order:
         // bin the markers from their positions, build with interpolation and
@@ -224,7 +224,7 @@ mls_status mls_step_counter_set(mls_ctx *ctx, uint64_t step, void *stream)
 
 mls_status mls_graph_create(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buffers *b, mls_graph **out)
 {
-    if (!ctx || !desc || !b || !out) return MLS_E_ARG;
+    if (!ctx || !desc || !b || !out || (desc->flags & ~MLS_STEP_COMPACT) != 0) return MLS_E_ARG;
     *out = nullptr;
     Ctx &c = ctx->c;
     // everything that allocates or synchronises happens before the capture

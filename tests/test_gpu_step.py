@@ -320,3 +320,64 @@ def test_compact_step_graph_replays_match_eager():
             assert np.array_equal(bufs.forcing[c].cpu().numpy(), ref[s][2][c]), "replay %d forcing %d" % (s, c)
         _ = (bufs.U * 2).sum().item()
     graph.close()
+
+
+def test_compact_step_ragged_counts_equal_full_step():
+    """1, 65 and 1037 markers (one partial 64-marker block, ragged tails): the
+    compact step's U, F and forcing equal the default step's bit for bit."""
+    import torch
+    from paper_1805_01113_amd import mls
+    wl = W.single_sphere(n=32, subdiv=3, cfg_id=310)
+    ctx = mls.Context(wl.grid.faces, wl.grid.periodic)
+    fields = wl.fields("cuda")
+    for k in (1, 65, 1037):
+        x0, y0, z0, area = [to_dev(np.ascontiguousarray(a[:k])) for a in (wl.x, wl.y, wl.z, wl.area)]
+        forcing = [torch.zeros(wl.grid.shape(c), device="cuda") for c in range(3)]
+        bufs = mls.StepBuffers(ctx, x0, y0, z0, area, fields, forcing)
+        full = _run_step(torch, mls, ctx, bufs, 2, False, jitter=0.1 / 32, seed=4)
+        comp = _run_step(torch, mls, ctx, bufs, 2, True, jitter=0.1 / 32, seed=4)
+        assert np.array_equal(full[0], comp[0]) and np.array_equal(full[1], comp[1]), k
+        for c in range(3):
+            assert np.array_equal(full[2][c], comp[2][c]), (k, c)
+            assert np.any(full[2][c] != 0.0), (k, c)
+
+
+def test_compact_step_reports_support_error_like_full_step():
+    """A marker whose support leaves a wall axis: the compact step reports
+    MLS_E_SUPPORT with the lowest such marker, and the other markers' U and
+    forcing equal the default step's."""
+    import torch
+    from paper_1805_01113_amd import mls
+    wl = W.stretched_channel(n_bodies=6, nxy=32, nz=48, cfg_id=311)
+    z = wl.z.copy()
+    z[[40, 17]] = 0.0
+    ctx = mls.Context(wl.grid.faces, wl.grid.periodic)
+    x0, y0, z0, area = [to_dev(a) for a in (wl.x, wl.y, z, wl.area)]
+    fields = wl.fields("cuda")
+    forcing = [torch.zeros(wl.grid.shape(c), device="cuda") for c in range(3)]
+    bufs = mls.StepBuffers(ctx, x0, y0, z0, area, fields, forcing)
+    res = []
+    for compact in (False, True):
+        for f in bufs.forcing:
+            f.zero_()
+        mls.step_counter_set(ctx, 0)
+        mls.step(ctx, bufs, method=mls.MLS_EXACT, dt=1.0, jitter=0.0, seed=0, compact=compact)
+        assert ctx.sync(raise_on_error=False) == (mls.MLS_E_SUPPORT, 17)
+        res.append((bufs.U.cpu().numpy().copy(), [f.cpu().numpy().copy() for f in bufs.forcing]))
+    keep = np.ones(wl.n, bool)
+    keep[[17, 40]] = False
+    assert np.array_equal(res[0][0][:, keep], res[1][0][:, keep])
+    assert np.all(np.isfinite(res[1][0][:, keep]))
+    for c in range(3):
+        assert np.array_equal(res[0][1][c], res[1][1][c])
+
+
+def test_step_rejects_unknown_flags():
+    import ctypes
+    import torch
+    from paper_1805_01113_amd import mls
+    wl = W.single_sphere(n=32, subdiv=2, cfg_id=312)
+    ctx, bufs = _setup(torch, wl)
+    d = mls._StepDesc(mls.MLS_EXACT, 1.0, 0.0, 0, 2)
+    b = bufs.struct()
+    assert ctx._lib.mls_step(ctx.h, ctypes.byref(d), ctypes.byref(b), None) == mls.MLS_E_ARG

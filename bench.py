@@ -403,20 +403,20 @@ def main():
     if method == mls.MLS_LEARNED and net_meta is None:
         raise SystemExit("--method learned needs the surrogate checkpoint")
     bufs = mls.StepBuffers(ctx, x0, y0, z0, area, fields, forcing)
+    # exact steps keep the transfer functions compact (gamma and the support
+    # offsets) unless --full-phi: the same U, F and forcing, fewer bytes
+    compact = method == mls.MLS_EXACT and not args.full_phi
+    nf = 7 if all(wl.grid.uniform_axis(d) for d in range(3)) else 13
     tune = None
     if not args.no_tune:
         t_a = time.time()
-        tune = ctx.autotune(bufs, method=method, cache_path=args.tune_cache)
+        tune = ctx.autotune(bufs, method=method, cache_path=args.tune_cache, compact=compact)
         for f in forcing:
             f.zero_()
         torch.cuda.synchronize()
         log("autotune (%.1fs): %s" % (time.time() - t_a, json.dumps(tune)))
     jitter = 0.1 * h_min
     seed = 20180503
-    # exact steps keep the transfer functions compact (gamma and the support
-    # offsets) unless --full-phi: the same U, F and forcing, fewer bytes
-    compact = method == mls.MLS_EXACT and not args.full_phi
-    nf = 7 if all(wl.grid.uniform_axis(d) for d in range(3)) else 13
     graph = mls.StepGraph(ctx, bufs, method=method, dt=1.0, jitter=jitter, seed=seed, compact=compact)
     stream = torch.cuda.current_stream()
 

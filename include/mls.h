@@ -443,14 +443,16 @@ mls_status mls_tune_set(mls_ctx *ctx, const mls_tune *in);
 /* Time candidate launch shapes of the build (method), the interpolation and
  * the spreading on the caller's step buffers (n, x0, y0, z0, area, vb, home,
  * phi, u, v, w, U, F, fx, fy, fz as for mls_step; markers at x0), keep the
- * fastest of each phase and apply them.  cache_path (may be NULL) names a
+ * fastest of each phase and apply them.  flags are the step flags the shapes
+ * are for (MLS_STEP_COMPACT times the compact exact build and spreading; other
+ * methods ignore it; other bits: MLS_E_ARG).  cache_path (may be NULL) names a
  * JSON-lines file: an entry whose key (device architecture, compute units,
- * grid, periodic flags, stretched axis, method, floor(log2 n)) matches is
- * applied without timing; otherwise the result is appended.  home, phi, U and
+ * grid, periodic flags, stretched axis, method, flags, floor(log2 n)) matches
+ * is applied without timing; otherwise the result is appended.  home, phi, U and
  * F are overwritten and the forcing fields receive the contributions of the
  * timed spreading calls (zero them afterwards).  Synchronises `stream`. */
-mls_status mls_autotune(mls_ctx *ctx, int32_t method, const mls_step_buffers *buf, const char *cache_path,
-                        mls_tune_report *out, void *stream);
+mls_status mls_autotune(mls_ctx *ctx, int32_t method, int32_t flags, const mls_step_buffers *buf,
+                        const char *cache_path, mls_tune_report *out, void *stream);
 
 /* ---- learned surrogate (an addition to the paper's method) ----------------
  * A network 6 -> 128 -> 128 -> 27 maps the features of a (marker, component)

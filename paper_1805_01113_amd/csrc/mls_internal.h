@@ -164,8 +164,8 @@ struct Ctx {
     int64_t colour_tiles[27] = {};   // tiles of each colour
     float *tile_hmin_block = nullptr;  // per-tile smallest control-volume width (all axes)
     // launch shapes (autotuned): resident workgroups per compute unit
-    int spread_blocks_per_cu = 8;      // effective (bounded by the LDS of the tile boxes)
-    int spread_blocks_per_cu_req = 8;  // requested
+    int spread_blocks_per_cu = 16;      // effective (bounded by the LDS of the tile boxes)
+    int spread_blocks_per_cu_req = 16;  // requested
     int build_blocks_per_cu = 32;
     int interp_blocks_per_cu = 32;
     int cu_count = 256;

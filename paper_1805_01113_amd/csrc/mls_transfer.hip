@@ -21,6 +21,7 @@ namespace mls {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kSpreadBlock = 128;   // threads of a spreading tile workgroup
 
 __global__ void __launch_bounds__(kBlock)
 k_interp(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home, const float *__restrict__ phi,
@@ -451,12 +452,15 @@ __device__ __forceinline__ void flush_box(const Grid &g, int c, unsigned long lo
 // row's compact transfer function (gamma and the support offsets, NF = 7 or
 // 13 floats, see k_build_interp) with the build's own arithmetic, or read
 // from phi for a row the build solved in FP64 (NaN gamma_0).
+// Workgroups of kSpreadBlock = 128 threads: a tile holds some 200 rows, so a
+// smaller workgroup leaves fewer lanes idle and its barriers are cheaper,
+// and more tiles are in flight per compute unit (measured against 64 and 256).
 // Sorted rows: at most 80 registers (6 wavefronts per SIMD).  The tile phases
 // are bound by memory latency and barriers, and a sixth wavefront per SIMD
 // hides more of it than the registers cost (measured; an eighth spills).  The
 // standalone spreading, which gathers by marker, would spill at 80.
 template <bool SORTED, int NF>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SORTED ? 6 : 5)))
+__global__ void __launch_bounds__(kSpreadBlock) __attribute__((amdgpu_waves_per_eu(SORTED ? 6 : 5)))
 k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32_t *__restrict__ home,
                 const float *__restrict__ phi, const float *__restrict__ area, const float *__restrict__ Fx,
                 const float *__restrict__ Fy, const float *__restrict__ Fz, float *__restrict__ fx,
@@ -675,7 +679,7 @@ static hipError_t launch_tiles(Ctx &c, int64_t n, const uint32_t *home, const fl
     TimedLaunch tt(c, MLS_K_SPREAD_TILES, s);
     for (int col = 0; col < 27; ++col) {
         if (c.colour_tiles[col] == 0) continue;
-        hipLaunchKernelGGL((k_spread_colour<SORTED, NF>), dim3(persist), dim3(kBlock), lds, s, c.d_grid, col, n, home,
+        hipLaunchKernelGGL((k_spread_colour<SORTED, NF>), dim3(persist), dim3(kSpreadBlock), lds, s, c.d_grid, col, n, home,
                            phi, area, Fx, Fy, Fz, fx, fy, fz, c.tile_off, c.entries, c.tile_active, c.work, c.work + 64,
                            SORTED ? c.af_rows : nullptr, c.af_stride, NF ? c.coef_rows : nullptr, c.w, c.err);
     }

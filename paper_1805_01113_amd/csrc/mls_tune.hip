@@ -45,7 +45,7 @@ double time_call(hipStream_t s, int reps, F fn, bool &ok)
     return best;
 }
 
-std::string tune_key(const Ctx &c, int method, int64_t n)
+std::string tune_key(const Ctx &c, int method, int flags, int64_t n)
 {
     hipDeviceProp_t prop;
     std::string arch = "unknown";
@@ -56,9 +56,9 @@ std::string tune_key(const Ctx &c, int method, int64_t n)
     }
     const int oct = n > 0 ? (int)std::floor(std::log2((double)n)) : 0;
     char buf[256];
-    snprintf(buf, sizeof(buf), "%s|cu%d|%dx%dx%d|p%d%d%d|s%d|m%d|n%d", arch.c_str(), c.cu_count, c.g.ax[0].n,
+    snprintf(buf, sizeof(buf), "%s|cu%d|%dx%dx%d|p%d%d%d|s%d|m%d|f%d|n%d", arch.c_str(), c.cu_count, c.g.ax[0].n,
              c.g.ax[1].n, c.g.ax[2].n, c.g.ax[0].periodic, c.g.ax[1].periodic, c.g.ax[2].periodic, c.stretched_axis,
-             method, oct);
+             method, flags, oct);
     return buf;
 }
 
@@ -155,10 +155,10 @@ mls_status mls_tune_set(mls_ctx *ctx, const mls_tune *in)
     return MLS_OK;
 }
 
-mls_status mls_autotune(mls_ctx *ctx, int32_t method, const mls_step_buffers *b, const char *cache_path,
-                        mls_tune_report *out, void *stream)
+mls_status mls_autotune(mls_ctx *ctx, int32_t method, int32_t flags, const mls_step_buffers *b,
+                        const char *cache_path, mls_tune_report *out, void *stream)
 {
-    if (!ctx || !b || !out) return MLS_E_ARG;
+    if (!ctx || !b || !out || (flags & ~MLS_STEP_COMPACT) != 0) return MLS_E_ARG;
     Ctx &c = ctx->c;
     const int64_t n = b->n;
     if (n < 1 || !b->x0 || !b->y0 || !b->z0 || !b->area || !b->home || !b->phi || !b->u || !b->v || !b->w || !b->U ||
@@ -169,7 +169,9 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, const mls_step_buffers *b,
     memset(out, 0, sizeof(*out));
     mls_tune cur;
     mls_tune_get(ctx, &cur);
-    const std::string key = tune_key(c, method, n);
+    // the compact rows apply to exact MLS only; other methods tune as without them
+    if (method != MLS_EXACT) flags = 0;
+    const std::string key = tune_key(c, method, flags, n);
     if (cache_lookup(cache_path, key, *out)) {
         out->from_cache = 1;
         const mls_status st = mls_tune_set(ctx, &out->best);
@@ -178,6 +180,18 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, const mls_step_buffers *b,
     }
     mls_status st = mls_reserve(ctx, n);
     if (st != MLS_OK) return st;
+    const bool compact = (flags & MLS_STEP_COMPACT) != 0;
+    if (compact) {
+        st = reserve_compact(ctx, n);
+        if (st != MLS_OK) return st;
+    }
+    // the build and spreading launches below use the row width of the step
+    // being tuned, and only during tuning
+    struct NfReset {
+        Ctx &c;
+        ~NfReset() { c.step_nf = 0; }
+    } nf_reset{c};
+    c.step_nf = compact ? compact_nf(c) : 0;
     const bool timing = c.timing;
     c.timing = false;
     float *U = b->U, *V = b->U + n, *Wv = b->U + 2 * n;
@@ -247,7 +261,7 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, const mls_step_buffers *b,
     // spreading: tile edge x resident workgroups
     double t_spread = 1e30;
     const int tiles[] = {4, 6, 8, 10, 12, 16};
-    const int spcs[] = {1, 2, 4, 8};
+    const int spcs[] = {4, 8, 16, 32};
     std::vector<std::vector<int>> seen;
     for (int tile : tiles) {
         if (!ok) break;

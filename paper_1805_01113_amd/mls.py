@@ -129,7 +129,8 @@ def load(path: str = LIB_PATH, need_torch: bool = True):
     L.mls_timing_get.argtypes = [P, ctypes.POINTER(_Timing), I32]
     L.mls_tune_get.argtypes = [P, ctypes.POINTER(_Tune)]
     L.mls_tune_set.argtypes = [P, ctypes.POINTER(_Tune)]
-    L.mls_autotune.argtypes = [P, I32, ctypes.POINTER(_StepBuf), ctypes.c_char_p, ctypes.POINTER(_TuneReport), P]
+    L.mls_autotune.argtypes = [P, I32, I32, ctypes.POINTER(_StepBuf), ctypes.c_char_p, ctypes.POINTER(_TuneReport),
+                               P]
     L.mls_mlp_load.argtypes = [P, P, P]
     L.mls_mlp_get.argtypes = [P, P, P]
     L.mls_features.argtypes = [P, I64, P, P, P, P, P]
@@ -427,13 +428,15 @@ class Context:
         t = _Tune(**cur)
         self._raise(self._lib.mls_tune_set(self.h, ctypes.byref(t)), "mls_tune_set")
 
-    def autotune(self, bufs: "StepBuffers", method=MLS_EXACT, cache_path=None, stream=None):
+    def autotune(self, bufs: "StepBuffers", method=MLS_EXACT, cache_path=None, stream=None, compact=False):
         """Time launch shapes on the step buffers and apply the fastest
-        (mls_autotune); returns the report as a dict."""
+        (mls_autotune); compact=True tunes the compact exact step.  Returns
+        the report as a dict."""
         r = _TuneReport()
         b = bufs.struct()
         cp = None if cache_path is None else os.fsencode(cache_path)
-        self._raise(self._lib.mls_autotune(self.h, int(method), ctypes.byref(b), cp, ctypes.byref(r),
+        flags = MLS_STEP_COMPACT if compact else 0
+        self._raise(self._lib.mls_autotune(self.h, int(method), flags, ctypes.byref(b), cp, ctypes.byref(r),
                                            _stream(stream)), "mls_autotune")
         out = {k: getattr(r.best, k) for k, _ in _Tune._fields_}
         out.update(ms_build=r.ms_build, ms_interp=r.ms_interp, ms_spread=r.ms_spread,

@@ -60,7 +60,21 @@ def test_autotune_then_cache(orc, torch_cuda, tmp_path):
     assert r2["from_cache"] and r2["candidates"] == 0
     for k in ("spread_tile", "spread_blocks_per_cu", "build_blocks_per_cu", "interp_blocks_per_cu"):
         assert r2[k] == r1[k]
-    # the tuned context still computes the transfer of the oracle
+    # the compact exact step is tuned under its own key, then served from the cache
+    r3 = ctx.autotune(bufs, method=mls.MLS_EXACT, cache_path=cache, compact=True)
+    assert not r3["from_cache"] and r3["candidates"] >= 8
+    r4 = ctx.autotune(bufs, method=mls.MLS_EXACT, cache_path=cache, compact=True)
+    assert r4["from_cache"]
+    with open(cache) as f:
+        assert len(f.read().strip().splitlines()) == 2
+    # fast-MLS ignores the flag: served from the entry tuned without it
+    ctx.autotune(bufs, method=mls.MLS_FAST, cache_path=cache)
+    r5 = ctx.autotune(bufs, method=mls.MLS_FAST, cache_path=cache, compact=True)
+    assert r5["from_cache"]
+    with pytest.raises(mls.MLSError):
+        ctx._raise(ctx._lib.mls_autotune(ctx.h, mls.MLS_EXACT, 4, None, None, None, None), "mls_autotune")
+    # the tuned context still computes the transfer of the oracle, and the
+    # compact step is still the default step bit for bit
     _spread_vs_oracle(orc, torch, ctx, wl.grid, wl.x, wl.y, wl.z, wl.area, wl.force, "tuned")
 
 

@@ -235,7 +235,7 @@ def compare_methods(torch, ctx, wl, bufs, fields, forcing, x0, y0, z0, area, jit
         row["per_body"] = {"markers_per_s": round(rate, 1), "bodies_timed": sub}
         if saved is not None:
             ctx.tune_set(**{k: saved[k] for k in ("spread_tile", "spread_blocks_per_cu", "build_blocks_per_cu",
-                                                 "interp_blocks_per_cu")})
+                                                 "interp_blocks_per_cu", "spread_threads")})
         log("%s: batched %.3f ms/step (%.3e markers/s), per-body %.3e markers/s, interp err vs exact %.2e%s"
             % (name, ms, n / (ms * 1e-3), rate, err,
                (", fallback rate %.4f" % row["fallback_rate"]) if "fallback_rate" in row else ""))

@@ -416,12 +416,15 @@ mls_status mls_timing_get(mls_ctx *ctx, mls_timing *out, int32_t reset);
  * *_blocks_per_cu (1..64): workgroups per compute unit in the grid of the
  * spreading tile launches (bounded further by the LDS of a tile's boxes), of
  * the exact / fast build and of the interpolation; a grid-stride loop covers
- * the work beyond the grid. */
+ * the work beyond the grid.  spread_threads (128 or 256): threads of a
+ * spreading tile workgroup (fewer suit many tiles per workgroup, more suit
+ * few). */
 typedef struct {
     int32_t spread_tile;
     int32_t spread_blocks_per_cu;
     int32_t build_blocks_per_cu;
     int32_t interp_blocks_per_cu;
+    int32_t spread_threads;
 } mls_tune;
 
 typedef struct {

@@ -21,7 +21,7 @@ namespace mls {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kSpreadBlock = 128;   // threads of a spreading tile workgroup
+constexpr int kSpreadBlock = 256;   // most threads of a spreading tile workgroup
 
 __global__ void __launch_bounds__(kBlock)
 k_interp(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home, const float *__restrict__ phi,
@@ -452,9 +452,11 @@ __device__ __forceinline__ void flush_box(const Grid &g, int c, unsigned long lo
 // row's compact transfer function (gamma and the support offsets, NF = 7 or
 // 13 floats, see k_build_interp) with the build's own arithmetic, or read
 // from phi for a row the build solved in FP64 (NaN gamma_0).
-// Workgroups of kSpreadBlock = 128 threads: a tile holds some 200 rows, so a
-// smaller workgroup leaves fewer lanes idle and its barriers are cheaper,
-// and more tiles are in flight per compute unit (measured against 64 and 256).
+// Workgroups of 128 or 256 threads (tuned, at most kSpreadBlock).  A tile
+// holds some 200 rows: when each workgroup handles many tiles, 128 threads
+// leave fewer lanes idle, pay cheaper barriers and keep more tiles in flight
+// per compute unit (cfg 3: 2.86 against 3.10 ms); when a colour has only a
+// tile or two per workgroup, 256 threads finish each tile sooner.
 // Sorted rows: at most 80 registers (6 wavefronts per SIMD).  The tile phases
 // are bound by memory latency and barriers, and a sixth wavefront per SIMD
 // hides more of it than the registers cost (measured; an eighth spills).  The
@@ -679,7 +681,7 @@ static hipError_t launch_tiles(Ctx &c, int64_t n, const uint32_t *home, const fl
     TimedLaunch tt(c, MLS_K_SPREAD_TILES, s);
     for (int col = 0; col < 27; ++col) {
         if (c.colour_tiles[col] == 0) continue;
-        hipLaunchKernelGGL((k_spread_colour<SORTED, NF>), dim3(persist), dim3(kSpreadBlock), lds, s, c.d_grid, col, n, home,
+        hipLaunchKernelGGL((k_spread_colour<SORTED, NF>), dim3(persist), dim3(c.spread_threads), lds, s, c.d_grid, col, n, home,
                            phi, area, Fx, Fy, Fz, fx, fy, fz, c.tile_off, c.entries, c.tile_active, c.work, c.work + 64,
                            SORTED ? c.af_rows : nullptr, c.af_stride, NF ? c.coef_rows : nullptr, c.w, c.err);
     }

@@ -94,7 +94,8 @@ bool cache_lookup(const char *path, const std::string &key, mls_tune_report &rep
         if (json_int(line, "spread_tile", t.spread_tile) &&
             json_int(line, "spread_blocks_per_cu", t.spread_blocks_per_cu) &&
             json_int(line, "build_blocks_per_cu", t.build_blocks_per_cu) &&
-            json_int(line, "interp_blocks_per_cu", t.interp_blocks_per_cu)) {
+            json_int(line, "interp_blocks_per_cu", t.interp_blocks_per_cu) &&
+            json_int(line, "spread_threads", t.spread_threads)) {
             rep.best = t;
             json_double(line, "ms_build", rep.ms_build);
             json_double(line, "ms_interp", rep.ms_interp);
@@ -112,9 +113,11 @@ void cache_append(const char *path, const std::string &key, const mls_tune_repor
     if (!f) return;
     fprintf(f,
             "{\"key\":\"%s\",\"spread_tile\":%d,\"spread_blocks_per_cu\":%d,\"build_blocks_per_cu\":%d,"
-            "\"interp_blocks_per_cu\":%d,\"ms_build\":%.4f,\"ms_interp\":%.4f,\"ms_spread\":%.4f,\"candidates\":%d}\n",
+            "\"interp_blocks_per_cu\":%d,\"spread_threads\":%d,\"ms_build\":%.4f,\"ms_interp\":%.4f,"
+            "\"ms_spread\":%.4f,\"candidates\":%d}\n",
             key.c_str(), rep.best.spread_tile, rep.best.spread_blocks_per_cu, rep.best.build_blocks_per_cu,
-            rep.best.interp_blocks_per_cu, rep.ms_build, rep.ms_interp, rep.ms_spread, rep.candidates);
+            rep.best.interp_blocks_per_cu, rep.best.spread_threads, rep.ms_build, rep.ms_interp, rep.ms_spread,
+            rep.candidates);
     fclose(f);
 }
 
@@ -132,6 +135,7 @@ mls_status mls_tune_get(mls_ctx *ctx, mls_tune *out)
     out->spread_blocks_per_cu = c.spread_blocks_per_cu_req;
     out->build_blocks_per_cu = c.build_blocks_per_cu;
     out->interp_blocks_per_cu = c.interp_blocks_per_cu;
+    out->spread_threads = c.spread_threads;
     return MLS_OK;
 }
 
@@ -140,9 +144,11 @@ mls_status mls_tune_set(mls_ctx *ctx, const mls_tune *in)
     if (!ctx || !in) return MLS_E_ARG;
     Ctx &c = ctx->c;
     if (!bpc_ok(in->spread_blocks_per_cu) || !bpc_ok(in->build_blocks_per_cu) || !bpc_ok(in->interp_blocks_per_cu) ||
-        in->spread_tile < 4 || in->spread_tile > kMaxBoxTile)
+        in->spread_tile < 4 || in->spread_tile > kMaxBoxTile ||
+        (in->spread_threads != 128 && in->spread_threads != 256))
         return MLS_E_ARG;
     c.spread_blocks_per_cu_req = in->spread_blocks_per_cu;
+    c.spread_threads = in->spread_threads;
     c.build_blocks_per_cu = in->build_blocks_per_cu;
     c.interp_blocks_per_cu = in->interp_blocks_per_cu;
     if (in->spread_tile != c.opts.spread_tile) {
@@ -261,7 +267,8 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, int32_t flags, const mls_s
     // spreading: tile edge x resident workgroups
     double t_spread = 1e30;
     const int tiles[] = {4, 6, 8, 10, 12, 16};
-    const int spcs[] = {4, 8, 16, 32};
+    const int spcs[] = {1, 2, 4, 8, 16, 32};
+    const int sthreads[] = {128, 256};
     std::vector<std::vector<int>> seen;
     for (int tile : tiles) {
         if (!ok) break;
@@ -270,18 +277,26 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, int32_t flags, const mls_s
         if (std::find(seen.begin(), seen.end(), shape) != seen.end()) continue;
         seen.push_back(shape);
         if (exact) ok = build() == MLS_OK;   // bin for this tiling (untimed)
-        int last_eff = -1;
-        for (int v : spcs) {
-            const int64_t lds = (int64_t)c.g.box[0] * c.g.box[1] * c.g.box[2] * 8;
-            const int eff = std::max(1, std::min(v, (int)((160 * 1024) / (lds + 512))));
-            if (eff == last_eff) continue;
-            last_eff = eff;
-            c.spread_blocks_per_cu_req = v;
-            c.spread_blocks_per_cu = eff;
-            const double t = time_call(s, 3, spread, ok);
-            if (!ok) break;
-            ++cand;
-            if (t < t_spread) { t_spread = t; best.spread_tile = tile; best.spread_blocks_per_cu = v; }
+        for (int th : sthreads) {
+            int last_eff = -1;
+            c.spread_threads = th;
+            for (int v : spcs) {
+                const int64_t lds = (int64_t)c.g.box[0] * c.g.box[1] * c.g.box[2] * 8;
+                const int eff = std::max(1, std::min(v, (int)((160 * 1024) / (lds + 512))));
+                if (eff == last_eff) continue;
+                last_eff = eff;
+                c.spread_blocks_per_cu_req = v;
+                c.spread_blocks_per_cu = eff;
+                const double t = time_call(s, 3, spread, ok);
+                if (!ok) break;
+                ++cand;
+                if (t < t_spread) {
+                    t_spread = t;
+                    best.spread_tile = tile;
+                    best.spread_blocks_per_cu = v;
+                    best.spread_threads = th;
+                }
+            }
         }
     }
     c.timing = timing;

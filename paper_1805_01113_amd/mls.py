@@ -68,7 +68,8 @@ MLP_PARAMS = 20891   # 6*128 + 128 + 128*128 + 128 + 128*27 + 27
 
 class _Tune(ctypes.Structure):
     _fields_ = [("spread_tile", ctypes.c_int32), ("spread_blocks_per_cu", ctypes.c_int32),
-                ("build_blocks_per_cu", ctypes.c_int32), ("interp_blocks_per_cu", ctypes.c_int32)]
+                ("build_blocks_per_cu", ctypes.c_int32), ("interp_blocks_per_cu", ctypes.c_int32),
+                ("spread_threads", ctypes.c_int32)]
 
 
 class _TuneReport(ctypes.Structure):

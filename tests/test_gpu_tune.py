@@ -58,7 +58,7 @@ def test_autotune_then_cache(orc, torch_cuda, tmp_path):
         assert len(f.read().strip().splitlines()) == 1
     r2 = ctx.autotune(bufs, method=mls.MLS_EXACT, cache_path=cache)
     assert r2["from_cache"] and r2["candidates"] == 0
-    for k in ("spread_tile", "spread_blocks_per_cu", "build_blocks_per_cu", "interp_blocks_per_cu"):
+    for k in ("spread_tile", "spread_blocks_per_cu", "build_blocks_per_cu", "interp_blocks_per_cu", "spread_threads"):
         assert r2[k] == r1[k]
     # the compact exact step is tuned under its own key, then served from the cache
     r3 = ctx.autotune(bufs, method=mls.MLS_EXACT, cache_path=cache, compact=True)
@@ -97,3 +97,33 @@ def test_every_tile_edge_matches_oracle(orc, torch_cuda):
     with pytest.raises(mls.MLSError):
         ctx.tune_set(build_blocks_per_cu=0)
     assert ctx.tune_get()["spread_tile"] == 16
+
+
+def test_spread_shapes_give_identical_forcing(torch_cuda):
+    """The compact exact step's forcing is the same bit for bit for 128- and
+    256-thread spreading workgroups and any number of them per compute unit
+    (fixed-point sums per tile), and out-of-range shapes are rejected."""
+    from paper_1805_01113_amd import mls
+    from paper_1805_01113_amd import workloads as W
+    torch = torch_cuda
+    wl = W.ellipsoids(n_bodies=40, n=128, cfg_id=320)
+    ctx = mls.Context(wl.grid.faces, wl.grid.periodic)
+    x0, y0, z0, area = [torch.from_numpy(a).cuda() for a in (wl.x, wl.y, wl.z, wl.area)]
+    fields = wl.fields("cuda")
+    forcing = [torch.zeros(wl.grid.shape(c), dtype=torch.float32, device="cuda") for c in range(3)]
+    bufs = mls.StepBuffers(ctx, x0, y0, z0, area, fields, forcing)
+    outs = []
+    for th, bpc in ((128, 16), (256, 1), (256, 8), (128, 2)):
+        ctx.tune_set(spread_threads=th, spread_blocks_per_cu=bpc)
+        for f in forcing:
+            f.zero_()
+        mls.step_counter_set(ctx, 3)
+        mls.step(ctx, bufs, method=mls.MLS_EXACT, dt=1.0, jitter=0.1 / 128, seed=2, compact=True)
+        ctx.sync()
+        outs.append([f.cpu().numpy().copy() for f in forcing])
+    for o in outs[1:]:
+        for c in range(3):
+            assert np.array_equal(o[c], outs[0][c])
+    for bad in (64, 192, 512):
+        with pytest.raises(mls.MLSError):
+            ctx.tune_set(spread_threads=bad)

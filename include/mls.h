@@ -385,7 +385,10 @@ mls_status mls_step_counter_set(mls_ctx *ctx, uint64_t step, void *stream);
 /* A step captured once as a HIP graph and replayed: the capture contains no
  * allocation, no memset node and no host synchronisation, so a replay costs
  * one graph launch.  The buffers are baked into the graph; they must stay
- * allocated until mls_graph_destroy. */
+ * allocated until mls_graph_destroy.  So is the context's scratch: after it
+ * grows (mls_reserve or a step with more markers than any before) or the
+ * spreading tile changes (mls_tune_set, mls_autotune), mls_graph_launch
+ * returns MLS_E_ARG and the graph must be created again. */
 typedef struct mls_graph mls_graph;
 mls_status mls_graph_create(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buffers *buf,
                             mls_graph **out);

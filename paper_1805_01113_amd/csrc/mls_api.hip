@@ -151,6 +151,7 @@ mls_status mls::setup_tiles(Ctx &c, int want)
     c.tile_hmin_block = th;
     c.tile_count = tcount; c.tile_off = toff; c.tile_cursor = tcur; c.tile_active = tact; c.block_sums = bsum;
     c.g = g;
+    ++c.scratch_gen;
     for (int k = 0; k < 27; ++k) c.colour_tiles[k] = colour_tiles[k];
     c.spread_blocks_per_cu = std::max(1, std::min(c.spread_blocks_per_cu_req, (int)((160 * 1024) / (lds + 512))));
     c.opts.spread_tile = want;
@@ -174,6 +175,7 @@ mls_status reserve_compact(mls_ctx *ctx, int64_t n)
     Ctx &c = ctx->c;
     if (n <= c.coef_cap) return MLS_OK;
     hipDeviceSynchronize();
+    ++c.scratch_gen;
     hipFree(c.coef_rows);
     hipFree(c.route_queue);
     c.coef_rows = nullptr;
@@ -409,6 +411,7 @@ mls_status mls_reserve(mls_ctx *ctx, int64_t n)
     if (n > (int64_t)0x1fffffff) return fail(ctx, MLS_E_ARG, "too many markers (%lld)", (long long)n);
     if (n <= c.cap_markers) return MLS_OK;
     hipDeviceSynchronize();
+    ++c.scratch_gen;
     hipFree(c.entries);
     hipFree(c.af_rows);
     hipFree(c.marker_tile);

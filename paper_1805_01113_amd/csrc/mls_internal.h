@@ -157,6 +157,8 @@ struct Ctx {
     uint32_t *route_queue = nullptr;   // [1 + 3 cap]: count, then row << 2 | component of its FP64-solved rows
     int64_t coef_cap = 0;              // markers the two buffers above hold
     int step_nf = 0;                   // row width of the step being enqueued: 0 (full phi), 7 or 13
+    uint64_t scratch_gen = 0;          // bumped whenever context scratch moves or the tiling changes
+                                       // (a captured step graph holds the old addresses and tiling)
     int64_t af_stride = 0;             // cap_markers rounded up to 64
     uint32_t *block_fmax = nullptr;    // per-block force maxima of the counting pass (3 per block)
     uint32_t *work = nullptr;          // [0..26] active-list sizes per colour, [32..58] cursors,

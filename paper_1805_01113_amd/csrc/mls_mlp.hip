@@ -656,6 +656,7 @@ hipError_t mlp_reserve(Ctx &c, int64_t M)
     if (M <= net.cap_batch) return hipSuccess;
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return e;
+    ++c.scratch_gen;
     if (net.scratch) hipFree(net.scratch);
     net.scratch = nullptr;
     net.cap_batch = 0;

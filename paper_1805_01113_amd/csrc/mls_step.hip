@@ -119,6 +119,7 @@ struct mls_graph {
     mls_ctx *ctx = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    uint64_t scratch_gen = 0;   // the context's scratch generation the capture saw
 };
 
 extern "C" {
@@ -251,6 +252,7 @@ mls_status mls_graph_create(mls_ctx *ctx, const mls_step_desc *desc, const mls_s
     }
     c.capturing = false;
     if (e == hipSuccess && st == MLS_OK) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    g->scratch_gen = c.scratch_gen;
     hipStreamDestroy(cs);
     if (e != hipSuccess || st != MLS_OK) {
         mls_graph_destroy(g);
@@ -263,6 +265,12 @@ mls_status mls_graph_create(mls_ctx *ctx, const mls_step_desc *desc, const mls_s
 mls_status mls_graph_launch(mls_graph *g, int32_t n_steps, void *stream)
 {
     if (!g || !g->exec || n_steps < 0) return MLS_E_ARG;
+    // the context's scratch moved or its tiling changed since the capture:
+    // the graph would address freed memory
+    if (g->scratch_gen != g->ctx->c.scratch_gen) {
+        g->ctx->c.last_error = "step graph captured before the context's scratch or tiling changed; create it again";
+        return MLS_E_ARG;
+    }
     for (int32_t i = 0; i < n_steps; ++i)
         if (hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)) != hipSuccess) return MLS_E_HIP;
     return MLS_OK;

@@ -381,3 +381,34 @@ def test_step_rejects_unknown_flags():
     d = mls._StepDesc(mls.MLS_EXACT, 1.0, 0.0, 0, 2)
     b = bufs.struct()
     assert ctx._lib.mls_step(ctx.h, ctypes.byref(d), ctypes.byref(b), None) == mls.MLS_E_ARG
+
+
+def test_graph_refuses_to_run_after_scratch_or_tiling_changes():
+    """A graph holds the context's scratch addresses and tiling: after the
+    spreading tile changes or the scratch grows, launching it is refused
+    (MLS_E_ARG) instead of touching freed memory; a new capture runs."""
+    import torch
+    from paper_1805_01113_amd import mls
+    wl = W.ellipsoids(n_bodies=20, n=128, cfg_id=313)
+    ctx, bufs = _setup(torch, wl)
+    graph = mls.StepGraph(ctx, bufs, method=mls.MLS_EXACT, dt=1.0, jitter=0.0, seed=0, compact=True)
+    graph.launch(1)
+    ctx.sync()
+    tile = ctx.tune_get()["spread_tile"]
+    ctx.tune_set(spread_tile=4 if tile != 4 else 8)
+    with pytest.raises(mls.MLSError):
+        graph.launch(1)
+    graph.close()
+    graph = mls.StepGraph(ctx, bufs, method=mls.MLS_EXACT, dt=1.0, jitter=0.0, seed=0, compact=True)
+    graph.launch(1)
+    ctx.sync()
+    ctx.reserve(4 * wl.n)
+    with pytest.raises(mls.MLSError):
+        graph.launch(1)
+    graph.close()
+    # launch shapes that keep the tiling do not invalidate a graph
+    graph = mls.StepGraph(ctx, bufs, method=mls.MLS_EXACT, dt=1.0, jitter=0.0, seed=0, compact=True)
+    ctx.tune_set(spread_blocks_per_cu=2, spread_threads=256)
+    graph.launch(1)
+    ctx.sync()
+    graph.close()

@@ -466,7 +466,8 @@ def main():
         # homes, phi, A F by row (tile order; by marker for the standalone spreading:
         # A and F, 16 bytes), read-modify-write of the touched field values
         "spread_tiles": 12 + (tf if method == mls.MLS_EXACT else 324) + 12 + 8.0 * t_per,
-        "spread_bin": 0.0,
+        # the sorted step jitters inside its binning pass (x0 read, x written)
+        "spread_bin": 0.0 if "jitter" in kt else 24.0,
     }
     kernels = {}
     for k, (ms, cnt) in kt.items():

@@ -224,6 +224,34 @@ __device__ __forceinline__ void axis_offsets_d(const Axis &a, int is_face, doubl
 
 // ---- weight function ------------------------------------------------------
 
+// SplitMix64 (Steele, Lea, Flood 2014) output function of the state
+// seed + (ctr + 1) * golden gamma: a counter-based generator.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t ctr)
+{
+    uint64_t z = seed + (ctr + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+#pragma clang fp contract(off)
+// Jittered position of marker l of n in step `step`: p = p0 + (u - 1/2) amp2
+// per axis, u on the 2^-24 lattice of [0, 1) from counter (step n + l) 3 +
+// axis; plain FP32 operations (no fused multiply-add), so every kernel that
+// jitters obtains the same bits.
+__device__ __forceinline__ void jitter_marker(uint64_t seed, uint64_t step, int64_t n, int64_t l, float amp2,
+                                              float x0, float y0, float z0, float &x, float &y, float &z)
+{
+    const uint64_t base = ((uint64_t)step * (uint64_t)n + (uint64_t)l) * 3ull;
+    const float ux = (float)(splitmix64(seed, base + 0) >> 40) * 0x1p-24f;
+    const float uy = (float)(splitmix64(seed, base + 1) >> 40) * 0x1p-24f;
+    const float uz = (float)(splitmix64(seed, base + 2) >> 40) * 0x1p-24f;
+    x = x0 + (ux - 0.5f) * amp2;
+    y = y0 + (uy - 0.5f) * amp2;
+    z = z0 + (uz - 0.5f) * amp2;
+}
+#pragma clang fp contract(on)
+
 // Selects rather than branches on the (uniform) kind, so that consecutive
 // evaluations stay in one basic block and interleave.
 __device__ __forceinline__ float weight1(const Weight &w, float s)

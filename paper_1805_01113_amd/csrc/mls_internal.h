@@ -245,7 +245,12 @@ hipError_t launch_spread(Ctx &c, int64_t n, const uint32_t *home, const float *p
 // p of home / phi for marker entries[p] together with U, F and per-block
 // force maxima, and the tile kernels read the rows of a tile contiguously.
 int build_blocks(const Ctx &c, int64_t n);   // workgroups of a build launch over n markers
-hipError_t launch_sort_positions(Ctx &c, int64_t n, const float *x, const float *y, const float *z, hipStream_t s);
+// Bins the markers by spreading tile from their positions x, y, z; with jx
+// non-NULL the positions are first jittered (amplitude jitter, the step's
+// generator and device counter) into jx, jy, jz, and those are binned.
+hipError_t launch_sort_positions(Ctx &c, int64_t n, const float *x, const float *y, const float *z, hipStream_t s,
+                                 float *jx = nullptr, float *jy = nullptr, float *jz = nullptr, float jitter = 0.0f,
+                                 uint64_t seed = 0);
 int compact_nf(const Ctx &c);
 mls_status reserve_compact(mls_ctx *ctx, int64_t n);
 hipError_t launch_build_interp(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,

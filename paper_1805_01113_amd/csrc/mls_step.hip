@@ -12,16 +12,6 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// SplitMix64 (Steele, Lea, Flood 2014) output function of the state
-// seed + (ctr + 1) * golden gamma: a counter-based generator.
-__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t ctr)
-{
-    uint64_t z = seed + (ctr + 1ull) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
 #pragma clang fp contract(off)
 // x = x0 + (u - 1/2) (2 amp), u on the 2^-24 lattice of [0, 1); plain FP32
 // operations (no fused multiply-add) so the result is reproducible anywhere.
@@ -31,18 +21,8 @@ k_jitter(int64_t n, const float *__restrict__ x0, const float *__restrict__ y0, 
          const unsigned long long *__restrict__ step_ctr)
 {
     const uint64_t step = *step_ctr;
-    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n; l += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t base = ((uint64_t)step * (uint64_t)n + (uint64_t)l) * 3ull;
-        const float ux = (float)(splitmix64(seed, base + 0) >> 40) * 0x1p-24f;
-        const float uy = (float)(splitmix64(seed, base + 1) >> 40) * 0x1p-24f;
-        const float uz = (float)(splitmix64(seed, base + 2) >> 40) * 0x1p-24f;
-        const float dx = (ux - 0.5f) * amp2;
-        const float dy = (uy - 0.5f) * amp2;
-        const float dz = (uz - 0.5f) * amp2;
-        x[l] = x0[l] + dx;
-        y[l] = y0[l] + dy;
-        z[l] = z0[l] + dz;
-    }
+    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n; l += (int64_t)gridDim.x * blockDim.x)
+        jitter_marker(seed, step, n, l, amp2, x0[l], y0[l], z0[l], x[l], y[l], z[l]);
 }
 #pragma clang fp contract(on)
 
@@ -137,16 +117,8 @@ mls_status mls_step(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buff
         return MLS_E_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const float *bx = b->x0, *by = b->y0, *bz = b->z0;
-    if (desc->jitter > 0.0f) {
-        if (!b->x || !b->y || !b->z) return MLS_E_ARG;
-        hipError_t e;
-        {
-            TimedLaunch t(c, MLS_K_JITTER, s);
-            e = launch_jitter(c, n, b->x0, b->y0, b->z0, b->x, b->y, b->z, desc->jitter, desc->seed, s);
-        }
-        if (e != hipSuccess) return MLS_E_HIP;
-        bx = b->x; by = b->y; bz = b->z;
-    }
+    const bool jitter = desc->jitter > 0.0f;
+    if (jitter && (!b->x || !b->y || !b->z)) return MLS_E_ARG;
     mls_status st = MLS_OK;
     hipError_t e;
     const bool fast = desc->method == MLS_FAST || desc->method == MLS_FAST_LINEAR;
@@ -155,7 +127,17 @@ mls_status mls_step(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buff
         st = mls_fast_tables(ctx, nullptr, nullptr, nullptr, nullptr, nullptr, stream);
         if (st != MLS_OK) return st;
     }
-    if (desc->method == MLS_EXACT || (fast && fast_fused_ok(c))) {
+    const bool sorted = desc->method == MLS_EXACT || (fast && fast_fused_ok(c));
+    if (jitter) {
+        // the sorted step jitters inside its binning pass; the others first
+        if (!sorted) {
+            TimedLaunch t(c, MLS_K_JITTER, s);
+            e = launch_jitter(c, n, b->x0, b->y0, b->z0, b->x, b->y, b->z, desc->jitter, desc->seed, s);
+            if (e != hipSuccess) return MLS_E_HIP;
+        }
+        bx = b->x; by = b->y; bz = b->z;
+    }
+    if (sorted) {
         // exact MLS, or fast-MLS on a uniform grid, in spreading-tile order:
         // bin the markers from their positions, build with interpolation and
         // forcing fused (phi is not read back), spread reading each tile's
@@ -173,7 +155,8 @@ mls_status mls_step(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buff
             ~NfReset() { c.step_nf = 0; }
         } nf_reset{c};
         c.step_nf = compact ? compact_nf(c) : 0;
-        e = launch_sort_positions(c, n, bx, by, bz, s);
+        e = jitter ? launch_sort_positions(c, n, b->x0, b->y0, b->z0, s, b->x, b->y, b->z, desc->jitter, desc->seed)
+                   : launch_sort_positions(c, n, bx, by, bz, s);
         if (e != hipSuccess) return MLS_E_HIP;
         if (fast) {
             TimedLaunch t(c, MLS_K_FAST_INTERP, s);

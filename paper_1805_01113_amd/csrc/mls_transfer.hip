@@ -173,14 +173,19 @@ k_bin(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home,
 // axis); a marker whose cell support leaves a wall axis, or whose position is
 // not finite, goes to the extra bucket ntiles, after all tiles.  The counting
 // pass locates the markers and records each one's tile in tiles[]; the
-// filling pass reads it back.
+// filling pass reads it back.  With jitter (amp2 > 0) the counting pass reads
+// the rest positions x, y, z, jitters them (the time step's generator) and
+// stores the result in jx, jy, jz, which it then locates.
 template <bool FILL>
 __global__ void __launch_bounds__(kBlock)
 k_bin_pos(const Grid *__restrict__ gp, int64_t n, const float *__restrict__ x, const float *__restrict__ y,
           const float *__restrict__ z, uint32_t *__restrict__ count, uint32_t *__restrict__ cursor,
-          uint32_t *__restrict__ entries, uint32_t *__restrict__ tiles)
+          uint32_t *__restrict__ entries, uint32_t *__restrict__ tiles, float *__restrict__ jx,
+          float *__restrict__ jy, float *__restrict__ jz, float amp2, uint64_t seed,
+          const unsigned long long *__restrict__ step_ctr)
 {
     const Grid &g = *gp;
+    const uint64_t step = (!FILL && amp2 > 0.0f) ? *step_ctr : 0ull;
     const int lane = threadIdx.x & 63;
     const unsigned long long lower = (1ull << lane) - 1ull;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -192,7 +197,14 @@ k_bin_pos(const Grid *__restrict__ gp, int64_t n, const float *__restrict__ x, c
             if (FILL) {
                 t = tiles[l];
             } else {
-                const double p[3] = {(double)x[l], (double)y[l], (double)z[l]};
+                float px = x[l], py = y[l], pz = z[l];
+                if (amp2 > 0.0f) {
+                    jitter_marker(seed, step, n, l, amp2, px, py, pz, px, py, pz);
+                    jx[l] = px;
+                    jy[l] = py;
+                    jz[l] = pz;
+                }
+                const double p[3] = {(double)px, (double)py, (double)pz};
                 int cell[3];
                 bool ok = true;
 #pragma unroll
@@ -726,21 +738,24 @@ hipError_t launch_spread(Ctx &c, int64_t n, const uint32_t *home, const float *p
     return launch_tiles<false, 0>(c, n, home, phi, area, Fx, Fy, Fz, fx, fy, fz, s);
 }
 
-hipError_t launch_sort_positions(Ctx &c, int64_t n, const float *x, const float *y, const float *z, hipStream_t s)
+hipError_t launch_sort_positions(Ctx &c, int64_t n, const float *x, const float *y, const float *z, hipStream_t s,
+                                 float *jx, float *jy, float *jz, float jitter, uint64_t seed)
 {
+    const float amp2 = jx ? 2.0f * jitter : 0.0f;
     if (n == 0) return hipSuccess;
     const int64_t nt = c.g.ntiles + 1;   // tiles and the bucket of markers without a valid support
     const int64_t nb = (nt + kScanChunk - 1) / kScanChunk;
     TimedLaunch tb(c, MLS_K_SPREAD_BIN, s);
     hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(nt, c.cu_count)), dim3(kBlock), 0, s, c.tile_count, nt);
     hipLaunchKernelGGL(k_bin_pos<false>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, x, y, z,
-                       c.tile_count, c.tile_cursor, c.entries, c.marker_tile);
+                       c.tile_count, c.tile_cursor, c.entries, c.marker_tile, jx, jy, jz, amp2, seed, c.step_ctr);
     hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)nb), dim3(kBlock), 0, s, c.tile_count, nt, c.block_sums);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, c.block_sums, nb, c.block_fmax, 0, c.work + 64);
     hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kBlock), 0, s, c.tile_count, nt, c.block_sums,
                        c.tile_off, c.tile_cursor, c.work);
     hipLaunchKernelGGL(k_bin_pos<true>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, x, y, z,
-                       c.tile_count, c.tile_cursor, c.entries, c.marker_tile);
+                       c.tile_count, c.tile_cursor, c.entries, c.marker_tile, nullptr, nullptr, nullptr, 0.0f,
+                       (uint64_t)0, c.step_ctr);
     return hipGetLastError();
 }
 

@@ -325,14 +325,16 @@ mls_status mls_fast_tables(mls_ctx *ctx, float *dst, int64_t *count, int32_t *ro
  *   force    F = (V_b - U) / dt, the direct forcing of Sec. 2 (V_b = 0 if NULL);
  *   spread   f += c_l phi F (eq. 7-8);
  * and then increments the context's device step counter, which the jitter
- * of the next step reads.  With MLS_EXACT the step works in spreading-tile
- * order: markers are binned by the tile of their cell, the build,
- * interpolation and forcing run as one kernel (phi is not read back), and row
- * p of the blocked home / phi / route layout holds marker order[p] (see
- * mls_step_order), so that the tiles read their rows contiguously; U and F
- * stay indexed by marker.  Markers whose support leaves the grid come last.
- * The order of the markers inside a tile may differ between runs; U, F and
- * the forcing do not.  With the other methods rows are in marker order.  All buffers are caller-owned device arrays:
+ * of the next step reads.  With MLS_EXACT, and with fast-MLS on a grid whose
+ * axes are all uniform, the step works in spreading-tile order: markers are
+ * binned by the tile of their cell (the jitter runs inside that pass, with
+ * the same generator), the build, interpolation and forcing run as one kernel
+ * (phi is not read back), and row p of the blocked home / phi / route layout
+ * holds marker order[p] (see mls_step_order), so that the tiles read their
+ * rows contiguously; U and F stay indexed by marker.  Markers whose support
+ * leaves the grid come last.  The order of the markers inside a tile may
+ * differ between runs; U, F and the forcing do not.  With the other methods
+ * (and fast-MLS on a stretched grid) rows are in marker order.  All buffers are caller-owned device arrays:
  * x0,y0,z0 [n] (read), x,y,z [n] (written by jitter), area [n], vb [3][n] or
  * NULL, home, phi and route (or NULL) in the blocked layout above, U [3][n], F [3][n],
  * the velocity fields u,v,w and the forcing fields fx,fy,fz.
@@ -398,7 +400,11 @@ void mls_graph_destroy(mls_graph *graph);
 /* ---- per-kernel timing (HIP events on the launch stream) -----------------
  * When enabled, the library records a HIP event pair around each launch of
  * the kernels below (not inside a graph capture); mls_timing_get
- * synchronises and returns the summed milliseconds and launch counts. */
+ * synchronises and returns the summed milliseconds and launch counts.  In a
+ * step in spreading-tile order, MLS_K_SPREAD_BIN covers the binning (with
+ * the jitter inside it) and MLS_K_BUILD_INTERP the fused build with, for
+ * compact rows, the pass that finishes the rows solved in FP64; MLS_K_JITTER
+ * then records nothing. */
 enum {
     MLS_K_BUILD_EXACT = 0, MLS_K_BUILD_FAST = 1, MLS_K_BUILD_LEARNED = 2, MLS_K_INTERP = 3,
     MLS_K_SPREAD_BIN = 4, MLS_K_SPREAD_TILES = 5, MLS_K_JITTER = 6, MLS_K_FORCE = 7,

@@ -169,16 +169,14 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
         st_stream(hout, ok ? pack_home(G[0].ih, G[1].ih, G[2].ih) : 0xffffffffu);
         // the 27 field values are requested before the solve, which hides
         // their latency
-        int64_t ox[3], oy[3], oz[3];
+        int64_t oy[3], oz[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            ox[a] = ok ? nb_index(G[0].ih, a - 1, nxc, g.ax[0].periodic) : 0;
             oy[a] = ok ? (int64_t)nb_index(G[1].ih, a - 1, nyc, g.ax[1].periodic) * nxc : 0;
             oz[a] = ok ? (int64_t)nb_index(G[2].ih, a - 1, nzc, g.ax[2].periodic) * nxc * nyc : 0;
         }
         float qv[kNe];
-#pragma unroll
-        for (int k = 0; k < kNe; ++k) qv[k] = q[oz[k / 9] + oy[(k / 3) % 3] + ox[k % 3]];
+        load_support(q, ok ? G[0].ih : 1, nxc, oy, oz, qv);
         const float vbv = vb ? vb[c * n + m] : 0.0f;
         float ph[kNe];
         float gam[4] = {0.f, 0.f, 0.f, 0.f};
@@ -542,16 +540,14 @@ k_fast_interp(const Grid *__restrict__ gp, const float4 *__restrict__ tab, int n
         ok = ok && axis_geo(g.ax[2], c == 2, pz, G[2]);
         if (!ok) neutral_geo(G);
         st_stream(hout, ok ? pack_home(G[0].ih, G[1].ih, G[2].ih) : 0xffffffffu);
-        int64_t ox[3], oy[3], oz[3];
+        int64_t oy[3], oz[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            ox[a] = ok ? nb_index(G[0].ih, a - 1, nxc, g.ax[0].periodic) : 0;
             oy[a] = ok ? (int64_t)nb_index(G[1].ih, a - 1, nyc, g.ax[1].periodic) * nxc : 0;
             oz[a] = ok ? (int64_t)nb_index(G[2].ih, a - 1, nzc, g.ax[2].periodic) * nxc * nyc : 0;
         }
         float qv[kNe];
-#pragma unroll
-        for (int k = 0; k < kNe; ++k) qv[k] = q[oz[k / 9] + oy[(k / 3) % 3] + ox[k % 3]];
+        load_support(q, ok ? G[0].ih : 1, nxc, oy, oz, qv);
         const float vbv = vb ? vb[c * n + m] : 0.0f;
         // the sub-cell and the blend weights in the true frame, as the
         // whole-table lookup computes them (so a marker on a sub-cell face

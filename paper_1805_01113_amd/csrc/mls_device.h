@@ -491,4 +491,42 @@ __device__ __forceinline__ int nb_index(int i, int a, int n, int periodic)
     return j;
 }
 
+// The 27 values of field q on the support of a home node: x index i on rows
+// of length nx >= 3, the rows of the y and z neighbours at offsets
+// oy[b] + oz[cz], in the node order k = a + 3 b + 9 cz.  The three
+// x-neighbours of a row arrive in one 12-byte load from the window
+// i - 1 .. i + 1 clamped into the row: a third of the memory instructions of
+// one load per value, which matters because the vector L1 serves each
+// instruction cache line by cache line.  A stencil that wraps round a
+// periodic axis (i = 0 or nx - 1) then holds two of its values in the window
+// and needs the far end of the row; in a wavefront with such a lane every
+// lane loads that one extra value per row and the wrapping lanes rotate
+// their window.  The fix-up sits after the window loads, so the common path
+// keeps the loaded values in place and the solve that follows hides their
+// latency.  The values are those of one load per node.  A lane without a
+// support passes i = 1 and row offsets 0.
+__device__ __forceinline__ void load_support(const float *__restrict__ q, int i, int nx, const int64_t oy[3],
+                                             const int64_t oz[3], float qv[kNe])
+{
+    const int64_t sx = min(max(i - 1, 0), nx - 3);
+    struct Row3 { float v[3]; };
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        Row3 t;
+        __builtin_memcpy(&t, q + oz[r / 3] + oy[r % 3] + sx, sizeof t);
+        qv[3 * r] = t.v[0]; qv[3 * r + 1] = t.v[1]; qv[3 * r + 2] = t.v[2];
+    }
+    const bool lo = i < 1, hi = i > nx - 2;   // only on a periodic axis
+    if (__any(lo || hi)) {
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            const float e = q[oz[r / 3] + oy[r % 3] + (lo ? nx - 1 : 0)];
+            const float a0 = qv[3 * r], a1 = qv[3 * r + 1], a2 = qv[3 * r + 2];
+            qv[3 * r] = lo ? e : (hi ? a1 : a0);
+            qv[3 * r + 1] = lo ? a0 : (hi ? a2 : a1);
+            qv[3 * r + 2] = lo ? a1 : (hi ? e : a2);
+        }
+    }
+}
+
 }  // namespace mls

@@ -43,20 +43,18 @@ k_interp(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ ho
                 out[l] = __builtin_nanf("");
                 continue;
             }
-            int64_t ox[3], oy[3], oz[3];
+            int64_t oy[3], oz[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                ox[a] = nb_index(i, a - 1, g.dims[c][0], g.ax[0].periodic);
                 oy[a] = (int64_t)nb_index(j, a - 1, g.dims[c][1], g.ax[1].periodic) * g.dims[c][0];
                 oz[a] = (int64_t)nb_index(k, a - 1, g.dims[c][2], g.ax[2].periodic) * g.dims[c][0] * g.dims[c][1];
             }
+            float qv[kNe];
+            load_support(q, i, g.dims[c][0], oy, oz, qv);
             const float *p = phi + phi_at(l, c);
             float acc = 0.f;
 #pragma unroll
-            for (int kk = 0; kk < kNe; ++kk) {
-                const int a = kk % 3, b = (kk / 3) % 3, cz = kk / 9;
-                acc += p[kk * kLanes] * q[oz[cz] + oy[b] + ox[a]];
-            }
+            for (int kk = 0; kk < kNe; ++kk) acc += p[kk * kLanes] * qv[kk];
             out[l] = acc;
         }
     }

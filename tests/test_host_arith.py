@@ -31,3 +31,23 @@ def test_box_coordinates_from_fp32_reciprocals_are_exact():
             assert np.array_equal(lz, q // (bx * by))
             assert np.array_equal(ly, (q // bx) % by)
             assert np.array_equal(lx, q % bx)
+
+
+def test_support_window_and_wrap_rotation_give_the_wrapped_neighbours():
+    """The interpolation loads the three x-neighbours of a row from the window
+    i-1 .. i+1 clamped into the row, and a stencil that wraps round a periodic
+    row (i = 0 or n-1) takes one extra value from the far end and rotates.
+    Every row length 3 <= n <= 300 and home index 0 <= i < n gives the wrapped
+    neighbours (i-1, i, i+1) mod n."""
+    for n in range(3, 301):
+        row = np.arange(n) * 7 + 1000          # distinct values
+        for i in range(n):
+            sx = min(max(i - 1, 0), n - 3)
+            a0, a1, a2 = row[sx], row[sx + 1], row[sx + 2]
+            lo, hi = i < 1, i > n - 2
+            e = row[n - 1 if lo else 0]
+            got = (e if lo else (a1 if hi else a0),
+                   a0 if lo else (a2 if hi else a1),
+                   a1 if lo else (e if hi else a2))
+            want = tuple(row[(i + d) % n] for d in (-1, 0, 1))
+            assert got == want, (n, i)

@@ -296,21 +296,24 @@ k_interp_grad(const Grid *__restrict__ gp, Weight Wt, float tau, int64_t n, cons
                 continue;
             }
             const int nx = comp_dim(g, c, 0), ny = comp_dim(g, c, 1), nz = comp_dim(g, c, 2);
-            int64_t ox[3], oy[3], oz[3];
+            int64_t oy[3], oz[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                ox[a] = nb_index(ih[0], a - 1, nx, g.ax[0].periodic);
                 oy[a] = (int64_t)nb_index(ih[1], a - 1, ny, g.ax[1].periodic) * nx;
                 oz[a] = (int64_t)nb_index(ih[2], a - 1, nz, g.ax[2].periodic) * nx * ny;
             }
+            // the 27 field values are requested before the solve, which hides
+            // their latency
+            float qv[kNe];
+            load_support(fq, ih[0], nx, oy, oz, qv);
             float acc = 0.f, ga[3] = {0.f, 0.f, 0.f};
             if (grad_coef(Wt, tau, q, kmax)) {
                 // sum_k dphi_dk = 0, so the gradient is summed over q_k - q_home:
                 // the terms are O(h |grad q|) instead of O(|q|), which spares
                 // FP32 the cancellation of an O(|q|/h) sum down to O(|grad q|)
-                const float fh = fq[oz[1] + oy[1] + ox[1]];
+                const float fh = qv[13];
                 for_each_node<false>(q, Wt, [&](int a, int b, int cz, float ph, const float dv[3]) {
-                    const float fv = fq[oz[cz] + oy[b] + ox[a]];
+                    const float fv = qv[a + 3 * b + 9 * cz];
                     const float df = fv - fh;
                     acc += ph * fv;
                     ga[0] += dv[0] * df; ga[1] += dv[1] * df; ga[2] += dv[2] * df;

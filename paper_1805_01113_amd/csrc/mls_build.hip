@@ -175,8 +175,8 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
             oy[a] = ok ? (int64_t)nb_index(G[1].ih, a - 1, nyc, g.ax[1].periodic) * nxc : 0;
             oz[a] = ok ? (int64_t)nb_index(G[2].ih, a - 1, nzc, g.ax[2].periodic) * nxc * nyc : 0;
         }
-        float qv[kNe];
-        load_support(q, ok ? G[0].ih : 1, nxc, oy, oz, qv);
+        Support sp;
+        load_support(q, ok ? G[0].ih : 1, nxc, oy, oz, sp);
         const float vbv = vb ? vb[c * n + m] : 0.0f;
         float ph[kNe];
         float gam[4] = {0.f, 0.f, 0.f, 0.f};
@@ -220,7 +220,7 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
         }
         float acc = 0.f;
 #pragma unroll
-        for (int k = 0; k < kNe; ++k) acc += ph[k] * qv[k];
+        for (int k = 0; k < kNe; ++k) acc += ph[k] * sp.at(k);
         const float f = (vbv - acc) * inv_dt;
         st_stream(&U[c * n + m], ok ? acc : nan);
         st_stream(&F[c * n + m], ok ? f : nan);

@@ -491,20 +491,64 @@ __device__ __forceinline__ int nb_index(int i, int a, int n, int periodic)
     return j;
 }
 
-// The 27 values of field q on the support of a home node: x index i on rows
-// of length nx >= 3, the rows of the y and z neighbours at offsets
-// oy[b] + oz[cz], in the node order k = a + 3 b + 9 cz.  The three
-// x-neighbours of a row arrive in one 12-byte load from the window
-// i - 1 .. i + 1 clamped into the row: a third of the memory instructions of
-// one load per value, which matters because the vector L1 serves each
-// instruction cache line by cache line.  A stencil that wraps round a
-// periodic axis (i = 0 or nx - 1) then holds two of its values in the window
-// and needs the far end of the row; in a wavefront with such a lane every
-// lane loads that one extra value per row and the wrapping lanes rotate
-// their window.  The fix-up sits after the window loads, so the common path
-// keeps the loaded values in place and the solve that follows hides their
-// latency.  The values are those of one load per node.  A lane without a
-// support passes i = 1 and row offsets 0.
+// The 27 values of a field on the support of a home node, as loaded by
+// load_support: v holds the window of each row, e the far end of the row for
+// a stencil that wraps round a periodic x axis.  at(k) is the value of node
+// k = a + 3 b + 9 cz.
+struct Support {
+    float v[kNe];
+    float e[9];
+    bool lo, hi;   // the stencil wraps below node 0 / above node nx - 1
+    __device__ __forceinline__ float at(int k) const
+    {
+        const int r = k / 3, a = k % 3;
+        if (a == 0) return lo ? e[r] : (hi ? v[3 * r + 1] : v[3 * r]);
+        if (a == 1) return lo ? v[3 * r] : (hi ? v[3 * r + 2] : v[3 * r + 1]);
+        return lo ? v[3 * r + 1] : (hi ? e[r] : v[3 * r + 2]);
+    }
+};
+
+// Loads the support values of field q around home node (i, ., .): x index i
+// on rows of length nx >= 3, the rows of the y and z neighbours at offsets
+// oy[b] + oz[cz].  The three x-neighbours of a row arrive in one 12-byte load
+// from the window i - 1 .. i + 1 clamped into the row: a third of the memory
+// instructions of one load per value, which matters because the vector L1
+// serves each instruction cache line by cache line.  A stencil that wraps
+// round a periodic axis (i = 0 or nx - 1) holds two of its values in the
+// window and needs the far end of the row: in a wavefront with such a lane,
+// every lane loads that one extra value per row (elsewhere e stays 0), and
+// Support::at picks each node's value by selects where it is used.  The
+// window registers are never rewritten, so the common path does not wait for
+// the loads before the solve that follows them.  The values are those of one
+// load per node.  A lane without a support passes i = 1 and row offsets 0.
+__device__ __forceinline__ void load_support(const float *__restrict__ q, int i, int nx, const int64_t oy[3],
+                                             const int64_t oz[3], Support &sp)
+{
+    const int64_t sx = min(max(i - 1, 0), nx - 3);
+    struct Row3 { float v[3]; };
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        Row3 t;
+        __builtin_memcpy(&t, q + oz[r / 3] + oy[r % 3] + sx, sizeof t);
+        sp.v[3 * r] = t.v[0]; sp.v[3 * r + 1] = t.v[1]; sp.v[3 * r + 2] = t.v[2];
+    }
+    sp.lo = i < 1;
+    sp.hi = i > nx - 2;   // both only on a periodic axis
+#pragma unroll
+    for (int r = 0; r < 9; ++r) sp.e[r] = 0.f;
+    if (__any(sp.lo || sp.hi)) {
+#pragma unroll
+        for (int r = 0; r < 9; ++r) sp.e[r] = q[oz[r / 3] + oy[r % 3] + (sp.lo ? nx - 1 : 0)];
+    }
+}
+
+// The same values in a plain array, the wrapping lanes' windows rotated in
+// place by the fix-up.  The compiler then moves the window values into the
+// fix-up's registers on the common path and waits for the loads there, which
+// costs the latency that Support hides, but the array needs 9 registers fewer
+// than Support.  The fused fast-MLS kernel, at its limit of 128 registers, and
+// the velocity-gradient kernel, which uses the values inside its node visitor,
+// are faster this way.
 __device__ __forceinline__ void load_support(const float *__restrict__ q, int i, int nx, const int64_t oy[3],
                                              const int64_t oz[3], float qv[kNe])
 {

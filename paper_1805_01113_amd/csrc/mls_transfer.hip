@@ -49,12 +49,12 @@ k_interp(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ ho
                 oy[a] = (int64_t)nb_index(j, a - 1, g.dims[c][1], g.ax[1].periodic) * g.dims[c][0];
                 oz[a] = (int64_t)nb_index(k, a - 1, g.dims[c][2], g.ax[2].periodic) * g.dims[c][0] * g.dims[c][1];
             }
-            float qv[kNe];
-            load_support(q, i, g.dims[c][0], oy, oz, qv);
+            Support sp;
+            load_support(q, i, g.dims[c][0], oy, oz, sp);
             const float *p = phi + phi_at(l, c);
             float acc = 0.f;
 #pragma unroll
-            for (int kk = 0; kk < kNe; ++kk) acc += p[kk * kLanes] * qv[kk];
+            for (int kk = 0; kk < kNe; ++kk) acc += p[kk * kLanes] * sp.at(kk);
             out[l] = acc;
         }
     }

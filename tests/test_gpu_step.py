@@ -258,6 +258,54 @@ def _compact_vs_full(torch, mls, wl, amp, label, **ctx_kw):
     return ctx, bufs, phi_full
 
 
+@pytest.mark.parametrize("method,blend,compact", [(0, None, True), (0, None, False), (1, 0, False), (3, 1, False)])
+def test_step_kernels_at_the_periodic_x_edges(orc, method, blend, compact):
+    """Stencils that wrap round the periodic x axis take their support values
+    from a second load at the far end of the row: half of the markers lie in
+    the first or last cell along x of a periodic 32^3 grid, the rest anywhere,
+    so that wavefronts hold wrapping and non-wrapping lanes.  U and the forcing
+    of the fused step kernels (exact full and compact rows, fast-MLS with both
+    blends) against the oracle on the same positions."""
+    import torch
+    from paper_1805_01113_amd import mls
+    ng = 32
+    gs = W.GridSpec([W.uniform_faces(ng)] * 3, [True] * 3)
+    r = np.random.default_rng(41 + method)
+    n = 2111
+    x = r.uniform(0.0, 1.0, n)
+    edge = np.nonzero(r.random(n) < 0.5)[0]
+    low = r.random(len(edge)) < 0.5
+    x[edge] = np.where(low, r.uniform(0.0, 1.0 / ng, len(edge)), r.uniform(1.0 - 1.0 / ng, 1.0, len(edge)))
+    x = x.astype(np.float32)
+    y, z = [r.uniform(0.0, 1.0, n).astype(np.float32) for _ in range(2)]
+    area = (r.uniform(0.2, 1.0, n) / ng ** 2).astype(np.float32)
+    fields_h = [r.normal(size=gs.shape(c)).astype(np.float32) for c in range(3)]
+    fields = [to_dev(f) for f in fields_h]
+    forcing = [torch.zeros(gs.shape(c), device="cuda") for c in range(3)]
+    ctx = mls.Context(gs.faces, gs.periodic)
+    bufs = mls.StepBuffers(ctx, to_dev(x), to_dev(y), to_dev(z), to_dev(area), fields, forcing)
+    mls.timing_enable(ctx, True)
+    mls.step(ctx, bufs, method=method, dt=1.0, jitter=0.0, seed=1, compact=compact)
+    ctx.sync()
+    kt = mls.timing_get(ctx, reset=True)
+    assert ("build_interp" if method == 0 else "fast_interp") in kt, kt
+    xj = [x, y, z]   # without jitter the step builds from x0
+    g = orc.Grid(gs.faces, gs.periodic)
+    Ug = bufs.U.cpu().numpy()
+    eu, ef = [], []
+    for c in range(3):
+        ref = orc.build_exact(g, c, *xj) if method == 0 else orc.build_fast(g, c, *xj, blend=blend)
+        hx = ref["home"][:, 0]
+        assert np.any(hx == 0) and np.any(hx == gs.shape(c)[2] - 1), "no stencil wraps along x"
+        Uo = orc.interp(g, c, ref["home"], ref["phi"], fields_h[c])
+        eu.append(normwise(Ug[c], Uo))
+        fo, _ = orc.spread(g, c, ref["home"], ref["phi"], area, (-Uo).astype(np.float32))
+        ef.append(normwise(bufs.forcing[c].cpu().numpy(), fo))
+    say("x-edge step (method %d, compact %s): U %s, forcing %s" %
+        (method, compact, ["%.1e" % e for e in eu], ["%.1e" % e for e in ef]))
+    assert max(eu) <= U_TOL and max(ef) <= F_TOL
+
+
 def test_compact_step_equals_full_step_uniform(orc):
     """Uniform grid (rows of 7 floats): U, F and the forcing of a compact exact
     step equal the default step's bit for bit, and match the oracle."""

@@ -47,16 +47,18 @@ def source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, step):
     """HBM bytes per launch of `kernel` from the rocprofv3 counter summary in
     profiles/ (FETCH_SIZE and WRITE_SIZE scaled by the factors a plain device
-    copy reads for them), or None if there is none for the current sources."""
+    copy reads for them), or None if there is none for the current sources,
+    this workload and this step (method and transfer-function form: the same
+    timing label covers different kernels in other steps)."""
     path = os.path.join(ROOT, "profiles", "counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("source_sha256") != source_hash() or d.get("workload") != workload:
+    if d.get("source_sha256") != source_hash() or d.get("workload") != workload or d.get("step") != step:
         return None
     k = d.get("kernels", {}).get(kernel)
     return None if k is None else int(k["traffic_bytes_per_launch"])
@@ -412,6 +414,8 @@ def main():
     # offsets) unless --full-phi: the same U, F and forcing, fewer bytes
     compact = method == mls.MLS_EXACT and not args.full_phi
     nf = 7 if all(wl.grid.uniform_axis(d) for d in range(3)) else 13
+    step_cfg = {"method": args.method,
+                "transfer_function": ("compact, %d floats per row" % nf) if compact else "27 floats per row"}
     tune = None
     if not args.no_tune:
         t_a = time.time()
@@ -484,7 +488,7 @@ def main():
     step_bytes = sum(alg.get(k, 0.0) for k in kernels) * n
     log("eager: %.3f ms/step; kernels: %s" % (ms_eager, json.dumps(kernels)))
     roof = {"bound": "hbm", "kernel": dom[0], "achieved": dom[1]["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(dom[1]["GBs"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom[0], wl.name),
+            "frac": round(dom[1]["GBs"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom[0], wl.name, step_cfg),
             "alg_bytes_per_marker": round(alg[dom[0]], 1), "markers_per_launch": n}
 
     extra = {"ms_per_step_eager": round(ms_eager, 4), "kernels": kernels, "autotune": tune,
@@ -526,7 +530,7 @@ def main():
         "config": {"workload": wl.name, "markers": n, "bodies": int(len(wl.body_offsets) - 1),
                    "grid": list(wl.grid.n), "method": args.method, "execution": "hipgraph_batched",
                    "step": "jitter+build+interp+force+spread",
-                   "transfer_function": ("compact, %d floats per row" % nf) if compact else "27 floats per row"},
+                   "transfer_function": step_cfg["transfer_function"]},
         "roofline": roof,
         "cpu_baseline": cpu,
         "extra": extra,

@@ -35,16 +35,8 @@ def log(*a):
 def source_hash():
     """SHA-256 over the HIP sources and headers of the library (the counter
     summaries under profiles/ name the sources they were measured on)."""
-    import glob
-    import hashlib
-    h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1805_01113_amd", "csrc", "*"))) + \
-        [os.path.join(ROOT, "include", "mls.h")]
-    for f in files:
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+    from paper_1805_01113_amd import build
+    return build.source_sha256()
 
 
 def measured_traffic(kernel, workload, step):
@@ -384,6 +376,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     mls.load()
+    lib_version = mls.version()
+    if not lib_version.endswith(source_hash()):
+        log("warning: libmls_hip.so was not built from the current sources (%s)" % lib_version)
     t0 = time.time()
     wl = make_workload(args.workload)
     log("workload %s: %d markers, %d bodies, generated in %.1fs" % (wl.name, wl.n, len(wl.body_offsets) - 1,
@@ -491,7 +486,7 @@ def main():
             "frac": round(dom[1]["GBs"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom[0], wl.name, step_cfg),
             "alg_bytes_per_marker": round(alg[dom[0]], 1), "markers_per_launch": n}
 
-    extra = {"ms_per_step_eager": round(ms_eager, 4), "kernels": kernels, "autotune": tune,
+    extra = {"library": lib_version, "ms_per_step_eager": round(ms_eager, 4), "kernels": kernels, "autotune": tune,
              "touched_nodes_per_marker": round(t_per, 3),
              "step_alg_bytes_per_marker": round(step_bytes / n, 1),
              "step_hbm_frac": round(step_bytes / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}

@@ -124,7 +124,10 @@ typedef struct {
     int64_t spread_tiles;    /* tiles of the forcing grid */
 } mls_stats;
 
-/* Library version string. */
+/* Library version string: "mls_hip <version> (gfx950) src <sha256>", the
+   last field the SHA-256 of the HIP sources and this header the library was
+   compiled from ("unstamped" for a build outside the package's build step).
+   Static storage; never NULL. */
 const char *mls_version(void);
 
 /* Create a context on the current HIP device for one grid, weight and
@@ -229,7 +232,7 @@ mls_status mls_interp_grad(mls_ctx *ctx, int64_t n, const float *x, const float 
                            const float *u, const float *v, const float *w, float *U, float *G, const float *p,
                            float *P, float *GP, void *stream);
 
-/* Coarse-grained collision detection (Sec. 5, the integer cell array of its
+/* Coarse-grained collision detection (Sec. 4, the integer cell array of its
  * detection algorithm).  coll is a device int32 array with one entry per
  * Eulerian cell, C order [z][y][x] over the n_z x n_y x n_x cells of the
  * context's grid (cells, not velocity nodes), holding only zeros on entry (a
@@ -255,7 +258,7 @@ mls_status mls_collide(mls_ctx *ctx, int64_t n, const float *x, const float *y, 
 mls_status mls_collide_clear(mls_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
                              int32_t *coll, void *stream);
 
-/* Adaptive Lagrangian mesh refinement (Sec. 4, Fig. 4, Table 1): markers
+/* Adaptive Lagrangian mesh refinement (Sec. 3, Fig. 5, Table 1): markers
  * for the interfacial condition generated from a base triangle mesh.
  * tri (device int32 [ntri][3]) indexes the nvert vertices xv, yv, zv
  * (device FP32).  Base triangle V1 V2 V3 gets a level L in 0..3 and L + 1

@@ -785,7 +785,7 @@ int orc_axis_nodes(const double *faces, const int32_t *n, const int32_t *periodi
 }
 
 /* ------------------------------------------------------------------------ */
-/* Coarse-grained collision detection (Sec. 5, the integer cell array coll). */
+/* Coarse-grained collision detection (Sec. 4, the integer cell array coll). */
 /* ------------------------------------------------------------------------ */
 /* The cell of a marker is the Eulerian cell that contains it: along each
  * axis the i with f[i] <= X < f[i+1], X being the wrapped coordinate on a
@@ -851,7 +851,7 @@ int orc_collide(const double *faces, const int32_t *n, const int32_t *periodic,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Adaptive Lagrangian mesh refinement (Sec. 4, Fig. 4, Table 1).            */
+/* Adaptive Lagrangian mesh refinement (Sec. 3, Fig. 5, Table 1).            */
 /* ------------------------------------------------------------------------ */
 /* A base triangle V1 V2 V3 carries one marker at its centroid
  * C = (V1 + V2 + V3)/3 (level 0).  The three refinement levels split it into

@@ -262,7 +262,7 @@ def spread(grid: Grid, comp, home, phi, area, F, f=None):
 
 
 def collide(grid: Grid, x, y, z, body, check=True):
-    """Coarse-grained collision detection (Sec. 5): returns dict(coll
+    """Coarse-grained collision detection (Sec. 4): returns dict(coll
     [nz, ny, nx] int32 with 0 = empty cell, b + 1 = markers of body b only,
     -1 = markers of several bodies; flag [N] uint8 = 1 where the marker's
     cell holds -1; cell [N] linear cell index)."""
@@ -283,7 +283,7 @@ def collide(grid: Grid, x, y, z, body, check=True):
 
 
 def refine(grid: Grid, tri, xv, yv, zv, ratio=1.0, level=-1, check=True):
-    """Adaptive Lagrangian mesh refinement (Sec. 4): returns dict(x, y, z,
+    """Adaptive Lagrangian mesh refinement (Sec. 3): returns dict(x, y, z,
     area [M] FP64, normal [M, 3], parent [M] int32, level [T] uint8, count)
     for the base triangles tri [T, 3] over FP32 vertices; level -1 chooses
     each triangle's level from its size against the local cell size."""

@@ -197,7 +197,12 @@ mls_status reserve_compact(mls_ctx *ctx, int64_t n)
 
 extern "C" {
 
-const char *mls_version(void) { return "mls_hip 0.1.0 (gfx950)"; }
+#ifndef MLS_SOURCE_SHA256
+#define MLS_SOURCE_SHA256 "unstamped"
+#endif
+// The build stamps the SHA-256 of the sources it compiled (csrc/ and
+// include/mls.h), so a loaded library names them.
+const char *mls_version(void) { return "mls_hip 0.2.0 (gfx950) src " MLS_SOURCE_SHA256; }
 
 mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight *weight, const mls_opts *opts)
 {

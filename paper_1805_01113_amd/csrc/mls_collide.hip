@@ -1,4 +1,4 @@
-// Coarse-grained collision detection (Sec. 5): an integer array over the
+// Coarse-grained collision detection (Sec. 4): an integer array over the
 // Eulerian cells records, per cell, whether no marker, the markers of one
 // body, or markers of several bodies lie in it; markers in a cell of the last
 // kind are flagged for a collision force.

@@ -1,4 +1,4 @@
-// Adaptive Lagrangian mesh refinement (Sec. 4, Fig. 4): markers for the
+// Adaptive Lagrangian mesh refinement (Sec. 3, Fig. 5): markers for the
 // interfacial condition generated on the fly from a base triangle mesh.
 //
 // A base triangle V1 V2 V3 carries one marker at its centroid C (level 0).

@@ -278,7 +278,7 @@ class Context:
         return tuple(int(v) for v in self.n[::-1])
 
     def collide(self, x, y, z, body, coll, flags=None, stream=None):
-        """Coarse-grained collision detection (Sec. 5): enters the markers'
+        """Coarse-grained collision detection (Sec. 4): enters the markers'
         body ids into the zeroed int32 cell array coll (0 empty, body + 1 one
         body, -1 several bodies) and, if given, sets flags [n] uint8 to 1 for
         markers in a cell holding -1."""
@@ -344,7 +344,7 @@ class Context:
         return dict(U=U, G=G, P=P, GP=GP)
 
     def refine(self, tri, xv, yv, zv, ratio=1.0, level=-1, stream=None, sync=True):
-        """Adaptive Lagrangian mesh refinement (Sec. 4): markers of the base
+        """Adaptive Lagrangian mesh refinement (Sec. 3): markers of the base
         triangles tri [T, 3] (int32) over vertices xv, yv, zv.  Returns a dict
         of device tensors x, y, z, area [M], normal [3, M], parent [M],
         level [T] and the marker count M (syncs the stream to read it)."""
@@ -618,6 +618,12 @@ def timing_get(ctx: "Context", reset=True):
     t = _Timing()
     ctx._raise(ctx._lib.mls_timing_get(ctx.h, ctypes.byref(t), 1 if reset else 0), "mls_timing_get")
     return {K_NAMES[i]: (t.ms[i], t.launches[i]) for i in range(len(K_NAMES)) if t.launches[i] > 0}
+
+
+def version() -> str:
+    """mls_version(): library version and the SHA-256 of the sources it was
+    compiled from."""
+    return load().mls_version().decode()
 
 
 def npad(n: int) -> int:

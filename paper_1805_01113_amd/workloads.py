@@ -400,7 +400,7 @@ def uneven_bodies(n_bodies: int = 10000, n: int = 1024, n_modes: int = 16, cfg_i
 
 def contact_pairs(n_pairs: int = 5000, n: int = 1024, n_modes: int = 16, cfg_id: int = 6,
                   subdivs=(2, 3, 4), radii_h=(2.72, 5.31, 10.6), gap_h=(-1.5, 0.5)):
-    """Bodies in contact, for the collision detection of Sec. 5: n_pairs pairs
+    """Bodies in contact, for the collision detection of Sec. 4: n_pairs pairs
     of spheres (subdivision and radius drawn as in uneven_bodies, l/h ~ 0.8)
     whose surfaces are a gap U(gap_h) h apart along a random direction (a
     negative gap overlaps), pairs placed without overlapping each other in a

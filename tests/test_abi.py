@@ -29,6 +29,16 @@ def test_library_exports_every_declared_symbol():
     assert b"gfx950" in lib.mls_version()
 
 
+def test_library_was_built_from_these_sources():
+    """mls_version() carries the SHA-256 of the sources the library was
+    compiled from; it must be that of csrc/ and include/mls.h as they are."""
+    from paper_1805_01113_amd import build, mls
+    lib = ctypes.CDLL(mls.LIB_PATH)
+    lib.mls_version.restype = ctypes.c_char_p
+    v = lib.mls_version().decode()
+    assert v.endswith("src " + build.source_sha256()), (v, build.source_sha256())
+
+
 def test_null_arguments_are_rejected_on_the_host():
     """Host-side argument checks return MLS_E_ARG before touching a device."""
     from paper_1805_01113_amd import mls

@@ -1,4 +1,4 @@
-"""GPU parity of coarse-grained collision detection (Sec. 5) against the
+"""GPU parity of coarse-grained collision detection (Sec. 4) against the
 oracle: the cell array and the marker flags must match bit for bit."""
 import numpy as np
 import pytest

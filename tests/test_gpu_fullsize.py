@@ -1,5 +1,8 @@
 """GPU parity at the full workload sizes, in the configuration bench.py
-times: the autotuned launch shapes and one replay of the captured step.
+times: the autotuned launch shapes and one replay of the captured step.  The
+exact step is checked in both forms: with compact transfer functions (gamma
+and the support offsets per row, the form bench.py times, with the launch
+shapes the autotuner picks for it) and with the 27-value rows.
 
 The FP64 oracle cannot process 22.66 M markers in a test, so it checks
 samples it can compute one by one:
@@ -42,7 +45,7 @@ def _cells(faces, periodic, x):
     return np.clip(np.searchsorted(f, xx, side="right") - 1, 0, len(f) - 2)
 
 
-def _run_step(torch, wl, method, cache, counter=11):
+def _run_step(torch, wl, method, cache, counter=11, compact=False):
     from paper_1805_01113_amd import mls, train_mlp
     ctx = mls.Context(wl.grid.faces, wl.grid.periodic)
     ctx.reserve(wl.n)
@@ -53,17 +56,17 @@ def _run_step(torch, wl, method, cache, counter=11):
     fields = wl.fields("cuda")
     forcing = [torch.zeros(wl.grid.shape(c), dtype=torch.float32, device="cuda") for c in range(3)]
     bufs = mls.StepBuffers(ctx, x0, y0, z0, area, fields, forcing)
-    tune = ctx.autotune(bufs, method=method, cache_path=cache)
+    tune = ctx.autotune(bufs, method=method, cache_path=cache, compact=compact)
     for f in forcing:
         f.zero_()
     amp = 0.1 * wl.grid.h_min
-    graph = mls.StepGraph(ctx, bufs, method=method, dt=1.0, jitter=amp, seed=20180503)
+    graph = mls.StepGraph(ctx, bufs, method=method, dt=1.0, jitter=amp, seed=20180503, compact=compact)
     mls.step_counter_set(ctx, counter)
     graph.launch(1)
     ctx.sync()
     graph.close()
-    say("%s: %d markers, shapes %s" % (wl.name, wl.n, {k: tune[k] for k in ("spread_tile", "spread_blocks_per_cu",
-                                                                         "build_blocks_per_cu")}))
+    say("%s: %d markers, compact %s, shapes %s" % (wl.name, wl.n, compact, {
+        k: tune[k] for k in ("spread_tile", "spread_blocks_per_cu", "build_blocks_per_cu", "spread_threads")}))
     return ctx, bufs, fields, forcing, amp, counter
 
 
@@ -135,13 +138,16 @@ def _check(orc, torch, wl, bufs, fields, forcing, amp, counter, u_tol, label, fo
         say(msg)
 
 
-def test_uneven_bodies_full_size_exact(orc, tmp_path):
+@pytest.mark.parametrize("compact", [True, False], ids=["compact", "full_rows"])
+def test_uneven_bodies_full_size_exact(orc, tmp_path, compact):
     import torch
     from paper_1805_01113_amd import mls
     from paper_1805_01113_amd import workloads as W
     wl = W.uneven_bodies()
-    ctx, bufs, fields, forcing, amp, counter = _run_step(torch, wl, mls.MLS_EXACT, str(tmp_path / "t.jsonl"))
-    _check(orc, torch, wl, bufs, fields, forcing, amp, counter, U_TOL, "uneven exact")
+    ctx, bufs, fields, forcing, amp, counter = _run_step(torch, wl, mls.MLS_EXACT, str(tmp_path / "t.jsonl"),
+                                                         compact=compact)
+    _check(orc, torch, wl, bufs, fields, forcing, amp, counter, U_TOL,
+           "uneven exact (%s)" % ("compact" if compact else "full rows"))
     ctx.close()
 
 
@@ -150,9 +156,12 @@ def test_stretched_channel_full_size_exact_and_learned(orc, tmp_path):
     from paper_1805_01113_amd import mls
     from paper_1805_01113_amd import workloads as W
     wl = W.stretched_channel()
-    for method, tol, label in ((mls.MLS_EXACT, U_TOL, "stretched exact"), (mls.MLS_LEARNED, 1e-4, "stretched learned")):
+    for method, tol, label, compact in ((mls.MLS_EXACT, U_TOL, "stretched exact (compact)", True),
+                                        (mls.MLS_EXACT, U_TOL, "stretched exact (full rows)", False),
+                                        (mls.MLS_LEARNED, 1e-4, "stretched learned", False)):
         # the learned method keeps network shape functions where the gate passes
-        ctx, bufs, fields, forcing, amp, counter = _run_step(torch, wl, method, str(tmp_path / "t.jsonl"))
+        ctx, bufs, fields, forcing, amp, counter = _run_step(torch, wl, method, str(tmp_path / "t.jsonl"),
+                                                             compact=compact)
         st = ctx.stats()
         if method == mls.MLS_LEARNED:
             say("learned: %d kept, %d fell back to exact" % (st["learned"], st["fallbacks"]))

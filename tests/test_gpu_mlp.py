@@ -18,7 +18,12 @@ from parity import normwise, say, to_dev
 pytestmark = pytest.mark.gpu
 
 FWD_TOL = 2e-4
-GRAD_TOL = 1e-3
+# split-BF16 products (hi*hi + hi*lo + lo*hi) err by about 2^-17 = 7.6e-6
+# relative each; the gradient blocks, sums of such products in FP32, measured
+# at most 1.1e-5 normwise.  1e-4 keeps a margin of ~10x over that and over
+# the per-product bound, so a regression of the GEMM or the GELU backward
+# towards plain BF16 (2^-9 = 2e-3) fails.
+GRAD_TOL = 1e-4
 FUSED_TOL = 2e-5
 
 

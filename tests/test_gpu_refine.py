@@ -1,4 +1,4 @@
-"""GPU parity of adaptive Lagrangian mesh refinement (Sec. 4) against the
+"""GPU parity of adaptive Lagrangian mesh refinement (Sec. 3) against the
 oracle: levels, marker counts and parent triangles bit for bit; positions,
 areas and normals within one FP32 rounding of the FP64 oracle (both evaluate
 the construction in FP64; the GPU rounds to FP32 once)."""

@@ -1,4 +1,4 @@
-"""Pins of the oracle's coarse-grained collision detection (Sec. 5).
+"""Pins of the oracle's coarse-grained collision detection (Sec. 4).
 
 The oracle follows the paper's two sweeps over the markers in marker order.
 These tests check it against what the section states independently of that

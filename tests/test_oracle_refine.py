@@ -1,8 +1,8 @@
-"""Pins of the oracle's adaptive Lagrangian mesh refinement (Sec. 4).
+"""Pins of the oracle's adaptive Lagrangian mesh refinement (Sec. 3).
 
 Against what the paper prints and what geometry fixes: the marker counts of
 Table 1 (multiplicities 2, 3, 4 of levels 1-3), the refined positions of a
-unit triangle worked out by hand from Fig. 4, conservation of area and of the
+unit triangle worked out by hand from Fig. 5, conservation of area and of the
 first moment of area by every split, sub-markers inside their triangle with
 the parent's normal, level 0 equal to the base markers of the workloads, and
 the level rule against closed forms on uniform and stretched grids."""
@@ -63,8 +63,8 @@ def test_table1_marker_counts():
         np.testing.assert_array_equal(np.bincount(r["parent"], minlength=base), np.full(base, mult))
 
 
-def test_fig4_unit_triangle():
-    rows = _rows("fig4_unit_triangle_refined.txt")
+def test_fig5_unit_triangle():
+    rows = _rows("fig5_unit_triangle_refined.txt")
     g = _grid()
     for level in range(4):
         exp = np.array([[xn / den, yn / den] for lv, xn, yn, den in rows if int(lv) == level])

@@ -48,9 +48,8 @@ int32_t comp_nodes(const Axis &a, int c, int d)
 // cells is one tile; a longer one is cut into equal tiles (the requested edge
 // if it divides the axis, else its largest divisor between 4 and
 // kMaxBoxTile; none -> MLS_E_ARG); a wall axis uses the requested edge.
-// Derives the LDS boxes, the tile colours and the per-tile smallest control
-// volume width, (re)allocates the per-tile scratch and uploads the grid.
-// On error the previous tiling is kept.
+// Derives the LDS boxes and the tile colours, (re)allocates the per-tile
+// scratch and uploads the grid.  On error the previous tiling is kept.
 mls_status mls::setup_tiles(Ctx &c, int want)
 {
     if (want < 4 || want > kMaxBoxTile) return MLS_E_ARG;
@@ -108,48 +107,29 @@ mls_status mls::setup_tiles(Ctx &c, int want)
                     base += colour_tiles[col];
                 }
     }
-    // smallest control-volume width within three nodes of each tile, per axis
-    std::vector<float> thmin;
-    size_t off[3];
-    for (int d = 0; d < 3; ++d) {
-        const Axis &a = g.ax[d];
-        off[d] = thmin.size();
-        for (int t = 0; t < g.ntile[d]; ++t) {
-            double m = std::numeric_limits<double>::infinity();
-            for (int i = t * a.tile - 3; i <= (t + 1) * a.tile + 3; ++i) {
-                int ic = i;
-                if (a.periodic) ic = ((i % a.n) + a.n) % a.n;
-                if (ic >= 0 && ic < (int)c.h_wc[d].size()) m = std::min(m, (double)c.h_wc[d][ic]);
-                if (ic >= 0 && ic < (int)c.h_wf[d].size()) m = std::min(m, (double)c.h_wf[d][ic]);
-            }
-            thmin.push_back((float)m);
-        }
-    }
-    // device scratch for the new tiling
-    // one extra bucket (index nt) collects markers without a valid support
-    // when the step bins markers from their positions
+    // device scratch for the new tiling; one extra bucket (index nt) collects
+    // markers without a valid support when the step bins markers from their
+    // positions
     const int64_t nb = (nt + 1 + 2047) / 2048;
-    float *th = nullptr;
-    uint32_t *tcount = nullptr, *toff = nullptr, *tcur = nullptr, *tact = nullptr, *bsum = nullptr;
-    bool ok = hipMalloc((void **)&th, thmin.size() * sizeof(float)) == hipSuccess &&
-              hipMalloc((void **)&tcount, (nt + 1) * sizeof(uint32_t)) == hipSuccess &&
+    uint32_t *tcount = nullptr, *toff = nullptr, *tcur = nullptr, *tact = nullptr, *bsum = nullptr,
+             *tmax = nullptr;
+    bool ok = hipMalloc((void **)&tcount, (nt + 1) * sizeof(uint32_t)) == hipSuccess &&
               hipMalloc((void **)&toff, (nt + 2) * sizeof(uint32_t)) == hipSuccess &&
               hipMalloc((void **)&tcur, (nt + 1) * sizeof(uint32_t)) == hipSuccess &&
               hipMalloc((void **)&tact, nt * sizeof(uint32_t)) == hipSuccess &&
-              hipMalloc((void **)&bsum, (nb + 1) * sizeof(uint32_t)) == hipSuccess;
-    ok = ok && hipMemcpy(th, thmin.data(), thmin.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
-    for (int d = 0; d < 3; ++d) g.ax[d].tile_hmin = th + off[d];
+              hipMalloc((void **)&bsum, (nb + 1) * sizeof(uint32_t)) == hipSuccess &&
+              hipMalloc((void **)&tmax, 3 * (nt + 1) * sizeof(uint32_t)) == hipSuccess;
     ok = ok && hipDeviceSynchronize() == hipSuccess &&
          hipMemcpy(c.d_grid, &g, sizeof(Grid), hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) {
-        hipFree(th); hipFree(tcount); hipFree(toff); hipFree(tcur); hipFree(tact); hipFree(bsum);
+        hipFree(tcount); hipFree(toff); hipFree(tcur); hipFree(tact); hipFree(bsum); hipFree(tmax);
         hipMemcpy(c.d_grid, &c.g, sizeof(Grid), hipMemcpyHostToDevice);
         return MLS_E_NOMEM;
     }
-    hipFree(c.tile_hmin_block); hipFree(c.tile_count); hipFree(c.tile_off); hipFree(c.tile_cursor);
-    hipFree(c.tile_active); hipFree(c.block_sums);
-    c.tile_hmin_block = th;
+    hipFree(c.tile_count); hipFree(c.tile_off); hipFree(c.tile_cursor);
+    hipFree(c.tile_active); hipFree(c.block_sums); hipFree(c.tile_fmax);
     c.tile_count = tcount; c.tile_off = toff; c.tile_cursor = tcur; c.tile_active = tact; c.block_sums = bsum;
+    c.tile_fmax = tmax;
     c.g = g;
     ++c.scratch_gen;
     for (int k = 0; k < 27; ++k) c.colour_tiles[k] = colour_tiles[k];
@@ -307,7 +287,9 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
     c.w.inv_eps = (float)(1.0 / W.eps);
     c.w.inv_eps_d = 1.0 / W.eps;
     c.w.cut_d = std::exp(-(W.radius / W.eps) * (W.radius / W.eps));
-    c.w.cut = (float)c.w.cut_d;
+    // the FP32 weight has one select-free form for every kind (see weight1)
+    c.w.cut = W.kind == MLS_W_GAUSS_SHIFTED ? (float)c.w.cut_d : 0.0f;
+    c.w.e2 = W.kind == MLS_W_CONST ? 0.0f : (float)(-1.4426950408889634 / (W.eps * W.eps));
     c.opts.kappa_tau = 1e6;
     c.opts.n_sub = 9;
     c.opts.fallback_tol = 1e-4;
@@ -366,10 +348,6 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
     hipMemset(c.stats, 0, sizeof(DevStats));
     hipMemset(c.work, 0, 128 * sizeof(uint32_t));
     hipMemset(c.step_ctr, 0, sizeof(unsigned long long));
-    if (hipMalloc((void **)&c.block_fmax, (size_t)3 * (c.cu_count * kMaxBlocksPerCu + kBuildGridMultiple) * sizeof(uint32_t)) != hipSuccess) {
-        mls_ctx_destroy(ctx);
-        return MLS_E_NOMEM;
-    }
     const mls_status ts = setup_tiles(c, want_tile);
     if (ts != MLS_OK) { mls_ctx_destroy(ctx); return ts; }
     if (hipDeviceSynchronize() != hipSuccess) { mls_ctx_destroy(ctx); return MLS_E_HIP; }
@@ -393,13 +371,12 @@ void mls_ctx_destroy(mls_ctx *ctx)
     hipFree(c.tile_cursor);
     hipFree(c.tile_active);
     hipFree(c.block_sums);
+    hipFree(c.tile_fmax);
     hipFree(c.entries);
-    hipFree(c.af_rows);
+    hipFree(c.cf_rows);
     hipFree(c.marker_tile);
     hipFree(c.coef_rows);
     hipFree(c.route_queue);
-    hipFree(c.block_fmax);
-    hipFree(c.tile_hmin_block);
     hipFree(c.refine_scratch);
     hipFree(c.grad_queue);
     hipFree(c.work);
@@ -418,26 +395,26 @@ mls_status mls_reserve(mls_ctx *ctx, int64_t n)
     hipDeviceSynchronize();
     ++c.scratch_gen;
     hipFree(c.entries);
-    hipFree(c.af_rows);
+    hipFree(c.cf_rows);
     hipFree(c.marker_tile);
     c.entries = nullptr;
-    c.af_rows = nullptr;
+    c.cf_rows = nullptr;
     c.marker_tile = nullptr;
     c.cap_markers = 0;
-    c.af_stride = 0;
+    c.cf_stride = 0;
     const int64_t stride = (n + 63) / 64 * 64;
     hipError_t e = hipMalloc((void **)&c.entries, (size_t)n * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMalloc((void **)&c.af_rows, (size_t)3 * stride * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&c.cf_rows, (size_t)3 * stride * sizeof(float));
     if (e == hipSuccess) e = hipMalloc((void **)&c.marker_tile, (size_t)n * sizeof(uint32_t));
     if (e != hipSuccess) {
         hipFree(c.entries);
-        hipFree(c.af_rows);
+        hipFree(c.cf_rows);
         c.entries = nullptr;
-        c.af_rows = nullptr;
+        c.cf_rows = nullptr;
         return hip_fail(ctx, e, "spread scratch");
     }
     c.cap_markers = n;
-    c.af_stride = stride;
+    c.cf_stride = stride;
     return MLS_OK;
 }
 

@@ -107,8 +107,8 @@ k_build_exact(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n,
 // lane has the shape function of its (marker, component) it gathers the 27
 // support values of that component's velocity and writes U[c][m] and
 // F[c][m] = (V_b - U) / dt, so phi is not read back (the FP64 route reads its
-// own stored values).  Each workgroup also records max |A_m F_m| per component
-// in block_fmax[3 blockIdx + c], the scale of the spreading sums.
+// own stored values).  It also writes c_m F_m of eq. 8 by row (cf_rows), the
+// value the spreading scatters with the shape function.
 //
 // NF = 0 stores the 27 values of phi per row.  NF = 7 or 13 stores the
 // compact transfer function instead (rows of NF floats, blocked like phi):
@@ -124,18 +124,19 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
                uint32_t *__restrict__ home, float *__restrict__ phi, uint8_t *__restrict__ route,
                const float *__restrict__ u, const float *__restrict__ v, const float *__restrict__ w,
                const float *__restrict__ vb, const float *__restrict__ area, float inv_dt, float *__restrict__ U,
-               float *__restrict__ F, float *__restrict__ af_rows, int64_t af_stride, uint32_t *__restrict__ block_fmax,
-               float *__restrict__ coef, uint32_t *__restrict__ rq, ErrWord *err, DevStats *st)
+               float *__restrict__ F, float *__restrict__ cf_rows, int64_t cf_stride, float *__restrict__ coef,
+               uint32_t *__restrict__ rq, uint32_t *__restrict__ tmax, int64_t tstride, ErrWord *err,
+               DevStats *st)
 {
     const Grid &g = *gp;
-    const int wave = wave_id(), lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63;
     const WaveWork ww = wave_work();
     const int c = ww.c;
     const int64_t gstride = ww.stride;
     const float *q = c == 0 ? u : (c == 1 ? v : w);
     const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
     unsigned long long routed = 0;
-    float kmax = 0.f, fmx = 0.f;
+    float kmax = 0.f;
     int64_t base = ww.base;
     // Pipelined operand loads: the marker of the item after next, and the
     // position and area of the next item, are requested an iteration ahead.
@@ -224,33 +225,28 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
         const float f = (vbv - acc) * inv_dt;
         st_stream(&U[c * n + m], ok ? acc : nan);
         st_stream(&F[c * n + m], ok ? f : nan);
-        // A_l F_l by row for the spreading (row p < af_stride: padding rows too)
-        st_stream(&af_rows[c * af_stride + base + lane], ok ? ca * f : 0.0f);
+        // c_l F_l (eq. 8) by row for the spreading (row p < cf_stride: padding
+        // rows too); a queued compact row gets its U, F and c F from k_route_rows
+        const float cfv = eq8_coef(g, c, G[0].ih, G[1].ih, G[2].ih, ph, ca * f);
+        st_stream(&cf_rows[c * cf_stride + base + lane], ok ? cfv : 0.0f);
         if (!ok) {
             raise_error(err, m, isfinite(px) && isfinite(py) && isfinite(pz) ? MLS_E_SUPPORT : MLS_E_NONFINITE);
-        } else if (NF == 0 || !fp64) {   // a queued compact row gets its U, F and A F from k_route_rows
-            const float af = fabsf(ca) * fabsf(f);
-            if (!(af <= 3.0e38f)) raise_error(err, m, MLS_E_RANGE);   // non-finite force (NaN fails too)
-            else fmx = fmaxf(fmx, af);
+        } else if (NF == 0 || !fp64) {
+            // a non-finite force or coefficient (NaN fails too)
+            if (!(fabsf(cfv) <= 3.0e38f)) raise_error(err, m, MLS_E_RANGE);
         }
+        // the spreading tile's largest |c F| (rows come in tile order, so a
+        // wavefront holds one or two tiles)
+        const bool counted = valid && ok && (NF == 0 || !fp64);
+        wave_key_max(tmax + c * tstride, counted ? (int64_t)tile_from_geo(g, c, G) : -1, finite_abs(cfv));
     }
     unsigned long long tot = routed;
     for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
     float km = kmax;
     for (int off = 32; off > 0; off >>= 1) km = fmaxf(km, __shfl_xor(km, off));
-    for (int off = 32; off > 0; off >>= 1) fmx = fmaxf(fmx, __shfl_xor(fmx, off));
-    __shared__ float bm[kBuildWaves];
     if (lane == 0) {
         if (tot) atomicAdd(&st->fp64_solves, tot);
         if (km > 0.f) atomicMax(&st->kappa_max_bits, __float_as_uint(km));
-        bm[wave] = fmx;
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-        float v = 0.f;
-        for (int q2 = 0; q2 < kBuildWaves; ++q2)
-            if (wave_component(q2) == (int)threadIdx.x) v = fmaxf(v, bm[q2]);
-        block_fmax[3 * blockIdx.x + threadIdx.x] = __float_as_uint(v);
     }
 }
 
@@ -264,16 +260,15 @@ __global__ void k_clear_words(uint32_t *p, int64_t n)
 // count) is row << 2 | component, row in tile order.  For each, the FP64
 // re-solve of the pair, its phi stored into the blocked rows, and the
 // interpolation and direct forcing that the build skipped: U and F by marker,
-// A F by row, and max |A F| into fmax_slot[c] (reduced with the per-workgroup
-// maxima of the build).
+// c F (eq. 8) by row.
 __global__ void __launch_bounds__(kBlock)
 k_route_rows(const Grid *__restrict__ gp, const Weight W, int64_t n, const uint32_t *__restrict__ order,
              const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
              const uint32_t *__restrict__ home, const uint32_t *__restrict__ rq, float *__restrict__ phi,
              const float *__restrict__ u, const float *__restrict__ v, const float *__restrict__ w,
              const float *__restrict__ vb, const float *__restrict__ area, float inv_dt, float *__restrict__ U,
-             float *__restrict__ F, float *__restrict__ af_rows, int64_t af_stride, uint32_t *__restrict__ fmax_slot,
-             ErrWord *err)
+             float *__restrict__ F, float *__restrict__ cf_rows, int64_t cf_stride,
+             const uint32_t *__restrict__ marker_tile, uint32_t *__restrict__ tmax, int64_t tstride, ErrWord *err)
 {
     const Grid &g = *gp;
     const uint32_t cnt = rq[0];
@@ -304,10 +299,11 @@ k_route_rows(const Grid *__restrict__ gp, const Weight W, int64_t n, const uint3
         const float ca = area[m];
         U[c * n + m] = acc;
         F[c * n + m] = f;
-        af_rows[c * af_stride + row] = ca * f;
-        const float af = fabsf(ca) * fabsf(f);
-        if (!(af <= 3.0e38f)) raise_error(err, m, MLS_E_RANGE);
-        else atomicMax(&fmax_slot[c], __float_as_uint(af));
+        const float cfv = eq8_coef(g, c, hi, hj, hk, ph, ca * f);
+        cf_rows[c * cf_stride + row] = cfv;
+        if (!(fabsf(cfv) <= 3.0e38f)) raise_error(err, m, MLS_E_RANGE);
+        const float av = finite_abs(cfv);
+        if (av > 0.f) atomicMax(&tmax[c * tstride + marker_tile[m]], __float_as_uint(av));
     }
 }
 
@@ -492,8 +488,8 @@ k_fast_interp(const Grid *__restrict__ gp, const float4 *__restrict__ tab, int n
               const float *__restrict__ z, uint32_t *__restrict__ home, float *__restrict__ phi,
               uint8_t *__restrict__ route, const float *__restrict__ u, const float *__restrict__ v,
               const float *__restrict__ w, const float *__restrict__ vb, const float *__restrict__ area, float inv_dt,
-              float *__restrict__ U, float *__restrict__ F, float *__restrict__ af_rows, int64_t af_stride,
-              uint32_t *__restrict__ block_fmax, ErrWord *err)
+              float *__restrict__ U, float *__restrict__ F, float *__restrict__ cf_rows, int64_t cf_stride,
+              uint32_t *__restrict__ tmax, int64_t tstride, ErrWord *err)
 {
     extern __shared__ float4 oct[];   // [nh^3][7]
     const Grid &g = *gp;
@@ -508,7 +504,7 @@ k_fast_interp(const Grid *__restrict__ gp, const float4 *__restrict__ tab, int n
         }
     }
     __syncthreads();
-    const int wave = wave_id(), lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63;
     const WaveWork ww = wave_work();
     const int c = ww.c;
     const int64_t gstride = ww.stride;
@@ -516,7 +512,6 @@ k_fast_interp(const Grid *__restrict__ gp, const float4 *__restrict__ tab, int n
     const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
     const float scale = (float)(nsub - 1);   // sub-cells per unit of xi (home CV [-1/2, 1/2))
     const float step = 1.0f / scale;         // sub-cell width, (hi - lo) / (n_sub - 1)
-    float fmx = 0.f;
     int64_t base = ww.base;
     // Operand loads pipelined an iteration ahead and one sequence of memory
     // operations on every path, as in k_build_interp.
@@ -653,25 +648,16 @@ k_fast_interp(const Grid *__restrict__ gp, const float4 *__restrict__ tab, int n
         const float f = (vbv - acc) * inv_dt;
         st_stream(&U[c * n + m], ok ? acc : nan);
         st_stream(&F[c * n + m], ok ? f : nan);
-        // A_l F_l by row for the spreading (row p < af_stride: padding rows too)
-        st_stream(&af_rows[c * af_stride + base + lane], ok ? ca * f : 0.0f);
+        // c_l F_l (eq. 8) by row for the spreading (row p < cf_stride: padding rows too)
+        const float cfv = eq8_coef(g, c, G[0].ih, G[1].ih, G[2].ih, ph, ca * f);
+        st_stream(&cf_rows[c * cf_stride + base + lane], ok ? cfv : 0.0f);
         if (!ok) {
             raise_error(err, m, isfinite(px) && isfinite(py) && isfinite(pz) ? MLS_E_SUPPORT : MLS_E_NONFINITE);
-        } else {
-            const float af = fabsf(ca) * fabsf(f);
-            if (!(af <= 3.0e38f)) raise_error(err, m, MLS_E_RANGE);
-            else fmx = fmaxf(fmx, af);
+        } else if (!(fabsf(cfv) <= 3.0e38f)) {
+            raise_error(err, m, MLS_E_RANGE);
         }
-    }
-    for (int off = 32; off > 0; off >>= 1) fmx = fmaxf(fmx, __shfl_xor(fmx, off));
-    __shared__ float bm[kBuildWaves];
-    if (lane == 0) bm[wave] = fmx;
-    __syncthreads();
-    if (threadIdx.x < 3) {
-        float vv = 0.f;
-        for (int q2 = 0; q2 < kBuildWaves; ++q2)
-            if (wave_component(q2) == (int)threadIdx.x) vv = fmaxf(vv, bm[q2]);
-        block_fmax[3 * blockIdx.x + threadIdx.x] = __float_as_uint(vv);
+        const bool counted = base + lane < n && ok;
+        wave_key_max(tmax + c * tstride, counted ? (int64_t)tile_from_geo(g, c, G) : -1, finite_abs(cfv));
     }
 }
 
@@ -774,26 +760,23 @@ hipError_t launch_build_interp(const Ctx &c, int64_t n, const float *x, const fl
     const dim3 grid(build_grid(n, c.cu_count, c.build_blocks_per_cu));
     if (c.step_nf == 0) {
         hipLaunchKernelGGL(k_build_interp<0>, grid, dim3(kBuildBlock), 0, s, c.d_grid, c.w, tau, n, c.entries, x, y, z,
-                           home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.af_rows, c.af_stride, c.block_fmax,
-                           nullptr, nullptr, c.err, c.stats);
+                           home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.cf_rows, c.cf_stride, nullptr,
+                           nullptr, c.tile_fmax, c.g.ntiles + 1, c.err, c.stats);
         return hipGetLastError();
     }
-    // compact rows: clear the FP64 queue count and the extra force-maximum slot
-    // after the workgroups' own, build, then finish the queued rows
-    uint32_t *fmax_slot = c.block_fmax + 3 * (int64_t)grid.x;
+    // compact rows: clear the FP64 queue count, build, then finish the queued rows
     hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, s, c.route_queue, (int64_t)1);
-    hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, s, fmax_slot, (int64_t)3);
     if (c.step_nf == 7)
         hipLaunchKernelGGL(k_build_interp<7>, grid, dim3(kBuildBlock), 0, s, c.d_grid, c.w, tau, n, c.entries, x, y,
-                           z, home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.af_rows, c.af_stride,
-                           c.block_fmax, c.coef_rows, c.route_queue, c.err, c.stats);
+                           z, home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.cf_rows, c.cf_stride,
+                           c.coef_rows, c.route_queue, c.tile_fmax, c.g.ntiles + 1, c.err, c.stats);
     else
         hipLaunchKernelGGL(k_build_interp<13>, grid, dim3(kBuildBlock), 0, s, c.d_grid, c.w, tau, n, c.entries, x, y,
-                           z, home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.af_rows, c.af_stride,
-                           c.block_fmax, c.coef_rows, c.route_queue, c.err, c.stats);
+                           z, home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.cf_rows, c.cf_stride,
+                           c.coef_rows, c.route_queue, c.tile_fmax, c.g.ntiles + 1, c.err, c.stats);
     hipLaunchKernelGGL(k_route_rows, dim3(c.cu_count), dim3(kBlock), 0, s, c.d_grid, c.w, n, c.entries, x, y, z,
-                       home, c.route_queue, phi, u, v, w, vb, area, 1.0f / dt, U, F, c.af_rows, c.af_stride, fmax_slot,
-                       c.err);
+                       home, c.route_queue, phi, u, v, w, vb, area, 1.0f / dt, U, F, c.cf_rows, c.cf_stride,
+                       c.marker_tile, c.tile_fmax, c.g.ntiles + 1, c.err);
     return hipGetLastError();
 }
 
@@ -818,12 +801,12 @@ hipError_t launch_fast_interp(const Ctx &c, int64_t n, const float *x, const flo
     const float4 *tab = reinterpret_cast<const float4 *>(c.tables);
     if (trilinear_blend)
         hipLaunchKernelGGL(k_fast_interp<true>, grid, dim3(kBuildBlock), lds, s, c.d_grid, tab, nsub, n, c.entries, x,
-                           y, z, home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.af_rows, c.af_stride,
-                           c.block_fmax, c.err);
+                           y, z, home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.cf_rows, c.cf_stride,
+                           c.tile_fmax, c.g.ntiles + 1, c.err);
     else
         hipLaunchKernelGGL(k_fast_interp<false>, grid, dim3(kBuildBlock), lds, s, c.d_grid, tab, nsub, n, c.entries, x,
-                           y, z, home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.af_rows, c.af_stride,
-                           c.block_fmax, c.err);
+                           y, z, home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.cf_rows, c.cf_stride,
+                           c.tile_fmax, c.g.ntiles + 1, c.err);
     return hipGetLastError();
 }
 

@@ -252,14 +252,13 @@ __device__ __forceinline__ void jitter_marker(uint64_t seed, uint64_t step, int6
 }
 #pragma clang fp contract(on)
 
-// Selects rather than branches on the (uniform) kind, so that consecutive
-// evaluations stay in one basic block and interleave.
+// One form for every kind, with no select: w = max(2^(s^2 e2) - cut, 0) where
+// e2 = -log2(e) / eps^2 (0 for the constant weight, whose value is then
+// 2^0 - 0 = 1 exactly) and cut = exp(-(R/eps)^2) for the shifted Gaussian, 0
+// otherwise (max(g, 0) = g for the plain Gaussian).  Five VALU operations.
 __device__ __forceinline__ float weight1(const Weight &w, float s)
 {
-    const float t = s * w.inv_eps;
-    const float g = __expf(-t * t);
-    const float r = w.kind == MLS_W_GAUSS ? g : fmaxf(g - w.cut, 0.0f);
-    return w.kind == MLS_W_CONST ? 1.0f : r;
+    return fmaxf(__builtin_amdgcn_exp2f(s * s * w.e2) - w.cut, 0.0f);
 }
 
 __device__ __forceinline__ double weight1_d(const Weight &w, double s)
@@ -571,6 +570,110 @@ __device__ __forceinline__ void load_support(const float *__restrict__ q, int i,
             qv[3 * r + 2] = lo ? a1 : (hi ? e : a2);
         }
     }
+}
+
+// Control-volume width of node i along an axis: a cell width for a centre
+// node, the centre-to-centre distance for a face node.
+__device__ __forceinline__ float width_of(const Axis &a, int is_face, int i)
+{
+    return is_face ? a.width_f[i] : a.width_c[i];
+}
+
+// The factors of the spreading coefficient of eq. 8 for one (marker,
+// component) with home (hi, hj, hk) and shape function ph:
+// h3 = h_l / 3 = sum_k phi_k (dx_k + dy_k + dz_k) / 3 and
+// den = sum_k phi_k dV_k, so that c_l F_l = A_l F_l h3 / den.  On a grid
+// whose widths are all equal (const_width) the sums skip the width tables;
+// they are the same floats.
+__device__ __forceinline__ void eq8_sums(const Grid &g, int c, int hi, int hj, int hk, const float ph[kNe],
+                                         float &h3, float &den)
+{
+    float hl = 0.f, dn = 0.f;
+    const float cw = g.const_width;
+    if (cw > 0.f) {
+        const float s3 = cw + cw + cw, p3 = cw * cw * cw;
+#pragma unroll
+        for (int k = 0; k < kNe; ++k) {
+            hl += ph[k] * s3;
+            dn += ph[k] * p3;
+        }
+    } else {
+        float wx[3], wy[3], wz[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            wx[a] = width_of(g.ax[0], c == 0, nb_index(hi, a - 1, g.dims[c][0], g.ax[0].periodic));
+            wy[a] = width_of(g.ax[1], c == 1, nb_index(hj, a - 1, g.dims[c][1], g.ax[1].periodic));
+            wz[a] = width_of(g.ax[2], c == 2, nb_index(hk, a - 1, g.dims[c][2], g.ax[2].periodic));
+        }
+#pragma unroll
+        for (int k = 0; k < kNe; ++k) {
+            const int a = k % 3, b = (k / 3) % 3, cz = k / 9;
+            hl += ph[k] * (wx[a] + wy[b] + wz[cz]);
+            dn += ph[k] * (wx[a] * wy[b] * wz[cz]);
+        }
+    }
+    h3 = hl * (1.0f / 3.0f);
+    den = dn;
+}
+
+// c_l F_l of eq. 8 from A_l F_l: the per-row value the spreading scatters as
+// c_l F_l phi_k.
+__device__ __forceinline__ float eq8_coef(const Grid &g, int c, int hi, int hj, int hk, const float ph[kNe], float af)
+{
+    float h3, den;
+    eq8_sums(g, c, hi, hj, hk, ph, h3, den);
+    return af * h3 / den;
+}
+
+// Per-key maxima of the lanes of a wavefront: for every distinct key >= 0 the
+// largest v of the lanes holding it goes into tmax[key] with one atomic max
+// (v finite and >= 0; positive floats order as unsigned integers).  Every
+// lane of the wavefront must call it.
+__device__ __forceinline__ void wave_key_max(uint32_t *tmax, int64_t key, float v)
+{
+    unsigned long long pending = __ballot(key >= 0);
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int64_t kl = __shfl(key, leader);
+        const bool mine = key == kl;
+        float m = mine ? v : 0.f;
+        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+        if ((int)(threadIdx.x & 63) == leader && m > 0.f) atomicMax(&tmax[kl], __float_as_uint(m));
+        pending &= ~__ballot(mine);
+    }
+}
+
+// |v| when finite, else 0 (a non-finite value is reported where it is used).
+__device__ __forceinline__ float finite_abs(float v)
+{
+    const float a = fabsf(v);
+    return a <= 3.0e38f ? a : 0.f;
+}
+
+// Tile index of cell i on an axis with tile edge 1/inv_tile: the exact quotient
+// i / tile, since i + 1/2 stays at least 1/(2 tile) from a multiple of tile and
+// the FP32 product errs by far less for cells and tiles below 2^11.
+__device__ __forceinline__ int tile_of(int i, float inv_tile)
+{
+    return (int)(((float)i + 0.5f) * inv_tile);
+}
+
+// Spreading tile of the cell that holds a marker, from the support geometry G
+// of its component c: on the axes other than c the home node is the cell (a
+// centre node); on axis c it is the face node fd, and the cell is fd when the
+// marker lies at or above that face (offset s_1 = (x_fd - X) / H <= 0, its
+// sign exact), else fd - 1 (wrapped on a periodic axis).  The same cell as
+// the locate of the binning.
+__device__ __forceinline__ uint32_t tile_from_geo(const Grid &g, int c, const AxisGeo G[3])
+{
+    int t[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        int cell = G[d].ih;
+        if (d == c && G[d].s[1] > 0.0f) cell = cell > 0 ? cell - 1 : g.ax[d].n - 1;
+        t[d] = tile_of(cell, 1.0f / (float)g.ax[d].tile);
+    }
+    return (uint32_t)(((int64_t)t[2] * g.ntile[1] + t[1]) * g.ntile[0] + t[0]);
 }
 
 }  // namespace mls

@@ -87,9 +87,15 @@ __device__ __forceinline__ void mark_failed(ErrWord *err, int64_t l, double px, 
 // axes and gamma = A^{-1} e_0, in the node order of the blocked layout.  The
 // build and the compact spreading of a time step both evaluate phi here, so
 // that they obtain the same values from the same inputs.
+// With wyz = w_y w_z and pyz = gamma_0 + gamma_2 s_y + gamma_3 s_z per (y, z)
+// node pair, phi = wyz (w_x pyz + w_x gamma_1 s_x): one multiply-add and one
+// multiply per node.
 __device__ __forceinline__ void phi_from_gamma(const float w[3][3], const float s[3][3], const float gam[4],
                                                float ph[kNe])
 {
+    float vx[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) vx[ax] = w[0][ax] * (gam[1] * s[0][ax]);
 #pragma unroll
     for (int cz = 0; cz < 3; ++cz) {
 #pragma unroll
@@ -97,7 +103,7 @@ __device__ __forceinline__ void phi_from_gamma(const float w[3][3], const float 
             const float wyz = w[1][by] * w[2][cz];
             const float pyz = gam[0] + gam[2] * s[1][by] + gam[3] * s[2][cz];
 #pragma unroll
-            for (int ax = 0; ax < 3; ++ax) ph[ax + 3 * by + 9 * cz] = w[0][ax] * wyz * (pyz + gam[1] * s[0][ax]);
+            for (int ax = 0; ax < 3; ++ax) ph[ax + 3 * by + 9 * cz] = wyz * fmaf(w[0][ax], pyz, vx[ax]);
         }
     }
 }

@@ -39,13 +39,13 @@ struct Axis {
     const double *centres;  // n, 0.5 * (f[i] + f[i+1])
     const float *width_c;   // n     control-volume widths of centre nodes
     const float *width_f;   // n + 1 control-volume widths of face nodes
-    const float *tile_hmin; // ntile: smallest control-volume width near each tile (spreading bound)
 };
 
 struct Weight {
     int32_t kind;
     float inv_eps;   // 1/eps
-    float cut;       // exp(-(R/eps)^2) in FP32 (shifted Gaussian)
+    float cut;       // exp(-(R/eps)^2) in FP32 for the shifted Gaussian, 0 for the other kinds
+    float e2;        // -log2(e)/eps^2 (0 for the constant weight): w = max(2^(s^2 e2) - cut, 0)
     double inv_eps_d;
     double cut_d;
 };
@@ -145,13 +145,15 @@ struct Ctx {
     int32_t stretched_axis = -1;
     // spreading scratch
     int64_t cap_markers = 0;
-    uint32_t *tile_count = nullptr;    // ntiles
-    uint32_t *tile_off = nullptr;      // ntiles + 1
-    uint32_t *tile_cursor = nullptr;   // ntiles
+    uint32_t *tile_count = nullptr;    // ntiles + 1 (the last bucket: markers without a support)
+    uint32_t *tile_off = nullptr;      // ntiles + 2
+    uint32_t *tile_cursor = nullptr;   // ntiles + 1
     uint32_t *tile_active = nullptr;   // ntiles: non-empty tiles, grouped by colour
     uint32_t *block_sums = nullptr;    // scan partials
     uint32_t *entries = nullptr;       // cap_markers: markers sorted by tile
-    float *af_rows = nullptr;          // [3][af_stride]: A_l F_l of the exact step's rows (tile order)
+    float *cf_rows = nullptr;          // [3][cf_stride]: c_l F_l (eq. 8) by row (step, tile order) or by marker
+    uint32_t *tile_fmax = nullptr;     // [3][ntiles + 1]: largest finite |c_l F_l| of each tile's markers (FP32
+                                       // bits), the fixed-point scale of its spreading sums
     uint32_t *marker_tile = nullptr;   // [cap_markers]: spreading tile of each marker (binning from positions)
     float *coef_rows = nullptr;        // compact transfer functions of a compact exact step, rows of step_nf floats
     uint32_t *route_queue = nullptr;   // [1 + 3 cap]: count, then row << 2 | component of its FP64-solved rows
@@ -159,12 +161,9 @@ struct Ctx {
     int step_nf = 0;                   // row width of the step being enqueued: 0 (full phi), 7 or 13
     uint64_t scratch_gen = 0;          // bumped whenever context scratch moves or the tiling changes
                                        // (a captured step graph holds the old addresses and tiling)
-    int64_t af_stride = 0;             // cap_markers rounded up to 64
-    uint32_t *block_fmax = nullptr;    // per-block force maxima of the counting pass (3 per block)
-    uint32_t *work = nullptr;          // [0..26] active-list sizes per colour, [32..58] cursors,
-                                       // [64..66] max |A F| per component (FP32 bits)
-    int64_t colour_tiles[27] = {};   // tiles of each colour
-    float *tile_hmin_block = nullptr;  // per-tile smallest control-volume width (all axes)
+    int64_t cf_stride = 0;             // cap_markers rounded up to 64
+    uint32_t *work = nullptr;          // [0..26] active-list sizes per colour, [32..58] cursors
+    int64_t colour_tiles[27] = {};     // tiles of each colour
     // launch shapes (autotuned): resident workgroups per compute unit
     int spread_blocks_per_cu = 16;      // effective (bounded by the LDS of the tile boxes)
     int spread_blocks_per_cu_req = 16;  // requested
@@ -257,9 +256,10 @@ hipError_t launch_build_interp(const Ctx &c, int64_t n, const float *x, const fl
                                uint32_t *home, float *phi, uint8_t *route, const float *u, const float *v,
                                const float *w, const float *vb, const float *area, float dt, float *U, float *F,
                                hipStream_t s);
-hipError_t launch_spread_sorted(Ctx &c, int64_t n, const uint32_t *home, const float *phi, const float *area,
-                                const float *Fx, const float *Fy, const float *Fz, float *fx, float *fy, float *fz,
-                                hipStream_t s);
+hipError_t launch_spread_sorted(Ctx &c, int64_t n, const uint32_t *home, const float *phi, float *fx, float *fy,
+                                float *fz, hipStream_t s);
+// Dynamic LDS of a spreading tile workgroup: the int64 box of one component.
+size_t spread_lds_bytes(const Ctx &c);
 
 hipError_t launch_jitter(const Ctx &c, int64_t n, const float *x0, const float *y0, const float *z0,
                          float *x, float *y, float *z, float amp, uint64_t seed, hipStream_t s);

@@ -168,8 +168,7 @@ mls_status mls_step(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buff
                                     desc->dt, b->U, b->F, s);
         }
         if (e != hipSuccess) return MLS_E_HIP;
-        e = launch_spread_sorted(c, n, b->home, b->phi, b->area, b->F, b->F + n, b->F + 2 * n, b->fx, b->fy, b->fz,
-                                 s);
+        e = launch_spread_sorted(c, n, b->home, b->phi, b->fx, b->fy, b->fz, s);
         if (e != hipSuccess) return MLS_E_HIP;
         c.step_sorted_n = n;
         return launch_step_advance(c, s) == hipSuccess ? MLS_OK : MLS_E_HIP;

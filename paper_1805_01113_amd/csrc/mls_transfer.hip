@@ -13,7 +13,8 @@
 //      the caller's field.  Each node belongs to exactly one tile, so the
 //      global update is a plain read-modify-write.
 // The fixed-point scale of a tile is a power of two chosen from the largest
-// |A_l F_l| among the tile's markers, so that no sum can overflow.
+// |c_l F_l| (eq. 8) among the tile's markers, so that no sum can overflow and
+// the quantum follows the tile's own forces.
 #include "mls_exact.h"
 
 namespace mls {
@@ -74,13 +75,6 @@ k_interp(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ ho
 // contributions are summed in 64-bit fixed point, whose sum does not depend on
 // the order of the markers: the result is bitwise reproducible.
 
-// Tile index of cell i on an axis with tile edge 1/inv_tile: the exact quotient
-// i / tile, since i + 1/2 stays at least 1/(2 tile) from a multiple of tile and
-// the FP32 product errs by far less for cells and tiles below 2^11.
-__device__ __forceinline__ int tile_of(int i, float inv_tile)
-{
-    return (int)(((float)i + 0.5f) * inv_tile);
-}
 
 __device__ __forceinline__ int64_t marker_tile(const Grid &g, const uint32_t *__restrict__ home, int64_t l,
                                                bool &valid)
@@ -102,19 +96,16 @@ __device__ __forceinline__ int64_t marker_tile(const Grid &g, const uint32_t *__
 // Lanes of a wavefront that hit the same tile are combined into one atomic:
 // the leader adds the count and the others take consecutive slots in lane
 // order, so a tile's marker list is made of runs of consecutive markers.
-// The counting pass also records max_l |A_l F_l| per component (FP32 bits,
-// positive floats order as unsigned integers), the scale of the fixed-point
-// spreading sums.
+// The counting pass also records each marker's tile (ntiles for a marker
+// without a usable support) for the per-tile force maxima.
 template <bool FILL>
 __global__ void __launch_bounds__(kBlock)
 k_bin(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home, uint32_t *__restrict__ count,
-      uint32_t *__restrict__ cursor, uint32_t *__restrict__ entries, ErrWord *err,
-      const float *__restrict__ area, const float *__restrict__ Fx, const float *__restrict__ Fy,
-      const float *__restrict__ Fz, uint32_t *__restrict__ fmax_bits)
+      uint32_t *__restrict__ cursor, uint32_t *__restrict__ entries, uint32_t *__restrict__ tile_of_marker,
+      ErrWord *err)
 {
     const Grid &g = *gp;
     const int lane = threadIdx.x & 63;
-    float mx[3] = {0.f, 0.f, 0.f};
     const unsigned long long lower = (1ull << lane) - 1ull;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     // the loop bound is wave-uniform so that the ballots see the whole wave
@@ -126,15 +117,7 @@ k_bin(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home,
             const int64_t tt = marker_tile(g, home, l, valid);
             if (valid) t = tt;
             else if (!FILL) raise_error(err, l, MLS_E_SUPPORT);   // contributes nothing
-            if (!FILL && valid) {
-                const float a = fabsf(area[l]);
-                // a non-finite force is caught here: fmaxf would drop a NaN
-                const float f0 = a * fabsf(Fx[l]), f1 = a * fabsf(Fy[l]), f2 = a * fabsf(Fz[l]);
-                if (!(f0 <= 3.0e38f && f1 <= 3.0e38f && f2 <= 3.0e38f)) raise_error(err, l, MLS_E_RANGE);
-                mx[0] = fmaxf(mx[0], f0);
-                mx[1] = fmaxf(mx[1], f1);
-                mx[2] = fmaxf(mx[2], f2);
-            }
+            if (!FILL) tile_of_marker[l] = valid ? (uint32_t)tt : (uint32_t)g.ntiles;
         }
         unsigned long long pending = __ballot(t >= 0);
         while (pending) {
@@ -146,22 +129,6 @@ k_bin(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home,
             pos = __shfl(pos, leader);
             if (FILL && ((mask >> lane) & 1ull)) entries[pos + __popcll(mask & lower)] = (uint32_t)l;
             pending &= ~mask;
-        }
-    }
-    if (!FILL) {
-        // block maximum -> fmax_bits[3 * blockIdx + c]; the scan reduces them
-        __shared__ float bm[3][kBlock / 64];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float v = mx[c];
-            for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-            if (lane == 0) bm[c][threadIdx.x >> 6] = v;
-        }
-        __syncthreads();
-        if (threadIdx.x < 3) {
-            const int c = threadIdx.x;
-            fmax_bits[3 * blockIdx.x + c] =
-                __float_as_uint(fmaxf(fmaxf(bm[c][0], bm[c][1]), fmaxf(bm[c][2], bm[c][3])));
         }
     }
 }
@@ -257,26 +224,9 @@ __global__ void __launch_bounds__(kBlock) k_scan_partials(const uint32_t *__rest
     if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
-__global__ void __launch_bounds__(kBlock) k_scan_top(uint32_t *__restrict__ partial, int64_t nb,
-                                                     const uint32_t *__restrict__ bmax, int nbmax,
-                                                     uint32_t *__restrict__ fmax_bits)
+__global__ void __launch_bounds__(kBlock) k_scan_top(uint32_t *__restrict__ partial, int64_t nb)
 {
     __shared__ uint32_t sh[4];
-    // maximum of the per-block force maxima of the counting pass (positive
-    // floats order as unsigned integers)
-    {
-        uint32_t m[3] = {0u, 0u, 0u};
-        for (int i = threadIdx.x; i < nbmax; i += blockDim.x)
-            for (int c = 0; c < 3; ++c) m[c] = max(m[c], bmax[3 * i + c]);
-        for (int c = 0; c < 3; ++c) {
-            uint32_t v = m[c];
-            for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
-            if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-            __syncthreads();
-            if (threadIdx.x == 0) fmax_bits[c] = max(max(sh[0], sh[1]), max(sh[2], sh[3]));
-            __syncthreads();
-        }
-    }
     uint32_t carry = 0;
     for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
         const int64_t i = b0 + threadIdx.x;
@@ -289,10 +239,13 @@ __global__ void __launch_bounds__(kBlock) k_scan_top(uint32_t *__restrict__ part
     }
 }
 
+// Also clears the per-tile force maxima tmax[3][tstride] of the scanned
+// tiles, ahead of the kernels that write c_l F_l.
 __global__ void __launch_bounds__(kBlock) k_scan_final(const uint32_t *__restrict__ count, int64_t nt,
                                                        const uint32_t *__restrict__ partial,
                                                        uint32_t *__restrict__ off, uint32_t *__restrict__ cursor,
-                                                       uint32_t *__restrict__ work)
+                                                       uint32_t *__restrict__ work, uint32_t *__restrict__ tmax,
+                                                       int64_t tstride)
 {
     __shared__ uint32_t sh[4];
     const int64_t base = (int64_t)blockIdx.x * kScanChunk;
@@ -312,6 +265,9 @@ __global__ void __launch_bounds__(kBlock) k_scan_final(const uint32_t *__restric
         if (i < nt) {
             off[i] = run;
             cursor[i] = run;
+            tmax[i] = 0u;
+            tmax[tstride + i] = 0u;
+            tmax[2 * tstride + i] = 0u;
         }
         run += vals[q];
     }
@@ -374,11 +330,6 @@ k_active_tiles(const Grid *__restrict__ gp, const uint32_t *__restrict__ off, ui
 
 // ---- spreading: per-tile fixed-point accumulation ------------------------------
 
-__device__ __forceinline__ float width_of(const Axis &a, int is_face, int i)
-{
-    return is_face ? a.width_f[i] : a.width_c[i];
-}
-
 // Box-local index of node i (wrapped) on axis a for a box starting at node b0.
 __device__ __forceinline__ int box_local(const Axis &a, int ntile, int nodes, int b0, int i)
 {
@@ -401,26 +352,33 @@ __device__ __forceinline__ void lds_barrier()
     asm volatile("" ::: "memory");
 }
 
-// SORTED: row e of home / phi belongs to marker entries[e] (the exact time
-// step writes them in tile order), so a tile reads its rows contiguously;
-// otherwise home / phi are indexed by marker.
 // Adds a tile's box (64-bit fixed point, scale qscale) into the FP32 field f
-// and returns its nodes to zero.  A thread's box nodes are read in batches of
-// kFlush before any is written back, so their loads overlap.  Box coordinates
-// come from FP32 reciprocals of the box edges (exact below 2^22 nodes).
+// and returns its nodes to zero.  Consecutive threads take consecutive box
+// nodes (their field accesses coalesce along x rows), kFlush per thread at a
+// time: the kFlush sums are read from LDS together, then the nonzero ones are
+// decoded into box coordinates, their field values loaded together and
+// written back.  Box coordinates come from the compile-time row length BX
+// (BX > 0) or FP32 reciprocals of the box edges (exact below 2^22 nodes).
 // INSIDE: the box lies inside the grid, so a node's index is the origin's
 // plus an affine offset; otherwise periodic axes wrap and nodes past a wall
 // are skipped.
-template <bool INSIDE>
-__device__ __forceinline__ void flush_box(const Grid &g, int c, unsigned long long *acc, int bnodes, int bx, int by,
-                                          int b0x, int b0y, int b0z, int nxc, int nyc, int nzc, float inv_bx,
-                                          float inv_bxy, double qscale, float *__restrict__ f)
+template <bool INSIDE, int BX>
+__device__ __forceinline__ void flush_box(const Grid &g, int c, unsigned long long *acc, int bnodes, int bx_rt,
+                                          int by, int b0x, int b0y, int b0z, int nxc, int nyc, int nzc, float inv_bx,
+                                          float inv_by, float inv_bxy, double qscale, float *__restrict__ f)
 {
     constexpr int kFlush = 8;
+    const int bx = BX > 0 ? BX : bx_rt;
     const Axis &AX = g.ax[0], &AY = g.ax[1], &AZ = g.ax[2];
     float *const fo = INSIDE ? f + field_index(g, c, b0x, b0y, b0z) : f;
     const int sz = nxc * nyc;
     for (int q0 = threadIdx.x; q0 < bnodes; q0 += kFlush * blockDim.x) {
+        long long sv[kFlush];
+#pragma unroll
+        for (int u = 0; u < kFlush; ++u) {
+            const int q = q0 + u * (int)blockDim.x;
+            sv[u] = q < bnodes ? (long long)acc[q] : 0;
+        }
         float *dst[kFlush];
         float add[kFlush];
         float old[kFlush];
@@ -428,15 +386,21 @@ __device__ __forceinline__ void flush_box(const Grid &g, int c, unsigned long lo
         for (int u = 0; u < kFlush; ++u) {
             dst[u] = nullptr;
             add[u] = 0.f;
-            const int q = q0 + u * blockDim.x;
-            if (q >= bnodes) continue;
-            const long long sv = (long long)acc[q];
-            if (sv == 0) continue;
+            const int q = q0 + u * (int)blockDim.x;
+            if (sv[u] == 0) continue;
             acc[q] = 0ull;
-            const int lz = (int)(((float)q + 0.5f) * inv_bxy);
-            const int rq = q - lz * (bx * by);
-            const int ly = (int)(((float)rq + 0.5f) * inv_bx);
-            const int lx = rq - ly * bx;
+            int lx, ly, lz;
+            if constexpr (BX > 0) {
+                const int rq = q / BX;
+                lx = q - rq * BX;
+                lz = (int)(((float)rq + 0.5f) * inv_by);
+                ly = rq - lz * by;
+            } else {
+                lz = (int)(((float)q + 0.5f) * inv_bxy);
+                const int rq = q - lz * (bx * by);
+                ly = (int)(((float)rq + 0.5f) * inv_bx);
+                lx = rq - ly * bx;
+            }
             if constexpr (INSIDE) {
                 dst[u] = fo + (lz * sz + ly * nxc + lx);
             } else {
@@ -448,7 +412,7 @@ __device__ __forceinline__ void flush_box(const Grid &g, int c, unsigned long lo
                     continue;
                 dst[u] = f + field_index(g, c, gx, gy, gz);
             }
-            add[u] = (float)((double)sv * qscale);
+            add[u] = (float)((double)sv[u] * qscale);
         }
 #pragma unroll
         for (int u = 0; u < kFlush; ++u) old[u] = dst[u] ? *dst[u] : 0.f;
@@ -462,30 +426,35 @@ __device__ __forceinline__ void flush_box(const Grid &g, int c, unsigned long lo
 // row's compact transfer function (gamma and the support offsets, NF = 7 or
 // 13 floats, see k_build_interp) with the build's own arithmetic, or read
 // from phi for a row the build solved in FP64 (NaN gamma_0).
+// cf holds c_l F_l of eq. 8 per component: by row in tile order (SORTED, the
+// exact time step's rows; its fused build writes them) or by marker (a
+// standalone call: k_spread_coef).  Per tile, the largest finite |c_l F_l|
+// of its rows sets the fixed-point scale of each component.
 // Workgroups of 128 or 256 threads (tuned, at most kSpreadBlock).  A tile
 // holds some 200 rows: when each workgroup handles many tiles, 128 threads
 // leave fewer lanes idle, pay cheaper barriers and keep more tiles in flight
-// per compute unit (cfg 3: 2.86 against 3.10 ms); when a colour has only a
-// tile or two per workgroup, 256 threads finish each tile sooner.
-// Sorted rows: at most 80 registers (6 wavefronts per SIMD).  The tile phases
-// are bound by memory latency and barriers, and a sixth wavefront per SIMD
-// hides more of it than the registers cost (measured; an eighth spills).  The
-// standalone spreading, which gathers by marker, would spill at 80.
-template <bool SORTED, int NF>
+// per compute unit; when a colour has only a tile or two per workgroup, 256
+// threads finish each tile sooner.
+// BX > 0: every axis has more than one tile and the box rows hold BX nodes.
+// Then the 27 support nodes of a row are three consecutive nodes on each box
+// axis, so one box address per row serves all 27 atomics (the others are
+// immediate offsets) and the flush decodes box coordinates with it.
+// BX = 0: any tiling (a short periodic axis kept whole wraps inside its box).
+template <bool SORTED, int NF, int BX>
 __global__ void __launch_bounds__(kSpreadBlock) __attribute__((amdgpu_waves_per_eu(SORTED ? 6 : 5)))
-k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32_t *__restrict__ home,
-                const float *__restrict__ phi, const float *__restrict__ area, const float *__restrict__ Fx,
-                const float *__restrict__ Fy, const float *__restrict__ Fz, float *__restrict__ fx,
-                float *__restrict__ fy, float *__restrict__ fz, const uint32_t *__restrict__ off,
-                const uint32_t *__restrict__ entries, const uint32_t *__restrict__ active, uint32_t *work,
-                const uint32_t *__restrict__ fmax_bits, const float *__restrict__ af_rows, int64_t af_stride,
-                const float *__restrict__ coef, const Weight W, ErrWord *err)
+k_spread_colour(const Grid *__restrict__ gp, int colour, const uint32_t *__restrict__ home,
+                const float *__restrict__ phi, const float *__restrict__ cf, int64_t cf_stride,
+                float *__restrict__ fx, float *__restrict__ fy, float *__restrict__ fz,
+                const uint32_t *__restrict__ off, const uint32_t *__restrict__ entries,
+                const uint32_t *__restrict__ active, uint32_t *work, const float *__restrict__ coef, const Weight W,
+                const uint32_t *__restrict__ tmax, int64_t tstride, ErrWord *err)
 {
     const Grid &g = *gp;
     extern __shared__ unsigned long long acc[];     // the box of one component
     const Axis &AX = g.ax[0], &AY = g.ax[1], &AZ = g.ax[2];
-    const int bx = g.box[0], by = g.box[1], bz = g.box[2];
+    const int bx = BX > 0 ? BX : g.box[0], by = g.box[1], bz = g.box[2];
     const int bnodes = bx * by * bz;
+    const float inv_by = 1.0f / (float)by;
     const int64_t abase = g.colour_base[colour];
     const uint32_t nact = (uint32_t)min((int64_t)work[colour], colour_end(g, colour) - abase);
     __shared__ int64_t tile_sh;
@@ -496,7 +465,6 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
     // fewer than 2^22 nodes, (q + 1/2) times the FP32 reciprocal of the divisor
     // stays within 1/2 of a quotient's interval from its floor
     const float inv_bx = 1.0f / (float)bx, inv_bxy = 1.0f / (float)(bx * by);
-    const float cw = g.const_width;
     for (;;) {
         if (threadIdx.x == 0) {
             const uint32_t i = atomicAdd(&work[32 + colour], 1u);
@@ -514,34 +482,31 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
         const int b0x = (AX.periodic && g.ntile[0] == 1) ? 0 : tx * AX.tile - 1;
         const int b0y = (AY.periodic && g.ntile[1] == 1) ? 0 : ty * AY.tile - 1;
         const int b0z = (AZ.periodic && g.ntile[2] == 1) ? 0 : tz * AZ.tile - 1;
-        const float hloc = fminf(fminf(AX.tile_hmin[tx], AY.tile_hmin[ty]), AZ.tile_hmin[tz]);
-        const double inv_h2 = 1.0 / ((double)hloc * (double)hloc);
         // one component at a time: a third of the LDS per workgroup, so more
         // workgroups fit a compute unit and tiles can be larger
 #pragma unroll 1
         for (int c = 0; c < 3; ++c) {
-            // c_l <= A_l / h^2 for a shape function with sum phi dV close to dV, h
-            // the smallest control-volume width near the tile; with |phi| <= 2
-            // every contribution |c_l phi_k F_l| stays below bound = 8 max|A F| / h^2.
-            // A scaled contribution stays below 2^30 (converted to int32 and
-            // summed in int64); its quantum is 2^-30 of the bound.
-            const double bound = 8.0 * (double)__uint_as_float(fmax_bits[c]) * inv_h2;
-            int ebits = 0;
-            if (bound > 0.0 && bound < 1e300) frexp(bound, &ebits);   // bound < 2^ebits
-            const int S = 30 - ebits;
-            const float scale_f = (bound > 0.0 && bound < 1e300) ? ldexpf(1.0f, S) : 0.0f;
-            const float lim = 1073741824.0f;            // 2^30
-            const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
-            const float *Fc = c == 0 ? Fx : (c == 1 ? Fy : Fz);
             lds_barrier();
+            // The tile's largest finite |c_l F_l| (written with c_l F_l by the
+            // build, or k_spread_coef) sets its scale: with |phi_k| <= 4 every
+            // scaled contribution stays below 2^30 (converted to int32, summed
+            // in int64), |c_l F_l| is scaled below 2^28, and the quantum is
+            // 2^-30 of 4 max |c_l F_l| over the tile.  A non-finite c_l F_l is
+            // left out of the maximum and fails the range test below.
+            const float fm = __uint_as_float(tmax[c * tstride + t]);
+            int ebits = 0;
+            frexpf(fm, &ebits);                    // fm < 2^ebits
+            const int S = min(28 - ebits, 126);
+            const float scale_f = fm > 0.f ? ldexpf(1.0f, S) : 0.0f;
+            const float lim = 1073741824.0f;       // 2^30
+            const int nxc = g.dims[c][0], nyc = g.dims[c][1], nzc = g.dims[c][2];
             for (uint32_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
-                // tile order: the row is the entry and A_l F_l comes by row, so
-                // no load waits for the marker index (read on the error path only)
-                const uint32_t m = SORTED ? 0u : entries[e];
-                const int64_t row = SORTED ? (int64_t)e : (int64_t)m;
+                // tile order: the row is the entry, so no load waits for the
+                // marker index (read on the error path only)
+                const int64_t row = SORTED ? (int64_t)e : (int64_t)entries[e];
                 int hi, hj, hk;
                 unpack_home(home[home_at(row, c)], hi, hj, hk);
-                const float af = SORTED ? af_rows[c * af_stride + e] : area[m] * Fc[m];
+                const float cfv = cf[c * cf_stride + row];
                 float ph[kNe];
                 if constexpr (NF == 0) {
                     const float *p = phi + phi_at(row, c);
@@ -549,9 +514,9 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                     for (int k = 0; k < kNe; ++k) ph[k] = p[k * kLanes];
                 } else {
                     const float *cr = coef + ((((row >> 6) * 3 + c) * NF) << 6) + (row & 63);
-                    float cf[NF];
+                    float cfr[NF];
 #pragma unroll
-                    for (int j = 0; j < NF; ++j) cf[j] = cr[j * kLanes];
+                    for (int j = 0; j < NF; ++j) cfr[j] = cr[j * kLanes];
                     // evaluated for every row (all loads issue at once); a row the
                     // build solved in FP64 has a NaN gamma_0 and its stored phi is
                     // read instead, under a wavefront-wide test
@@ -559,18 +524,18 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
                         if constexpr (NF == 7) {
-                            sv[d][1] = cf[4 + d];
+                            sv[d][1] = cfr[4 + d];
                             sv[d][0] = sv[d][1] - 1.0f;
                             sv[d][2] = sv[d][1] + 1.0f;
                         } else {
 #pragma unroll
-                            for (int a = 0; a < 3; ++a) sv[d][a] = cf[4 + 3 * d + a];
+                            for (int a = 0; a < 3; ++a) sv[d][a] = cfr[4 + 3 * d + a];
                         }
 #pragma unroll
                         for (int a = 0; a < 3; ++a) wv[d][a] = weight1(W, sv[d][a]);
                     }
-                    phi_from_gamma(wv, sv, cf, ph);
-                    const bool stored = cf[0] != cf[0];
+                    phi_from_gamma(wv, sv, cfr, ph);
+                    const bool stored = cfr[0] != cfr[0];
                     if (__any(stored)) {
                         if (stored) {
                             const float *p = phi + phi_at(row, c);
@@ -579,73 +544,70 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
                         }
                     }
                 }
-                int gx[3], gy[3], gz[3], ix[3], iy[3], iz[3];
+                int ix[3], iy[3], iz[3];
                 bool inbox = true;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    gx[a] = nb_index(hi, a - 1, nxc, AX.periodic);
-                    gy[a] = nb_index(hj, a - 1, nyc, AY.periodic);
-                    gz[a] = nb_index(hk, a - 1, nzc, AZ.periodic);
-                    ix[a] = box_local(AX, g.ntile[0], nxc, b0x, gx[a]);
-                    iy[a] = box_local(AY, g.ntile[1], nyc, b0y, gy[a]);
-                    iz[a] = box_local(AZ, g.ntile[2], nzc, b0z, gz[a]);
-                    inbox = inbox && (unsigned)ix[a] < (unsigned)bx && (unsigned)iy[a] < (unsigned)by &&
-                            (unsigned)iz[a] < (unsigned)bz;
-                }
-                if (!inbox) {           // cannot happen for a home written by the build
-                    raise_error(err, SORTED ? entries[e] : m, MLS_E_RANGE);
-                    continue;
-                }
-                float hl = 0.f, den = 0.f;
-                if (cw > 0.f) {
-                    // every width equals cw: the same sums as below without the
-                    // width tables
-                    const float s3 = cw + cw + cw, p3 = cw * cw * cw;
-#pragma unroll
-                    for (int k = 0; k < kNe; ++k) {
-                        hl += ph[k] * s3;
-                        den += ph[k] * p3;
-                    }
+                if constexpr (BX > 0) {
+                    // the support's first node on each axis; the others follow it
+                    ix[0] = box_local(AX, g.ntile[0], nxc, b0x, nb_index(hi, -1, nxc, AX.periodic));
+                    iy[0] = box_local(AY, g.ntile[1], nyc, b0y, nb_index(hj, -1, nyc, AY.periodic));
+                    iz[0] = box_local(AZ, g.ntile[2], nzc, b0z, nb_index(hk, -1, nzc, AZ.periodic));
+                    inbox = (unsigned)ix[0] <= (unsigned)(BX - 3) && (unsigned)iy[0] <= (unsigned)(by - 3) &&
+                            (unsigned)iz[0] <= (unsigned)(bz - 3);
                 } else {
-                    float wx[3], wy[3], wz[3];
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        wx[a] = width_of(AX, c == 0, gx[a]);
-                        wy[a] = width_of(AY, c == 1, gy[a]);
-                        wz[a] = width_of(AZ, c == 2, gz[a]);
-                    }
-#pragma unroll
-                    for (int k = 0; k < kNe; ++k) {
-                        const int a = k % 3, b = (k / 3) % 3, cz = k / 9;
-                        hl += ph[k] * (wx[a] + wy[b] + wz[cz]);
-                        den += ph[k] * (wx[a] * wy[b] * wz[cz]);
+                        ix[a] = box_local(AX, g.ntile[0], nxc, b0x, nb_index(hi, a - 1, nxc, AX.periodic));
+                        iy[a] = box_local(AY, g.ntile[1], nyc, b0y, nb_index(hj, a - 1, nyc, AY.periodic));
+                        iz[a] = box_local(AZ, g.ntile[2], nzc, b0z, nb_index(hk, a - 1, nzc, AZ.periodic));
+                        inbox = inbox && (unsigned)ix[a] < (unsigned)bx && (unsigned)iy[a] < (unsigned)by &&
+                                (unsigned)iz[a] < (unsigned)bz;
                     }
                 }
-                // c_l F_l = A_l h_l F_l / sum_k phi_k dV_k   (eq. 8), pre-scaled
-                const float vsc = af * (hl * (1.0f / 3.0f)) / den * scale_f;
+                if (!inbox) {           // cannot happen for a home written by the build
+                    raise_error(err, SORTED ? (int64_t)entries[e] : row, MLS_E_RANGE);
+                    continue;
+                }
+                // c_l F_l (eq. 8), pre-scaled
+                const float vsc = cfv * scale_f;
                 // Rounding is monotonic, so |phi_k vsc| <= max_k |phi_k| |vsc| for
                 // every k, with equality at the largest: one comparison bounds all
-                // 27 scaled contributions.  A NaN or infinity in phi or the force
-                // reaches vsc through hl, den or af and fails it too.
+                // 27 scaled contributions.  A NaN or infinity in the force or the
+                // coefficient reaches vsc and fails it too (one in phi reaches c_l
+                // through h_l and the denominator of eq. 8).
                 float pm = 0.f;
 #pragma unroll
                 for (int k = 0; k < kNe; ++k) pm = fmaxf(pm, fabsf(ph[k]));
                 if (!(fabsf(vsc) * pm < lim)) {
-                    raise_error(err, SORTED ? entries[e] : m, MLS_E_RANGE);
+                    raise_error(err, SORTED ? (int64_t)entries[e] : row, MLS_E_RANGE);
                     continue;
                 }
-                // byte offsets of the box rows (b, cz) and columns a
-                uint32_t rowo[9], colo[3];
+                // truncation toward zero: within one quantum, the same on every run
+                if constexpr (BX > 0) {
+                    // byte address of the first node per z layer; node (a, b) of a
+                    // layer sits (b BX + a) nodes further
+                    char *const a0 = reinterpret_cast<char *>(acc) +
+                                     (uint32_t)__umul24(__umul24(iz[0], by) + iy[0], BX) * 8u + (uint32_t)ix[0] * 8u;
+                    const uint32_t zs = (uint32_t)(by * BX) * 8u;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) colo[a] = (uint32_t)ix[a] * 8u;
+                    for (int k = 0; k < kNe; ++k) {
+                        const long long qv = (long long)(int)(ph[k] * vsc);
+                        char *const p = a0 + (k / 9) * zs + (((k / 3) % 3) * BX + (k % 3)) * 8;
+                        atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)qv);
+                    }
+                } else {
+                    // byte offsets of the box rows (b, cz) and columns a
+                    uint32_t rowo[9], colo[3];
 #pragma unroll
-                for (int r = 0; r < 9; ++r) rowo[r] = (uint32_t)((iz[r / 3] * by + iy[r % 3]) * bx) * 8u;
+                    for (int a = 0; a < 3; ++a) colo[a] = (uint32_t)ix[a] * 8u;
 #pragma unroll
-                for (int k = 0; k < kNe; ++k) {
-                    const long long qv = (long long)(int)rintf(ph[k] * vsc);
-                    atomicAdd(reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(acc) + rowo[k / 3] +
-                                                                     colo[k % 3]),
-                              (unsigned long long)qv);
+                    for (int r = 0; r < 9; ++r) rowo[r] = (uint32_t)((iz[r / 3] * by + iy[r % 3]) * bx) * 8u;
+#pragma unroll
+                    for (int k = 0; k < kNe; ++k) {
+                        const long long qv = (long long)(int)(ph[k] * vsc);
+                        atomicAdd(reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(acc) +
+                                                                         rowo[k / 3] + colo[k % 3]),
+                                  (unsigned long long)qv);
+                    }
                 }
             }
             lds_barrier();
@@ -658,10 +620,51 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, int64_t n, const uint32
             const bool inside = b0x >= 0 && b0y >= 0 && b0z >= 0 && b0x + bx <= nxc && b0y + by <= nyc &&
                                 b0z + bz <= nzc;
             if (inside)
-                flush_box<true>(g, c, acc, bnodes, bx, by, b0x, b0y, b0z, nxc, nyc, nzc, inv_bx, inv_bxy, qscale, f);
+                flush_box<true, BX>(g, c, acc, bnodes, bx, by, b0x, b0y, b0z, nxc, nyc, nzc, inv_bx, inv_by, inv_bxy,
+                                    qscale, f);
             else
-                flush_box<false>(g, c, acc, bnodes, bx, by, b0x, b0y, b0z, nxc, nyc, nzc, inv_bx, inv_bxy, qscale, f);
-            lds_barrier();
+                flush_box<false, BX>(g, c, acc, bnodes, bx, by, b0x, b0y, b0z, nxc, nyc, nzc, inv_bx, inv_by, inv_bxy,
+                                     qscale, f);
+        }
+        lds_barrier();
+    }
+}
+
+// c_l F_l (eq. 8) by marker for a standalone spreading call, from the stored
+// shape functions, homes, areas and forces.  A marker whose homes are not
+// usable gets 0 (the binning leaves it out).
+// It also records the largest finite |c_l F_l| per tile (marker_tile from
+// the binning) and component in tmax.
+__global__ void __launch_bounds__(kBlock)
+k_spread_coef(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home,
+              const float *__restrict__ phi, const float *__restrict__ area, const float *__restrict__ Fx,
+              const float *__restrict__ Fy, const float *__restrict__ Fz, float *__restrict__ cf, int64_t cf_stride,
+              const uint32_t *__restrict__ marker_tile, uint32_t *__restrict__ tmax, int64_t tstride)
+{
+    const Grid &g = *gp;
+    // wave-uniform loop bound: every lane takes part in the per-tile maxima
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = xcd_block() * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
+        const int64_t l = base + (threadIdx.x & 63);
+        const bool in = l < n;
+        const float a = in ? area[l] : 0.f;
+        const uint32_t tl = in ? marker_tile[l] : (uint32_t)g.ntiles;
+        const int64_t key = tl < (uint32_t)g.ntiles ? (int64_t)tl : -1;
+#pragma unroll 1
+        for (int c = 0; c < 3; ++c) {
+            int hi = 0, hj = 0, hk = 0;
+            if (in) unpack_home(home[home_at(l, c)], hi, hj, hk);
+            float v = 0.0f;
+            if (in && home_ok(g, c, hi, hj, hk)) {
+                const float *p = phi + phi_at(l, c);
+                float ph[kNe];
+#pragma unroll
+                for (int k = 0; k < kNe; ++k) ph[k] = p[k * kLanes];
+                const float Fc = c == 0 ? Fx[l] : (c == 1 ? Fy[l] : Fz[l]);
+                v = eq8_coef(g, c, hi, hj, hk, ph, a * Fc);
+            }
+            if (in) cf[c * cf_stride + l] = v;
+            wave_key_max(tmax + c * tstride, key, finite_abs(v));
         }
     }
 }
@@ -676,26 +679,58 @@ int grid_for(int64_t work, int cu)
 
 }  // namespace
 
-template <bool SORTED, int NF>
-static hipError_t launch_tiles(Ctx &c, int64_t n, const uint32_t *home, const float *phi, const float *area,
-                               const float *Fx, const float *Fy, const float *Fz, float *fx, float *fy, float *fz,
-                               hipStream_t s)
+size_t spread_lds_bytes(const Ctx &c)
 {
-    const size_t lds = (size_t)c.g.box[0] * c.g.box[1] * c.g.box[2] * sizeof(unsigned long long);
+    return (size_t)c.g.box[0] * c.g.box[1] * c.g.box[2] * sizeof(unsigned long long);
+}
+
+template <bool SORTED, int NF, int BX>
+static hipError_t launch_tiles_bx(Ctx &c, const uint32_t *home, const float *phi, float *fx, float *fy, float *fz,
+                                  hipStream_t s)
+{
+    const size_t lds = spread_lds_bytes(c);
     const int persist = c.cu_count * c.spread_blocks_per_cu;
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_spread_colour<SORTED, NF>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_spread_colour<SORTED, NF, BX>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     TimedLaunch tt(c, MLS_K_SPREAD_TILES, s);
     for (int col = 0; col < 27; ++col) {
         if (c.colour_tiles[col] == 0) continue;
-        hipLaunchKernelGGL((k_spread_colour<SORTED, NF>), dim3(persist), dim3(c.spread_threads), lds, s, c.d_grid, col, n, home,
-                           phi, area, Fx, Fy, Fz, fx, fy, fz, c.tile_off, c.entries, c.tile_active, c.work, c.work + 64,
-                           SORTED ? c.af_rows : nullptr, c.af_stride, NF ? c.coef_rows : nullptr, c.w, c.err);
+        hipLaunchKernelGGL((k_spread_colour<SORTED, NF, BX>), dim3(persist), dim3(c.spread_threads), lds, s, c.d_grid,
+                           col, home, phi, c.cf_rows, c.cf_stride, fx, fy, fz, c.tile_off, c.entries, c.tile_active,
+                           c.work, NF ? c.coef_rows : nullptr, c.w, c.tile_fmax, c.g.ntiles + 1, c.err);
     }
     return hipGetLastError();
+}
+
+// The box-row length the tile kernels are specialised for: the boxes of tile
+// edges 4, 6, 8, 10, 12 and 16 on grids whose every axis has several tiles;
+// 0 (the general kernel) otherwise.
+static int box_row_template(const Ctx &c)
+{
+    const Grid &g = c.g;
+    if (g.ntile[0] < 2 || g.ntile[1] < 2 || g.ntile[2] < 2) return 0;
+    switch (g.box[0]) {
+    case 7: case 9: case 11: case 13: case 15: case 19: return g.box[0];
+    default: return 0;
+    }
+}
+
+template <bool SORTED, int NF>
+static hipError_t launch_tiles(Ctx &c, const uint32_t *home, const float *phi, float *fx, float *fy, float *fz,
+                               hipStream_t s)
+{
+    switch (box_row_template(c)) {
+    case 7: return launch_tiles_bx<SORTED, NF, 7>(c, home, phi, fx, fy, fz, s);
+    case 9: return launch_tiles_bx<SORTED, NF, 9>(c, home, phi, fx, fy, fz, s);
+    case 11: return launch_tiles_bx<SORTED, NF, 11>(c, home, phi, fx, fy, fz, s);
+    case 13: return launch_tiles_bx<SORTED, NF, 13>(c, home, phi, fx, fy, fz, s);
+    case 15: return launch_tiles_bx<SORTED, NF, 15>(c, home, phi, fx, fy, fz, s);
+    case 19: return launch_tiles_bx<SORTED, NF, 19>(c, home, phi, fx, fy, fz, s);
+    default: return launch_tiles_bx<SORTED, NF, 0>(c, home, phi, fx, fy, fz, s);
+    }
 }
 
 hipError_t launch_interp(const Ctx &c, int64_t n, const uint32_t *home, const float *phi,
@@ -721,19 +756,21 @@ hipError_t launch_spread(Ctx &c, int64_t n, const uint32_t *home, const float *p
         TimedLaunch tb(c, MLS_K_SPREAD_BIN, s);
         hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(nt, c.cu_count)), dim3(kBlock), 0, s, c.tile_count, nt);
         const int gbin = grid_for(n, c.cu_count);
-        hipLaunchKernelGGL(k_bin<false>, dim3(gbin), dim3(kBlock), 0, s, c.d_grid, n, home,
-                           c.tile_count, c.tile_cursor, c.entries, c.err, area, Fx, Fy, Fz, c.block_fmax);
+        hipLaunchKernelGGL(k_bin<false>, dim3(gbin), dim3(kBlock), 0, s, c.d_grid, n, home, c.tile_count,
+                           c.tile_cursor, c.entries, c.marker_tile, c.err);
         hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)nb), dim3(kBlock), 0, s, c.tile_count, nt, c.block_sums);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, c.block_sums, nb, c.block_fmax, gbin,
-                           c.work + 64);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, c.block_sums, nb);
         hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kBlock), 0, s, c.tile_count, nt, c.block_sums,
-                           c.tile_off, c.tile_cursor, c.work);
+                           c.tile_off, c.tile_cursor, c.work, c.tile_fmax, nt + 1);
         hipLaunchKernelGGL(k_bin<true>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, home,
-                           c.tile_count, c.tile_cursor, c.entries, c.err, area, Fx, Fy, Fz, c.work + 64);
+                           c.tile_count, c.tile_cursor, c.entries, c.marker_tile, c.err);
         hipLaunchKernelGGL(k_active_tiles, dim3((unsigned)((nt + kActiveChunk - 1) / kActiveChunk)), dim3(kBlock), 0,
                            s, c.d_grid, c.tile_off, c.tile_active, c.work);
+        hipLaunchKernelGGL(k_spread_coef, dim3((unsigned)round_up8(grid_for(n, c.cu_count))), dim3(kBlock), 0, s,
+                           c.d_grid, n, home, phi, area, Fx, Fy, Fz, c.cf_rows, c.cf_stride, c.marker_tile,
+                           c.tile_fmax, nt + 1);
     }
-    return launch_tiles<false, 0>(c, n, home, phi, area, Fx, Fy, Fz, fx, fy, fz, s);
+    return launch_tiles<false, 0>(c, home, phi, fx, fy, fz, s);
 }
 
 hipError_t launch_sort_positions(Ctx &c, int64_t n, const float *x, const float *y, const float *z, hipStream_t s,
@@ -748,18 +785,17 @@ hipError_t launch_sort_positions(Ctx &c, int64_t n, const float *x, const float 
     hipLaunchKernelGGL(k_bin_pos<false>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, x, y, z,
                        c.tile_count, c.tile_cursor, c.entries, c.marker_tile, jx, jy, jz, amp2, seed, c.step_ctr);
     hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)nb), dim3(kBlock), 0, s, c.tile_count, nt, c.block_sums);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, c.block_sums, nb, c.block_fmax, 0, c.work + 64);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, c.block_sums, nb);
     hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kBlock), 0, s, c.tile_count, nt, c.block_sums,
-                       c.tile_off, c.tile_cursor, c.work);
+                       c.tile_off, c.tile_cursor, c.work, c.tile_fmax, c.g.ntiles + 1);
     hipLaunchKernelGGL(k_bin_pos<true>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, x, y, z,
                        c.tile_count, c.tile_cursor, c.entries, c.marker_tile, nullptr, nullptr, nullptr, 0.0f,
                        (uint64_t)0, c.step_ctr);
     return hipGetLastError();
 }
 
-hipError_t launch_spread_sorted(Ctx &c, int64_t n, const uint32_t *home, const float *phi, const float *area,
-                                const float *Fx, const float *Fy, const float *Fz, float *fx, float *fy, float *fz,
-                                hipStream_t s)
+hipError_t launch_spread_sorted(Ctx &c, int64_t n, const uint32_t *home, const float *phi, float *fx, float *fy,
+                                float *fz, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const int64_t nt = c.g.ntiles;
@@ -768,16 +804,12 @@ hipError_t launch_spread_sorted(Ctx &c, int64_t n, const uint32_t *home, const f
         // colour list sizes and tile cursors start at zero on every call (the
         // call may follow another spreading of the same sort)
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBlock), 0, s, c.work, (int64_t)64);
-        // force bound from the build's per-block maxima (no scan: nb = 0)
-        // (a compact step's FP64 rows keep their maximum in one more slot)
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, c.block_sums, (int64_t)0, c.block_fmax,
-                           build_blocks(c, n) + (c.step_nf ? 1 : 0), c.work + 64);
         hipLaunchKernelGGL(k_active_tiles, dim3((unsigned)((nt + kActiveChunk - 1) / kActiveChunk)), dim3(kBlock), 0,
                            s, c.d_grid, c.tile_off, c.tile_active, c.work);
     }
-    if (c.step_nf == 7) return launch_tiles<true, 7>(c, n, home, phi, area, Fx, Fy, Fz, fx, fy, fz, s);
-    if (c.step_nf == 13) return launch_tiles<true, 13>(c, n, home, phi, area, Fx, Fy, Fz, fx, fy, fz, s);
-    return launch_tiles<true, 0>(c, n, home, phi, area, Fx, Fy, Fz, fx, fy, fz, s);
+    if (c.step_nf == 7) return launch_tiles<true, 7>(c, home, phi, fx, fy, fz, s);
+    if (c.step_nf == 13) return launch_tiles<true, 13>(c, home, phi, fx, fy, fz, s);
+    return launch_tiles<true, 0>(c, home, phi, fx, fy, fz, s);
 }
 
 }  // namespace mls

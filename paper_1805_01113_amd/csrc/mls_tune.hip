@@ -155,7 +155,7 @@ mls_status mls_tune_set(mls_ctx *ctx, const mls_tune *in)
         const mls_status st = setup_tiles(c, in->spread_tile);
         if (st != MLS_OK) return st;
     } else {
-        const int64_t lds = (int64_t)c.g.box[0] * c.g.box[1] * c.g.box[2] * 8;
+        const int64_t lds = (int64_t)spread_lds_bytes(c);
         c.spread_blocks_per_cu = std::max(1, std::min(c.spread_blocks_per_cu_req, (int)((160 * 1024) / (lds + 512))));
     }
     return MLS_OK;
@@ -227,8 +227,8 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, int32_t flags, const mls_s
     auto interp = [&]() { return mls_interp(ctx, n, b->home, b->phi, b->u, b->v, b->w, U, V, Wv, stream); };
     auto spread = [&]() {
         if (exact)
-            return launch_spread_sorted(c, n, b->home, b->phi, b->area, F, F + n, F + 2 * n, b->fx, b->fy, b->fz,
-                                        s) == hipSuccess ? MLS_OK : MLS_E_HIP;
+            return launch_spread_sorted(c, n, b->home, b->phi, b->fx, b->fy, b->fz, s) == hipSuccess ? MLS_OK
+                                                                                                     : MLS_E_HIP;
         return mls_spread(ctx, n, b->home, b->phi, b->area, F, F + n, F + 2 * n, b->fx, b->fy, b->fz, stream);
     };
     bool ok = true;
@@ -281,7 +281,7 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, int32_t flags, const mls_s
             int last_eff = -1;
             c.spread_threads = th;
             for (int v : spcs) {
-                const int64_t lds = (int64_t)c.g.box[0] * c.g.box[1] * c.g.box[2] * 8;
+                const int64_t lds = (int64_t)spread_lds_bytes(c);
                 const int eff = std::max(1, std::min(v, (int)((160 * 1024) / (lds + 512))));
                 if (eff == last_eff) continue;
                 last_eff = eff;

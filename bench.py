@@ -178,6 +178,42 @@ def per_body_rate(torch, ctx, wl, bufs, fields, forcing, x0, y0, z0, area, metho
     return int(offs[sub]) / (t_b - t_a)
 
 
+def byte_models(method, compact, nf, t_per, jitter_kernel):
+    """Algorithmic bytes per marker of each timed kernel, two ways.
+
+    survey: the hot-path contract's figures (transfer functions stored as 27
+    FP32 values and read back): build 12 + 12 + 324 = 348, interpolation
+    336 + 12 + 4T, spreading 336 + 12 + 4 + 8T (T = touched (component, node)
+    pairs per marker); a fused kernel carries the sum of the phases it does.
+    own: what this implementation's kernel has to move at least once (compact
+    rows of nf floats for an exact step, c_l F_l by row, U and F by marker)."""
+    tf = 4.0 * 3 * (nf if compact else 27)
+    survey = {
+        "build_exact": 348.0, "build_fast": 348.0, "build_learned": 348.0,
+        "interp": 336 + 12 + 4.0 * t_per,
+        "build_interp": 348 + 336 + 12 + 4.0 * t_per,
+        "fast_interp": 348 + 336 + 12 + 4.0 * t_per,
+        "spread_tiles": 336 + 12 + 4 + 8.0 * t_per,
+    }
+    own = {
+        "jitter": 24.0,
+        "build_exact": 12 + 12 + 324.0, "build_fast": 12 + 12 + 324.0, "build_learned": 12 + 12 + 324.0,
+        "interp": 12 + 324 + 12 + 4.0 * t_per,
+        # positions and area, homes, transfer functions, touched field values,
+        # U and F by marker, c_l F_l by row
+        "build_interp": 16 + 12 + tf + 4.0 * t_per + 12 + 12 + 12,
+        "fast_interp": 16 + 12 + 324 + 4.0 * t_per + 12 + 12 + 12,
+        "force": 24.0,
+        # homes, transfer functions, c_l F_l by row, read-modify-write of the
+        # touched field values
+        "spread_tiles": 12 + (tf if method == 0 else 324) + 12 + 8.0 * t_per,
+        # positions (and the jitter's read and write when the binning does it)
+        # the tile of each marker, the sorted marker list
+        "spread_bin": (24.0 if jitter_kernel else 36.0) + 8.0,
+    }
+    return survey, own
+
+
 def compare_methods(torch, ctx, wl, bufs, fields, forcing, x0, y0, z0, area, jitter, seed, args, ms_main,
                     main_method):
     """{per-body, batched} x {exact, fast, learned}: markers/s, and the
@@ -239,6 +275,95 @@ def compare_methods(torch, ctx, wl, bufs, fields, forcing, x0, y0, z0, area, jit
             % (name, ms, n / (ms * 1e-3), rate, err,
                (", fallback rate %.4f" % row["fallback_rate"]) if "fallback_rate" in row else ""))
         out[name] = row
+    return out
+
+
+def config_matrix(torch, args, names=("sphere", "ellipsoids", "stretched")):
+    """The other workloads of the hot path (one sphere on 64^3; 1,000
+    ellipsoids on 512^3; 2,000 spheres in the tanh-stretched 512x512x768
+    channel): every method's batched step (graph replays, autotuned shapes),
+    its interpolation error against exact MLS on the same jittered positions,
+    the learned method's fallback rate, and the dominant kernel's HBM
+    fraction on the contract's bytes."""
+    from paper_1805_01113_amd import mls
+    from paper_1805_01113_amd import workloads as W
+    out = {}
+    stream = torch.cuda.current_stream()
+    for name in names:
+        t0 = time.time()
+        wl = make_workload(name)
+        n = wl.n
+        x0, y0, z0 = [torch.from_numpy(a).cuda() for a in (wl.x, wl.y, wl.z)]
+        area = torch.from_numpy(wl.area).cuda()
+        fields = [W.fourier_field(wl.grid, c, wl.modes[c], wl.lengths, device="cuda") for c in range(3)]
+        forcing = [torch.zeros(wl.grid.shape(c), dtype=torch.float32, device="cuda") for c in range(3)]
+        ctx = mls.Context(wl.grid.faces, wl.grid.periodic)
+        ctx.reserve(n)
+        net = load_network(ctx, args.weights)
+        bufs = mls.StepBuffers(ctx, x0, y0, z0, area, fields, forcing)
+        nf = 7 if all(wl.grid.uniform_axis(d) for d in range(3)) else 13
+        jitter = 0.1 * wl.grid.h_min
+        seed = 20180503
+        row = {"markers": n, "bodies": int(len(wl.body_offsets) - 1), "grid": list(wl.grid.n), "methods": {}}
+        ref = None
+        t_per = None
+        names_m = ["exact", "fast", "fast_linear"] + (["learned"] if net is not None else [])
+        for mname in names_m:
+            m = METHODS[mname]
+            compact = m == mls.MLS_EXACT
+            if not args.no_tune:
+                ctx.autotune(bufs, method=m, cache_path=args.tune_cache, compact=compact)
+            # interpolation error against exact MLS at a fixed jitter counter
+            mls.step_counter_set(ctx, 1 << 20)
+            ctx.stats_reset()
+            mls.step(ctx, bufs, method=m, dt=1.0, jitter=jitter, seed=seed, compact=compact)
+            ctx.sync()
+            U = bufs.U.clone()
+            if ref is None:
+                ref = U
+                t_per = touched_nodes(torch, ctx, bufs.home, n) / n
+            r = {"interp_err_vs_exact": float((U - ref).abs().max().item() / ref.abs().max().item())}
+            if m == mls.MLS_LEARNED:
+                st = ctx.stats()
+                r["fallback_rate"] = st["fallbacks"] / max(1, st["learned"] + st["fallbacks"])
+            g = mls.StepGraph(ctx, bufs, method=m, dt=1.0, jitter=jitter, seed=seed, compact=compact)
+            g.launch(args.warmup)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            g.launch(args.steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ctx.sync()
+            ms = e0.elapsed_time(e1) / max(args.steps, 1)
+            g.close()
+            r["batched"] = {"ms_per_step": round(ms, 4), "markers_per_s": round(n / (ms * 1e-3), 1)}
+            # per-kernel times of eager steps: the dominant kernel's roofline
+            mls.timing_enable(ctx, True)
+            mls.timing_get(ctx, reset=True)
+            for _ in range(args.steps):
+                mls.step(ctx, bufs, method=m, dt=1.0, jitter=jitter, seed=seed, compact=compact)
+            torch.cuda.synchronize()
+            kt = mls.timing_get(ctx, reset=True)
+            mls.timing_enable(ctx, False)
+            ctx.sync()
+            survey, _ = byte_models(m, compact, nf, t_per, "jitter" in kt)
+            times = {k: v[0] / v[1] for k, v in kt.items()}
+            dom = max((k for k in times if survey.get(k)), key=lambda k: times[k])
+            gbs = survey[dom] * n / (times[dom] * 1e-3) / 1e9
+            r["kernels_ms"] = {k: round(v, 4) for k, v in times.items()}
+            r["roofline"] = {"kernel": dom, "achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                             "alg_bytes_per_marker": round(survey[dom], 1)}
+            row["methods"][mname] = r
+            log("%s %s: %.3f ms/step (%.3e markers/s), err vs exact %.2e, dominant %s %.1f%% of HBM"
+                % (name, mname, ms, n / (ms * 1e-3), r["interp_err_vs_exact"], dom, 100 * gbs / HBM_PEAK_GBS))
+        row["touched_nodes_per_marker"] = round(t_per, 3)
+        row["seconds"] = round(time.time() - t0, 1)
+        out[wl.name] = row
+        ctx.close()
+        del bufs, fields, forcing, x0, y0, z0, area, ref, U
+        torch.cuda.empty_cache()
     return out
 
 
@@ -354,6 +479,7 @@ def main():
     ap.add_argument("--full-phi", action="store_true",
                     help="exact steps store all 27 shape-function values per row instead of the compact form")
     ap.add_argument("--no-extra", action="store_true", help="skip the eager / per-body / fast comparisons")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other workloads' method matrix")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -454,46 +580,50 @@ def main():
     ctx.sync()
     T = touched_nodes(torch, ctx, bufs.home, n)
     t_per = T / n
-    # algorithmic bytes per marker: what each kernel must move at least once;
-    # the transfer function of a row is 27 floats, or nf in the compact form
-    tf = 4.0 * 3 * (nf if compact else 27)
-    alg = {
-        "jitter": 24.0,
-        "build_exact": 12 + 12 + 324.0,
-        "build_fast": 12 + 12 + 324.0,
-        "build_learned": 12 + 12 + 324.0,
-        "interp": 12 + 324 + 12 + 4.0 * t_per,
-        # positions, homes, phi, touched field values, U and F by marker, A F by row
-        "build_interp": 12 + 12 + tf + 4.0 * t_per + 12 + 12 + 12,
-        "fast_interp": 12 + 12 + 324 + 4.0 * t_per + 12 + 12 + 12,
-        "force": 24.0,
-        # homes, phi, A F by row (tile order; by marker for the standalone spreading:
-        # A and F, 16 bytes), read-modify-write of the touched field values
-        "spread_tiles": 12 + (tf if method == mls.MLS_EXACT else 324) + 12 + 8.0 * t_per,
-        # the sorted step jitters inside its binning pass (x0 read, x written)
-        "spread_bin": 0.0 if "jitter" in kt else 24.0,
-    }
+    survey, own = byte_models(method, compact, nf, t_per, "jitter" in kt)
     kernels = {}
     for k, (ms, cnt) in kt.items():
         avg = ms / cnt
-        b = alg.get(k, 0.0) * n
-        kernels[k] = {"avg_ms": round(avg, 4), "launches": cnt, "alg_bytes": int(b),
-                      "GBs": round(b / (avg * 1e-3) / 1e9, 1) if b else None}
-    dom = max(((k, v) for k, v in kernels.items() if v["alg_bytes"]), key=lambda kv: kv[1]["avg_ms"])
-    step_bytes = sum(alg.get(k, 0.0) for k in kernels) * n
+        kernels[k] = {"avg_ms": round(avg, 4), "launches": cnt}
+        if survey.get(k):
+            kernels[k]["survey_bytes_per_marker"] = round(survey[k], 1)
+            kernels[k]["GBs_survey_bytes"] = round(survey[k] * n / (avg * 1e-3) / 1e9, 1)
+        if own.get(k):
+            kernels[k]["kernel_bytes_per_marker"] = round(own[k], 1)
+            kernels[k]["GBs_kernel_bytes"] = round(own[k] * n / (avg * 1e-3) / 1e9, 1)
+    dom = max(((k, v) for k, v in kernels.items() if survey.get(k)), key=lambda kv: kv[1]["avg_ms"])
+    step_survey = sum(survey.get(k, 0.0) for k in kernels) * n
+    step_own = sum(own.get(k, 0.0) for k in kernels) * n
     log("eager: %.3f ms/step; kernels: %s" % (ms_eager, json.dumps(kernels)))
-    roof = {"bound": "hbm", "kernel": dom[0], "achieved": dom[1]["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(dom[1]["GBs"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom[0], wl.name, step_cfg),
-            "alg_bytes_per_marker": round(alg[dom[0]], 1), "markers_per_launch": n}
+    traffic = measured_traffic(dom[0], wl.name, step_cfg)
+    achieved = dom[1]["GBs_survey_bytes"]
+    roof = {"bound": "hbm", "kernel": dom[0], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "alg_bytes_per_marker": round(survey[dom[0]], 1), "markers_per_launch": n,
+            "bytes_basis": "the hot-path contract's bytes per marker (Phi stored and read, 27 floats)",
+            "frac_kernel_bytes": round(dom[1].get("GBs_kernel_bytes", 0.0) / HBM_PEAK_GBS, 4),
+            "kernel_bytes_per_marker": round(own.get(dom[0], 0.0), 1),
+            "frac_counter_bytes": (round(traffic / (dom[1]["avg_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                   if traffic else None)}
 
     extra = {"library": lib_version, "ms_per_step_eager": round(ms_eager, 4), "kernels": kernels, "autotune": tune,
              "touched_nodes_per_marker": round(t_per, 3),
-             "step_alg_bytes_per_marker": round(step_bytes / n, 1),
-             "step_hbm_frac": round(step_bytes / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+             "step_survey_bytes_per_marker": round(step_survey / n, 1),
+             "step_hbm_frac_survey_bytes": round(step_survey / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+             "step_kernel_bytes_per_marker": round(step_own / n, 1),
+             "step_hbm_frac_kernel_bytes": round(step_own / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     if not args.no_extra:
         extra["methods"] = compare_methods(torch, ctx, wl, bufs, fields, forcing, x0, y0, z0, area, jitter, seed,
                                            args, ms_graph, method)
+        mt = extra["methods"]
+        if "learned" in mt and "exact" in mt:
+            # the target's status: the learned, batched step against the exact one
+            extra["learned_vs_exact"] = {
+                "speed_ratio": round(mt["learned"]["batched"]["markers_per_s"] /
+                                     mt["exact"]["batched"]["markers_per_s"], 4),
+                "interp_err_vs_exact": mt["learned"]["interp_err_vs_exact"],
+                "fallback_rate": mt["learned"].get("fallback_rate")}
 
         extra["collision"] = collision_cost(torch, ctx, wl, x0, y0, z0, args.steps, ms_graph)
         log("collision detection: %s" % json.dumps(extra["collision"]))
@@ -508,6 +638,15 @@ def main():
         log("cpu baseline (oracle) ...")
         cpu = cpu_baseline(wl, fields, args.cpu_seconds)
         log("cpu baseline: %.3e markers/s on %d threads" % (cpu["value"], cpu["cores"]))
+
+    if not args.no_extra and not args.no_configs:
+        # the main workload's buffers are released first (25.8 GB of fields)
+        graph.close()
+        ctx.close()
+        del bufs, fields, forcing, x0, y0, z0, area
+        torch.cuda.empty_cache()
+        extra["configs"] = config_matrix(torch, args)
+        graph = ctx = None
 
     out = {
         "metric": "markers/s build+interp+spread: learned/batched vs exact MLS, 1 GPU, ≤1e-4 err",
@@ -533,8 +672,9 @@ def main():
     if net_meta is not None:
         extra["surrogate"] = net_meta
     print(json.dumps(out), flush=True)
-    graph.close()
-    ctx.close()
+    if graph is not None:
+        graph.close()
+        ctx.close()
 
 
 if __name__ == "__main__":

@@ -272,6 +272,7 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
         for (float v : wc[d]) if (v != c.g.const_width) c.g.const_width = 0.f;
         for (float v : wf[d]) if (v != c.g.const_width) c.g.const_width = 0.f;
     }
+    c.g.inv_cw2 = c.g.const_width > 0.f ? (float)(1.0 / ((double)c.g.const_width * c.g.const_width)) : 0.f;
     for (int d = 0; d < 3; ++d) {
         c.h_wc[d] = wc[d];
         c.h_wf[d] = wf[d];

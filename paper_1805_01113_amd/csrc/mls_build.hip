@@ -227,7 +227,7 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
         st_stream(&F[c * n + m], ok ? f : nan);
         // c_l F_l (eq. 8) by row for the spreading (row p < cf_stride: padding
         // rows too); a queued compact row gets its U, F and c F from k_route_rows
-        const float cfv = eq8_coef(g, c, G[0].ih, G[1].ih, G[2].ih, ph, ca * f);
+        const float cfv = eq8_coef_built(g, c, G[0].ih, G[1].ih, G[2].ih, ph, ca * f);
         st_stream(&cf_rows[c * cf_stride + base + lane], ok ? cfv : 0.0f);
         if (!ok) {
             raise_error(err, m, isfinite(px) && isfinite(py) && isfinite(pz) ? MLS_E_SUPPORT : MLS_E_NONFINITE);
@@ -299,7 +299,7 @@ k_route_rows(const Grid *__restrict__ gp, const Weight W, int64_t n, const uint3
         const float ca = area[m];
         U[c * n + m] = acc;
         F[c * n + m] = f;
-        const float cfv = eq8_coef(g, c, hi, hj, hk, ph, ca * f);
+        const float cfv = eq8_coef_built(g, c, hi, hj, hk, ph, ca * f);
         cf_rows[c * cf_stride + row] = cfv;
         if (!(fabsf(cfv) <= 3.0e38f)) raise_error(err, m, MLS_E_RANGE);
         const float av = finite_abs(cfv);
@@ -649,7 +649,7 @@ k_fast_interp(const Grid *__restrict__ gp, const float4 *__restrict__ tab, int n
         st_stream(&U[c * n + m], ok ? acc : nan);
         st_stream(&F[c * n + m], ok ? f : nan);
         // c_l F_l (eq. 8) by row for the spreading (row p < cf_stride: padding rows too)
-        const float cfv = eq8_coef(g, c, G[0].ih, G[1].ih, G[2].ih, ph, ca * f);
+        const float cfv = eq8_coef_built(g, c, G[0].ih, G[1].ih, G[2].ih, ph, ca * f);
         st_stream(&cf_rows[c * cf_stride + base + lane], ok ? cfv : 0.0f);
         if (!ok) {
             raise_error(err, m, isfinite(px) && isfinite(py) && isfinite(pz) ? MLS_E_SUPPORT : MLS_E_NONFINITE);

@@ -617,12 +617,25 @@ __device__ __forceinline__ void eq8_sums(const Grid &g, int c, int hi, int hj, i
 }
 
 // c_l F_l of eq. 8 from A_l F_l: the per-row value the spreading scatters as
-// c_l F_l phi_k.
+// c_l F_l phi_k.  Computed with the sums of shape-function values given from
+// outside (a standalone spreading call), so that a non-finite value among
+// them reaches c_l F_l and is reported.
 __device__ __forceinline__ float eq8_coef(const Grid &g, int c, int hi, int hj, int hk, const float ph[kNe], float af)
 {
     float h3, den;
     eq8_sums(g, c, hi, hj, hk, ph, h3, den);
     return af * h3 / den;
+}
+
+// The same for shape functions the library has just computed.  On a grid
+// whose widths all equal w, h_l = w sum_k phi_k and sum_k phi_k dV_k =
+// w^3 sum_k phi_k, so c_l = A_l / w^2 exactly, whatever the (nonzero) sum of
+// the shape functions; elsewhere the sums are taken.
+__device__ __forceinline__ float eq8_coef_built(const Grid &g, int c, int hi, int hj, int hk, const float ph[kNe],
+                                                float af)
+{
+    if (g.inv_cw2 > 0.f) return af * g.inv_cw2;
+    return eq8_coef(g, c, hi, hj, hk, ph, af);
 }
 
 // Per-key maxima of the lanes of a wavefront: for every distinct key >= 0 the

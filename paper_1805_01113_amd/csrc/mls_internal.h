@@ -63,6 +63,7 @@ struct Grid {
     double h_min;         // smallest node spacing over all axes and components
     float const_width;    // the control-volume width when every width of every axis and node kind is
                           // bitwise equal (uniform periodic grids), else 0
+    float inv_cw2;        // 1 / const_width^2 (0 when the widths differ)
 };
 
 // Device error word: lowest offending marker index in the upper 56 bits, the

@@ -196,10 +196,12 @@ mls_status mls_interp(mls_ctx *ctx, int64_t n, const uint32_t *home, const float
  * time); tiles are coloured by the parity of their index per axis (a third
  * colour for the last tile of a periodic axis with an odd tile count) so that
  * boxes of one colour never overlap, and the colours add their boxes into the
- * field one after another.  A contribution larger than the
- * fixed-point bound (|c_l phi_k F_l| > 8 max|A_l F_l| / h_min^2, which a
- * shape function with |phi| <= 2 and sum phi dV close to dV never reaches)
- * raises MLS_E_RANGE. */
+ * field one after another.  The fixed-point scale is chosen per tile and
+ * component from the largest finite |c_l F_l| of the tile's markers (its
+ * quantum is 2^-30 of 4 times that value), so weak forces keep their
+ * precision beside strong ones elsewhere on the grid.  A non-finite
+ * c_l F_l, or a contribution beyond the bound (a shape function with
+ * |phi_k| > 4), raises MLS_E_RANGE at that marker. */
 mls_status mls_spread(mls_ctx *ctx, int64_t n, const uint32_t *home, const float *phi,
                       const float *area, const float *Fx, const float *Fy, const float *Fz,
                       float *fx, float *fy, float *fz, void *stream);

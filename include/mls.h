@@ -206,6 +206,29 @@ mls_status mls_spread(mls_ctx *ctx, int64_t n, const uint32_t *home, const float
                       const float *area, const float *Fx, const float *Fy, const float *Fz,
                       float *fx, float *fy, float *fz, void *stream);
 
+/* Fixed size of the library's scratch array for mls_spread_noalloc (bytes). */
+#define MLS_SPREAD_NOALLOC_BYTES (64u << 20)
+
+/* mls_spread for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, arithmetic, result (bitwise equal to mls_spread's) and errors,
+ * but it calls no hipMalloc, hipFree or allocating library routine and never
+ * grows the context.  Its scratch (tile counts and offsets, binned marker
+ * entries, c_l F_l per marker, per-tile maxima) lives in one fixed device
+ * array of MLS_SPREAD_NOALLOC_BYTES in the library, one copy per GPU, held
+ * from the first context created on that GPU (mls_ctx_create takes its
+ * address) until the process ends.  It needs about
+ *   20 bytes per marker + 28 bytes per spreading tile of the grid
+ * (plus 256-byte alignment of each part); a call that needs more returns
+ * MLS_E_ARG with a message and launches nothing.  Every call on one GPU
+ * shares that GPU's array and overwrites it (whatever must start at zero is
+ * cleared by the call's own kernels): calls that overlap on one GPU, from
+ * any context or stream, race, so order them on one stream or synchronise
+ * between them. */
+mls_status mls_spread_noalloc(mls_ctx *ctx, int64_t n, const uint32_t *home, const float *phi,
+                              const float *area, const float *Fx, const float *Fy, const float *Fz,
+                              float *fx, float *fy, float *fz, void *stream);
+
 /* Derivative shape functions: the gradient with respect to the marker
  * position x of the exact MLS shape functions of eq. 6, Phi(x) =
  * W(x) p^T A(x)^-1 B(x), the weights (and so A and B) moving with the marker;

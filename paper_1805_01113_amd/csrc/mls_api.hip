@@ -351,6 +351,8 @@ mls_status mls_ctx_create(mls_ctx **out, const mls_grid *grid, const mls_weight 
     hipMemset(c.step_ctr, 0, sizeof(unsigned long long));
     const mls_status ts = setup_tiles(c, want_tile);
     if (ts != MLS_OK) { mls_ctx_destroy(ctx); return ts; }
+    // the allocation-free spreading's scratch address on this device
+    if (noalloc_setup(c.device) != hipSuccess) { mls_ctx_destroy(ctx); return MLS_E_HIP; }
     if (hipDeviceSynchronize() != hipSuccess) { mls_ctx_destroy(ctx); return MLS_E_HIP; }
     *out = ctx;
     return MLS_OK;
@@ -514,6 +516,24 @@ mls_status mls_spread(mls_ctx *ctx, int64_t n, const uint32_t *home, const float
     if (st != MLS_OK) return st;
     hipError_t e = launch_spread(ctx->c, n, home, phi, area, Fx, Fy, Fz, fx, fy, fz, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(ctx, e, "spread launch");
+    return MLS_OK;
+}
+
+mls_status mls_spread_noalloc(mls_ctx *ctx, int64_t n, const uint32_t *home, const float *phi, const float *area,
+                              const float *Fx, const float *Fy, const float *Fz, float *fx, float *fy, float *fz,
+                              void *stream)
+{
+    if (!ctx) return MLS_E_ARG;
+    if (n < 0 || n > (int64_t)0x1fffffff) return fail(ctx, MLS_E_ARG, "bad marker count");
+    if (n > 0 && (!home || !phi || !area || !Fx || !Fy || !Fz || !fx || !fy || !fz))
+        return fail(ctx, MLS_E_ARG, "null array");
+    if (n == 0) return MLS_OK;
+    if (noalloc_bytes(ctx->c, n) > (size_t)MLS_SPREAD_NOALLOC_BYTES)
+        return fail(ctx, MLS_E_ARG, "spread_noalloc: markers and grid tiles need more scratch than the fixed "
+                                    "MLS_SPREAD_NOALLOC_BYTES array holds");
+    hipError_t e = launch_spread_noalloc(ctx->c, n, home, phi, area, Fx, Fy, Fz, fx, fy, fz,
+                                         static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(ctx, e, "spread_noalloc launch");
     return MLS_OK;
 }
 

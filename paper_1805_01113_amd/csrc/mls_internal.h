@@ -262,6 +262,15 @@ hipError_t launch_spread_sorted(Ctx &c, int64_t n, const uint32_t *home, const f
 // Dynamic LDS of a spreading tile workgroup: the int64 box of one component.
 size_t spread_lds_bytes(const Ctx &c);
 
+// Allocation-free spreading: its scratch is the library's fixed device array.
+// noalloc_setup takes that array's address on the current device (once per
+// device); noalloc_bytes is the scratch a call of n markers needs.
+hipError_t noalloc_setup(int device);
+size_t noalloc_bytes(const Ctx &c, int64_t n);
+hipError_t launch_spread_noalloc(Ctx &c, int64_t n, const uint32_t *home, const float *phi, const float *area,
+                                 const float *Fx, const float *Fy, const float *Fz, float *fx, float *fy, float *fz,
+                                 hipStream_t s);
+
 hipError_t launch_jitter(const Ctx &c, int64_t n, const float *x0, const float *y0, const float *z0,
                          float *x, float *y, float *z, float amp, uint64_t seed, hipStream_t s);
 hipError_t launch_force(const Ctx &c, int64_t n, const float *vb, const float *U, float dt, float *F,

@@ -74,7 +74,7 @@ hipError_t launch_step_advance(const Ctx &c, hipStream_t s)
 
 TimedLaunch::TimedLaunch(Ctx &c_, int id_, hipStream_t s_) : c(c_), id(id_), s(s_)
 {
-    if (!c.timing || c.capturing) return;
+    if (id < 0 || !c.timing || c.capturing) return;
     while (c.ev_used + 2 > c.ev_pool.size()) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return;

@@ -15,6 +15,8 @@
 // The fixed-point scale of a tile is a power of two chosen from the largest
 // |c_l F_l| (eq. 8) among the tile's markers, so that no sum can overflow and
 // the quantum follows the tile's own forces.
+#include <mutex>
+
 #include "mls_exact.h"
 
 namespace mls {
@@ -684,9 +686,24 @@ size_t spread_lds_bytes(const Ctx &c)
     return (size_t)c.g.box[0] * c.g.box[1] * c.g.box[2] * sizeof(unsigned long long);
 }
 
+// Device buffers of one spreading call: the context's own (mls_spread, the
+// time step) or carved out of the library's fixed array (mls_spread_noalloc).
+struct SpreadScratch {
+    uint32_t *tile_count, *tile_off, *tile_cursor, *tile_active, *block_sums, *work, *tile_fmax, *marker_tile,
+        *entries;
+    float *cf;
+    int64_t cf_stride;
+};
+
+static SpreadScratch ctx_scratch(Ctx &c)
+{
+    return {c.tile_count, c.tile_off, c.tile_cursor, c.tile_active, c.block_sums, c.work, c.tile_fmax,
+            c.marker_tile, c.entries, c.cf_rows, c.cf_stride};
+}
+
 template <bool SORTED, int NF, int BX>
-static hipError_t launch_tiles_bx(Ctx &c, const uint32_t *home, const float *phi, float *fx, float *fy, float *fz,
-                                  hipStream_t s)
+static hipError_t launch_tiles_bx(Ctx &c, const SpreadScratch &sc, const uint32_t *home, const float *phi, float *fx,
+                                  float *fy, float *fz, hipStream_t s, bool timed)
 {
     const size_t lds = spread_lds_bytes(c);
     const int persist = c.cu_count * c.spread_blocks_per_cu;
@@ -695,12 +712,12 @@ static hipError_t launch_tiles_bx(Ctx &c, const uint32_t *home, const float *phi
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    TimedLaunch tt(c, MLS_K_SPREAD_TILES, s);
+    TimedLaunch tt(c, timed ? MLS_K_SPREAD_TILES : -1, s);
     for (int col = 0; col < 27; ++col) {
         if (c.colour_tiles[col] == 0) continue;
         hipLaunchKernelGGL((k_spread_colour<SORTED, NF, BX>), dim3(persist), dim3(c.spread_threads), lds, s, c.d_grid,
-                           col, home, phi, c.cf_rows, c.cf_stride, fx, fy, fz, c.tile_off, c.entries, c.tile_active,
-                           c.work, NF ? c.coef_rows : nullptr, c.w, c.tile_fmax, c.g.ntiles + 1, c.err);
+                           col, home, phi, sc.cf, sc.cf_stride, fx, fy, fz, sc.tile_off, sc.entries, sc.tile_active,
+                           sc.work, NF ? c.coef_rows : nullptr, c.w, sc.tile_fmax, c.g.ntiles + 1, c.err);
     }
     return hipGetLastError();
 }
@@ -719,17 +736,17 @@ static int box_row_template(const Ctx &c)
 }
 
 template <bool SORTED, int NF>
-static hipError_t launch_tiles(Ctx &c, const uint32_t *home, const float *phi, float *fx, float *fy, float *fz,
-                               hipStream_t s)
+static hipError_t launch_tiles(Ctx &c, const SpreadScratch &sc, const uint32_t *home, const float *phi, float *fx,
+                               float *fy, float *fz, hipStream_t s, bool timed = true)
 {
     switch (box_row_template(c)) {
-    case 7: return launch_tiles_bx<SORTED, NF, 7>(c, home, phi, fx, fy, fz, s);
-    case 9: return launch_tiles_bx<SORTED, NF, 9>(c, home, phi, fx, fy, fz, s);
-    case 11: return launch_tiles_bx<SORTED, NF, 11>(c, home, phi, fx, fy, fz, s);
-    case 13: return launch_tiles_bx<SORTED, NF, 13>(c, home, phi, fx, fy, fz, s);
-    case 15: return launch_tiles_bx<SORTED, NF, 15>(c, home, phi, fx, fy, fz, s);
-    case 19: return launch_tiles_bx<SORTED, NF, 19>(c, home, phi, fx, fy, fz, s);
-    default: return launch_tiles_bx<SORTED, NF, 0>(c, home, phi, fx, fy, fz, s);
+    case 7: return launch_tiles_bx<SORTED, NF, 7>(c, sc, home, phi, fx, fy, fz, s, timed);
+    case 9: return launch_tiles_bx<SORTED, NF, 9>(c, sc, home, phi, fx, fy, fz, s, timed);
+    case 11: return launch_tiles_bx<SORTED, NF, 11>(c, sc, home, phi, fx, fy, fz, s, timed);
+    case 13: return launch_tiles_bx<SORTED, NF, 13>(c, sc, home, phi, fx, fy, fz, s, timed);
+    case 15: return launch_tiles_bx<SORTED, NF, 15>(c, sc, home, phi, fx, fy, fz, s, timed);
+    case 19: return launch_tiles_bx<SORTED, NF, 19>(c, sc, home, phi, fx, fy, fz, s, timed);
+    default: return launch_tiles_bx<SORTED, NF, 0>(c, sc, home, phi, fx, fy, fz, s, timed);
     }
 }
 
@@ -745,32 +762,43 @@ hipError_t launch_interp(const Ctx &c, int64_t n, const uint32_t *home, const fl
     return hipGetLastError();
 }
 
-hipError_t launch_spread(Ctx &c, int64_t n, const uint32_t *home, const float *phi,
-                         const float *area, const float *Fx, const float *Fy, const float *Fz,
-                         float *fx, float *fy, float *fz, hipStream_t s)
+// The standalone spreading on the buffers sc: binning from the homes, c_l F_l
+// and the per-tile maxima by marker, then the coloured tile launches.  timed:
+// per-kernel timing marks (they may create HIP events).
+static hipError_t launch_spread_with(Ctx &c, const SpreadScratch &sc, int64_t n, const uint32_t *home,
+                                     const float *phi, const float *area, const float *Fx, const float *Fy,
+                                     const float *Fz, float *fx, float *fy, float *fz, hipStream_t s, bool timed)
 {
     if (n == 0) return hipSuccess;
     const int64_t nt = c.g.ntiles;
     const int64_t nb = (nt + kScanChunk - 1) / kScanChunk;
     {
-        TimedLaunch tb(c, MLS_K_SPREAD_BIN, s);
-        hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(nt, c.cu_count)), dim3(kBlock), 0, s, c.tile_count, nt);
+        TimedLaunch tb(c, timed ? MLS_K_SPREAD_BIN : -1, s);
+        hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(nt, c.cu_count)), dim3(kBlock), 0, s, sc.tile_count, nt);
         const int gbin = grid_for(n, c.cu_count);
-        hipLaunchKernelGGL(k_bin<false>, dim3(gbin), dim3(kBlock), 0, s, c.d_grid, n, home, c.tile_count,
-                           c.tile_cursor, c.entries, c.marker_tile, c.err);
-        hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)nb), dim3(kBlock), 0, s, c.tile_count, nt, c.block_sums);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, c.block_sums, nb);
-        hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kBlock), 0, s, c.tile_count, nt, c.block_sums,
-                           c.tile_off, c.tile_cursor, c.work, c.tile_fmax, nt + 1);
+        hipLaunchKernelGGL(k_bin<false>, dim3(gbin), dim3(kBlock), 0, s, c.d_grid, n, home, sc.tile_count,
+                           sc.tile_cursor, sc.entries, sc.marker_tile, c.err);
+        hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)nb), dim3(kBlock), 0, s, sc.tile_count, nt,
+                           sc.block_sums);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, sc.block_sums, nb);
+        hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kBlock), 0, s, sc.tile_count, nt, sc.block_sums,
+                           sc.tile_off, sc.tile_cursor, sc.work, sc.tile_fmax, nt + 1);
         hipLaunchKernelGGL(k_bin<true>, dim3(grid_for(n, c.cu_count)), dim3(kBlock), 0, s, c.d_grid, n, home,
-                           c.tile_count, c.tile_cursor, c.entries, c.marker_tile, c.err);
+                           sc.tile_count, sc.tile_cursor, sc.entries, sc.marker_tile, c.err);
         hipLaunchKernelGGL(k_active_tiles, dim3((unsigned)((nt + kActiveChunk - 1) / kActiveChunk)), dim3(kBlock), 0,
-                           s, c.d_grid, c.tile_off, c.tile_active, c.work);
+                           s, c.d_grid, sc.tile_off, sc.tile_active, sc.work);
         hipLaunchKernelGGL(k_spread_coef, dim3((unsigned)round_up8(grid_for(n, c.cu_count))), dim3(kBlock), 0, s,
-                           c.d_grid, n, home, phi, area, Fx, Fy, Fz, c.cf_rows, c.cf_stride, c.marker_tile,
-                           c.tile_fmax, nt + 1);
+                           c.d_grid, n, home, phi, area, Fx, Fy, Fz, sc.cf, sc.cf_stride, sc.marker_tile,
+                           sc.tile_fmax, nt + 1);
     }
-    return launch_tiles<false, 0>(c, home, phi, fx, fy, fz, s);
+    return launch_tiles<false, 0>(c, sc, home, phi, fx, fy, fz, s, timed);
+}
+
+hipError_t launch_spread(Ctx &c, int64_t n, const uint32_t *home, const float *phi,
+                         const float *area, const float *Fx, const float *Fy, const float *Fz,
+                         float *fx, float *fy, float *fz, hipStream_t s)
+{
+    return launch_spread_with(c, ctx_scratch(c), n, home, phi, area, Fx, Fy, Fz, fx, fy, fz, s, true);
 }
 
 hipError_t launch_sort_positions(Ctx &c, int64_t n, const float *x, const float *y, const float *z, hipStream_t s,
@@ -807,9 +835,88 @@ hipError_t launch_spread_sorted(Ctx &c, int64_t n, const uint32_t *home, const f
         hipLaunchKernelGGL(k_active_tiles, dim3((unsigned)((nt + kActiveChunk - 1) / kActiveChunk)), dim3(kBlock), 0,
                            s, c.d_grid, c.tile_off, c.tile_active, c.work);
     }
-    if (c.step_nf == 7) return launch_tiles<true, 7>(c, home, phi, fx, fy, fz, s);
-    if (c.step_nf == 13) return launch_tiles<true, 13>(c, home, phi, fx, fy, fz, s);
-    return launch_tiles<true, 0>(c, home, phi, fx, fy, fz, s);
+    const SpreadScratch sc = ctx_scratch(c);
+    if (c.step_nf == 7) return launch_tiles<true, 7>(c, sc, home, phi, fx, fy, fz, s);
+    if (c.step_nf == 13) return launch_tiles<true, 13>(c, sc, home, phi, fx, fy, fz, s);
+    return launch_tiles<true, 0>(c, sc, home, phi, fx, fy, fz, s);
+}
+
+
+// ---- allocation-free spreading --------------------------------------------
+//
+// The scratch of mls_spread_noalloc lives in one fixed array in the library's
+// code object.  Each GPU the library runs on holds its own copy, allocated
+// when the code object is loaded on that device and kept until the process
+// ends.  In host code the array's name only stands for the symbol: its
+// address on a device comes from hipGetSymbolAddress, taken once per device
+// by noalloc_setup (called from mls_ctx_create, with that device current) and
+// kept in noalloc_ptr[]; every use on the host goes through that pointer.
+
+static __device__ __align__(256) unsigned char scratch[MLS_SPREAD_NOALLOC_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+void *noalloc_ptr[kMaxDevices] = {};
+std::mutex noalloc_mu;
+
+// Carves the buffers of a standalone spreading of n markers over nt tiles out
+// of base (or only measures them when base is NULL); returns the bytes needed.
+size_t carve(int64_t nt, int64_t n, unsigned char *base, SpreadScratch &sc)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        void *p = base ? base + off : nullptr;
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    const int64_t nb = (nt + 1 + kScanChunk - 1) / kScanChunk;
+    const int64_t stride = (n + 63) / 64 * 64;
+    sc.tile_count = (uint32_t *)take((size_t)(nt + 1) * 4);
+    sc.tile_off = (uint32_t *)take((size_t)(nt + 2) * 4);
+    sc.tile_cursor = (uint32_t *)take((size_t)(nt + 1) * 4);
+    sc.tile_active = (uint32_t *)take((size_t)nt * 4);
+    sc.block_sums = (uint32_t *)take((size_t)(nb + 1) * 4);
+    sc.work = (uint32_t *)take(128 * 4);
+    sc.tile_fmax = (uint32_t *)take((size_t)3 * (nt + 1) * 4);
+    sc.marker_tile = (uint32_t *)take((size_t)n * 4);
+    sc.entries = (uint32_t *)take((size_t)n * 4);
+    sc.cf = (float *)take((size_t)3 * stride * 4);
+    sc.cf_stride = stride;
+    return off;
+}
+}  // namespace
+
+hipError_t noalloc_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (noalloc_ptr[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    noalloc_ptr[device] = p;
+    return hipSuccess;
+}
+
+size_t noalloc_bytes(const Ctx &c, int64_t n)
+{
+    SpreadScratch sc;
+    return carve(c.g.ntiles, n, nullptr, sc);
+}
+
+hipError_t launch_spread_noalloc(Ctx &c, int64_t n, const uint32_t *home, const float *phi, const float *area,
+                                 const float *Fx, const float *Fy, const float *Fz, float *fx, float *fy, float *fz,
+                                 hipStream_t s)
+{
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(noalloc_mu);
+        if (c.device >= 0 && c.device < kMaxDevices) base = noalloc_ptr[c.device];
+    }
+    if (!base) return hipErrorInvalidDevicePointer;
+    SpreadScratch sc;
+    carve(c.g.ntiles, n, static_cast<unsigned char *>(base), sc);
+    return launch_spread_with(c, sc, n, home, phi, area, Fx, Fy, Fz, fx, fy, fz, s, false);
 }
 
 }  // namespace mls

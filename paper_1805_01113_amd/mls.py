@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libmls_hip.so")
 
 MLS_EXACT, MLS_FAST, MLS_LEARNED, MLS_FAST_LINEAR = 0, 1, 2, 3
 MLS_STEP_COMPACT = 1
+SPREAD_NOALLOC_BYTES = 64 << 20   # MLS_SPREAD_NOALLOC_BYTES
 MLS_OK, MLS_E_ARG, MLS_E_SUPPORT, MLS_E_SINGULAR, MLS_E_NONFINITE, MLS_E_HIP, MLS_E_NOMEM, MLS_E_RANGE = \
     0, -1, -2, -3, -4, -5, -6, -7
 W_GAUSS_SHIFTED, W_GAUSS, W_CONST = 0, 1, 2
@@ -107,6 +108,7 @@ def load(path: str = LIB_PATH, need_torch: bool = True):
     L.mls_build.argtypes = [P, I64, P, P, P, I32, P, P, P, P]
     L.mls_interp.argtypes = [P, I64, P, P, P, P, P, P, P, P, P]
     L.mls_spread.argtypes = [P, I64, P, P, P, P, P, P, P, P, P, P]
+    L.mls_spread_noalloc.argtypes = [P, I64, P, P, P, P, P, P, P, P, P, P]
     L.mls_collide.argtypes = [P, I64, P, P, P, P, P, P, P]
     L.mls_collide_clear.argtypes = [P, I64, P, P, P, P, P]
     L.mls_build_grad.argtypes = [P, I64, P, P, P, I32, P, P, P, P]
@@ -139,7 +141,7 @@ def load(path: str = LIB_PATH, need_torch: bool = True):
     L.mls_mlp_grad.argtypes = [P, I64, P, P, I64, P, ctypes.c_float, P, P, P]
     L.mls_mlp_train_step.argtypes = [P, I64, P, P, I64, P, ctypes.c_float, ctypes.c_float, P, P]
     for name in ("mls_tune_get", "mls_tune_set", "mls_autotune", "mls_mlp_load", "mls_mlp_get", "mls_features", "mls_mlp_forward", "mls_mlp_grad",
-                 "mls_mlp_train_step","mls_ctx_create", "mls_reserve", "mls_build", "mls_interp", "mls_spread", "mls_sync",
+                 "mls_mlp_train_step","mls_ctx_create", "mls_reserve", "mls_build", "mls_interp", "mls_spread", "mls_spread_noalloc", "mls_sync",
                  "mls_stats_get", "mls_stats_reset", "mls_fast_tables", "mls_step", "mls_step_counter_set", "mls_step_order",
                  "mls_graph_create", "mls_graph_launch", "mls_timing_enable", "mls_timing_get"):
         getattr(L, name).restype = ctypes.c_int
@@ -271,6 +273,24 @@ class Context:
         st = self._lib.mls_spread(self.h, n, _ptr(home), _ptr(phi), _ptr(area), _ptr(F[0]), _ptr(F[1]),
                                   _ptr(F[2]), _ptr(fields[0]), _ptr(fields[1]), _ptr(fields[2]), _stream(stream))
         self._raise(st, "mls_spread")
+        return fields
+
+    def spread_noalloc(self, home, phi, area, F, fields, stream=None):
+        """spread() through the allocation-free entry point: its scratch is the
+        library's fixed per-GPU array (SPREAD_NOALLOC_BYTES), so calls that
+        overlap on one GPU race."""
+        import torch
+        n = area.numel()
+        _check_dev(home, torch.int32, 3 * npad(n), "home")
+        _check_dev(phi, torch.float32, 81 * npad(n), "phi")
+        _check_dev(area, torch.float32, n, "area")
+        _check_dev(F, torch.float32, 3 * n, "F")
+        for c, q in enumerate(fields):
+            _check_dev(q, torch.float32, int(np.prod(self.shape(c))), "force field %d" % c)
+        st = self._lib.mls_spread_noalloc(self.h, n, _ptr(home), _ptr(phi), _ptr(area), _ptr(F[0]), _ptr(F[1]),
+                                          _ptr(F[2]), _ptr(fields[0]), _ptr(fields[1]), _ptr(fields[2]),
+                                          _stream(stream))
+        self._raise(st, "mls_spread_noalloc")
         return fields
 
     def cell_shape(self):

@@ -71,12 +71,17 @@ def make_workload(name):
     raise SystemExit("unknown workload %s" % name)
 
 
-def touched_nodes(torch, ctx, home, n):
+def touched_nodes(torch, ctx, home, n, footprint=None):
     """Unique (component, node) pairs in the supports of all markers (for the
-    algorithmic bytes of interpolation and spreading)."""
+    algorithmic bytes of interpolation and spreading).  If footprint is a
+    dict, it also receives the unique 32-byte sectors, 64-byte and 128-byte
+    lines of the FP32 component fields that hold those nodes: the least a
+    gather (or a read-modify-write) of the touched values moves at each
+    memory access granularity."""
     from paper_1805_01113_amd import mls
     h = mls.unblock(home, n)[:, :, 0].to(torch.int64) & 0xFFFFFFFF
     total = 0
+    sect = {32: 0, 64: 0, 128: 0}
     for c in range(3):
         nx, ny, nz = ctx.dims(c)
         mask = torch.zeros(nx * ny * nz, dtype=torch.bool, device=home.device)
@@ -91,7 +96,16 @@ def touched_nodes(torch, ctx, home, n):
                     ii = (i + dx) % nx if ctx.periodic[0] else i + dx
                     mask[(kk * ny + jj) * nx + ii] = True
         total += int(mask.sum().item())
+        if footprint is not None:
+            for b in sect:
+                per = b // 4
+                m = mask
+                if m.numel() % per:
+                    m = torch.cat([m, torch.zeros(per - m.numel() % per, dtype=torch.bool, device=m.device)])
+                sect[b] += int(m.view(-1, per).any(dim=1).sum().item())
         del mask
+    if footprint is not None:
+        footprint.update({"nodes": total, "sectors_32B": sect[32], "lines_64B": sect[64], "lines_128B": sect[128]})
     return total
 
 
@@ -578,7 +592,8 @@ def main():
     kt = mls.timing_get(ctx, reset=True)
     mls.timing_enable(ctx, False)
     ctx.sync()
-    T = touched_nodes(torch, ctx, bufs.home, n)
+    fp = {}
+    T = touched_nodes(torch, ctx, bufs.home, n, fp)
     t_per = T / n
     survey, own = byte_models(method, compact, nf, t_per, "jitter" in kt)
     kernels = {}
@@ -608,6 +623,13 @@ def main():
 
     extra = {"library": lib_version, "ms_per_step_eager": round(ms_eager, 4), "kernels": kernels, "autotune": tune,
              "touched_nodes_per_marker": round(t_per, 3),
+             # bytes per marker of the touched field values at 4 B, and at
+             # the 32 B sector, 64 B and 128 B line granularity of the memory
+             # system (one read each; the spreading reads and writes them)
+             "touched_field_bytes_per_marker": {
+                 "values_4B": round(4.0 * fp["nodes"] / n, 2), "sectors_32B": round(32.0 * fp["sectors_32B"] / n, 2),
+                 "lines_64B": round(64.0 * fp["lines_64B"] / n, 2),
+                 "lines_128B": round(128.0 * fp["lines_128B"] / n, 2)},
              "step_survey_bytes_per_marker": round(step_survey / n, 1),
              "step_hbm_frac_survey_bytes": round(step_survey / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
              "step_kernel_bytes_per_marker": round(step_own / n, 1),

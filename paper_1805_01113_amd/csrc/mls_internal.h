@@ -103,11 +103,17 @@ constexpr int kMlpParams = kOffB3 + kMlpOut;   // 20891
 // Inference image of the network (built from the FP32 parameters): the
 // matrix-core operands of every (layer, 32-row output tile, 16-wide k block)
 // as split BF16 (high part, low part), 64 lanes x 8 values each, followed by
-// the FP32 biases (b1, b2, b3 padded to 32) and norm.
+// the FP32 biases (b1, b2, b3 padded to 32) and norm, then the GELU table of
+// the inference kernel: for z >= 0, z Q(z) (Q the standard normal tail) as
+// one cubic in s = 16 z - i per interval [i/16, (i+1)/16), i < 96, 4 FP32
+// coefficients each (value and slope matched at both ends).
 constexpr int kMlpSlots = 4 + 4 * 8 + 8;                       // layer 1, 2, 3
 constexpr int kMlpImageOps = kMlpSlots * 2 * 64;               // 16-byte operand words
 constexpr int kMlpImageFloats = 2 * kMlpHidden + 32 + 12;      // biases + norm
-constexpr size_t kMlpImageBytes = (size_t)kMlpImageOps * 16 + kMlpImageFloats * sizeof(float);
+constexpr int kGeluPerUnit = 16, kGeluIntervals = 96;          // table over [0, 6)
+constexpr size_t kMlpImageTableOffset = (size_t)kMlpImageOps * 16 + kMlpImageFloats * sizeof(float);
+constexpr size_t kMlpImageBytes = kMlpImageTableOffset + (size_t)kGeluIntervals * 4 * sizeof(float);
+static_assert(kMlpImageTableOffset % 16 == 0, "GELU table rows are 16-byte aligned");
 
 struct Mlp {
     bool loaded = false;

@@ -72,6 +72,20 @@ __device__ __forceinline__ float gelu_grad(float z)
     return (z >= 0.0f ? 1.0f - q : q) + z * ez * 0.39894228040143268f;
 }
 
+// gelu(z) = max(z, 0) - |z| Q(|z|) from the cubic table of the network image
+// (inference only; training keeps the closed form above).  Beyond |z| = 6 the
+// last interval's end value, 6 Q(6) < 6e-9, stands in for |z| Q(|z|).
+// max(z, 0) is taken as z - min(z, 0), which passes a NaN argument on to the
+// result (min returns its other operand for a NaN).
+__device__ __forceinline__ float gelu_tab(float z, const float4 *__restrict__ tab)
+{
+    const float t = fminf(fabsf(z) * (float)kGeluPerUnit, 95.99999f);
+    const float4 c = tab[(int)t];
+    const float sv = __builtin_amdgcn_fractf(t);
+    const float p = fmaf(fmaf(fmaf(c.w, sv, c.z), sv, c.y), sv, c.x);
+    return (z - fminf(z, 0.0f)) - p;
+}
+
 __device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &lo)
 {
     hi = (__bf16)v;
@@ -371,12 +385,12 @@ __device__ __forceinline__ f32x16 bias_tile(const float *b, int T, int h)
 }
 
 // GELU of result registers 8 q .. 8 q + 7 as the split B operand of the next layer.
-__device__ __forceinline__ void gelu_operand(const f32x16 &acc, int q, bf16x8 &hi, bf16x8 &lo)
+__device__ __forceinline__ void gelu_operand(const f32x16 &acc, int q, const float4 *tab, bf16x8 &hi, bf16x8 &lo)
 {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         __bf16 p, r;
-        split_bf16(gelu(acc[8 * q + i]), p, r);
+        split_bf16(gelu_tab(acc[8 * q + i], tab), p, r);
         hi[i] = p; lo[i] = r;
     }
 }
@@ -384,7 +398,7 @@ __device__ __forceinline__ void gelu_operand(const f32x16 &acc, int q, bf16x8 &h
 // Network output for the 32 markers whose features lane l % 32 holds (ft);
 // returns the 32 x 32 result tile (rows 0..26 are the outputs).
 __device__ __forceinline__ f32x16 evaluate(const uint4 *img, const float *b1, const float *b2, const float *b3,
-                                           const float *norm, const float ft[6], int lane)
+                                           const float *norm, const float4 *tab, const float ft[6], int lane)
 {
     const int h = lane >> 5;
     bf16x8 uh, ul;
@@ -397,25 +411,37 @@ __device__ __forceinline__ f32x16 evaluate(const uint4 *img, const float *b1, co
         split_bf16(v, p, r);
         uh[i] = p; ul[i] = r;
     }
-    bf16x8 Bh[8], Bl[8];
+    // Layer 2 is accumulated k block by k block: each 32-unit tile of layer 1
+    // is computed, activated and consumed by the four layer-2 output tiles
+    // at once, so only its own 16-register operand pair is live instead of
+    // all of layer 1, and the four accumulators give the matrix cores four
+    // independent chains.  Each accumulator still sums its k blocks in
+    // order 0..7, so the result is the same as tile by tile.
+    f32x16 acc[4];
 #pragma unroll
-    for (int T = 0; T < 4; ++T) {
-        f32x16 a = bias_tile(b1, T, h);
-        a = mfma3(op_at(img, T, 0, lane), op_at(img, T, 1, lane), uh, ul, a);
-        gelu_operand(a, 0, Bh[2 * T], Bl[2 * T]);
-        gelu_operand(a, 1, Bh[2 * T + 1], Bl[2 * T + 1]);
+    for (int T = 0; T < 4; ++T) acc[T] = bias_tile(b2, T, h);
+#pragma unroll
+    for (int T1 = 0; T1 < 4; ++T1) {
+        f32x16 a = bias_tile(b1, T1, h);
+        a = mfma3(op_at(img, T1, 0, lane), op_at(img, T1, 1, lane), uh, ul, a);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int kb = 2 * T1 + q;
+            bf16x8 bh, bl;
+            gelu_operand(a, q, tab, bh, bl);
+#pragma unroll
+            for (int T = 0; T < 4; ++T)
+                acc[T] = mfma3(op_at(img, 4 + 8 * T + kb, 0, lane), op_at(img, 4 + 8 * T + kb, 1, lane), bh, bl,
+                               acc[T]);
+        }
     }
     f32x16 y3 = bias_tile(b3, 0, h);
 #pragma unroll
     for (int T = 0; T < 4; ++T) {
-        f32x16 a = bias_tile(b2, T, h);
-#pragma unroll
-        for (int kb = 0; kb < 8; ++kb)
-            a = mfma3(op_at(img, 4 + 8 * T + kb, 0, lane), op_at(img, 4 + 8 * T + kb, 1, lane), Bh[kb], Bl[kb], a);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             bf16x8 ch, cl;
-            gelu_operand(a, q, ch, cl);
+            gelu_operand(acc[T], q, tab, ch, cl);
             const int slot = 36 + 2 * T + q;
             y3 = mfma3(op_at(img, slot, 0, lane), op_at(img, slot, 1, lane), ch, cl, y3);
         }
@@ -430,8 +456,14 @@ k_build_learned(const Grid *__restrict__ gp, const Weight W, float tau, float to
                 uint8_t *__restrict__ route, ErrWord *err, DevStats *st)
 {
     extern __shared__ uint4 lds[];
+    // the GELU table in a static LDS array (placed first, so its rows are
+    // addressed with small immediate offsets)
+    __shared__ float4 tab[kGeluIntervals];
     constexpr int kWords = (int)(kMlpImageBytes / 16);
     for (int i = threadIdx.x; i < kWords; i += kLearnBlock) lds[i] = image[i];
+    if (threadIdx.x < kGeluIntervals)
+        tab[threadIdx.x] = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(image) +
+                                                            kMlpImageTableOffset)[threadIdx.x];
     __syncthreads();
     const float *b1 = reinterpret_cast<const float *>(lds + kMlpImageOps);
     const float *b2 = b1 + kMlpHidden, *b3 = b2 + kMlpHidden, *norm = b3 + 32;
@@ -475,19 +507,27 @@ k_build_learned(const Grid *__restrict__ gp, const Weight W, float tau, float to
             float ft[6];
 #pragma unroll
             for (int q = 0; q < 6; ++q) ft[q] = __shfl(f[q], src);
-            const f32x16 yv = evaluate(lds, b1, b2, b3, norm, ft, lane);
+            const f32x16 yv = evaluate(lds, b1, b2, b3, norm, tab, ft, lane);
             // consistency residuals; a marker's outputs are split between lanes r and r + 32
             float s[3][3];
             node_offsets(ft, s);
             float sy = 0.0f, r1x = 0.0f, r1y = 0.0f, r1z = 0.0f;
+            // the offsets of a row are picked by a bit mask on h, so that the
+            // array stays in registers (a select of two elements would become
+            // a select of two addresses and put the array in scratch)
+            const uint32_t hm = h ? 0xffffffffu : 0u;
+            auto pick = [hm](float a0, float a1) {
+                return __builtin_bit_cast(float, (__builtin_bit_cast(uint32_t, a1) & hm) |
+                                                     (__builtin_bit_cast(uint32_t, a0) & ~hm));
+            };
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 const int k0 = 8 * (j / 4) + (j % 4), k1 = k0 + 4;   // output row for h = 0, 1
                 const int kk1 = k1 < kNe ? k1 : 0;
                 const bool valid = h ? (k1 < kNe) : true;
-                const float sx = h ? s[0][kk1 % 3] : s[0][k0 % 3];
-                const float sv = h ? s[1][(kk1 / 3) % 3] : s[1][(k0 / 3) % 3];
-                const float sz = h ? s[2][kk1 / 9] : s[2][k0 / 9];
+                const float sx = pick(s[0][k0 % 3], s[0][kk1 % 3]);
+                const float sv = pick(s[1][(k0 / 3) % 3], s[1][(kk1 / 3) % 3]);
+                const float sz = pick(s[2][k0 / 9], s[2][kk1 / 9]);
                 const float yj = valid ? yv[j] : 0.0f;
                 sy += yj;
                 r1x += yj * sx;
@@ -549,6 +589,26 @@ int grid_for(int64_t work, int cu)
 
 // ---- host side ---------------------------------------------------------------
 
+// The inference GELU table: f(a) = a Q(a), Q(a) = erfc(a / sqrt 2) / 2, on
+// intervals of width 1/16 as cubic Hermite pieces in s = 16 a - i (value and
+// derivative f'(a) = Q(a) - a phi(a) matched at both ends), in FP64.
+static void gelu_table(float *t)
+{
+    auto f = [](double a) { return 0.5 * a * std::erfc(a * 0.70710678118654752440); };
+    auto df = [](double a) {
+        return 0.5 * std::erfc(a * 0.70710678118654752440) - a * std::exp(-0.5 * a * a) * 0.39894228040143267794;
+    };
+    const double h = 1.0 / kGeluPerUnit;
+    for (int i = 0; i < kGeluIntervals; ++i) {
+        const double a0 = i * h, a1 = (i + 1) * h;
+        const double f0 = f(a0), f1 = f(a1), d0 = df(a0) * h, d1 = df(a1) * h;
+        t[4 * i + 0] = (float)f0;
+        t[4 * i + 1] = (float)d0;
+        t[4 * i + 2] = (float)(3.0 * (f1 - f0) - 2.0 * d0 - d1);
+        t[4 * i + 3] = (float)(2.0 * (f0 - f1) + d0 + d1);
+    }
+}
+
 hipError_t mlp_alloc(Ctx &c)
 {
     Mlp &net = c.mlp;
@@ -566,6 +626,14 @@ hipError_t mlp_alloc(Ctx &c)
     net.norm = fp + 4 * kMlpParams;
     net.loss = net.norm + 12;
     net.image = block + head;
+    float tab[4 * kGeluIntervals];
+    gelu_table(tab);
+    e = hipMemcpy(static_cast<char *>(net.image) + kMlpImageTableOffset, tab, sizeof(tab), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(block);
+        net.params = nullptr;
+        return e;
+    }
     return hipFuncSetAttribute((const void *)k_build_learned, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)kMlpImageBytes);
 }

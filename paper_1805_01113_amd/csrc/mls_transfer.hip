@@ -574,11 +574,21 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, const uint32_t *__restr
                 // Rounding is monotonic, so |phi_k vsc| <= max_k |phi_k| |vsc| for
                 // every k, with equality at the largest: one comparison bounds all
                 // 27 scaled contributions.  A NaN or infinity in the force or the
-                // coefficient reaches vsc and fails it too (one in phi reaches c_l
-                // through h_l and the denominator of eq. 8).
+                // coefficient reaches vsc and fails it too.  Sorted rows hold the
+                // library's own shape functions (finite for a usable support);
+                // a caller's phi is checked here.
                 float pm = 0.f;
 #pragma unroll
                 for (int k = 0; k < kNe; ++k) pm = fmaxf(pm, fabsf(ph[k]));
+                if constexpr (!SORTED) {
+                    // caller-provided phi: a NaN or infinite value fails through
+                    // the sum (fmaxf above ignores a NaN operand); c_l of a grid
+                    // with equal widths does not depend on phi
+                    float ps = 0.f;
+#pragma unroll
+                    for (int k = 0; k < kNe; ++k) ps += ph[k];
+                    if (!(fabsf(ps) <= 3.0e38f)) pm = __builtin_inff();
+                }
                 if (!(fabsf(vsc) * pm < lim)) {
                     raise_error(err, SORTED ? (int64_t)entries[e] : row, MLS_E_RANGE);
                     continue;
@@ -658,12 +668,19 @@ k_spread_coef(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict
             if (in) unpack_home(home[home_at(l, c)], hi, hj, hk);
             float v = 0.0f;
             if (in && home_ok(g, c, hi, hj, hk)) {
-                const float *p = phi + phi_at(l, c);
-                float ph[kNe];
-#pragma unroll
-                for (int k = 0; k < kNe; ++k) ph[k] = p[k * kLanes];
                 const float Fc = c == 0 ? Fx[l] : (c == 1 ? Fy[l] : Fz[l]);
-                v = eq8_coef(g, c, hi, hj, hk, ph, a * Fc);
+                if (g.inv_cw2 > 0.f) {
+                    // equal control-volume widths w: c_l = A_l / w^2 whatever
+                    // the shape functions (a non-finite phi is caught by the
+                    // tile kernel, which reads phi anyway)
+                    v = a * Fc * g.inv_cw2;
+                } else {
+                    const float *p = phi + phi_at(l, c);
+                    float ph[kNe];
+#pragma unroll
+                    for (int k = 0; k < kNe; ++k) ph[k] = p[k * kLanes];
+                    v = eq8_coef(g, c, hi, hj, hk, ph, a * Fc);
+                }
             }
             if (in) cf[c * cf_stride + l] = v;
             wave_key_max(tmax + c * tstride, key, finite_abs(v));

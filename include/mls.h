@@ -353,13 +353,15 @@ mls_status mls_fast_tables(mls_ctx *ctx, float *dst, int64_t *count, int32_t *ro
  *   force    F = (V_b - U) / dt, the direct forcing of Sec. 2 (V_b = 0 if NULL);
  *   spread   f += c_l phi F (eq. 7-8);
  * and then increments the context's device step counter, which the jitter
- * of the next step reads.  With MLS_EXACT, and with fast-MLS on a grid whose
- * axes are all uniform, the step works in spreading-tile order: markers are
- * binned by the tile of their cell (the jitter runs inside that pass, with
- * the same generator), the build, interpolation and forcing run as one kernel
- * (phi is not read back), and row p of the blocked home / phi / route layout
- * holds marker order[p] (see mls_step_order), so that the tiles read their
- * rows contiguously; U and F stay indexed by marker.  Markers whose support
+ * of the next step reads.  With MLS_EXACT, with fast-MLS on a grid whose
+ * axes are all uniform, and with MLS_LEARNED, the step works in
+ * spreading-tile order: markers are binned by the tile of their cell (the
+ * jitter runs inside that pass, with the same generator), row p of the
+ * blocked home / phi / route layout holds marker order[p] (see
+ * mls_step_order), so that the tiles read their rows contiguously, and U and
+ * F stay indexed by marker.  The exact and fast-MLS builds run fused with the
+ * interpolation and forcing (phi is not read back); the learned build stores
+ * its rows and one more kernel interpolates and forces from them.  Markers whose support
  * leaves the grid come last.  The order of the markers inside a tile may
  * differ between runs; U, F and the forcing do not.  With the other methods
  * (and fast-MLS on a stretched grid) rows are in marker order.  All buffers are caller-owned device arrays:
@@ -404,9 +406,10 @@ typedef struct {
 /* Enqueue one step.  Reserves scratch on first use for n markers. */
 mls_status mls_step(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buffers *buf, void *stream);
 
-/* Copy the row order of the last MLS_EXACT step of n markers into order
- * (device, n uint32): row p of its home / phi / route holds marker order[p].
- * MLS_E_ARG if the last exact step had a different marker count. */
+/* Copy the row order of the last step in spreading-tile order (MLS_EXACT,
+ * fast-MLS on a uniform grid, MLS_LEARNED) of n markers into order (device,
+ * n uint32): row p of its home / phi / route holds marker order[p].
+ * MLS_E_ARG if that step had a different marker count. */
 mls_status mls_step_order(mls_ctx *ctx, uint32_t *order, int64_t n, void *stream);
 
 /* Set the device step counter read by the jitter (enqueued on stream). */

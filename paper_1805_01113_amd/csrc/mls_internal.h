@@ -222,8 +222,9 @@ hipError_t launch_fast_interp(const Ctx &c, int64_t n, const float *x, const flo
                               uint32_t *home, float *phi, uint8_t *route, const float *u, const float *v,
                               const float *w, const float *vb, const float *area, float dt, float *U, float *F,
                               hipStream_t s, bool trilinear_blend);
+// order: row p holds marker order[p] (the time step's tile order); NULL: row = marker.
 hipError_t launch_build_learned(Ctx &c, int64_t n, const float *x, const float *y, const float *z,
-                                uint32_t *home, float *phi, uint8_t *route, hipStream_t s);
+                                uint32_t *home, float *phi, uint8_t *route, hipStream_t s, const uint32_t *order = nullptr);
 hipError_t launch_table_build(const Ctx &c, hipStream_t s);
 hipError_t launch_collide(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
                           const int32_t *body, int32_t *coll, uint8_t *flags, hipStream_t s);
@@ -263,6 +264,11 @@ hipError_t launch_build_interp(const Ctx &c, int64_t n, const float *x, const fl
                                uint32_t *home, float *phi, uint8_t *route, const float *u, const float *v,
                                const float *w, const float *vb, const float *area, float dt, float *U, float *F,
                                hipStream_t s);
+// U, F by marker and c_l F_l by row from shape functions stored in the rows of
+// the last binning (the learned time step).
+hipError_t launch_interp_rows(const Ctx &c, int64_t n, const uint32_t *home, const float *phi, const float *u,
+                              const float *v, const float *w, const float *vb, const float *area, float dt, float *U,
+                              float *F, hipStream_t s);
 hipError_t launch_spread_sorted(Ctx &c, int64_t n, const uint32_t *home, const float *phi, float *fx, float *fy,
                                 float *fz, hipStream_t s);
 // Dynamic LDS of a spreading tile workgroup: the int64 box of one component.

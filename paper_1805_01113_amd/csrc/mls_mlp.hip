@@ -453,7 +453,7 @@ __global__ void __launch_bounds__(kLearnBlock)
 k_build_learned(const Grid *__restrict__ gp, const Weight W, float tau, float tol, int64_t n,
                 const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
                 const uint4 *__restrict__ image, uint32_t *__restrict__ home, float *__restrict__ phi,
-                uint8_t *__restrict__ route, ErrWord *err, DevStats *st)
+                uint8_t *__restrict__ route, ErrWord *err, DevStats *st, const uint32_t *__restrict__ order)
 {
     extern __shared__ uint4 lds[];
     // the GELU table in a static LDS array (placed first, so its rows are
@@ -478,19 +478,21 @@ k_build_learned(const Grid *__restrict__ gp, const Weight W, float tau, float to
         const int64_t blk = it / 3;
         const int c = (int)(it - blk * 3);
         const int64_t l = (blk << 6) + lane;
+        // the marker of row l (rows in tile order in the time step)
+        const int64_t mk = l < n ? (order ? (int64_t)order[l] : l) : 0;
         float *out = phi + (((blk * 3 + c) * kNe) << 6);          // + k * 64 + marker in block
         uint32_t *hout = home + ((blk * 3 + c) << 6) + lane;
         uint8_t *rout = route ? route + ((blk * 3 + c) << 6) : nullptr;
         float f[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         bool ok = false;
         if (l < n) {
-            const double px = (double)x[l], py = (double)y[l], pz = (double)z[l];
+            const double px = (double)x[mk], py = (double)y[mk], pz = (double)z[mk];
             AxisGeo G[3];
             ok = axis_geo(g.ax[0], c == 0, px, G[0]);
             ok = ok && axis_geo(g.ax[1], c == 1, py, G[1]);
             ok = ok && axis_geo(g.ax[2], c == 2, pz, G[2]);
             if (!ok) {
-                mark_failed(err, l, px, py, pz, hout, out + lane, rout ? rout + lane : nullptr);
+                mark_failed(err, mk, px, py, pz, hout, out + lane, rout ? rout + lane : nullptr);
             } else {
                 *hout = pack_home(G[0].ih, G[1].ih, G[2].ih);
                 f[0] = G[0].xi; f[1] = G[1].xi; f[2] = G[2].xi;
@@ -555,13 +557,13 @@ k_build_learned(const Grid *__restrict__ gp, const Weight W, float tau, float to
         n_ok += (unsigned long long)__popcll(accept);
         n_fb += (unsigned long long)__popcll(rej);
         if ((rej >> lane) & 1ull) {
-            const double px = (double)x[l], py = (double)y[l], pz = (double)z[l];
+            const double px = (double)x[mk], py = (double)y[mk], pz = (double)z[mk];
             AxisGeo G[3];
             axis_geo(g.ax[0], c == 0, px, G[0]);
             axis_geo(g.ax[1], c == 1, py, G[1]);
             axis_geo(g.ax[2], c == 2, pz, G[2]);
             float ph[kNe];
-            exact_from_geo(g, W, tau, c, l, px, py, pz, G, out + lane, rout ? rout + lane : nullptr, 4, err, routed,
+            exact_from_geo(g, W, tau, c, mk, px, py, pz, G, out + lane, rout ? rout + lane : nullptr, 4, err, routed,
                            kmax, ph);
         }
     }
@@ -658,7 +660,7 @@ hipError_t mlp_pack(Ctx &c, hipStream_t s)
 }
 
 hipError_t launch_build_learned(Ctx &c, int64_t n, const float *x, const float *y, const float *z, uint32_t *home,
-                                float *phi, uint8_t *route, hipStream_t s)
+                                float *phi, uint8_t *route, hipStream_t s, const uint32_t *order)
 {
     if (n == 0) return hipSuccess;
     Mlp &net = c.mlp;
@@ -672,7 +674,8 @@ hipError_t launch_build_learned(Ctx &c, int64_t n, const float *x, const float *
     int64_t blocks = (waves + kLearnBlock / 64 - 1) / (kLearnBlock / 64);
     if (blocks > c.cu_count) blocks = c.cu_count;
     hipLaunchKernelGGL(k_build_learned, dim3((unsigned)blocks), dim3(kLearnBlock), kMlpImageBytes, s, c.d_grid, c.w,
-                       tau, tol, n, x, y, z, static_cast<const uint4 *>(net.image), home, phi, route, c.err, c.stats);
+                       tau, tol, n, x, y, z, static_cast<const uint4 *>(net.image), home, phi, route, c.err, c.stats,
+                       order);
     return hipGetLastError();
 }
 

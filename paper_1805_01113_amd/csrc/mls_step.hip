@@ -127,7 +127,9 @@ mls_status mls_step(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buff
         st = mls_fast_tables(ctx, nullptr, nullptr, nullptr, nullptr, nullptr, stream);
         if (st != MLS_OK) return st;
     }
-    const bool sorted = desc->method == MLS_EXACT || (fast && fast_fused_ok(c));
+    const bool learned = desc->method == MLS_LEARNED;
+    if (learned && !c.mlp.loaded) return MLS_E_ARG;
+    const bool sorted = desc->method == MLS_EXACT || (fast && fast_fused_ok(c)) || learned;
     if (jitter) {
         // the sorted step jitters inside its binning pass; the others first
         if (!sorted) {
@@ -158,7 +160,17 @@ mls_status mls_step(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buff
         e = jitter ? launch_sort_positions(c, n, b->x0, b->y0, b->z0, s, b->x, b->y, b->z, desc->jitter, desc->seed)
                    : launch_sort_positions(c, n, bx, by, bz, s);
         if (e != hipSuccess) return MLS_E_HIP;
-        if (fast) {
+        if (learned) {
+            // the network (with its exact fallback) in tile order, then
+            // interpolation, forcing and c_l F_l of the stored rows
+            {
+                TimedLaunch t(c, MLS_K_BUILD_LEARNED, s);
+                e = launch_build_learned(c, n, bx, by, bz, b->home, b->phi, b->route, s, c.entries);
+            }
+            if (e != hipSuccess) return MLS_E_HIP;
+            TimedLaunch t(c, MLS_K_INTERP, s);
+            e = launch_interp_rows(c, n, b->home, b->phi, b->u, b->v, b->w, b->vb, b->area, desc->dt, b->U, b->F, s);
+        } else if (fast) {
             TimedLaunch t(c, MLS_K_FAST_INTERP, s);
             e = launch_fast_interp(c, n, bx, by, bz, b->home, b->phi, b->route, b->u, b->v, b->w, b->vb, b->area,
                                    desc->dt, b->U, b->F, s, desc->method == MLS_FAST_LINEAR);

@@ -209,13 +209,21 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, int32_t flags, const mls_s
         st = mls_fast_tables(ctx, nullptr, nullptr, nullptr, nullptr, nullptr, stream);
         if (st != MLS_OK) { c.timing = timing; return st; }
     }
-    // exact and (on uniform grids) fast-MLS run fused and in tile order
-    const bool exact = method == MLS_EXACT || (fast && fast_fused_ok(c));
+    // exact and (on uniform grids) fast-MLS run fused and in tile order; the
+    // learned step runs in tile order too (network, then interpolation,
+    // forcing and c_l F_l of the rows)
+    const bool learned = method == MLS_LEARNED;
+    const bool exact = method == MLS_EXACT || (fast && fast_fused_ok(c)) || learned;
     auto build = [&]() {
         if (!exact) return mls_build(ctx, n, b->x0, b->y0, b->z0, method, b->home, b->phi, nullptr, stream);
         hipError_t e = launch_sort_positions(c, n, b->x0, b->y0, b->z0, s);
         if (e == hipSuccess) {
-            if (fast)
+            if (learned) {
+                e = launch_build_learned(c, n, b->x0, b->y0, b->z0, b->home, b->phi, nullptr, s, c.entries);
+                if (e == hipSuccess)
+                    e = launch_interp_rows(c, n, b->home, b->phi, b->u, b->v, b->w, b->vb, b->area, 1.0f, b->U, b->F,
+                                           s);
+            } else if (fast)
                 e = launch_fast_interp(c, n, b->x0, b->y0, b->z0, b->home, b->phi, nullptr, b->u, b->v, b->w, b->vb,
                                        b->area, 1.0f, b->U, b->F, s, method == MLS_FAST_LINEAR);
             else
@@ -224,7 +232,14 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, int32_t flags, const mls_s
         }
         return e == hipSuccess ? MLS_OK : MLS_E_HIP;
     };
-    auto interp = [&]() { return mls_interp(ctx, n, b->home, b->phi, b->u, b->v, b->w, U, V, Wv, stream); };
+    auto interp = [&]() {
+        if (learned)
+            return launch_interp_rows(c, n, b->home, b->phi, b->u, b->v, b->w, b->vb, b->area, 1.0f, b->U, b->F, s) ==
+                           hipSuccess
+                       ? MLS_OK
+                       : MLS_E_HIP;
+        return mls_interp(ctx, n, b->home, b->phi, b->u, b->v, b->w, U, V, Wv, stream);
+    };
     auto spread = [&]() {
         if (exact)
             return launch_spread_sorted(c, n, b->home, b->phi, b->fx, b->fy, b->fz, s) == hipSuccess ? MLS_OK

@@ -195,14 +195,14 @@ def per_body_rate(torch, ctx, wl, bufs, fields, forcing, x0, y0, z0, area, metho
 def byte_models(method, compact, nf, t_per, jitter_kernel):
     """Algorithmic bytes per marker of each timed kernel, two ways.
 
-    survey: the hot-path contract's figures (transfer functions stored as 27
+    contract: the hot-path contract's figures (transfer functions stored as 27
     FP32 values and read back): build 12 + 12 + 324 = 348, interpolation
     336 + 12 + 4T, spreading 336 + 12 + 4 + 8T (T = touched (component, node)
     pairs per marker); a fused kernel carries the sum of the phases it does.
     own: what this implementation's kernel has to move at least once (compact
     rows of nf floats for an exact step, c_l F_l by row, U and F by marker)."""
     tf = 4.0 * 3 * (nf if compact else 27)
-    survey = {
+    contract = {
         "build_exact": 348.0, "build_fast": 348.0, "build_learned": 348.0,
         "interp": 336 + 12 + 4.0 * t_per,
         "build_interp": 348 + 336 + 12 + 4.0 * t_per,
@@ -225,7 +225,7 @@ def byte_models(method, compact, nf, t_per, jitter_kernel):
         # the tile of each marker, the sorted marker list
         "spread_bin": (24.0 if jitter_kernel else 36.0) + 8.0,
     }
-    return survey, own
+    return contract, own
 
 
 def compare_methods(torch, ctx, wl, bufs, fields, forcing, x0, y0, z0, area, jitter, seed, args, ms_main,
@@ -362,13 +362,13 @@ def config_matrix(torch, args, names=("sphere", "ellipsoids", "stretched")):
             kt = mls.timing_get(ctx, reset=True)
             mls.timing_enable(ctx, False)
             ctx.sync()
-            survey, _ = byte_models(m, compact, nf, t_per, "jitter" in kt)
+            contract, _ = byte_models(m, compact, nf, t_per, "jitter" in kt)
             times = {k: v[0] / v[1] for k, v in kt.items()}
-            dom = max((k for k in times if survey.get(k)), key=lambda k: times[k])
-            gbs = survey[dom] * n / (times[dom] * 1e-3) / 1e9
+            dom = max((k for k in times if contract.get(k)), key=lambda k: times[k])
+            gbs = contract[dom] * n / (times[dom] * 1e-3) / 1e9
             r["kernels_ms"] = {k: round(v, 4) for k, v in times.items()}
             r["roofline"] = {"kernel": dom, "achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
-                             "alg_bytes_per_marker": round(survey[dom], 1)}
+                             "alg_bytes_per_marker": round(contract[dom], 1)}
             row["methods"][mname] = r
             log("%s %s: %.3f ms/step (%.3e markers/s), err vs exact %.2e, dominant %s %.1f%% of HBM"
                 % (name, mname, ms, n / (ms * 1e-3), r["interp_err_vs_exact"], dom, 100 * gbs / HBM_PEAK_GBS))
@@ -595,26 +595,26 @@ def main():
     fp = {}
     T = touched_nodes(torch, ctx, bufs.home, n, fp)
     t_per = T / n
-    survey, own = byte_models(method, compact, nf, t_per, "jitter" in kt)
+    contract, own = byte_models(method, compact, nf, t_per, "jitter" in kt)
     kernels = {}
     for k, (ms, cnt) in kt.items():
         avg = ms / cnt
         kernels[k] = {"avg_ms": round(avg, 4), "launches": cnt}
-        if survey.get(k):
-            kernels[k]["survey_bytes_per_marker"] = round(survey[k], 1)
-            kernels[k]["GBs_survey_bytes"] = round(survey[k] * n / (avg * 1e-3) / 1e9, 1)
+        if contract.get(k):
+            kernels[k]["contract_bytes_per_marker"] = round(contract[k], 1)
+            kernels[k]["GBs_contract_bytes"] = round(contract[k] * n / (avg * 1e-3) / 1e9, 1)
         if own.get(k):
             kernels[k]["kernel_bytes_per_marker"] = round(own[k], 1)
             kernels[k]["GBs_kernel_bytes"] = round(own[k] * n / (avg * 1e-3) / 1e9, 1)
-    dom = max(((k, v) for k, v in kernels.items() if survey.get(k)), key=lambda kv: kv[1]["avg_ms"])
-    step_survey = sum(survey.get(k, 0.0) for k in kernels) * n
+    dom = max(((k, v) for k, v in kernels.items() if contract.get(k)), key=lambda kv: kv[1]["avg_ms"])
+    step_contract = sum(contract.get(k, 0.0) for k in kernels) * n
     step_own = sum(own.get(k, 0.0) for k in kernels) * n
     log("eager: %.3f ms/step; kernels: %s" % (ms_eager, json.dumps(kernels)))
     traffic = measured_traffic(dom[0], wl.name, step_cfg)
-    achieved = dom[1]["GBs_survey_bytes"]
+    achieved = dom[1]["GBs_contract_bytes"]
     roof = {"bound": "hbm", "kernel": dom[0], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "alg_bytes_per_marker": round(survey[dom[0]], 1), "markers_per_launch": n,
+            "alg_bytes_per_marker": round(contract[dom[0]], 1), "markers_per_launch": n,
             "bytes_basis": "the hot-path contract's bytes per marker (Phi stored and read, 27 floats)",
             "frac_kernel_bytes": round(dom[1].get("GBs_kernel_bytes", 0.0) / HBM_PEAK_GBS, 4),
             "kernel_bytes_per_marker": round(own.get(dom[0], 0.0), 1),
@@ -630,8 +630,8 @@ def main():
                  "values_4B": round(4.0 * fp["nodes"] / n, 2), "sectors_32B": round(32.0 * fp["sectors_32B"] / n, 2),
                  "lines_64B": round(64.0 * fp["lines_64B"] / n, 2),
                  "lines_128B": round(128.0 * fp["lines_128B"] / n, 2)},
-             "step_survey_bytes_per_marker": round(step_survey / n, 1),
-             "step_hbm_frac_survey_bytes": round(step_survey / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+             "step_contract_bytes_per_marker": round(step_contract / n, 1),
+             "step_hbm_frac_contract_bytes": round(step_contract / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
              "step_kernel_bytes_per_marker": round(step_own / n, 1),
              "step_hbm_frac_kernel_bytes": round(step_own / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 

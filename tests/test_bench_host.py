@@ -31,13 +31,13 @@ def test_contract_byte_model():
     12 + 12 + 324, interpolation 336 + 12 + 4T, spreading 336 + 12 + 4 + 8T;
     the fused build-and-interpolate kernel carries both phases."""
     T = 3.5
-    survey, own = bench.byte_models(0, True, 7, T, False)
-    assert survey["build_exact"] == 348.0
-    assert survey["interp"] == 348.0 + 4 * T
-    assert survey["spread_tiles"] == 352.0 + 8 * T
-    assert survey["build_interp"] == survey["build_exact"] + survey["interp"]
+    contract, own = bench.byte_models(0, True, 7, T, False)
+    assert contract["build_exact"] == 348.0
+    assert contract["interp"] == 348.0 + 4 * T
+    assert contract["spread_tiles"] == 352.0 + 8 * T
+    assert contract["build_interp"] == contract["build_exact"] + contract["interp"]
     # compact rows of 7 floats per component move less than the 27-value rows
-    assert own["build_interp"] < survey["build_interp"]
+    assert own["build_interp"] < contract["build_interp"]
     assert own["spread_tiles"] == 12 + 84 + 12 + 8 * T
     _, own_full = bench.byte_models(0, False, 7, T, False)
     assert own_full["spread_tiles"] == 12 + 324 + 12 + 8 * T

@@ -285,7 +285,7 @@ def test_trained_network_gain(orc, torch_cuda, which):
     keeps the network's shape functions for a large share of the (marker,
     component) pairs, where the untrained network keeps almost none; in both
     cases the interpolated velocity stays within 1e-4 of the FP64 oracle's
-    exact-MLS interpolation (the gate is the judge).
+    exact-MLS interpolation (the gate decides).
 
     The gate enforces the consistency conditions, which make the interpolation
     exact for fields that are linear over the stencil; what remains scales

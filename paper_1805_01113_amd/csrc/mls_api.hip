@@ -68,6 +68,7 @@ mls_status mls::setup_tiles(Ctx &c, int want)
             a.tile = want;
         }
     }
+    for (int d = 0; d < 3; ++d) g.ax[d].inv_tile = 1.0f / (float)g.ax[d].tile;
     int64_t nt = 1;
     for (int d = 0; d < 3; ++d) {
         const Axis &a = g.ax[d];

@@ -170,12 +170,8 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
         st_stream(hout, ok ? pack_home(G[0].ih, G[1].ih, G[2].ih) : 0xffffffffu);
         // the 27 field values are requested before the solve, which hides
         // their latency
-        int64_t oy[3], oz[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            oy[a] = ok ? (int64_t)nb_index(G[1].ih, a - 1, nyc, g.ax[1].periodic) * nxc : 0;
-            oz[a] = ok ? (int64_t)nb_index(G[2].ih, a - 1, nzc, g.ax[2].periodic) * nxc * nyc : 0;
-        }
+        uint32_t oy[3], oz[3];
+        support_rows(ok, G[1].ih, G[2].ih, nxc, nyc, nzc, g.ax[1].periodic, g.ax[2].periodic, oy, oz);
         Support sp;
         load_support(q, ok ? G[0].ih : 1, nxc, oy, oz, sp);
         const float vbv = vb ? vb[c * n + m] : 0.0f;
@@ -535,12 +531,8 @@ k_fast_interp(const Grid *__restrict__ gp, const float4 *__restrict__ tab, int n
         ok = ok && axis_geo(g.ax[2], c == 2, pz, G[2]);
         if (!ok) neutral_geo(G);
         st_stream(hout, ok ? pack_home(G[0].ih, G[1].ih, G[2].ih) : 0xffffffffu);
-        int64_t oy[3], oz[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            oy[a] = ok ? (int64_t)nb_index(G[1].ih, a - 1, nyc, g.ax[1].periodic) * nxc : 0;
-            oz[a] = ok ? (int64_t)nb_index(G[2].ih, a - 1, nzc, g.ax[2].periodic) * nxc * nyc : 0;
-        }
+        uint32_t oy[3], oz[3];
+        support_rows(ok, G[1].ih, G[2].ih, nxc, nyc, nzc, g.ax[1].periodic, g.ax[2].periodic, oy, oz);
         float qv[kNe];
         load_support(q, ok ? G[0].ih : 1, nxc, oy, oz, qv);
         const float vbv = vb ? vb[c * n + m] : 0.0f;

@@ -490,6 +490,23 @@ __device__ __forceinline__ int nb_index(int i, int a, int n, int periodic)
     return j;
 }
 
+// Node offsets of the three y rows (oy) and z layers (oz) of the support of
+// home (., j, k) on a component grid of nx x ny x nz nodes; zero when ok is
+// false (a lane without a support, which loads row 0).  The grid limits (at
+// most 2048 x 2048 x 1024 nodes per component) keep every node index below
+// 2^32 and nx ny at most 2^22, so the offsets are exact 24-bit products in
+// 32 bits (full-rate multiplies instead of 64-bit ones).
+__device__ __forceinline__ void support_rows(bool ok, int j, int k, int nx, int ny, int nz, int py, int pz,
+                                             uint32_t oy[3], uint32_t oz[3])
+{
+    const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        oy[a] = ok ? __umul24((uint32_t)nb_index(j, a - 1, ny, py), (uint32_t)nx) : 0u;
+        oz[a] = ok ? __umul24((uint32_t)nb_index(k, a - 1, nz, pz), nxy) : 0u;
+    }
+}
+
 // The 27 values of a field on the support of a home node, as loaded by
 // load_support: v holds the window of each row, e the far end of the row for
 // a stencil that wraps round a periodic x axis.  at(k) is the value of node
@@ -520,15 +537,15 @@ struct Support {
 // window registers are never rewritten, so the common path does not wait for
 // the loads before the solve that follows them.  The values are those of one
 // load per node.  A lane without a support passes i = 1 and row offsets 0.
-__device__ __forceinline__ void load_support(const float *__restrict__ q, int i, int nx, const int64_t oy[3],
-                                             const int64_t oz[3], Support &sp)
+__device__ __forceinline__ void load_support(const float *__restrict__ q, int i, int nx, const uint32_t oy[3],
+                                             const uint32_t oz[3], Support &sp)
 {
-    const int64_t sx = min(max(i - 1, 0), nx - 3);
+    const uint32_t sx = (uint32_t)min(max(i - 1, 0), nx - 3);
     struct Row3 { float v[3]; };
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
         Row3 t;
-        __builtin_memcpy(&t, q + oz[r / 3] + oy[r % 3] + sx, sizeof t);
+        __builtin_memcpy(&t, q + (oz[r / 3] + oy[r % 3] + sx), sizeof t);
         sp.v[3 * r] = t.v[0]; sp.v[3 * r + 1] = t.v[1]; sp.v[3 * r + 2] = t.v[2];
     }
     sp.lo = i < 1;
@@ -537,7 +554,7 @@ __device__ __forceinline__ void load_support(const float *__restrict__ q, int i,
     for (int r = 0; r < 9; ++r) sp.e[r] = 0.f;
     if (__any(sp.lo || sp.hi)) {
 #pragma unroll
-        for (int r = 0; r < 9; ++r) sp.e[r] = q[oz[r / 3] + oy[r % 3] + (sp.lo ? nx - 1 : 0)];
+        for (int r = 0; r < 9; ++r) sp.e[r] = q[oz[r / 3] + oy[r % 3] + (sp.lo ? (uint32_t)nx - 1u : 0u)];
     }
 }
 
@@ -548,22 +565,22 @@ __device__ __forceinline__ void load_support(const float *__restrict__ q, int i,
 // than Support.  The fused fast-MLS kernel, at its limit of 128 registers, and
 // the velocity-gradient kernel, which uses the values inside its node visitor,
 // are faster this way.
-__device__ __forceinline__ void load_support(const float *__restrict__ q, int i, int nx, const int64_t oy[3],
-                                             const int64_t oz[3], float qv[kNe])
+__device__ __forceinline__ void load_support(const float *__restrict__ q, int i, int nx, const uint32_t oy[3],
+                                             const uint32_t oz[3], float qv[kNe])
 {
-    const int64_t sx = min(max(i - 1, 0), nx - 3);
+    const uint32_t sx = (uint32_t)min(max(i - 1, 0), nx - 3);
     struct Row3 { float v[3]; };
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
         Row3 t;
-        __builtin_memcpy(&t, q + oz[r / 3] + oy[r % 3] + sx, sizeof t);
+        __builtin_memcpy(&t, q + (oz[r / 3] + oy[r % 3] + sx), sizeof t);
         qv[3 * r] = t.v[0]; qv[3 * r + 1] = t.v[1]; qv[3 * r + 2] = t.v[2];
     }
     const bool lo = i < 1, hi = i > nx - 2;   // only on a periodic axis
     if (__any(lo || hi)) {
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
-            const float e = q[oz[r / 3] + oy[r % 3] + (lo ? nx - 1 : 0)];
+            const float e = q[oz[r / 3] + oy[r % 3] + (lo ? (uint32_t)nx - 1u : 0u)];
             const float a0 = qv[3 * r], a1 = qv[3 * r + 1], a2 = qv[3 * r + 2];
             qv[3 * r] = lo ? e : (hi ? a1 : a0);
             qv[3 * r + 1] = lo ? a0 : (hi ? a2 : a1);
@@ -684,7 +701,7 @@ __device__ __forceinline__ uint32_t tile_from_geo(const Grid &g, int c, const Ax
     for (int d = 0; d < 3; ++d) {
         int cell = G[d].ih;
         if (d == c && G[d].s[1] > 0.0f) cell = cell > 0 ? cell - 1 : g.ax[d].n - 1;
-        t[d] = tile_of(cell, 1.0f / (float)g.ax[d].tile);
+        t[d] = tile_of(cell, g.ax[d].inv_tile);
     }
     return (uint32_t)(((int64_t)t[2] * g.ntile[1] + t[1]) * g.ntile[0] + t[0]);
 }

@@ -296,12 +296,8 @@ k_interp_grad(const Grid *__restrict__ gp, Weight Wt, float tau, int64_t n, cons
                 continue;
             }
             const int nx = comp_dim(g, c, 0), ny = comp_dim(g, c, 1), nz = comp_dim(g, c, 2);
-            int64_t oy[3], oz[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                oy[a] = (int64_t)nb_index(ih[1], a - 1, ny, g.ax[1].periodic) * nx;
-                oz[a] = (int64_t)nb_index(ih[2], a - 1, nz, g.ax[2].periodic) * nx * ny;
-            }
+            uint32_t oy[3], oz[3];
+            support_rows(true, ih[1], ih[2], nx, ny, nz, g.ax[1].periodic, g.ax[2].periodic, oy, oz);
             // the 27 field values are requested before the solve, which hides
             // their latency
             float qv[kNe];

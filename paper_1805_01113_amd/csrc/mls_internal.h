@@ -30,6 +30,7 @@ struct Axis {
     int32_t periodic;   // 1 = periodic
     int32_t uniform;    // 1 = all cell widths bitwise equal
     int32_t tile;       // tile edge (nodes) of the spreading grid along this axis
+    float inv_tile;     // 1.0f / tile in FP32 (correctly rounded, as the device division gives it)
     int32_t exact;      // 1: faces[i] == f0 + i*h and centres[i] == f0 + (i+0.5)*h bit for bit
     double h;           // L / n (exactly-uniform axes)
     double f0;          // faces[0]

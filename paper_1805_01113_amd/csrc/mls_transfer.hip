@@ -46,12 +46,9 @@ k_interp(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ ho
                 out[l] = __builtin_nanf("");
                 continue;
             }
-            int64_t oy[3], oz[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                oy[a] = (int64_t)nb_index(j, a - 1, g.dims[c][1], g.ax[1].periodic) * g.dims[c][0];
-                oz[a] = (int64_t)nb_index(k, a - 1, g.dims[c][2], g.ax[2].periodic) * g.dims[c][0] * g.dims[c][1];
-            }
+            uint32_t oy[3], oz[3];
+            support_rows(true, j, k, g.dims[c][0], g.dims[c][1], g.dims[c][2], g.ax[1].periodic, g.ax[2].periodic,
+                         oy, oz);
             Support sp;
             load_support(q, i, g.dims[c][0], oy, oz, sp);
             const float *p = phi + phi_at(l, c);
@@ -96,13 +93,9 @@ k_interp_rows(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict
             float acc = __builtin_nanf(""), f = __builtin_nanf(""), cfv = 0.f;
             if (ok) {
                 const float *q = c == 0 ? u : (c == 1 ? v : w);
-                int64_t oy[3], oz[3];
-#pragma unroll
-                for (int s3 = 0; s3 < 3; ++s3) {
-                    oy[s3] = (int64_t)nb_index(j, s3 - 1, g.dims[c][1], g.ax[1].periodic) * g.dims[c][0];
-                    oz[s3] = (int64_t)nb_index(k, s3 - 1, g.dims[c][2], g.ax[2].periodic) * g.dims[c][0] *
-                             g.dims[c][1];
-                }
+                uint32_t oy[3], oz[3];
+                support_rows(true, j, k, g.dims[c][0], g.dims[c][1], g.dims[c][2], g.ax[1].periodic,
+                             g.ax[2].periodic, oy, oz);
                 Support sp;
                 load_support(q, i, g.dims[c][0], oy, oz, sp);
                 const float *pp = phi + phi_at(p, c);
@@ -153,9 +146,9 @@ __device__ __forceinline__ int64_t marker_tile(const Grid &g, const uint32_t *__
         valid = valid && home_ok(g, c, hc[c][0], hc[c][1], hc[c][2]);
     }
     // the cell on axis d is the home of component (d + 1) % 3 (centre-staggered on d)
-    const int tx = tile_of(hc[1][0], 1.0f / (float)g.ax[0].tile);
-    const int ty = tile_of(hc[2][1], 1.0f / (float)g.ax[1].tile);
-    const int tz = tile_of(hc[0][2], 1.0f / (float)g.ax[2].tile);
+    const int tx = tile_of(hc[1][0], g.ax[0].inv_tile);
+    const int ty = tile_of(hc[2][1], g.ax[1].inv_tile);
+    const int tz = tile_of(hc[0][2], g.ax[2].inv_tile);
     return ((int64_t)tz * g.ntile[1] + ty) * g.ntile[0] + tx;
 }
 
@@ -220,7 +213,7 @@ k_bin_pos(const Grid *__restrict__ gp, int64_t n, const float *__restrict__ x, c
     const int lane = threadIdx.x & 63;
     const unsigned long long lower = (1ull << lane) - 1ull;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const float itx = 1.0f / (float)g.ax[0].tile, ity = 1.0f / (float)g.ax[1].tile, itz = 1.0f / (float)g.ax[2].tile;
+    const float itx = g.ax[0].inv_tile, ity = g.ax[1].inv_tile, itz = g.ax[2].inv_tile;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
         const int64_t l = base + lane;
         int64_t t = -1;

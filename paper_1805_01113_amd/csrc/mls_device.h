@@ -75,6 +75,39 @@ __device__ __forceinline__ double wrap_x(const Axis &a, double x)
     return X;
 }
 
+// The cell i with f[i] <= X < f[i+1] (i in [0, n-1], clamped at the ends),
+// from a guess i on a uniform axis.  The FP64 guess is off by at most one
+// cell unless the coordinates are close to the resolution of FP64, so one
+// step is taken first and only a lane that moved walks on; the result is
+// that of walking from the guess.
+__device__ __forceinline__ int fix_cell(const Axis &a, double X, int i)
+{
+    const int n = a.n;
+    const bool dn = i > 0 && X < fval(a, i);
+    const bool up = !dn && i < n - 1 && X >= fval(a, i + 1);
+    i += (int)up - (int)dn;
+    if (dn || up) {
+        while (i > 0 && X < fval(a, i)) --i;
+        while (i < n - 1 && X >= fval(a, i + 1)) ++i;
+    }
+    return i;
+}
+
+// The face node i in [1, n-1] with c[i-1] <= X < c[i] (clamped at the
+// ends), from a guess i on a uniform axis; as fix_cell.
+__device__ __forceinline__ int fix_face(const Axis &a, double X, int i)
+{
+    const int n = a.n;
+    const bool dn = i > 1 && X < cval(a, i - 1);
+    const bool up = !dn && i < n - 1 && X >= cval(a, i);
+    i += (int)up - (int)dn;
+    if (dn || up) {
+        while (i > 1 && X < cval(a, i - 1)) --i;
+        while (i < n - 1 && X >= cval(a, i)) ++i;
+    }
+    return i;
+}
+
 // Eulerian cell along one axis that contains x: f[i] <= X < f[i+1], X wrapped
 // into [f0, f0 + L) on a periodic axis.  false for a non-finite coordinate or
 // one outside [f0, fn) on a wall axis.
@@ -85,10 +118,7 @@ __device__ __forceinline__ bool cell_axis(const Axis &a, double x, int &i)
     const double X = a.periodic ? wrap_x(a, x) : x;
     if (!(X >= fval(a, 0) && X < fval(a, n))) return false;
     if (a.uniform) {
-        i = (int)floor((X - a.f0) * a.inv_h);
-        i = min(max(i, 0), n - 1);
-        while (i > 0 && X < fval(a, i)) --i;
-        while (i < n - 1 && X >= fval(a, i + 1)) ++i;
+        i = fix_cell(a, X, min(max((int)floor((X - a.f0) * a.inv_h), 0), n - 1));
     } else {
         int lo = 0, hi = n;   // faces[lo] <= X < faces[hi]
         while (hi - lo > 1) {
@@ -118,10 +148,7 @@ __device__ __forceinline__ bool locate(const Axis &a, int is_face, double x, int
     if (!is_face) {
         if (X >= fval(a, n)) return false;
         if (a.uniform) {
-            i = (int)floor((X - a.f0) * a.inv_h);
-            i = min(max(i, 0), n - 1);
-            while (i > 0 && X < fval(a, i)) --i;
-            while (i < n - 1 && X >= fval(a, i + 1)) ++i;
+            i = fix_cell(a, X, min(max((int)floor((X - a.f0) * a.inv_h), 0), n - 1));
         } else {
             int lo = 0, hi = n;   // faces[lo] <= X < faces[hi]
             while (hi - lo > 1) {
@@ -137,10 +164,7 @@ __device__ __forceinline__ bool locate(const Axis &a, int is_face, double x, int
             i = n;
         } else if (a.uniform) {
             // centres[i-1] <= X < centres[i], i in [1, n-1]
-            i = (int)floor((X - a.f0) * a.inv_h + 0.5);
-            i = min(max(i, 1), n - 1);
-            while (i > 1 && X < cval(a, i - 1)) --i;
-            while (i < n - 1 && X >= cval(a, i)) ++i;
+            i = fix_face(a, X, min(max((int)floor((X - a.f0) * a.inv_h + 0.5), 1), n - 1));
         } else {
             int lo = 0, hi = n - 1;   // centres[lo] <= X < centres[hi]
             while (hi - lo > 1) {

@@ -679,20 +679,35 @@ __device__ __forceinline__ float eq8_coef_built(const Grid &g, int c, int hi, in
     return eq8_coef(g, c, hi, hj, hk, ph, af);
 }
 
+// Largest value of the 64 lanes of a wavefront (all lanes active), returned
+// to every lane: four DPP steps give each 16-lane row its maximum (lane
+// pairs, quads, half rows, rows), then the four row maxima are read out.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));    // quad_perm [1,0,3,2]
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));    // quad_perm [2,3,0,1]
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));   // row_half_mirror
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));   // row_mirror
+    const uint32_t r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+    const uint32_t r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+    return max(max(r0, r1), max(r2, r3));
+}
+
 // Per-key maxima of the lanes of a wavefront: for every distinct key >= 0 the
 // largest v of the lanes holding it goes into tmax[key] with one atomic max
-// (v finite and >= 0; positive floats order as unsigned integers).  Every
-// lane of the wavefront must call it.
+// (v finite and >= 0; such floats order as their bit patterns do, so the
+// maximum is taken on those).  Every lane of the wavefront must call it.
 __device__ __forceinline__ void wave_key_max(uint32_t *tmax, int64_t key, float v)
 {
     unsigned long long pending = __ballot(key >= 0);
     while (pending) {
         const int leader = __ffsll((long long)pending) - 1;
-        const int64_t kl = __shfl(key, leader);
+        const int64_t kl = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)((uint64_t)key >> 32), leader)
+                                      << 32) |
+                                     (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)key, leader));
         const bool mine = key == kl;
-        float m = mine ? v : 0.f;
-        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-        if ((int)(threadIdx.x & 63) == leader && m > 0.f) atomicMax(&tmax[kl], __float_as_uint(m));
+        const uint32_t m = wave_max_u32(mine ? __float_as_uint(v) : 0u);
+        if ((int)(threadIdx.x & 63) == leader && m > 0u) atomicMax(&tmax[kl], m);
         pending &= ~__ballot(mine);
     }
 }

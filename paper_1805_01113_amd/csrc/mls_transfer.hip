@@ -157,6 +157,40 @@ __device__ __forceinline__ int64_t marker_tile(const Grid &g, const uint32_t *__
 // order, so a tile's marker list is made of runs of consecutive markers.
 // The counting pass also records each marker's tile (ntiles for a marker
 // without a usable support) for the per-tile force maxima.
+// Counting sort step of one wavefront (all lanes active): lanes with tile
+// t >= 0 are grouped by tile; the counting pass adds each group's size to
+// count[t], the filling pass reserves a range of cursor[t] per group and
+// writes the group's markers there in lane order.  The groups are found with
+// ballots first, then every group leader issues its atomic in one
+// instruction, so the wavefront waits for one round trip, not one per tile.
+template <bool FILL>
+__device__ __forceinline__ void wave_bin(int64_t t, int lane, uint32_t *count, uint32_t *cursor, uint32_t *entries,
+                                         uint32_t marker)
+{
+    unsigned long long pending = __ballot(t >= 0);
+    unsigned long long group = 0;   // lanes of this lane's tile
+    int leader = 0;
+    while (pending) {
+        const int lead = __ffsll((long long)pending) - 1;
+        const int64_t tl = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)((uint64_t)t >> 32), lead)
+                                      << 32) |
+                                     (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)t, lead));
+        const unsigned long long mask = __ballot(t == tl) & pending;
+        if (t == tl) { group = mask; leader = lead; }
+        pending &= ~mask;
+    }
+    if (t < 0) return;
+    const uint32_t cnt = (uint32_t)__popcll(group);
+    if (!FILL) {
+        if (lane == leader) atomicAdd(&count[t], cnt);
+    } else {
+        uint32_t pos = 0;
+        if (lane == leader) pos = atomicAdd(&cursor[t], cnt);
+        pos = __shfl(pos, leader);
+        entries[pos + __popcll(group & ((1ull << lane) - 1ull))] = marker;
+    }
+}
+
 template <bool FILL>
 __global__ void __launch_bounds__(kBlock)
 k_bin(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home, uint32_t *__restrict__ count,
@@ -165,7 +199,6 @@ k_bin(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home,
 {
     const Grid &g = *gp;
     const int lane = threadIdx.x & 63;
-    const unsigned long long lower = (1ull << lane) - 1ull;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     // the loop bound is wave-uniform so that the ballots see the whole wave
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
@@ -178,17 +211,7 @@ k_bin(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ home,
             else if (!FILL) raise_error(err, l, MLS_E_SUPPORT);   // contributes nothing
             if (!FILL) tile_of_marker[l] = valid ? (uint32_t)tt : (uint32_t)g.ntiles;
         }
-        unsigned long long pending = __ballot(t >= 0);
-        while (pending) {
-            const int leader = __ffsll((long long)pending) - 1;
-            const int64_t tlead = __shfl(t, leader);
-            const unsigned long long mask = __ballot(t == tlead) & pending;
-            uint32_t pos = 0;
-            if (lane == leader) pos = atomicAdd(FILL ? &cursor[tlead] : &count[tlead], (uint32_t)__popcll(mask));
-            pos = __shfl(pos, leader);
-            if (FILL && ((mask >> lane) & 1ull)) entries[pos + __popcll(mask & lower)] = (uint32_t)l;
-            pending &= ~mask;
-        }
+        wave_bin<FILL>(t, lane, count, cursor, entries, (uint32_t)l);
     }
 }
 
@@ -211,7 +234,6 @@ k_bin_pos(const Grid *__restrict__ gp, int64_t n, const float *__restrict__ x, c
     const Grid &g = *gp;
     const uint64_t step = (!FILL && amp2 > 0.0f) ? *step_ctr : 0ull;
     const int lane = threadIdx.x & 63;
-    const unsigned long long lower = (1ull << lane) - 1ull;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const float itx = g.ax[0].inv_tile, ity = g.ax[1].inv_tile, itz = g.ax[2].inv_tile;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
@@ -244,17 +266,7 @@ k_bin_pos(const Grid *__restrict__ gp, int64_t n, const float *__restrict__ x, c
                 tiles[l] = (uint32_t)t;
             }
         }
-        unsigned long long pending = __ballot(t >= 0);
-        while (pending) {
-            const int leader = __ffsll((long long)pending) - 1;
-            const int64_t tlead = __shfl(t, leader);
-            const unsigned long long mask = __ballot(t == tlead) & pending;
-            uint32_t pos = 0;
-            if (lane == leader) pos = atomicAdd(FILL ? &cursor[tlead] : &count[tlead], (uint32_t)__popcll(mask));
-            pos = __shfl(pos, leader);
-            if (FILL && ((mask >> lane) & 1ull)) entries[pos + __popcll(mask & lower)] = (uint32_t)l;
-            pending &= ~mask;
-        }
+        wave_bin<FILL>(t, lane, count, cursor, entries, (uint32_t)l);
     }
 }
 

@@ -311,7 +311,10 @@ __global__ void __launch_bounds__(kBlock) k_scan_top(uint32_t *__restrict__ part
 }
 
 // Also clears the per-tile force maxima tmax[3][tstride] of the scanned
-// tiles, ahead of the kernels that write c_l F_l.
+// tiles, ahead of the kernels that write c_l F_l.  Each thread scans 8
+// consecutive counts; the counts come in and the offsets go out through LDS
+// so that every global access of a wavefront is one contiguous run (8-element
+// strided stores leave partial lines that reach memory several times over).
 __global__ void __launch_bounds__(kBlock) k_scan_final(const uint32_t *__restrict__ count, int64_t nt,
                                                        const uint32_t *__restrict__ partial,
                                                        uint32_t *__restrict__ off, uint32_t *__restrict__ cursor,
@@ -319,31 +322,41 @@ __global__ void __launch_bounds__(kBlock) k_scan_final(const uint32_t *__restric
                                                        int64_t tstride)
 {
     __shared__ uint32_t sh[4];
+    __shared__ uint32_t buf[kScanChunk];
     const int64_t base = (int64_t)blockIdx.x * kScanChunk;
-    // each thread owns 8 consecutive elements
     const int per = kScanChunk / kBlock;
+    for (int q = 0; q < per; ++q) {
+        const int64_t i = base + q * kBlock + threadIdx.x;
+        buf[q * kBlock + threadIdx.x] = i < nt ? count[i] : 0u;
+    }
+    __syncthreads();
     uint32_t vals[kScanChunk / kBlock];
     uint32_t s = 0;
     for (int q = 0; q < per; ++q) {
-        const int64_t i = base + (int64_t)threadIdx.x * per + q;
-        vals[q] = i < nt ? count[i] : 0u;
+        vals[q] = buf[threadIdx.x * per + q];
         s += vals[q];
     }
     uint32_t total;
     uint32_t run = partial[blockIdx.x] + block_exclusive_scan(s, sh, total);
     for (int q = 0; q < per; ++q) {
-        const int64_t i = base + (int64_t)threadIdx.x * per + q;
+        buf[threadIdx.x * per + q] = run;
+        run += vals[q];
+    }
+    // the owner of the last tile also writes off[nt] = total
+    const int64_t first = base + (int64_t)threadIdx.x * per;
+    if (first <= nt - 1 && nt - 1 < first + per) off[nt] = run;
+    __syncthreads();
+    for (int q = 0; q < per; ++q) {
+        const int64_t i = base + q * kBlock + threadIdx.x;
         if (i < nt) {
-            off[i] = run;
-            cursor[i] = run;
+            const uint32_t o = buf[q * kBlock + threadIdx.x];
+            off[i] = o;
+            cursor[i] = o;
             tmax[i] = 0u;
             tmax[tstride + i] = 0u;
             tmax[2 * tstride + i] = 0u;
         }
-        run += vals[q];
     }
-    const int64_t first = base + (int64_t)threadIdx.x * per;
-    if (first <= nt - 1 && nt - 1 < first + per) off[nt] = run;   // the owner of the last tile
     if (blockIdx.x == 0 && threadIdx.x < 64) work[threadIdx.x] = 0u;   // colour list sizes and cursors
 }
 

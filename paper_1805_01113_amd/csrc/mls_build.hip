@@ -166,7 +166,7 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
         bool ok = axis_geo(g.ax[0], c == 0, px, G[0]);
         ok = ok && axis_geo(g.ax[1], c == 1, py, G[1]);
         ok = ok && axis_geo(g.ax[2], c == 2, pz, G[2]);
-        if (!ok) neutral_geo(G);
+        neutral_geo_unless(ok, G);
         st_stream(hout, ok ? pack_home(G[0].ih, G[1].ih, G[2].ih) : 0xffffffffu);
         // the 27 field values are requested before the solve, which hides
         // their latency
@@ -529,7 +529,7 @@ k_fast_interp(const Grid *__restrict__ gp, const float4 *__restrict__ tab, int n
         bool ok = axis_geo(g.ax[0], c == 0, px, G[0]);
         ok = ok && axis_geo(g.ax[1], c == 1, py, G[1]);
         ok = ok && axis_geo(g.ax[2], c == 2, pz, G[2]);
-        if (!ok) neutral_geo(G);
+        neutral_geo_unless(ok, G);
         st_stream(hout, ok ? pack_home(G[0].ih, G[1].ih, G[2].ih) : 0xffffffffu);
         uint32_t oy[3], oz[3];
         support_rows(ok, G[1].ih, G[2].ih, nxc, nyc, nzc, g.ax[1].periodic, g.ax[2].periodic, oy, oz);

@@ -248,11 +248,14 @@ __device__ __forceinline__ void axis_offsets_d(const Axis &a, int is_face, doubl
 
 // ---- weight function ------------------------------------------------------
 
-// SplitMix64 (Steele, Lea, Flood 2014) output function of the state
-// seed + (ctr + 1) * golden gamma: a counter-based generator.
-__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t ctr)
+// SplitMix64 (Steele, Lea, Flood 2014) as a counter-based generator: value
+// ctr is the output function applied to the state seed + (ctr + 1) * gamma
+// (mod 2^64), gamma the golden-ratio increment below.
+constexpr uint64_t kSplitMixGamma = 0x9E3779B97F4A7C15ull;
+
+// The output function applied to a state z.
+__device__ __forceinline__ uint64_t splitmix64_mix(uint64_t z)
 {
-    uint64_t z = seed + (ctr + 1ull) * 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
@@ -267,9 +270,12 @@ __device__ __forceinline__ void jitter_marker(uint64_t seed, uint64_t step, int6
                                               float x0, float y0, float z0, float &x, float &y, float &z)
 {
     const uint64_t base = ((uint64_t)step * (uint64_t)n + (uint64_t)l) * 3ull;
-    const float ux = (float)(splitmix64(seed, base + 0) >> 40) * 0x1p-24f;
-    const float uy = (float)(splitmix64(seed, base + 1) >> 40) * 0x1p-24f;
-    const float uz = (float)(splitmix64(seed, base + 2) >> 40) * 0x1p-24f;
+    // the states of counters base, base + 1, base + 2 are consecutive
+    // multiples of the increment (mod 2^64): one multiply, two adds
+    const uint64_t st = seed + (base + 1ull) * kSplitMixGamma;
+    const float ux = (float)(splitmix64_mix(st) >> 40) * 0x1p-24f;
+    const float uy = (float)(splitmix64_mix(st + kSplitMixGamma) >> 40) * 0x1p-24f;
+    const float uz = (float)(splitmix64_mix(st + 2ull * kSplitMixGamma) >> 40) * 0x1p-24f;
     x = x0 + (ux - 0.5f) * amp2;
     y = y0 + (uy - 0.5f) * amp2;
     z = z0 + (uz - 0.5f) * amp2;

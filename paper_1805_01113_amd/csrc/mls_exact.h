@@ -72,6 +72,22 @@ __device__ __forceinline__ void neutral_geo(AxisGeo G[3])
     }
 }
 
+// The same stencil where ok is false, by selects on every field (G may hold
+// anything there), so that the compiler does not first set every register to
+// the neutral values and then copy the located ones over them.
+__device__ __forceinline__ void neutral_geo_unless(bool ok, AxisGeo G[3])
+{
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        G[d].ih = ok ? G[d].ih : 0;
+        G[d].s[0] = ok ? G[d].s[0] : -1.f;
+        G[d].s[1] = ok ? G[d].s[1] : 0.f;
+        G[d].s[2] = ok ? G[d].s[2] : 1.f;
+        G[d].xi = ok ? G[d].xi : 0.f;
+        G[d].rho = ok ? G[d].rho : 1.f;
+    }
+}
+
 __device__ __forceinline__ void mark_failed(ErrWord *err, int64_t l, double px, double py, double pz,
                                             uint32_t *hout, float *out, uint8_t *rout)
 {

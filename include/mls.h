@@ -360,8 +360,9 @@ mls_status mls_fast_tables(mls_ctx *ctx, float *dst, int64_t *count, int32_t *ro
  * blocked home / phi / route layout holds marker order[p] (see
  * mls_step_order), so that the tiles read their rows contiguously, and U and
  * F stay indexed by marker.  The exact and fast-MLS builds run fused with the
- * interpolation and forcing (phi is not read back); the learned build stores
- * its rows and one more kernel interpolates and forces from them.  Markers whose support
+ * interpolation and forcing (phi is not read back); the learned build
+ * stores its rows and interpolates and forces from a copy of them in LDS
+ * in the same kernel.  Markers whose support
  * leaves the grid come last.  The order of the markers inside a tile may
  * differ between runs; U, F and the forcing do not.  With the other methods
  * (and fast-MLS on a stretched grid) rows are in marker order.  All buffers are caller-owned device arrays:

@@ -45,19 +45,6 @@ __device__ __forceinline__ bool solve_fp64_regs(const Grid &g, const Weight &W, 
     return ok;
 }
 
-// The same FP64 re-solve storing phi (out points at the marker's first support
-// node, consecutive nodes kLanes floats apart), so that every path that
-// re-solves a pair stores the same values.
-__device__ __forceinline__ bool solve_fp64(const Grid &g, const Weight &W, int c, double px, double py, double pz,
-                                           float *out)
-{
-    float ph[kNe];
-    const bool ok = solve_fp64_regs(g, W, c, px, py, pz, ph);
-#pragma unroll
-    for (int k = 0; k < kNe; ++k) out[k * kLanes] = ph[k];
-    return ok;
-}
-
 // Stencil for a marker without a support: the uniform node offsets -1, 0, 1
 // at node 0.  The fused kernels compute such a marker like any other (so all
 // lanes issue the same memory operations) and store NaN in its place.
@@ -171,9 +158,9 @@ __device__ __forceinline__ bool exact_fp32(const Weight &W, float tau, const Axi
 
 // Shape functions of component c from the support geometry G of a located
 // marker, stored at out (the marker's first support node, nodes kLanes floats
-// apart).  route_bits is stored with bit 0 set when the solve went to FP64;
-// routed and kmax accumulate the lane's statistics.  Returns true if the FP32
-// solve was used (then ph holds the values).
+// apart) and returned in ph.  route_bits is stored with bit 0 set when the
+// solve went to FP64; routed and kmax accumulate the lane's statistics.
+// Returns true if the FP32 solve was used.
 __device__ __forceinline__ bool exact_from_geo(const Grid &g, const Weight &W, float tau, int c, int64_t l,
                                                double px, double py, double pz, const AxisGeo G[3], float *out,
                                                uint8_t *rout, uint8_t route_bits, ErrWord *err,
@@ -186,7 +173,9 @@ __device__ __forceinline__ bool exact_from_geo(const Grid &g, const Weight &W, f
         return true;
     }
     ++routed;
-    if (!solve_fp64(g, W, c, px, py, pz, out)) raise_error(err, l, MLS_E_SINGULAR);
+    if (!solve_fp64_regs(g, W, c, px, py, pz, ph)) raise_error(err, l, MLS_E_SINGULAR);
+#pragma unroll
+    for (int k = 0; k < kNe; ++k) out[k * kLanes] = ph[k];
     if (rout) *rout = route_bits | 1;
     return false;
 }

@@ -224,8 +224,25 @@ hipError_t launch_fast_interp(const Ctx &c, int64_t n, const float *x, const flo
                               const float *w, const float *vb, const float *area, float dt, float *U, float *F,
                               hipStream_t s, bool trilinear_blend);
 // order: row p holds marker order[p] (the time step's tile order); NULL: row = marker.
+// Outputs of the interpolation (eq. 6), direct forcing and c_l F_l (eq. 8)
+// that the learned build computes from its rows in a time step: U and F by
+// marker, c_l F_l by row (cf, cf_stride), tile maxima in tmax (tstride per
+// component) keyed by tile_of_marker.  U == nullptr: no interpolation.
+struct LearnedInterp {
+    const float *u = nullptr, *v = nullptr, *w = nullptr, *vb = nullptr, *area = nullptr;
+    float inv_dt = 0.0f;
+    float *U = nullptr, *F = nullptr, *cf = nullptr;
+    int64_t cf_stride = 0;
+    const uint32_t *tile_of_marker = nullptr;
+    uint32_t *tmax = nullptr;
+    int64_t tstride = 0;
+};
 hipError_t launch_build_learned(Ctx &c, int64_t n, const float *x, const float *y, const float *z,
-                                uint32_t *home, float *phi, uint8_t *route, hipStream_t s, const uint32_t *order = nullptr);
+                                uint32_t *home, float *phi, uint8_t *route, hipStream_t s, const uint32_t *order = nullptr,
+                                const LearnedInterp *interp = nullptr);
+// The interpolation arguments of a learned time step on the context's rows.
+LearnedInterp learned_interp(const Ctx &c, const float *u, const float *v, const float *w, const float *vb,
+                             const float *area, float dt, float *U, float *F);
 hipError_t launch_table_build(const Ctx &c, hipStream_t s);
 hipError_t launch_collide(const Ctx &c, int64_t n, const float *x, const float *y, const float *z,
                           const int32_t *body, int32_t *coll, uint8_t *flags, hipStream_t s);
@@ -265,11 +282,6 @@ hipError_t launch_build_interp(const Ctx &c, int64_t n, const float *x, const fl
                                uint32_t *home, float *phi, uint8_t *route, const float *u, const float *v,
                                const float *w, const float *vb, const float *area, float dt, float *U, float *F,
                                hipStream_t s);
-// U, F by marker and c_l F_l by row from shape functions stored in the rows of
-// the last binning (the learned time step).
-hipError_t launch_interp_rows(const Ctx &c, int64_t n, const uint32_t *home, const float *phi, const float *u,
-                              const float *v, const float *w, const float *vb, const float *area, float dt, float *U,
-                              float *F, hipStream_t s);
 hipError_t launch_spread_sorted(Ctx &c, int64_t n, const uint32_t *home, const float *phi, float *fx, float *fy,
                                 float *fz, hipStream_t s);
 // Dynamic LDS of a spreading tile workgroup: the int64 box of one component.

@@ -449,11 +449,16 @@ __device__ __forceinline__ f32x16 evaluate(const uint4 *img, const float *b1, co
     return y3;
 }
 
+// Rows of one wavefront staged in LDS for the fused interpolation (after the
+// network image): 27 values of 64 rows, node-major like the stored rows.
+constexpr size_t kLearnStageBytes = (size_t)(kLearnBlock / 64) * kNe * 64 * sizeof(float);
+
 __global__ void __launch_bounds__(kLearnBlock)
 k_build_learned(const Grid *__restrict__ gp, const Weight W, float tau, float tol, int64_t n,
                 const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
                 const uint4 *__restrict__ image, uint32_t *__restrict__ home, float *__restrict__ phi,
-                uint8_t *__restrict__ route, ErrWord *err, DevStats *st, const uint32_t *__restrict__ order)
+                uint8_t *__restrict__ route, ErrWord *err, DevStats *st, const uint32_t *__restrict__ order,
+                const LearnedInterp li)
 {
     extern __shared__ uint4 lds[];
     // the GELU table in a static LDS array (placed first, so its rows are
@@ -470,6 +475,8 @@ k_build_learned(const Grid *__restrict__ gp, const Weight W, float tau, float to
 
     const Grid &g = *gp;
     const int lane = threadIdx.x & 63, h = lane >> 5, r = lane & 31;
+    float *const stage = reinterpret_cast<float *>(reinterpret_cast<char *>(lds) + kMlpImageBytes) +
+                         wave_id() * (kNe * 64);
     const int64_t items = ((n + 63) >> 6) * 3;
     const int64_t wstride = (int64_t)gridDim.x * (kLearnBlock / 64);
     unsigned long long routed = 0, n_fb = 0, n_ok = 0;
@@ -485,6 +492,7 @@ k_build_learned(const Grid *__restrict__ gp, const Weight W, float tau, float to
         uint8_t *rout = route ? route + ((blk * 3 + c) << 6) : nullptr;
         float f[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         bool ok = false;
+        uint32_t hv = 0xffffffffu;
         if (l < n) {
             const double px = (double)x[mk], py = (double)y[mk], pz = (double)z[mk];
             AxisGeo G[3];
@@ -494,7 +502,8 @@ k_build_learned(const Grid *__restrict__ gp, const Weight W, float tau, float to
             if (!ok) {
                 mark_failed(err, mk, px, py, pz, hout, out + lane, rout ? rout + lane : nullptr);
             } else {
-                *hout = pack_home(G[0].ih, G[1].ih, G[2].ih);
+                hv = pack_home(G[0].ih, G[1].ih, G[2].ih);
+                *hout = hv;
                 f[0] = G[0].xi; f[1] = G[1].xi; f[2] = G[2].xi;
                 f[3] = G[0].rho; f[4] = G[1].rho; f[5] = G[2].rho;
             }
@@ -546,7 +555,10 @@ k_build_learned(const Grid *__restrict__ gp, const Weight W, float tau, float to
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
                     const int k = 8 * (j / 4) + 4 * h + (j % 4);
-                    if (k < kNe) out[k * kLanes + 32 * t + r] = yv[j];
+                    if (k < kNe) {
+                        out[k * kLanes + 32 * t + r] = yv[j];
+                        if (li.U) stage[k * 64 + 32 * t + r] = yv[j];
+                    }
                 }
                 if (rout && h == 0) rout[32 * t + r] = 2;
             }
@@ -565,6 +577,54 @@ k_build_learned(const Grid *__restrict__ gp, const Weight W, float tau, float to
             float ph[kNe];
             exact_from_geo(g, W, tau, c, mk, px, py, pz, G, out + lane, rout ? rout + lane : nullptr, 4, err, routed,
                            kmax, ph);
+            if (li.U) {
+#pragma unroll
+                for (int k = 0; k < kNe; ++k) stage[k * 64 + lane] = ph[k];
+            }
+        }
+        if (li.U) {
+            // Interpolation (eq. 6), direct forcing and c_l F_l (eq. 8) of the
+            // rows just built, from the wavefront's LDS copy of them: the same
+            // arithmetic as interpolating the stored rows, without reading
+            // them back from memory.  U and F go out by marker, c_l F_l by row,
+            // and the largest |c_l F_l| per spreading tile into tmax.
+            __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): this wavefront's LDS writes are done
+            __builtin_amdgcn_wave_barrier();
+            asm volatile("" ::: "memory");
+            const bool in = l < n;
+            float acc = __builtin_nanf(""), fo = __builtin_nanf(""), cfv = 0.0f;
+            if (ok) {
+                int i, j, k;
+                unpack_home(hv, i, j, k);
+                const float *q = c == 0 ? li.u : (c == 1 ? li.v : li.w);
+                uint32_t oy[3], oz[3];
+                support_rows(true, j, k, g.dims[c][0], g.dims[c][1], g.dims[c][2], g.ax[1].periodic,
+                             g.ax[2].periodic, oy, oz);
+                Support sp;
+                load_support(q, i, g.dims[c][0], oy, oz, sp);
+                float ph[kNe];
+#pragma unroll
+                for (int kk = 0; kk < kNe; ++kk) ph[kk] = stage[kk * 64 + lane];
+                acc = 0.0f;
+#pragma unroll
+                for (int kk = 0; kk < kNe; ++kk) acc += ph[kk] * sp.at(kk);
+                const float vbv = li.vb ? li.vb[c * n + mk] : 0.0f;
+                fo = (vbv - acc) * li.inv_dt;
+                cfv = eq8_coef_built(g, c, i, j, k, ph, li.area[mk] * fo);
+                if (!(fabsf(cfv) <= 3.0e38f)) raise_error(err, mk, MLS_E_RANGE);
+            }
+            if (in) {
+                li.U[c * n + mk] = acc;
+                li.F[c * n + mk] = fo;
+                li.cf[c * li.cf_stride + l] = ok ? cfv : 0.0f;
+            }
+            const uint32_t tl = in ? li.tile_of_marker[mk] : (uint32_t)g.ntiles;
+            wave_key_max(li.tmax + c * li.tstride, ok && tl < (uint32_t)g.ntiles ? (int64_t)tl : -1,
+                         finite_abs(cfv));
+            // the next item's stage writes come after every lane's reads
+            __builtin_amdgcn_s_waitcnt(0xc07f);
+            __builtin_amdgcn_wave_barrier();
+            asm volatile("" ::: "memory");
         }
     }
     unsigned long long tot = routed;
@@ -637,7 +697,7 @@ hipError_t mlp_alloc(Ctx &c)
         return e;
     }
     return hipFuncSetAttribute((const void *)k_build_learned, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)kMlpImageBytes);
+                               (int)(kMlpImageBytes + kLearnStageBytes));
 }
 
 void mlp_free(Ctx &c)
@@ -659,8 +719,22 @@ hipError_t mlp_pack(Ctx &c, hipStream_t s)
     return hipGetLastError();
 }
 
+LearnedInterp learned_interp(const Ctx &c, const float *u, const float *v, const float *w, const float *vb,
+                             const float *area, float dt, float *U, float *F)
+{
+    LearnedInterp li;
+    li.u = u; li.v = v; li.w = w; li.vb = vb; li.area = area;
+    li.inv_dt = 1.0f / dt;
+    li.U = U; li.F = F;
+    li.cf = c.cf_rows; li.cf_stride = c.cf_stride;
+    li.tile_of_marker = c.marker_tile;
+    li.tmax = c.tile_fmax; li.tstride = c.g.ntiles + 1;
+    return li;
+}
+
 hipError_t launch_build_learned(Ctx &c, int64_t n, const float *x, const float *y, const float *z, uint32_t *home,
-                                float *phi, uint8_t *route, hipStream_t s, const uint32_t *order)
+                                float *phi, uint8_t *route, hipStream_t s, const uint32_t *order,
+                                const LearnedInterp *interp)
 {
     if (n == 0) return hipSuccess;
     Mlp &net = c.mlp;
@@ -673,9 +747,10 @@ hipError_t launch_build_learned(Ctx &c, int64_t n, const float *x, const float *
     const int64_t waves = ((n + 63) / 64) * 3;
     int64_t blocks = (waves + kLearnBlock / 64 - 1) / (kLearnBlock / 64);
     if (blocks > c.cu_count) blocks = c.cu_count;
-    hipLaunchKernelGGL(k_build_learned, dim3((unsigned)blocks), dim3(kLearnBlock), kMlpImageBytes, s, c.d_grid, c.w,
-                       tau, tol, n, x, y, z, static_cast<const uint4 *>(net.image), home, phi, route, c.err, c.stats,
-                       order);
+    const LearnedInterp li = interp ? *interp : LearnedInterp{};
+    hipLaunchKernelGGL(k_build_learned, dim3((unsigned)blocks), dim3(kLearnBlock),
+                       kMlpImageBytes + (li.U ? kLearnStageBytes : 0), s, c.d_grid, c.w, tau, tol, n, x, y, z,
+                       static_cast<const uint4 *>(net.image), home, phi, route, c.err, c.stats, order, li);
     return hipGetLastError();
 }
 

@@ -161,15 +161,11 @@ mls_status mls_step(mls_ctx *ctx, const mls_step_desc *desc, const mls_step_buff
                    : launch_sort_positions(c, n, bx, by, bz, s);
         if (e != hipSuccess) return MLS_E_HIP;
         if (learned) {
-            // the network (with its exact fallback) in tile order, then
-            // interpolation, forcing and c_l F_l of the stored rows
-            {
-                TimedLaunch t(c, MLS_K_BUILD_LEARNED, s);
-                e = launch_build_learned(c, n, bx, by, bz, b->home, b->phi, b->route, s, c.entries);
-            }
-            if (e != hipSuccess) return MLS_E_HIP;
-            TimedLaunch t(c, MLS_K_INTERP, s);
-            e = launch_interp_rows(c, n, b->home, b->phi, b->u, b->v, b->w, b->vb, b->area, desc->dt, b->U, b->F, s);
+            // the network (with its exact fallback) in tile order, fused with
+            // the interpolation, forcing and c_l F_l of its rows
+            TimedLaunch t(c, MLS_K_BUILD_LEARNED, s);
+            const LearnedInterp li = learned_interp(c, b->u, b->v, b->w, b->vb, b->area, desc->dt, b->U, b->F);
+            e = launch_build_learned(c, n, bx, by, bz, b->home, b->phi, b->route, s, c.entries, &li);
         } else if (fast) {
             TimedLaunch t(c, MLS_K_FAST_INTERP, s);
             e = launch_fast_interp(c, n, bx, by, bz, b->home, b->phi, b->route, b->u, b->v, b->w, b->vb, b->area,

@@ -60,66 +60,6 @@ k_interp(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ ho
     }
 }
 
-// Interpolation (eq. 6), direct forcing and c_l F_l (eq. 8) of the rows of a
-// time step whose shape functions were built in tile order (the learned
-// step): row p holds marker order[p].  U and F go out by marker, c_l F_l by
-// row, and each tile's largest |c_l F_l| (tile of the marker from the
-// binning) into tmax for the spreading's fixed-point scale.  A row without a
-// usable support (its error already raised by the build) gets NaN U and F and
-// c_l F_l = 0.
-__global__ void __launch_bounds__(kBlock)
-k_interp_rows(const Grid *__restrict__ gp, int64_t n, const uint32_t *__restrict__ order,
-              const uint32_t *__restrict__ home, const float *__restrict__ phi, const float *__restrict__ u,
-              const float *__restrict__ v, const float *__restrict__ w, const float *__restrict__ vb,
-              const float *__restrict__ area, float inv_dt, float *__restrict__ U, float *__restrict__ F,
-              float *__restrict__ cf, int64_t cf_stride, const uint32_t *__restrict__ tile_of_marker,
-              uint32_t *__restrict__ tmax, int64_t tstride, ErrWord *err)
-{
-    const Grid &g = *gp;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    // wave-uniform loop bound: every lane takes part in the per-tile maxima
-    for (int64_t base = xcd_block() * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
-        const int64_t p = base + (threadIdx.x & 63);
-        const bool in = p < n;
-        const int64_t m = in ? (int64_t)order[p] : 0;
-        const float a = in ? area[m] : 0.f;
-        const uint32_t tl = in ? tile_of_marker[m] : (uint32_t)g.ntiles;
-        const int64_t key = tl < (uint32_t)g.ntiles ? (int64_t)tl : -1;
-#pragma unroll 1
-        for (int c = 0; c < 3; ++c) {
-            int i = 0, j = 0, k = 0;
-            if (in) unpack_home(home[home_at(p, c)], i, j, k);
-            const bool ok = in && home_ok(g, c, i, j, k);
-            float acc = __builtin_nanf(""), f = __builtin_nanf(""), cfv = 0.f;
-            if (ok) {
-                const float *q = c == 0 ? u : (c == 1 ? v : w);
-                uint32_t oy[3], oz[3];
-                support_rows(true, j, k, g.dims[c][0], g.dims[c][1], g.dims[c][2], g.ax[1].periodic,
-                             g.ax[2].periodic, oy, oz);
-                Support sp;
-                load_support(q, i, g.dims[c][0], oy, oz, sp);
-                const float *pp = phi + phi_at(p, c);
-                float ph[kNe];
-#pragma unroll
-                for (int kk = 0; kk < kNe; ++kk) ph[kk] = pp[kk * kLanes];
-                acc = 0.f;
-#pragma unroll
-                for (int kk = 0; kk < kNe; ++kk) acc += ph[kk] * sp.at(kk);
-                const float vbv = vb ? vb[c * n + m] : 0.0f;
-                f = (vbv - acc) * inv_dt;
-                cfv = eq8_coef_built(g, c, i, j, k, ph, a * f);
-                if (!(fabsf(cfv) <= 3.0e38f)) raise_error(err, m, MLS_E_RANGE);
-            }
-            if (in) {
-                U[c * n + m] = acc;
-                F[c * n + m] = f;
-                cf[c * cf_stride + p] = ok ? cfv : 0.f;
-            }
-            wave_key_max(tmax + c * tstride, ok ? key : -1, finite_abs(cfv));
-        }
-    }
-}
-
 // ---- spreading: tile binning -------------------------------------------------
 //
 // Every marker belongs to exactly one tile of the grid: the tile holding its
@@ -847,19 +787,6 @@ static hipError_t launch_tiles(Ctx &c, const SpreadScratch &sc, const uint32_t *
     case 19: return launch_tiles_bx<SORTED, NF, 19>(c, sc, home, phi, fx, fy, fz, s, timed);
     default: return launch_tiles_bx<SORTED, NF, 0>(c, sc, home, phi, fx, fy, fz, s, timed);
     }
-}
-
-hipError_t launch_interp_rows(const Ctx &c, int64_t n, const uint32_t *home, const float *phi, const float *u,
-                              const float *v, const float *w, const float *vb, const float *area, float dt, float *U,
-                              float *F, hipStream_t s)
-{
-    if (n == 0) return hipSuccess;
-    int64_t blocks = (n + kBlock - 1) / kBlock;
-    blocks = round_up8(std::min(blocks, (int64_t)c.cu_count * c.interp_blocks_per_cu));
-    hipLaunchKernelGGL(k_interp_rows, dim3((unsigned)blocks), dim3(kBlock), 0, s, c.d_grid, n, c.entries, home, phi,
-                       u, v, w, vb, area, 1.0f / dt, U, F, c.cf_rows, c.cf_stride, c.marker_tile, c.tile_fmax,
-                       c.g.ntiles + 1, c.err);
-    return hipGetLastError();
 }
 
 hipError_t launch_interp(const Ctx &c, int64_t n, const uint32_t *home, const float *phi,

@@ -210,8 +210,8 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, int32_t flags, const mls_s
         if (st != MLS_OK) { c.timing = timing; return st; }
     }
     // exact and (on uniform grids) fast-MLS run fused and in tile order; the
-    // learned step runs in tile order too (network, then interpolation,
-    // forcing and c_l F_l of the rows)
+    // learned step runs in tile order too (the network fused with the
+    // interpolation, forcing and c_l F_l of its rows)
     const bool learned = method == MLS_LEARNED;
     const bool exact = method == MLS_EXACT || (fast && fast_fused_ok(c)) || learned;
     auto build = [&]() {
@@ -219,10 +219,8 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, int32_t flags, const mls_s
         hipError_t e = launch_sort_positions(c, n, b->x0, b->y0, b->z0, s);
         if (e == hipSuccess) {
             if (learned) {
-                e = launch_build_learned(c, n, b->x0, b->y0, b->z0, b->home, b->phi, nullptr, s, c.entries);
-                if (e == hipSuccess)
-                    e = launch_interp_rows(c, n, b->home, b->phi, b->u, b->v, b->w, b->vb, b->area, 1.0f, b->U, b->F,
-                                           s);
+                const LearnedInterp li = learned_interp(c, b->u, b->v, b->w, b->vb, b->area, 1.0f, b->U, b->F);
+                e = launch_build_learned(c, n, b->x0, b->y0, b->z0, b->home, b->phi, nullptr, s, c.entries, &li);
             } else if (fast)
                 e = launch_fast_interp(c, n, b->x0, b->y0, b->z0, b->home, b->phi, nullptr, b->u, b->v, b->w, b->vb,
                                        b->area, 1.0f, b->U, b->F, s, method == MLS_FAST_LINEAR);
@@ -233,11 +231,7 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, int32_t flags, const mls_s
         return e == hipSuccess ? MLS_OK : MLS_E_HIP;
     };
     auto interp = [&]() {
-        if (learned)
-            return launch_interp_rows(c, n, b->home, b->phi, b->u, b->v, b->w, b->vb, b->area, 1.0f, b->U, b->F, s) ==
-                           hipSuccess
-                       ? MLS_OK
-                       : MLS_E_HIP;
+        if (learned) return MLS_OK;   // fused into the learned build
         return mls_interp(ctx, n, b->home, b->phi, b->u, b->v, b->w, U, V, Wv, stream);
     };
     auto spread = [&]() {

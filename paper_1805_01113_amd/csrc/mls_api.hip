@@ -163,7 +163,7 @@ mls_status reserve_compact(mls_ctx *ctx, int64_t n)
     c.route_queue = nullptr;
     c.coef_cap = 0;
     const int64_t npad = (n + 63) / 64 * 64;
-    hipError_t e = hipMalloc((void **)&c.coef_rows, (size_t)3 * 13 * npad * sizeof(float));
+    hipError_t e = hipMalloc((void **)&c.coef_rows, (size_t)3 * kCoefStride<13> * npad * sizeof(float));
     if (e == hipSuccess) e = hipMalloc((void **)&c.route_queue, (size_t)(1 + 3 * n) * sizeof(uint32_t));
     if (e != hipSuccess) {
         hipFree(c.coef_rows);

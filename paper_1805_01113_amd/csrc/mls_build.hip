@@ -110,13 +110,15 @@ k_build_exact(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n,
 // own stored values).  It also writes c_m F_m of eq. 8 by row (cf_rows), the
 // value the spreading scatters with the shape function.
 //
-// NF = 0 stores the 27 values of phi per row.  NF = 7 or 13 stores the
-// compact transfer function instead (rows of NF floats, blocked like phi):
-// gamma = A^{-1} e_0, then per axis the centre offset s_1 (NF = 7, every axis
-// uniform: the outer offsets are s_1 -+ 1 in FP32) or the three offsets s_a
-// (NF = 13).  phi_k = W_k (gamma . p_k) follows from them with the weights;
-// a row solved in FP64 is marked by a NaN gamma_0 and its position in tile
-// order is queued in rq (count first), so that k_route_phi stores its phi.
+// NF = 0 stores the 27 values of phi per row and c_l F_l in cf_rows.  NF = 7
+// or 13 stores the compact transfer function instead, with c_l F_l after it
+// (rows of kCoefStride<NF> floats, one lane's row in 16-byte words, see
+// coef_word): gamma = A^{-1} e_0, then per axis the centre offset s_1 (NF = 7,
+// every axis uniform: the outer offsets are s_1 -+ 1 in FP32) or the three
+// offsets s_a (NF = 13).  phi_k = W_k (gamma . p_k) follows from them with the
+// weights; a row solved in FP64 is marked by a NaN gamma_0 and its position in
+// tile order is queued in rq (count first), so that k_route_rows stores its
+// phi and its c_l F_l.
 template <int NF>
 __global__ void __launch_bounds__(kBuildBlock) __attribute__((amdgpu_waves_per_eu(NF == 0 ? 2 : 3)))
 k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n, const uint32_t *__restrict__ order,
@@ -192,19 +194,6 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
 #pragma unroll
             for (int k = 0; k < kNe; ++k) st_stream(&out[k * kLanes], ok ? ph[k] : nan);
         } else {
-            float *cr = coef + ((((base >> 6) * 3 + c) * NF) << 6) + lane;
-            st_stream(&cr[0], ok && !fp64 ? gam[0] : nan);
-#pragma unroll
-            for (int j = 1; j < 4; ++j) st_stream(&cr[j * kLanes], gam[j]);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                if constexpr (NF == 7) {
-                    st_stream(&cr[(4 + d) * kLanes], G[d].s[1]);
-                } else {
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) st_stream(&cr[(4 + 3 * d + a) * kLanes], G[d].s[a]);
-                }
-            }
             // queue the rows solved in FP64 (rare; one reservation per wavefront)
             const unsigned long long rmask = __ballot(fp64 && ok && valid);
             if (rmask) {
@@ -221,10 +210,27 @@ k_build_interp(const Grid *__restrict__ gp, const Weight W, float tau, int64_t n
         const float f = (vbv - acc) * inv_dt;
         st_stream(&U[c * n + m], ok ? acc : nan);
         st_stream(&F[c * n + m], ok ? f : nan);
-        // c_l F_l (eq. 8) by row for the spreading (row p < cf_stride: padding
-        // rows too); a queued compact row gets its U, F and c F from k_route_rows
+        // c_l F_l (eq. 8) by row for the spreading (padding rows too); a queued
+        // compact row gets its U, F and c F from k_route_rows
         const float cfv = eq8_coef_built(g, c, G[0].ih, G[1].ih, G[2].ih, ph, ca * f);
-        st_stream(&cf_rows[c * cf_stride + base + lane], ok ? cfv : 0.0f);
+        if constexpr (NF == 0) {
+            st_stream(&cf_rows[c * cf_stride + base + lane], ok ? cfv : 0.0f);
+        } else {
+            // the compact row: gamma (NaN gamma_0 marks a row solved in FP64),
+            // the offsets and c_l F_l, in 16-byte words
+            constexpr int rs = kCoefStride<NF>;
+            const int64_t row = base + lane;
+            auto word = [&](int q) { return reinterpret_cast<f32x4 *>(coef + coef_word(row, c, rs, q)); };
+            const float cfs = ok ? cfv : 0.0f;
+            st_stream(word(0), f32x4{ok && !fp64 ? gam[0] : nan, gam[1], gam[2], gam[3]});
+            if constexpr (NF == 7) {
+                st_stream(word(1), f32x4{G[0].s[1], G[1].s[1], G[2].s[1], cfs});
+            } else {
+                st_stream(word(1), f32x4{G[0].s[0], G[0].s[1], G[0].s[2], G[1].s[0]});
+                st_stream(word(2), f32x4{G[1].s[1], G[1].s[2], G[2].s[0], G[2].s[1]});
+                st_stream(word(3), f32x4{G[2].s[2], cfs, 0.0f, 0.0f});
+            }
+        }
         if (!ok) {
             raise_error(err, m, isfinite(px) && isfinite(py) && isfinite(pz) ? MLS_E_SUPPORT : MLS_E_NONFINITE);
         } else if (NF == 0 || !fp64) {
@@ -256,18 +262,19 @@ __global__ void k_clear_words(uint32_t *p, int64_t n)
 // count) is row << 2 | component, row in tile order.  For each, the FP64
 // re-solve of the pair, its phi stored into the blocked rows, and the
 // interpolation and direct forcing that the build skipped: U and F by marker,
-// c F (eq. 8) by row.
+// c F (eq. 8) into the row's compact slot (index nf of the row).
 __global__ void __launch_bounds__(kBlock)
 k_route_rows(const Grid *__restrict__ gp, const Weight W, int64_t n, const uint32_t *__restrict__ order,
              const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
              const uint32_t *__restrict__ home, const uint32_t *__restrict__ rq, float *__restrict__ phi,
              const float *__restrict__ u, const float *__restrict__ v, const float *__restrict__ w,
              const float *__restrict__ vb, const float *__restrict__ area, float inv_dt, float *__restrict__ U,
-             float *__restrict__ F, float *__restrict__ cf_rows, int64_t cf_stride,
-             const uint32_t *__restrict__ marker_tile, uint32_t *__restrict__ tmax, int64_t tstride, ErrWord *err)
+             float *__restrict__ F, float *__restrict__ coef, int nf, const uint32_t *__restrict__ marker_tile,
+             uint32_t *__restrict__ tmax, int64_t tstride, ErrWord *err)
 {
     const Grid &g = *gp;
     const uint32_t cnt = rq[0];
+    const int rs = nf == 7 ? kCoefStride<7> : kCoefStride<13>;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
         const uint32_t e = rq[1 + i];
         const int64_t row = e >> 2;
@@ -296,7 +303,7 @@ k_route_rows(const Grid *__restrict__ gp, const Weight W, int64_t n, const uint3
         U[c * n + m] = acc;
         F[c * n + m] = f;
         const float cfv = eq8_coef_built(g, c, hi, hj, hk, ph, ca * f);
-        cf_rows[c * cf_stride + row] = cfv;
+        coef[coef_word(row, c, rs, nf >> 2) + (nf & 3)] = cfv;
         if (!(fabsf(cfv) <= 3.0e38f)) raise_error(err, m, MLS_E_RANGE);
         const float av = finite_abs(cfv);
         if (av > 0.f) atomicMax(&tmax[c * tstride + marker_tile[m]], __float_as_uint(av));
@@ -767,7 +774,7 @@ hipError_t launch_build_interp(const Ctx &c, int64_t n, const float *x, const fl
                            z, home, phi, route, u, v, w, vb, area, 1.0f / dt, U, F, c.cf_rows, c.cf_stride,
                            c.coef_rows, c.route_queue, c.tile_fmax, c.g.ntiles + 1, c.err, c.stats);
     hipLaunchKernelGGL(k_route_rows, dim3(c.cu_count), dim3(kBlock), 0, s, c.d_grid, c.w, n, c.entries, x, y, z,
-                       home, c.route_queue, phi, u, v, w, vb, area, 1.0f / dt, U, F, c.cf_rows, c.cf_stride,
+                       home, c.route_queue, phi, u, v, w, vb, area, 1.0f / dt, U, F, c.coef_rows, c.step_nf,
                        c.marker_tile, c.tile_fmax, c.g.ntiles + 1, c.err);
     return hipGetLastError();
 }

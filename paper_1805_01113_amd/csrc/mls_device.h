@@ -430,6 +430,18 @@ __device__ __forceinline__ int64_t phi_at(int64_t l, int c)
 {
     return ((((l >> 6) * 3 + c) * kNe) << 6) + (l & 63);   // + k * kLanes for node k
 }
+// Compact transfer-function rows of a compact exact step (NF = 7 or 13 values:
+// gamma, the support offsets) with c_l F_l of eq. 8 after them, rs floats per
+// row (kCoefStride): two or four 16-byte words per row, and for a (64-row
+// block, component) the words q of its 64 rows consecutive, so that one
+// wavefront instruction moves 1 KB of whole cache lines.  Float offset of
+// word q of row l.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int64_t coef_word(int64_t l, int c, int rs, int q)
+{
+    return (((((l >> 6) * 3 + c) * (rs >> 2) + q) << 6) + (l & 63)) << 2;
+}
+
 __device__ __forceinline__ int64_t home_at(int64_t l, int c)
 {
     return (((l >> 6) * 3 + c) << 6) + (l & 63);

@@ -22,6 +22,10 @@ constexpr int kMaxBoxTile = 16;   // largest tile edge cut from a longer axis (a
 constexpr int kMaxBlocksPerCu = 64;   // largest tunable workgroups per compute unit of a launch
 constexpr int kBuildGridMultiple = 24;   // build grids are a multiple of this many workgroups
 constexpr int kPackI = 11, kPackJ = 11;  // home packing i | j << 11 | k << 22
+// Floats per compact transfer-function row (NF = 7 or 13 values and c_l F_l,
+// padded to 16-byte words).
+template <int NF>
+constexpr int kCoefStride = NF == 7 ? 8 : 16;
 constexpr uint32_t kMaskI = (1u << kPackI) - 1, kMaskJ = (1u << kPackJ) - 1;
 
 // One axis of the Eulerian grid as the device sees it.

@@ -450,9 +450,9 @@ __device__ __forceinline__ void flush_box(const Grid &g, int c, unsigned long lo
 // row's compact transfer function (gamma and the support offsets, NF = 7 or
 // 13 floats, see k_build_interp) with the build's own arithmetic, or read
 // from phi for a row the build solved in FP64 (NaN gamma_0).
-// cf holds c_l F_l of eq. 8 per component: by row in tile order (SORTED, the
-// exact time step's rows; its fused build writes them) or by marker (a
-// standalone call: k_spread_coef).  Per tile, the largest finite |c_l F_l|
+// c_l F_l of eq. 8 per component comes with a compact row (NF > 0), or from
+// cf: by row in tile order (SORTED with full rows, the time step's fused
+// builds write them) or by marker (a standalone call: k_spread_coef).  Per tile, the largest finite |c_l F_l|
 // of its rows sets the fixed-point scale of each component.
 // Workgroups of 128 or 256 threads (tuned, at most kSpreadBlock).  A tile
 // holds some 200 rows: when each workgroup handles many tiles, 128 threads
@@ -530,17 +530,23 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, const uint32_t *__restr
                 const int64_t row = SORTED ? (int64_t)e : (int64_t)entries[e];
                 int hi, hj, hk;
                 unpack_home(home[home_at(row, c)], hi, hj, hk);
-                const float cfv = cf[c * cf_stride + row];
+                float cfv;
                 float ph[kNe];
                 if constexpr (NF == 0) {
+                    cfv = cf[c * cf_stride + row];
                     const float *p = phi + phi_at(row, c);
 #pragma unroll
                     for (int k = 0; k < kNe; ++k) ph[k] = p[k * kLanes];
                 } else {
-                    const float *cr = coef + ((((row >> 6) * 3 + c) * NF) << 6) + (row & 63);
-                    float cfr[NF];
+                    // the compact row and c_l F_l in two or four 16-byte loads
+                    float cfr[kCoefStride<NF>];
 #pragma unroll
-                    for (int j = 0; j < NF; ++j) cfr[j] = cr[j * kLanes];
+                    for (int q = 0; q < kCoefStride<NF> / 4; ++q) {
+                        const f32x4 t =
+                            *reinterpret_cast<const f32x4 *>(coef + coef_word(row, c, kCoefStride<NF>, q));
+                        cfr[4 * q] = t.x; cfr[4 * q + 1] = t.y; cfr[4 * q + 2] = t.z; cfr[4 * q + 3] = t.w;
+                    }
+                    cfv = cfr[NF];
                     // evaluated for every row (all loads issue at once); a row the
                     // build solved in FP64 has a NaN gamma_0 and its stored phi is
                     // read instead, under a wavefront-wide test

@@ -123,6 +123,29 @@ def test_uneven_grid_tiles(orc, torch_cuda, dims, tile):
                 kw=dict(spread_tile=tile))
 
 
+def test_face_and_centre_markers_non_power_of_two(orc, torch_cuda):
+    """Markers at the faces and centres of a 24 x 40 x 36 periodic grid, as
+    FP32 coordinates: the FP64 faces i/n are not FP32 values, so every marker
+    lies within one FP32 rounding below or above a control-volume boundary.
+    Homes must follow the oracle's control-volume rule bit for bit on either
+    side, and the interpolation and spreading stay within tolerance."""
+    dims = (24, 40, 36)
+    gs = W.GridSpec([W.uniform_faces(n) for n in dims], [True] * 3)
+    r = np.random.default_rng(2024)
+    n = 3000
+    coords = []
+    for d, nd in enumerate(dims):
+        i = r.integers(0, nd, n)
+        half = r.integers(0, 2, n) * 0.5          # faces and centres
+        coords.append(((i + half) / nd).astype(np.float32))
+    x, y, z = coords
+    area = r.uniform(0.2, 1.0, n).astype(np.float32) / 900
+    F = r.normal(size=(3, n)).astype(np.float32)
+    fields = [r.normal(size=gs.shape(c)).astype(np.float32) for c in range(3)]
+    _full_check(orc, torch_cuda, gs, x, y, z, area, F, fields, label="faces and centres 24x40x36",
+                kw=dict(spread_tile=4))
+
+
 def test_grid_rejected_without_tile_divisor(torch_cuda):
     """A periodic axis of 17 cells has no tile edge between 4 and 12."""
     from paper_1805_01113_amd import mls

@@ -203,7 +203,9 @@ def byte_models(method, compact, nf, t_per, jitter_kernel):
     rows of nf floats for an exact step, c_l F_l by row, U and F by marker)."""
     tf = 4.0 * 3 * (nf if compact else 27)
     contract = {
-        "build_exact": 348.0, "build_fast": 348.0, "build_learned": 348.0,
+        "build_exact": 348.0, "build_fast": 348.0,
+        # the learned build of a time step interpolates and forces as well
+        "build_learned": 348 + 336 + 12 + 4.0 * t_per,
         "interp": 336 + 12 + 4.0 * t_per,
         "build_interp": 348 + 336 + 12 + 4.0 * t_per,
         "fast_interp": 348 + 336 + 12 + 4.0 * t_per,
@@ -211,7 +213,10 @@ def byte_models(method, compact, nf, t_per, jitter_kernel):
     }
     own = {
         "jitter": 24.0,
-        "build_exact": 12 + 12 + 324.0, "build_fast": 12 + 12 + 324.0, "build_learned": 12 + 12 + 324.0,
+        "build_exact": 12 + 12 + 324.0, "build_fast": 12 + 12 + 324.0,
+        # positions and area, homes, full rows, touched field values, U and F
+        # by marker, c_l F_l by row
+        "build_learned": 16 + 12 + 324 + 4.0 * t_per + 12 + 12 + 12,
         "interp": 12 + 324 + 12 + 4.0 * t_per,
         # positions and area, homes, transfer functions, touched field values,
         # U and F by marker, c_l F_l by row

@@ -457,7 +457,7 @@ mls_status mls_timing_get(mls_ctx *ctx, mls_timing *out, int32_t reset);
  * *_blocks_per_cu (1..64): workgroups per compute unit in the grid of the
  * spreading tile launches (bounded further by the LDS of a tile's boxes), of
  * the exact / fast build and of the interpolation; a grid-stride loop covers
- * the work beyond the grid.  spread_threads (128 or 256): threads of a
+ * the work beyond the grid.  spread_threads (128, 192 or 256): threads of a
  * spreading tile workgroup (fewer suit many tiles per workgroup, more suit
  * few). */
 typedef struct {

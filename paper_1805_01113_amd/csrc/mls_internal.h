@@ -179,7 +179,7 @@ struct Ctx {
     // launch shapes (autotuned): resident workgroups per compute unit
     int spread_blocks_per_cu = 16;      // effective (bounded by the LDS of the tile boxes)
     int spread_blocks_per_cu_req = 16;  // requested
-    int spread_threads = 128;           // threads of a spreading tile workgroup (128 or 256)
+    int spread_threads = 128;           // threads of a spreading tile workgroup (128, 192 or 256)
     int build_blocks_per_cu = 32;
     int interp_blocks_per_cu = 32;
     int cu_count = 256;

@@ -454,7 +454,7 @@ __device__ __forceinline__ void flush_box(const Grid &g, int c, unsigned long lo
 // cf: by row in tile order (SORTED with full rows, the time step's fused
 // builds write them) or by marker (a standalone call: k_spread_coef).  Per tile, the largest finite |c_l F_l|
 // of its rows sets the fixed-point scale of each component.
-// Workgroups of 128 or 256 threads (tuned, at most kSpreadBlock).  A tile
+// Workgroups of 128, 192 or 256 threads (tuned, at most kSpreadBlock).  A tile
 // holds some 200 rows: when each workgroup handles many tiles, 128 threads
 // leave fewer lanes idle, pay cheaper barriers and keep more tiles in flight
 // per compute unit; when a colour has only a tile or two per workgroup, 256

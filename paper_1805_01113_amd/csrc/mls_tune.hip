@@ -145,7 +145,7 @@ mls_status mls_tune_set(mls_ctx *ctx, const mls_tune *in)
     Ctx &c = ctx->c;
     if (!bpc_ok(in->spread_blocks_per_cu) || !bpc_ok(in->build_blocks_per_cu) || !bpc_ok(in->interp_blocks_per_cu) ||
         in->spread_tile < 4 || in->spread_tile > kMaxBoxTile ||
-        (in->spread_threads != 128 && in->spread_threads != 256))
+        (in->spread_threads != 128 && in->spread_threads != 192 && in->spread_threads != 256))
         return MLS_E_ARG;
     c.spread_blocks_per_cu_req = in->spread_blocks_per_cu;
     c.spread_threads = in->spread_threads;
@@ -277,7 +277,7 @@ mls_status mls_autotune(mls_ctx *ctx, int32_t method, int32_t flags, const mls_s
     double t_spread = 1e30;
     const int tiles[] = {4, 6, 8, 10, 12, 16};
     const int spcs[] = {1, 2, 4, 8, 16, 32};
-    const int sthreads[] = {128, 256};
+    const int sthreads[] = {128, 192, 256};
     std::vector<std::vector<int>> seen;
     for (int tile : tiles) {
         if (!ok) break;

@@ -100,9 +100,9 @@ def test_every_tile_edge_matches_oracle(orc, torch_cuda):
 
 
 def test_spread_shapes_give_identical_forcing(torch_cuda):
-    """The compact exact step's forcing is the same bit for bit for 128- and
-    256-thread spreading workgroups and any number of them per compute unit
-    (fixed-point sums per tile), and out-of-range shapes are rejected."""
+    """The compact exact step's forcing is the same bit for bit for 128-, 192-
+    and 256-thread spreading workgroups and any number of them per compute
+    unit (fixed-point sums per tile), and out-of-range shapes are rejected."""
     from paper_1805_01113_amd import mls
     from paper_1805_01113_amd import workloads as W
     torch = torch_cuda
@@ -113,7 +113,7 @@ def test_spread_shapes_give_identical_forcing(torch_cuda):
     forcing = [torch.zeros(wl.grid.shape(c), dtype=torch.float32, device="cuda") for c in range(3)]
     bufs = mls.StepBuffers(ctx, x0, y0, z0, area, fields, forcing)
     outs = []
-    for th, bpc in ((128, 16), (256, 1), (256, 8), (128, 2)):
+    for th, bpc in ((128, 16), (256, 1), (256, 8), (192, 10), (128, 2)):
         ctx.tune_set(spread_threads=th, spread_blocks_per_cu=bpc)
         for f in forcing:
             f.zero_()
@@ -124,6 +124,6 @@ def test_spread_shapes_give_identical_forcing(torch_cuda):
     for o in outs[1:]:
         for c in range(3):
             assert np.array_equal(o[c], outs[0][c])
-    for bad in (64, 192, 512):
+    for bad in (64, 320, 512):
         with pytest.raises(mls.MLSError):
             ctx.tune_set(spread_threads=bad)

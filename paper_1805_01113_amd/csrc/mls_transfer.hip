@@ -489,9 +489,18 @@ k_spread_colour(const Grid *__restrict__ gp, int colour, const uint32_t *__restr
     // fewer than 2^22 nodes, (q + 1/2) times the FP32 reciprocal of the divisor
     // stays within 1/2 of a quotient's interval from its floor
     const float inv_bx = 1.0f / (float)bx, inv_bxy = 1.0f / (float)(bx * by);
+    // Tiles are claimed through one device-wide counter, whose atomics are
+    // served one after another.  A colour with only a few tiles per workgroup
+    // would have every workgroup queue on it at the start, and the last one to
+    // get its tile sets the launch's end; there the first round is handed out
+    // by position (tile b to workgroup b) and only the rest is claimed.
+    const uint32_t G = gridDim.x;
+    const uint32_t nfixed = nact < 4u * G ? min(nact, G) : 0u;
+    bool first = true;
     for (;;) {
         if (threadIdx.x == 0) {
-            const uint32_t i = atomicAdd(&work[32 + colour], 1u);
+            const uint32_t i = first && blockIdx.x < nfixed ? blockIdx.x : nfixed + atomicAdd(&work[32 + colour], 1u);
+            first = false;
             const int64_t t = i < nact ? (int64_t)active[abase + i] : -1;
             tile_sh = t < g.ntiles ? t : -1;
         }

@@ -31,9 +31,6 @@ constexpr int kBuildBlock = 64 * kBuildWaves;
 
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
-// component of wavefront w of this workgroup
-__device__ __forceinline__ int wave_component(int w) { return (int)((xcd_block() * kBuildWaves + w) % 3); }
-
 struct WaveWork {
     int c;            // velocity component
     int64_t base;     // first row of the first item

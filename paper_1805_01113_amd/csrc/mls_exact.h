@@ -45,23 +45,12 @@ __device__ __forceinline__ bool solve_fp64_regs(const Grid &g, const Weight &W, 
     return ok;
 }
 
-// Stencil for a marker without a support: the uniform node offsets -1, 0, 1
-// at node 0.  The fused kernels compute such a marker like any other (so all
-// lanes issue the same memory operations) and store NaN in its place.
-__device__ __forceinline__ void neutral_geo(AxisGeo G[3])
-{
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        G[d].ih = 0;
-        G[d].s[0] = -1.f; G[d].s[1] = 0.f; G[d].s[2] = 1.f;
-        G[d].xi = 0.f;
-        G[d].rho = 1.f;
-    }
-}
-
-// The same stencil where ok is false, by selects on every field (G may hold
-// anything there), so that the compiler does not first set every register to
-// the neutral values and then copy the located ones over them.
+// Stencil for a marker without a support (where ok is false): the uniform
+// node offsets -1, 0, 1 at node 0.  The fused kernels compute such a marker
+// like any other (so all lanes issue the same memory operations) and store
+// NaN in its place.  Selects on every field (G may hold anything there), so
+// that the compiler does not first set every register to the neutral values
+// and then copy the located ones over them.
 __device__ __forceinline__ void neutral_geo_unless(bool ok, AxisGeo G[3])
 {
 #pragma unroll

@@ -82,14 +82,16 @@ TimedLaunch::TimedLaunch(Ctx &c_, int id_, hipStream_t s_) : c(c_), id(id_), s(s
     }
     a = c.ev_pool[c.ev_used++];
     b = c.ev_pool[c.ev_used++];
-    hipEventRecord(a, s);
+    if (hipEventRecord(a, s) != hipSuccess) {   // no timing for this launch
+        a = nullptr;
+        c.ev_used -= 2;
+    }
 }
 
 TimedLaunch::~TimedLaunch()
 {
     if (!a) return;
-    hipEventRecord(b, s);
-    c.ev_marks.push_back({id, {a, b}});
+    if (hipEventRecord(b, s) == hipSuccess) c.ev_marks.push_back({id, {a, b}});
 }
 
 }  // namespace mls

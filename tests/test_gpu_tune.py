@@ -127,3 +127,38 @@ def test_spread_shapes_give_identical_forcing(torch_cuda):
     for bad in (64, 320, 512):
         with pytest.raises(mls.MLSError):
             ctx.tune_set(spread_threads=bad)
+
+
+def test_tile_handout_regimes_give_identical_forcing(torch_cuda):
+    """The spreading hands a colour's tiles out through a shared counter, or
+    its first round by position when the colour has fewer than four tiles per
+    workgroup.  On 1000 ellipsoids in 512^3 (about 1300 non-empty tiles of 8^3
+    cells per colour) 256 workgroups take the counter only, 512 a first round
+    by position and the counter, 2048 and more by position only (some get no
+    tile); the forcing of the compact exact step is the same bit for bit in
+    every case."""
+    from paper_1805_01113_amd import mls
+    from paper_1805_01113_amd import workloads as W
+    torch = torch_cuda
+    wl = W.ellipsoids()
+    ctx = mls.Context(wl.grid.faces, wl.grid.periodic)
+    x0, y0, z0, area = [torch.from_numpy(a).cuda() for a in (wl.x, wl.y, wl.z, wl.area)]
+    fields = wl.fields("cuda")
+    forcing = [torch.zeros(wl.grid.shape(c), dtype=torch.float32, device="cuda") for c in range(3)]
+    bufs = mls.StepBuffers(ctx, x0, y0, z0, area, fields, forcing)
+    outs = []
+    shapes = ((192, 1), (192, 2), (256, 4), (192, 8), (128, 32))
+    for th, bpc in shapes:
+        ctx.tune_set(spread_tile=8, spread_threads=th, spread_blocks_per_cu=bpc)
+        for f in forcing:
+            f.zero_()
+        mls.step_counter_set(ctx, 5)
+        mls.step(ctx, bufs, method=mls.MLS_EXACT, dt=1.0, jitter=0.2 / 512, seed=7, compact=True)
+        ctx.sync()
+        outs.append([f.cpu().numpy().copy() for f in forcing])
+        say("threads %d, %d per CU: forcing sum %s" % (th, bpc, ["%.6e" % float(o.sum(dtype=np.float64))
+                                                               for o in outs[-1]]))
+    assert max(float(np.abs(o).max()) for o in outs[0]) > 0.0
+    for o in outs[1:]:
+        for c in range(3):
+            assert np.array_equal(o[c], outs[0][c])
